@@ -1,0 +1,265 @@
+"""Oracle for the quantization-tree forward step and backward dynamic programming.
+
+TEST INFRASTRUCTURE ONLY.  Loaded by ``tests/``, by the smoke check in
+``__graft_entry__`` and by the CPU-baseline leg of ``bench.py``; never by the
+product package.  It shares no code with the GPU library.
+
+The numerical work lives in ``oracle.c`` (plain C, FP32 with explicit fused
+multiply-adds, FP64 for the backward step); this module only loads it with
+ctypes and marshals numpy arrays.  The paper is Pages & Wilbertz,
+arXiv:1101.3228: Sec. 2 (Voronoi cells, transition weights, quantized BDP),
+Sec. 3 (AR(1) proposition, Algorithm I), Sec. 4 (Algorithm III).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+LAYERWISE = 0
+PATHWISE = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (IEEE FP32, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-Wall", "-o", _LIB_PATH + ".tmp", _SRC, "-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("T", ctypes.c_void_p),
+                ("mu", ctypes.c_void_p), ("L", ctypes.c_void_p), ("x0", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        L.oracle_philox4x32_10.argtypes = [P, P, P]
+        L.oracle_ln_u24.argtypes = [ctypes.c_uint32]
+        L.oracle_ln_u24.restype = ctypes.c_float
+        L.oracle_sincos_2pi_u24.argtypes = [ctypes.c_uint32, P, P]
+        L.oracle_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32, P, P]
+        L.oracle_layer_pair.argtypes = [P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint32, P, P]
+        L.oracle_path_noise.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_uint32, P]
+        L.oracle_cell.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
+        L.oracle_cell.restype = ctypes.c_int32
+        L.oracle_transitions.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
+                                         P, ctypes.c_int32]
+        L.oracle_transitions.restype = ctypes.c_int
+        L.oracle_bdp.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, P, P]
+        L.oracle_bdp.restype = ctypes.c_int64
+        L.oracle_payoff.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def ln_u24(K: int) -> float:
+    return float(np.float32(lib().oracle_ln_u24(int(K))))
+
+
+def sincos_2pi_u24(J: int):
+    s = np.zeros(1, np.float32)
+    c = np.zeros(1, np.float32)
+    lib().oracle_sincos_2pi_u24(int(J), _ptr(s), _ptr(c))
+    return s[0], c[0]
+
+
+def box_muller(ra: int, rb: int):
+    z0 = np.zeros(1, np.float32)
+    z1 = np.zeros(1, np.float32)
+    lib().oracle_box_muller(int(ra), int(rb), _ptr(z0), _ptr(z1))
+    return z0[0], z1[0]
+
+
+class Model:
+    """Host-side AR(1) model X_{k+1} = A_k X_k + b_k + T_k eps_k with the
+    marginal X_k ~ mu_k + L_k z (Proposition, Sec. 3).  FP32 arrays."""
+
+    def __init__(self, d, n, A, b, T, mu, L, x0):
+        self.d, self.n = int(d), int(n)
+        self.A = np.ascontiguousarray(A, np.float32).reshape(n, d, d)
+        self.b = np.ascontiguousarray(b, np.float32).reshape(n, d)
+        self.T = np.ascontiguousarray(T, np.float32).reshape(n, d, d)
+        self.mu = np.ascontiguousarray(mu, np.float32).reshape(n + 1, d)
+        self.L = np.ascontiguousarray(L, np.float32).reshape(n + 1, d, d)
+        self.x0 = np.ascontiguousarray(x0, np.float32).reshape(d)
+        self._c = _Model(self.d, self.n, self.A.ctypes.data, self.b.ctypes.data,
+                         self.T.ctypes.data, self.mu.ctypes.data, self.L.ctypes.data,
+                         self.x0.ctypes.data)
+
+    def cptr(self):
+        return ctypes.byref(self._c)
+
+
+def layer_pair(model: Model, k: int, m: int, seed: int, contract: int = 0):
+    x = np.zeros(3, np.float32)
+    y = np.zeros(3, np.float32)
+    lib().oracle_layer_pair(model.cptr(), k, m, seed, contract, _ptr(x), _ptr(y))
+    return x[:model.d].copy(), y[:model.d].copy()
+
+
+def path_noise(d: int, k: int, m: int, seed: int, contract: int = 0):
+    e = np.zeros(3, np.float32)
+    lib().oracle_path_noise(d, k, m, seed, contract, _ptr(e))
+    return e[:d].copy()
+
+
+def cell(grid_k: np.ndarray, d: int, x) -> int:
+    g = np.ascontiguousarray(grid_k, np.float32)
+    xv = np.ascontiguousarray(np.atleast_1d(x), np.float32)
+    N = g.size // d
+    return int(lib().oracle_cell(_ptr(g), N, d, _ptr(xv)))
+
+
+def count_offsets(N) -> np.ndarray:
+    N = np.asarray(N, np.int64)
+    return np.concatenate([[0], np.cumsum(N[:-1] * N[1:])])
+
+
+def point_offsets(N) -> np.ndarray:
+    N = np.asarray(N, np.int64)
+    return np.concatenate([[0], np.cumsum(N)])
+
+
+def transitions(model: Model, grid: np.ndarray, N, M: int, seed: int, contract: int = 0,
+                mode: int = LAYERWISE, m0: int = 0, nthreads: int = 1) -> np.ndarray:
+    """Integer transition counts, layers concatenated (Algorithm I / III)."""
+    N = np.ascontiguousarray(N, np.int32)
+    g = np.ascontiguousarray(grid, np.float32)
+    total = int(count_offsets(N)[-1])
+    counts = np.zeros(max(total, 1), np.int32)
+    rc = lib().oracle_transitions(model.cptr(), _ptr(g), _ptr(N), m0, M, seed, contract,
+                                  mode, _ptr(counts), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle_transitions rejected its arguments (code {rc})")
+    return counts[:total]
+
+
+def layer_counts(counts: np.ndarray, N, k: int) -> np.ndarray:
+    off = count_offsets(N)
+    return counts[off[k]:off[k + 1]].reshape(int(N[k]), int(N[k + 1]))
+
+
+def bdp(counts: np.ndarray, N, phi: np.ndarray, want_all: bool = False):
+    """Backward dynamic programming in FP64; returns (V0[n_pay], V_all or None, empty)."""
+    N = np.ascontiguousarray(N, np.int32)
+    n = N.size - 1
+    P = int(point_offsets(N)[-1])
+    phi = np.ascontiguousarray(phi, np.float64).reshape(-1, P)
+    n_pay = phi.shape[0]
+    c = np.ascontiguousarray(counts, np.int32)
+    V0 = np.zeros(n_pay, np.float64)
+    V_all = np.zeros((n_pay, P), np.float64) if want_all else None
+    empty = lib().oracle_bdp(_ptr(c), _ptr(N), n, _ptr(phi), n_pay,
+                             _ptr(V_all) if want_all else None, _ptr(V0))
+    return V0, V_all, int(empty)
+
+
+PUT, MAX_CALL, EUROPEAN = 0, 1, 2
+
+
+def payoff(kind: int, d: int, N, grid: np.ndarray, S0: float, K: float, r: float, T: float,
+           sigma) -> np.ndarray:
+    N = np.ascontiguousarray(N, np.int32)
+    n = N.size - 1
+    g = np.ascontiguousarray(grid, np.float32)
+    sig = np.ascontiguousarray(np.atleast_1d(sigma), np.float64)
+    if sig.size < d:
+        sig = np.resize(sig, d)
+    phi = np.zeros(int(point_offsets(N)[-1]), np.float64)
+    lib().oracle_payoff(kind, d, n, _ptr(N), _ptr(g), S0, K, r, T, _ptr(sig), _ptr(phi))
+    return phi
+
+
+def _bulk_setup():
+    L = lib()
+    if getattr(L, "_bulk", False):
+        return L
+    P = ctypes.c_void_p
+    L.oracle_ln_u24_bulk.argtypes = [ctypes.c_uint32, ctypes.c_int64, P]
+    L.oracle_sincos_bulk.argtypes = [ctypes.c_uint32, ctypes.c_int64, P, P]
+    L.oracle_box_muller_bulk.argtypes = [P, P, ctypes.c_int64, P, P]
+    L.oracle_philox_bulk.argtypes = [P, P, ctypes.c_int64, P]
+    L.oracle_layer_pairs_bulk.argtypes = [P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
+                                          ctypes.c_uint64, ctypes.c_uint32, P, P]
+    L.oracle_pi_estimate.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64]
+    L.oracle_pi_estimate.restype = ctypes.c_double
+    L._bulk = True
+    return L
+
+
+def ln_u24_bulk(K0: int, count: int) -> np.ndarray:
+    out = np.zeros(count, np.float32)
+    _bulk_setup().oracle_ln_u24_bulk(K0, count, _ptr(out))
+    return out
+
+
+def sincos_bulk(J0: int, count: int):
+    s = np.zeros(count, np.float32)
+    c = np.zeros(count, np.float32)
+    _bulk_setup().oracle_sincos_bulk(J0, count, _ptr(s), _ptr(c))
+    return s, c
+
+
+def box_muller_bulk(ra: np.ndarray, rb: np.ndarray):
+    ra = np.ascontiguousarray(ra, np.uint32)
+    rb = np.ascontiguousarray(rb, np.uint32)
+    z0 = np.zeros(ra.size, np.float32)
+    z1 = np.zeros(ra.size, np.float32)
+    _bulk_setup().oracle_box_muller_bulk(_ptr(ra), _ptr(rb), ra.size, _ptr(z0), _ptr(z1))
+    return z0, z1
+
+
+def philox_bulk(ctrs: np.ndarray, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctrs, np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros_like(c)
+    _bulk_setup().oracle_philox_bulk(_ptr(c), _ptr(k), c.shape[0], _ptr(out))
+    return out
+
+
+def layer_pairs(model: Model, k: int, m0: int, count: int, seed: int, contract: int = 0):
+    x = np.zeros((count, model.d), np.float32)
+    y = np.zeros((count, model.d), np.float32)
+    _bulk_setup().oracle_layer_pairs_bulk(model.cptr(), k, m0, count, seed, contract,
+                                          _ptr(x), _ptr(y))
+    return x, y
+
+
+def pi_estimate(seed: int, rep: int, npts: int) -> float:
+    return float(_bulk_setup().oracle_pi_estimate(seed, rep, npts))

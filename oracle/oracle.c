@@ -1,0 +1,530 @@
+/*
+ * Oracle: plain CPU implementation of the quantization-tree forward step
+ * (transition counts between Voronoi cells of consecutive layers) and of the
+ * backward dynamic programming on the tree, after Pages & Wilbertz,
+ * arXiv:1101.3228.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by tests/, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product path.  It shares
+ * no code with the GPU library.
+ *
+ * The paper fixes neither the random number generator nor the Gaussian
+ * transform nor the floating point rules of the cell search; the readings
+ * used here (counter-based Philox, Box-Muller with series-defined ln/sin/cos,
+ * fixed FP32 operation order) are the arithmetic specification written down
+ * in the design notes.  Everything is FP32 with explicit fmaf where the
+ * specification says "fused"; build with -ffp-contract=off -fno-fast-math.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10, as published by Salmon et al. (SC'11): ten rounds of
+   two 32x32->64 multiplies with the round keys bumped by the Weyl
+   increments between rounds.                                          */
+/* ------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static uint32_t f2u(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+static float u2f(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+
+/* ------------------------------------------------------------------ */
+/* ln(K 2^-24), K in [1, 2^24].  K = 2^e f exactly; f is folded into
+   [2/3, 4/3) by an exact halving; ln(1+t), t = f-1 (exact by Sterbenz),
+   is the Mercator series truncated after t^14, evaluated by Horner with
+   fused multiply-adds; ln 2 is split Cody-Waite style so that e*LN2_HI
+   is exact.                                                           */
+/* ------------------------------------------------------------------ */
+float oracle_ln_u24(uint32_t K) {
+  /* coefficients (-1)^(n+1)/n, n = 2..14, each the nearest FP32 value */
+  static const float c[15] = {
+      0.0f, 0.0f,
+      -0x1p-1f,          /*  -1/2  */
+      0x1.555556p-2f,    /*   1/3  */
+      -0x1p-2f,          /*  -1/4  */
+      0x1.99999ap-3f,    /*   1/5  */
+      -0x1.555556p-3f,   /*  -1/6  */
+      0x1.24924ap-3f,    /*   1/7  */
+      -0x1p-3f,          /*  -1/8  */
+      0x1.c71c72p-4f,    /*   1/9  */
+      -0x1.99999ap-4f,   /* -1/10  */
+      0x1.745d18p-4f,    /*  1/11  */
+      -0x1.555556p-4f,   /* -1/12  */
+      0x1.3b13b2p-4f,    /*  1/13  */
+      -0x1.24924ap-4f,   /* -1/14  */
+  };
+  const float LN2_HI = 0x1.62e4p-1f;      /* floor(ln2 * 2^16) / 2^16 */
+  const float LN2_LO = 0x1.7f7d1cp-20f;   /* nearest FP32 to ln2 - LN2_HI */
+  float F = (float)K;                     /* exact: K < 2^25 */
+  uint32_t bits = f2u(F);
+  int32_t e = (int32_t)(bits >> 23) - 127;
+  uint32_t mb = (bits & 0x007FFFFFu) | 0x3F800000u; /* f in [1, 2) */
+  if (mb >= 0x3FAAAAABu) {                 /* f >= 4/3: halve f, bump e */
+    mb -= 0x00800000u;
+    e += 1;
+  }
+  float t = u2f(mb) - 1.0f;                /* exact */
+  float P = c[14];
+  for (int n = 13; n >= 2; --n) P = fmaf(P, t, c[n]);
+  float w = t * t;
+  float r = fmaf(w, P, t);                 /* ln(1+t) = t + t^2 P(t) */
+  float ee = (float)(e - 24);
+  float s = fmaf(ee, LN2_LO, r);
+  return fmaf(ee, LN2_HI, s);
+}
+
+/* ------------------------------------------------------------------ */
+/* sin and cos of theta = 2 pi J 2^-24.  Quadrant q = J>>22 and the
+   in-quadrant fraction r (22 bits) are split in integer arithmetic; an
+   exact reflection r -> 2^22 - r keeps y = r 2^-22 in [0, 1/2]; the
+   Taylor series of sin(pi y/2) (to y^9) and cos(pi y/2) (to y^10) are
+   evaluated by Horner in w = y^2.                                     */
+/* ------------------------------------------------------------------ */
+void oracle_sincos_2pi_u24(uint32_t J, float *sn, float *cs) {
+  /* (-1)^k (pi/2)^(2k+1)/(2k+1)!, k = 0..4 */
+  const float S0 = 0x1.921fb6p+0f, S1 = -0x1.4abbcep-1f, S2 = 0x1.466bc6p-4f,
+              S3 = -0x1.32d2ccp-8f, S4 = 0x1.507834p-13f;
+  /* (-1)^k (pi/2)^(2k)/(2k)!, k = 0..5 */
+  const float C0 = 1.0f, C1 = -0x1.3bd3ccp+0f, C2 = 0x1.03c1f0p-2f,
+              C3 = -0x1.55d3c8p-6f, C4 = 0x1.e1f506p-11f, C5 = -0x1.a6d1f2p-16f;
+  uint32_t q = J >> 22;
+  uint32_t r = J & 0x003FFFFFu;
+  int swap = 0;
+  if (r > 0x00200000u) {
+    r = 0x00400000u - r;
+    swap = 1;
+  }
+  float y = (float)r * 0x1p-22f;           /* exact */
+  float w = y * y;
+  float ps = fmaf(S4, w, S3);
+  ps = fmaf(ps, w, S2);
+  ps = fmaf(ps, w, S1);
+  ps = fmaf(ps, w, S0);
+  float sy = ps * y;                       /* sin(pi y / 2) */
+  float pc = fmaf(C5, w, C4);
+  pc = fmaf(pc, w, C3);
+  pc = fmaf(pc, w, C2);
+  pc = fmaf(pc, w, C1);
+  float cy = fmaf(pc, w, C0);              /* cos(pi y / 2) */
+  float sp = swap ? cy : sy;               /* sin and cos of the in-quadrant angle */
+  float cp = swap ? sy : cy;
+  switch (q) {
+    case 0: *sn = sp;  *cs = cp;  break;
+    case 1: *sn = cp;  *cs = -sp; break;
+    case 2: *sn = -sp; *cs = -cp; break;
+    default: *sn = -cp; *cs = sp; break;
+  }
+}
+
+/* Box-Muller: rho = sqrt(-2 ln u_a), u_a = ((ra>>8)+1) 2^-24 in (0,1];
+   angle 2 pi u_b, u_b = (rb>>8) 2^-24 in [0,1). */
+void oracle_box_muller(uint32_t ra, uint32_t rb, float *z0, float *z1) {
+  float l = oracle_ln_u24((ra >> 8) + 1u);
+  float rho = sqrtf(-2.0f * l);
+  float s, c;
+  oracle_sincos_2pi_u24(rb >> 8, &s, &c);
+  *z0 = rho * c;
+  *z1 = rho * s;
+}
+
+static void seed_key(uint64_t seed, uint32_t key[2]) {
+  key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+  key[1] = (uint32_t)(seed >> 32);
+}
+
+/* Counter words: (c0, c1, c2, c3) = (sample block, layer, contract, tag).
+   Tag 0: time-layer sampling (Algorithm III), 16: its second block for d = 3;
+   tag 1: pathwise innovations (Algorithm I). */
+static void normals_layer(int32_t d, int32_t k, uint64_t m, uint64_t seed, uint32_t contract,
+                          float *zx, float *eps) {
+  uint32_t key[2], r[4];
+  seed_key(seed, key);
+  if (d == 1) {
+    uint32_t ctr[4] = {(uint32_t)(m >> 1), (uint32_t)k, contract, 0u};
+    oracle_philox4x32_10(ctr, key, r);
+    if ((m & 1u) == 0) oracle_box_muller(r[0], r[1], &zx[0], &eps[0]);
+    else oracle_box_muller(r[2], r[3], &zx[0], &eps[0]);
+  } else if (d == 2) {
+    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)k, contract, 0u};
+    oracle_philox4x32_10(ctr, key, r);
+    oracle_box_muller(r[0], r[1], &zx[0], &zx[1]);
+    oracle_box_muller(r[2], r[3], &eps[0], &eps[1]);
+  } else {
+    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)k, contract, 0u};
+    oracle_philox4x32_10(ctr, key, r);
+    oracle_box_muller(r[0], r[1], &zx[0], &zx[1]);
+    oracle_box_muller(r[2], r[3], &zx[2], &eps[0]);
+    uint32_t ctr2[4] = {(uint32_t)m, (uint32_t)k, contract, 16u};
+    oracle_philox4x32_10(ctr2, key, r);
+    oracle_box_muller(r[0], r[1], &eps[1], &eps[2]);
+  }
+}
+
+void oracle_path_noise(int32_t d, int32_t k, uint64_t m, uint64_t seed, uint32_t contract,
+                       float *eps) {
+  uint32_t key[2], r[4];
+  seed_key(seed, key);
+  float z[4];
+  if (d == 1) {
+    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)k >> 2, contract, 1u};
+    oracle_philox4x32_10(ctr, key, r);
+    oracle_box_muller(r[0], r[1], &z[0], &z[1]);
+    oracle_box_muller(r[2], r[3], &z[2], &z[3]);
+    eps[0] = z[k & 3];
+  } else if (d == 2) {
+    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)k >> 1, contract, 1u};
+    oracle_philox4x32_10(ctr, key, r);
+    if ((k & 1) == 0) oracle_box_muller(r[0], r[1], &eps[0], &eps[1]);
+    else oracle_box_muller(r[2], r[3], &eps[0], &eps[1]);
+  } else {
+    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)k, contract, 1u};
+    oracle_philox4x32_10(ctr, key, r);
+    oracle_box_muller(r[0], r[1], &eps[0], &eps[1]);
+    oracle_box_muller(r[2], r[3], &eps[2], &z[0]);
+  }
+}
+
+/* y = b + A x + T eps, each row a left-to-right chain of fused
+   multiply-adds starting from b (Proposition, Sec. 3). */
+static void ar_step(int32_t d, const float *A, const float *b, const float *T, const float *x,
+                    const float *eps, float *y) {
+  for (int r = 0; r < d; ++r) {
+    float v = b[r];
+    for (int c = 0; c < d; ++c) v = fmaf(A[r * d + c], x[c], v);
+    for (int c = 0; c < d; ++c) v = fmaf(T[r * d + c], eps[c], v);
+    y[r] = v;
+  }
+}
+
+void oracle_layer_pair(const oracle_model *mdl, int32_t k, uint64_t m, uint64_t seed,
+                       uint32_t contract, float *xk, float *xk1) {
+  int d = mdl->d;
+  float zx[3], eps[3];
+  normals_layer(d, k, m, seed, contract, zx, eps);
+  const float *mu = mdl->mu + (size_t)k * d;
+  const float *L = mdl->L + (size_t)k * d * d;
+  for (int r = 0; r < d; ++r) {       /* X_k = mu_k + L_k z */
+    float v = mu[r];
+    for (int c = 0; c < d; ++c) v = fmaf(L[r * d + c], zx[c], v);
+    xk[r] = v;
+  }
+  ar_step(d, mdl->A + (size_t)k * d * d, mdl->b + (size_t)k * d, mdl->T + (size_t)k * d * d,
+          xk, eps, xk1);
+}
+
+/* Nearest neighbour projection (Sec. 2).  d = 1: cell = number of
+   midpoints m_r = (x_r + x_{r+1})/2 strictly below x, so a point on a
+   midpoint goes to the lower cell.  d >= 2: the cell minimises the
+   half-norm form h_p - <x, g_p> of the squared distance
+   (|x - g_p|^2 = |x|^2 + 2 (h_p - <x, g_p>), h_p = |g_p|^2 / 2); the
+   lowest index wins ties. */
+static float half_norm(const float *g, int d) {
+  float t = g[0] * g[0];
+  for (int c = 1; c < d; ++c) t = fmaf(g[c], g[c], t);
+  return 0.5f * t;
+}
+
+int32_t oracle_cell(const float *grid_k, int32_t N, int32_t d, const float *x) {
+  if (d == 1) {
+    int32_t cnt = 0;
+    for (int32_t r = 0; r + 1 < N; ++r) {
+      float mid = 0.5f * (grid_k[r] + grid_k[r + 1]);
+      if (mid < x[0]) ++cnt;
+    }
+    return cnt;
+  }
+  int32_t best = 0;
+  float bestkey = 0.0f;
+  for (int32_t p = 0; p < N; ++p) {
+    const float *g = grid_k + (size_t)p * d;
+    float key = half_norm(g, d);
+    for (int c = 0; c < d; ++c) key = fmaf(-x[c], g[c], key);
+    if (p == 0 || key < bestkey) {
+      bestkey = key;
+      best = p;
+    }
+  }
+  return best;
+}
+
+/* Per-layer precomputation used by the sample loops: midpoints (d = 1) or
+   half norms (d >= 2) of the grid, exactly as in oracle_cell. */
+typedef struct {
+  const float *g;
+  float *aux;
+  int32_t N, d;
+} layer_grid;
+
+static void layer_grid_init(layer_grid *lg, const float *g, int32_t N, int32_t d) {
+  lg->g = g; lg->N = N; lg->d = d;
+  lg->aux = (float *)malloc(sizeof(float) * (size_t)(N > 0 ? N : 1));
+  if (d == 1) {
+    for (int32_t r = 0; r + 1 < N; ++r) lg->aux[r] = 0.5f * (g[r] + g[r + 1]);
+  } else {
+    for (int32_t p = 0; p < N; ++p) lg->aux[p] = half_norm(g + (size_t)p * d, d);
+  }
+}
+
+static int32_t layer_cell(const layer_grid *lg, const float *x) {
+  if (lg->d == 1) {
+    int32_t cnt = 0;
+    for (int32_t r = 0; r + 1 < lg->N; ++r)
+      if (lg->aux[r] < x[0]) ++cnt;
+    return cnt;
+  }
+  int32_t best = 0;
+  float bestkey = 0.0f;
+  for (int32_t p = 0; p < lg->N; ++p) {
+    const float *g = lg->g + (size_t)p * lg->d;
+    float key = lg->aux[p];
+    for (int c = 0; c < lg->d; ++c) key = fmaf(-x[c], g[c], key);
+    if (p == 0 || key < bestkey) {
+      bestkey = key;
+      best = p;
+    }
+  }
+  return best;
+}
+
+typedef struct {
+  const oracle_model *mdl;
+  const layer_grid *lg;   /* [n+1] */
+  const int64_t *coff;    /* [n] */
+  const int32_t *N;
+  uint64_t m0, M, seed;
+  uint32_t contract;
+  int32_t *counts;
+  int32_t mode;
+  int32_t tid, nthreads;
+} job;
+
+/* Serial Algorithm III for the layers owned by one thread (layers are
+   independent, so splitting them over threads changes nothing). */
+static void *run_layerwise(void *arg) {
+  job *J = (job *)arg;
+  const oracle_model *mdl = J->mdl;
+  for (int32_t k = J->tid; k < mdl->n; k += J->nthreads) {
+    int32_t *ck = J->counts + J->coff[k];
+    int32_t N1 = J->N[k + 1];
+    for (uint64_t m = J->m0; m < J->m0 + J->M; ++m) {
+      float x[3], y[3];
+      oracle_layer_pair(mdl, k, m, J->seed, J->contract, x, y);
+      int32_t i = layer_cell(&J->lg[k], x);
+      int32_t j = layer_cell(&J->lg[k + 1], y);
+      ck[(int64_t)i * N1 + j] += 1;
+    }
+  }
+  return NULL;
+}
+
+/* Serial Algorithm I for a slice of the paths; the increments are atomic
+   integer additions so that threads may share the counters. */
+static void *run_pathwise(void *arg) {
+  job *J = (job *)arg;
+  const oracle_model *mdl = J->mdl;
+  int d = mdl->d;
+  uint64_t per = (J->M + (uint64_t)J->nthreads - 1) / (uint64_t)J->nthreads;
+  uint64_t lo = J->m0 + per * (uint64_t)J->tid;
+  uint64_t hi = lo + per;
+  if (hi > J->m0 + J->M) hi = J->m0 + J->M;
+  for (uint64_t m = lo; m < hi; ++m) {
+    float x[3], y[3], eps[3];
+    for (int c = 0; c < d; ++c) x[c] = mdl->x0[c];
+    int32_t i = 0;
+    for (int32_t k = 0; k < mdl->n; ++k) {
+      oracle_path_noise(d, k, m, J->seed, J->contract, eps);
+      ar_step(d, mdl->A + (size_t)k * d * d, mdl->b + (size_t)k * d,
+              mdl->T + (size_t)k * d * d, x, eps, y);
+      int32_t j = layer_cell(&J->lg[k + 1], y);
+      int32_t *slot = J->counts + J->coff[k] + (int64_t)i * J->N[k + 1] + j;
+      if (J->nthreads > 1) __atomic_fetch_add(slot, 1, __ATOMIC_RELAXED);
+      else *slot += 1;
+      i = j;
+      for (int c = 0; c < d; ++c) x[c] = y[c];
+    }
+  }
+  return NULL;
+}
+
+int oracle_transitions(const oracle_model *mdl, const float *grid, const int32_t *N,
+                       uint64_t m0, uint64_t M, uint64_t seed, uint32_t contract,
+                       int32_t mode, int32_t *counts, int32_t nthreads) {
+  if (!mdl || !grid || !N || !counts) return 1;
+  int32_t d = mdl->d, n = mdl->n;
+  if (d < 1 || d > 3 || n < 1 || N[0] != 1) return 1;
+  if (M >= (1ull << 31) || m0 + M > (1ull << 32)) return 2;
+  for (int32_t k = 0; k <= n; ++k)
+    if (N[k] < 1) return 1;
+  if (nthreads < 1) nthreads = 1;
+  layer_grid *lg = (layer_grid *)malloc(sizeof(layer_grid) * (size_t)(n + 1));
+  int64_t *coff = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t poff = 0, co = 0;
+  for (int32_t k = 0; k <= n; ++k) {
+    layer_grid_init(&lg[k], grid + poff * d, N[k], d);
+    poff += N[k];
+    if (k < n) {
+      coff[k] = co;
+      co += (int64_t)N[k] * N[k + 1];
+    }
+  }
+  memset(counts, 0, sizeof(int32_t) * (size_t)co);
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+  job *jobs = (job *)malloc(sizeof(job) * (size_t)nthreads);
+  for (int32_t t = 0; t < nthreads; ++t) {
+    job J = {mdl, lg, coff, N, m0, M, seed, contract, counts, mode, t, nthreads};
+    jobs[t] = J;
+  }
+  void *(*fn)(void *) = (mode == ORACLE_PATHWISE) ? run_pathwise : run_layerwise;
+  if (nthreads == 1) {
+    fn(&jobs[0]);
+  } else {
+    for (int32_t t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, fn, &jobs[t]);
+    for (int32_t t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  }
+  for (int32_t k = 0; k <= n; ++k) free(lg[k].aux);
+  free(lg); free(coff); free(th); free(jobs);
+  return 0;
+}
+
+/* Backward dynamic programming on the quantization tree (Sec. 2):
+   V_n = phi_n;  V_k(i) = max(phi_k(i), sum_j pi_ij V_{k+1}(j)),
+   pi_ij = c_ij / p_i, p_i = sum_j c_ij.  A row that no sample reached
+   (p_i = 0) has continuation value 0. */
+int64_t oracle_bdp(const int32_t *counts, const int32_t *N, int32_t n, const double *phi,
+                   int32_t n_pay, double *V_all, double *V0) {
+  int64_t total = 0;
+  int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 2));
+  int64_t *coff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  poff[0] = 0;
+  coff[0] = 0;
+  for (int32_t k = 0; k <= n; ++k) poff[k + 1] = poff[k] + N[k];
+  for (int32_t k = 0; k < n; ++k) coff[k + 1] = coff[k] + (int64_t)N[k] * N[k + 1];
+  int64_t P = poff[n + 1];
+  double *V = (double *)malloc(sizeof(double) * (size_t)P);
+  int64_t empty = 0;
+  for (int32_t q = 0; q < n_pay; ++q) {
+    const double *ph = phi + (size_t)q * P;
+    for (int32_t i = 0; i < N[n]; ++i) V[poff[n] + i] = ph[poff[n] + i];
+    for (int32_t k = n - 1; k >= 0; --k) {
+      const int32_t *ck = counts + coff[k];
+      for (int32_t i = 0; i < N[k]; ++i) {
+        int64_t p = 0;
+        double s = 0.0;
+        for (int32_t j = 0; j < N[k + 1]; ++j) {
+          int32_t c = ck[(int64_t)i * N[k + 1] + j];
+          p += c;
+          s += (double)c * V[poff[k + 1] + j];
+        }
+        double cont = 0.0;
+        if (p > 0) cont = s / (double)p;
+        else ++empty;
+        double f = ph[poff[k] + i];
+        V[poff[k] + i] = (f > cont) ? f : cont;
+      }
+    }
+    if (V_all) memcpy(V_all + (size_t)q * P, V, sizeof(double) * (size_t)P);
+    if (V0) V0[q] = V[0];
+  }
+  total = empty;
+  free(V); free(poff); free(coff);
+  return total;
+}
+
+void oracle_payoff(int32_t kind, int32_t d, int32_t n, const int32_t *N, const float *grid,
+                   double S0, double K, double r, double Tm, const double *sigma,
+                   double *phi) {
+  int max_call = kind & 1, european = kind & 2;
+  int64_t off = 0;
+  for (int32_t k = 0; k <= n; ++k) {
+    double t = Tm * (double)k / (double)n;
+    double disc = exp(-r * t);
+    for (int32_t i = 0; i < N[k]; ++i) {
+      const float *x = grid + (off + i) * d;
+      double v;
+      if (max_call) {
+        double smax = -INFINITY;
+        for (int a = 0; a < d; ++a) {
+          double s = S0 * exp((r - 0.5 * sigma[a] * sigma[a]) * t + sigma[a] * (double)x[a]);
+          if (s > smax) smax = s;
+        }
+        v = disc * fmax(smax - K, 0.0);
+      } else {
+        double s = S0 * exp((r - 0.5 * sigma[0] * sigma[0]) * t + sigma[0] * (double)x[0]);
+        v = disc * fmax(K - s, 0.0);
+      }
+      if (european && k < n) v = -INFINITY;
+      phi[off + i] = v;
+    }
+    off += N[k];
+  }
+}
+
+/* Bulk helpers for the exhaustive and statistical tests (plain loops). */
+void oracle_ln_u24_bulk(uint32_t K0, int64_t count, float *out) {
+  for (int64_t i = 0; i < count; ++i) out[i] = oracle_ln_u24(K0 + (uint32_t)i);
+}
+
+void oracle_sincos_bulk(uint32_t J0, int64_t count, float *s, float *c) {
+  for (int64_t i = 0; i < count; ++i) oracle_sincos_2pi_u24(J0 + (uint32_t)i, &s[i], &c[i]);
+}
+
+void oracle_box_muller_bulk(const uint32_t *ra, const uint32_t *rb, int64_t count, float *z0,
+                            float *z1) {
+  for (int64_t i = 0; i < count; ++i) oracle_box_muller(ra[i], rb[i], &z0[i], &z1[i]);
+}
+
+void oracle_philox_bulk(const uint32_t *ctr, const uint32_t key[2], int64_t count,
+                        uint32_t *out) {
+  for (int64_t i = 0; i < count; ++i) oracle_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+/* Layer samples m0..m0+count-1 of layer k (Algorithm III): xk, xk1 [count][d]. */
+void oracle_layer_pairs_bulk(const oracle_model *mdl, int32_t k, uint64_t m0, int64_t count,
+                             uint64_t seed, uint32_t contract, float *xk, float *xk1) {
+  int d = mdl->d;
+  for (int64_t i = 0; i < count; ++i)
+    oracle_layer_pair(mdl, k, m0 + (uint64_t)i, seed, contract, xk + i * d, xk1 + i * d);
+}
+
+/* Monte Carlo estimate of pi from npts points (u, v) of the unit square,
+   u = (r0>>8) 2^-24, v = (r1>>8) 2^-24 and likewise (r2, r3), counter
+   (i, rep, 0, 3): four times the fraction of points with u^2 + v^2 <= 1
+   (the quarter-disc experiment of the RNG comparison in Sec. 3). */
+double oracle_pi_estimate(uint64_t seed, uint32_t rep, uint64_t npts) {
+  uint32_t key[2], r[4];
+  seed_key(seed, key);
+  uint64_t inside = 0;
+  for (uint64_t i = 0; i < npts / 2; ++i) {
+    uint32_t ctr[4] = {(uint32_t)i, rep, 0u, 3u};
+    oracle_philox4x32_10(ctr, key, r);
+    for (int h = 0; h < 2; ++h) {
+      double u = (double)(r[2 * h] >> 8) * 0x1p-24;
+      double v = (double)(r[2 * h + 1] >> 8) * 0x1p-24;
+      if (u * u + v * v <= 1.0) ++inside;
+    }
+  }
+  return 4.0 * (double)inside / (double)((npts / 2) * 2);
+}

@@ -1,0 +1,86 @@
+/*
+ * Oracle for the quantization-tree forward step and its backward dynamic
+ * programming (Pages & Wilbertz, "GPGPUs in computational finance: Massive
+ * parallel computing for American style options", arXiv:1101.3228).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, serial-per-sample CPU
+ * implementation written from the paper's definitions.  Only tests/, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no source, header, table or constant generator with the GPU
+ * library: every constant below is retyped from its mathematical definition.
+ *
+ * Layouts (all host memory, row-major):
+ *   grid   : float[sum_k N_k][d], layers concatenated k = 0..n
+ *   counts : int32[sum_{k<n} N_k*N_{k+1}], counts[k] is the N_k x N_{k+1}
+ *            block of layer k -> k+1, blocks concatenated k = 0..n-1
+ *   model  : A,T [n][d][d]; b [n][d]; mu [n+1][d]; L [n+1][d][d]; x0 [d]
+ *            X_{k+1} = A_k X_k + b_k + T_k eps_k   (Proposition, Sec. 3)
+ *            X_k    ~ mu_k + L_k z               (marginal, Algorithm III)
+ */
+#ifndef QTREE_ORACLE_H
+#define QTREE_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t d, n;
+  const float *A, *b, *T;
+  const float *mu, *L;
+  const float *x0;
+} oracle_model;
+
+enum { ORACLE_LAYERWISE = 0, ORACLE_PATHWISE = 1 };
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* ln(K * 2^-24) for K in [1, 2^24]. */
+float oracle_ln_u24(uint32_t K);
+/* sin and cos of 2*pi*J*2^-24 for J in [0, 2^24). */
+void oracle_sincos_2pi_u24(uint32_t J, float *s, float *c);
+/* Box-Muller pair from two Philox words. */
+void oracle_box_muller(uint32_t ra, uint32_t rb, float *z0, float *z1);
+/* LAYERWISE sample m of layer k: X_k and X_{k+1} (Algorithm III). */
+void oracle_layer_pair(const oracle_model *mdl, int32_t k, uint64_t m, uint64_t seed,
+                       uint32_t contract, float *xk, float *xk1);
+/* PATHWISE innovation eps_k of path m (Algorithm I / II). */
+void oracle_path_noise(int32_t d, int32_t k, uint64_t m, uint64_t seed, uint32_t contract,
+                       float *eps);
+/* Voronoi cell of x in a grid of N points (nearest neighbour projection). */
+int32_t oracle_cell(const float *grid_k, int32_t N, int32_t d, const float *x);
+/* Transition counts over samples (or paths) m0 .. m0+M-1; counts overwritten.
+   Returns 0 on success, nonzero on invalid arguments. */
+int oracle_transitions(const oracle_model *mdl, const float *grid, const int32_t *N,
+                       uint64_t m0, uint64_t M, uint64_t seed, uint32_t contract,
+                       int32_t mode, int32_t *counts, int32_t nthreads);
+/* Backward dynamic programming on the tree, FP64.  phi: [n_pay][sum N_k];
+   V_all (optional): [n_pay][sum N_k]; V0: [n_pay].  Returns the number of
+   empty source rows (p_i = 0) met, summed over payoffs. */
+int64_t oracle_bdp(const int32_t *counts, const int32_t *N, int32_t n, const double *phi,
+                   int32_t n_pay, double *V_all, double *V0);
+/* Discounted obstacle phi_k(x) = exp(-r t_k) * payoff(S_{t_k}(x)), t_k = k*Tm/n.
+   kind bit 0 clear: put (K - S)^+ on S = S0 exp((r - sigma^2/2) t + sigma x_0).
+   kind bit 0 set  : call on the max of d assets S^a = S0 exp((r - sigma_a^2/2) t + sigma_a x_a).
+   kind bit 1 set  : European, phi_k = -inf for k < n (the max in the BDP then
+                     always takes the continuation value). */
+void oracle_payoff(int32_t kind, int32_t d, int32_t n, const int32_t *N, const float *grid,
+                   double S0, double K, double r, double Tm, const double *sigma,
+                   double *phi);
+
+/* Bulk helpers for tests. */
+void oracle_ln_u24_bulk(uint32_t K0, int64_t count, float *out);
+void oracle_sincos_bulk(uint32_t J0, int64_t count, float *s, float *c);
+void oracle_box_muller_bulk(const uint32_t *ra, const uint32_t *rb, int64_t count, float *z0,
+                            float *z1);
+void oracle_philox_bulk(const uint32_t *ctr, const uint32_t key[2], int64_t count,
+                        uint32_t *out);
+void oracle_layer_pairs_bulk(const oracle_model *mdl, int32_t k, uint64_t m0, int64_t count,
+                             uint64_t seed, uint32_t contract, float *xk, float *xk1);
+double oracle_pi_estimate(uint64_t seed, uint32_t rep, uint64_t npts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,147 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds none of the method's arithmetic: it only builds input data
+of the shapes the paper's workloads have (Sec. 3: M samples, n layers, N_k
+points per layer) -- AR(1) coefficients of a standardized Brownian motion,
+sorted test grids, contract parameters -- with numpy in FP64, rounded once to
+FP32.  Both the GPU library and the oracle consume these arrays; neither
+imports the other.
+
+State convention: X_k = W_{t_k} (a d-dimensional Brownian motion with
+correlation matrix R), t_k = k T / n.  Then X_{k+1} = X_k + sqrt(dt) C eps
+(A = I, b = 0, T_k = sqrt(dt) C with C C^T = R) and X_k ~ sqrt(t_k) C z.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import ndtri
+
+SEED_BASE = 0x5EED0000
+
+
+def corr_matrix(d: int, rho: float) -> np.ndarray:
+    R = np.full((d, d), float(rho))
+    np.fill_diagonal(R, 1.0)
+    return R
+
+
+def bm_model(d: int, n: int, T: float = 1.0, rho: float = 0.0, x0=None):
+    """AR(1) coefficients (A, b, T, mu, L, x0) of the standardized Brownian
+    motion sampled at t_k = k T / n, FP32."""
+    C = np.linalg.cholesky(corr_matrix(d, rho)) if d > 1 else np.ones((1, 1))
+    dt = T / n
+    A = np.broadcast_to(np.eye(d), (n, d, d)).astype(np.float32)
+    b = np.zeros((n, d), np.float32)
+    Tm = np.broadcast_to(np.sqrt(dt) * C, (n, d, d)).astype(np.float32)
+    x0v = np.zeros(d) if x0 is None else np.asarray(x0, np.float64).reshape(d)
+    mu = np.broadcast_to(x0v, (n + 1, d)).astype(np.float32)
+    L = np.stack([np.sqrt(k * dt) * C for k in range(n + 1)]).astype(np.float32)
+    return dict(d=d, n=n, A=A, b=b, T=Tm, mu=mu, L=L, x0=x0v.astype(np.float32))
+
+
+def ou_model(n: int, alpha=(1.0, 5.0), sig=(1.0, 1.0), rho: float = 0.0, T: float = 1.0):
+    """Two-factor Ornstein-Uhlenbeck state of the swing-option model (Sec. 3):
+    X_{k+1} = diag(e^{-alpha dt}) X_k + T_k eps with the exact Gaussian
+    increment covariance; X_0 = 0.  FP32."""
+    a = np.asarray(alpha, np.float64)
+    s = np.asarray(sig, np.float64)
+    dt = T / n
+    R = corr_matrix(2, rho)
+
+    def cov(t):
+        S = np.zeros((2, 2))
+        for i in range(2):
+            for j in range(2):
+                lam = a[i] + a[j]
+                S[i, j] = s[i] * s[j] * R[i, j] * (1.0 - np.exp(-lam * t)) / lam
+        return S
+
+    Ad = np.diag(np.exp(-a * dt))
+    Tk = np.linalg.cholesky(cov(dt))
+    A = np.broadcast_to(Ad, (n, 2, 2)).astype(np.float32)
+    b = np.zeros((n, 2), np.float32)
+    Tm = np.broadcast_to(Tk, (n, 2, 2)).astype(np.float32)
+    mu = np.zeros((n + 1, 2), np.float32)
+    L = np.zeros((n + 1, 2, 2))
+    for k in range(1, n + 1):
+        L[k] = np.linalg.cholesky(cov(k * dt))
+    return dict(d=2, n=n, A=A, b=b, T=Tm, mu=mu, L=L.astype(np.float32),
+                x0=np.zeros(2, np.float32))
+
+
+def quantile_grid_1d(N: int) -> np.ndarray:
+    """Sorted N(0,1) test grid: quantiles of N(0, 3) (the point density
+    f^{1/3} of asymptotically optimal quadratic quantizers), FP64."""
+    if N == 1:
+        return np.zeros(1)
+    u = (np.arange(N) + 0.5) / N
+    return np.sqrt(3.0) * ndtri(u)
+
+
+def layer_grids(model: dict, Ns, base=None, rng=None, jitter: float = 0.0):
+    """Concatenated FP32 grid for layers 0..n: layer 0 is {x0}; layer k >= 1
+    is x0 + sqrt(t_k) C G_k with G_k a standard-normal test grid of N_k
+    points (1-D quantile grid, or the product of two/three 1-D grids).
+    Ns: list of per-layer sizes (len n+1, Ns[0] == 1) or per-layer shapes."""
+    d, n = model["d"], model["n"]
+    L = model["L"].astype(np.float64)
+    x0 = model["x0"].astype(np.float64)
+    parts = [x0.reshape(1, d)]
+    N = [1]
+    for k in range(1, n + 1):
+        spec = Ns[k]
+        if d == 1:
+            G = (quantile_grid_1d(int(spec)) if base is None else base(int(spec))).reshape(-1, 1)
+        else:
+            shape = spec if isinstance(spec, (tuple, list)) else _split(int(spec), d)
+            axes = [quantile_grid_1d(int(s)) if base is None else base(int(s)) for s in shape]
+            mesh = np.meshgrid(*axes, indexing="ij")
+            G = np.stack([m.reshape(-1) for m in mesh], axis=1)
+        if jitter > 0.0 and rng is not None:
+            G = G + jitter * rng.standard_normal(G.shape)
+            if d == 1:
+                G = np.sort(G, axis=0)
+        # L[k] = sqrt(t_k) C for the Brownian model; the marginal map is generic.
+        pts = x0 + G @ L[k].T
+        parts.append(pts)
+        N.append(pts.shape[0])
+    grid = np.concatenate(parts, axis=0).astype(np.float32)
+    if d == 1:
+        # rounding to FP32 must keep 1-D grids strictly increasing
+        off = 0
+        for Nk in N:
+            g = grid[off:off + Nk, 0]
+            assert np.all(np.diff(g) > 0), "1-D test grid not strictly increasing in FP32"
+            off += Nk
+    return grid, np.asarray(N, np.int32)
+
+
+def _split(N: int, d: int):
+    """Factor N into d near-equal integer sides (product grid shape)."""
+    if d == 2:
+        a = int(np.floor(np.sqrt(N)))
+        while N % a:
+            a -= 1
+        return (a, N // a)
+    a = int(round(N ** (1.0 / 3.0)))
+    while N % a:
+        a -= 1
+    b, c = _split(N // a, 2)
+    return (a, b, c)
+
+
+def seeds(R: int):
+    return [SEED_BASE + r for r in range(R)]
+
+
+def contract_box(rng: np.random.Generator, count: int, d: int = 1):
+    """Contract parameters drawn uniformly in the training box of the
+    surrogate: S0/K, sigma, r, T, n, rho."""
+    return dict(
+        s0_over_k=rng.uniform(1 / 1.2, 1 / 0.8, count),
+        sigma=rng.uniform(0.1, 0.4, count),
+        r=rng.uniform(0.0, 0.1, count),
+        T=rng.uniform(0.25, 2.0, count),
+        n=rng.integers(10, 101, count),
+        rho=(rng.uniform(-0.5, 0.9, count) if d > 1 else np.zeros(count)),
+    )
