@@ -1,0 +1,168 @@
+"""Benchmark: Monte Carlo transition samples per second of the quantization-tree
+forward step on one MI355X, with the FP64 backward step of a contract sweep.
+
+Workload (one step): 1-D Brownian state (standardized log-price of the
+Black-Scholes put), n = 50 layers of N = 500 Lloyd-optimal points, M = 1e7
+pairs (X_k, X_{k+1}) per layer sampled time-layer parallel (Algorithm III),
+counts zeroed and rebuilt, then the obstacle and the quantized BDP for 12
+American puts sharing the counts (sigma in {0.1, 0.2, 0.3, 0.4} x K/S0 in
+{0.8, 1.0, 1.2}).  Inputs (grids, model, payoff parameters) are resident on
+the GPU before timing starts.  The value is pairs per second of whole steps.
+
+Prints one JSON line.  Roofline of the dominant kernel (the forward kernel):
+algorithmic VALU lane-slots per pair (the fixed arithmetic of one pair, see
+ALG_SLOTS_PER_PAIR) times pairs per launch, divided by the launch duration
+measured with HIP events on the launch stream, against the MI355X peak of
+256 CUs x 64 lanes x 2.4 GHz lane-slots per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_LAYERS, N_POINTS, M_PAIRS = 50, 500, 10_000_000
+SIGMAS = (0.1, 0.2, 0.3, 0.4)
+K_RATIOS = (0.8, 1.0, 1.2)
+S0, RATE, MATURITY = 100.0, 0.05, 1.0
+
+# Algorithmic VALU lane-slots of one 1-D pair at N = 500 (issue cost: full-rate
+# ops 1, quarter-rate ops 4):
+#   Philox4x32-10, half a call per pair: 10 rounds x (2 x 32x32->64 mad [4] +
+#     2 x 3-input xor [1]) / 2                                          = 50
+#   Box-Muller, one per pair: word->integer split 2, convert 1, exponent and
+#     mantissa split 3, fold 3, t 1, Mercator series 13 fma + 2, Cody-Waite
+#     3 + 2, scale 1, correctly rounded sqrt 12 (v_sqrt [4] + 2 fma + 2 cmp
+#     + 2 select + 2 add); angle split 6, convert 2, sin 5 + cos 5 + square 1,
+#     reflection 2, quadrant 4; two products 2                           = 71
+#   AR(1) sample: 3 fma                                                  =  3
+#   two binary searches over 512 padded midpoints: 2 x 9 steps x
+#     (address, compare, select)                                         = 54
+#   count address (mad + 64-bit add)                                     =  3
+ALG_SLOTS_PER_PAIR = 50 + 71 + 3 + 54 + 3
+PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
+
+
+def _inputs():
+    import paper_1101_3228_amd as qt
+    import synth
+    spec = synth.bm_model(1, N_LAYERS, T=MATURITY)
+    base = qt.gauss_quantizer(N_POINTS)
+    grid, N = synth.layer_grids(spec, [1] + [N_POINTS] * N_LAYERS, base=lambda n: base)
+    return spec, grid, N
+
+
+def cpu_baseline(spec, grid, N, pairs_per_layer: int):
+    """The oracle (plain C, one thread per host core over layers) on a bounded
+    sample: every layer with `pairs_per_layer` pairs."""
+    import oracle as O
+    threads = min(os.cpu_count() or 1, N_LAYERS)
+    mdl = O.Model(spec["d"], spec["n"], spec["A"], spec["b"], spec["T"], spec["mu"], spec["L"],
+                  spec["x0"])
+    t0 = time.perf_counter()
+    O.transitions(mdl, grid, N, pairs_per_layer, seed=0x5EED0000, nthreads=threads)
+    dt = time.perf_counter() - t0
+    pairs = pairs_per_layer * N_LAYERS
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {N_LAYERS} layers x {pairs_per_layer} pairs "
+                      f"({pairs:.3g} pairs, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=400_000,
+                    help="pairs per layer in the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; the quantization-tree "
+                                   "forward step is measured on a single MI355X "
+                                   "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1101_3228_amd as qt
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    spec, grid, N = _inputs()
+    plan = qt.Plan(spec, grid, N, device="cuda:0")
+    counts = plan.new_counts()
+    contracts = [(s, kr) for s in SIGMAS for kr in K_RATIOS]
+    phi = torch.empty((len(contracts), plan.points), dtype=torch.float64, device=dev)
+    V = torch.empty_like(phi)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        plan.transitions(0, 0, counts=counts)                 # zero fill only
+        if ev is not None:
+            ev[0].record(stream)
+        plan.transitions_add(counts, M_PAIRS, 0x5EED0000)
+        if ev is not None:
+            ev[1].record(stream)
+        for q, (s, kr) in enumerate(contracts):
+            plan.payoff(qt.PUT, S0, S0 * kr, RATE, MATURITY, s, out=phi[q])
+        plan.bdp(counts, phi, V=V, want_v0=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(args.steps):
+        step(evs[i])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    V0 = V[:, 0].cpu().numpy()
+    pairs = N_LAYERS * M_PAIRS
+    achieved = ALG_SLOTS_PER_PAIR * pairs / (fwd_ms * 1e-3)
+    out = {
+        "metric": "MC transition samples/s (cell search+count)",
+        "value": pairs / (ms_step * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 samples, int32 counts, f64 BDP",
+        "data": "synthetic",
+        "config": {"workload": "1-D Bermudan put tree, time-layer parallel: n=50 layers, "
+                               "N=500 Lloyd points/layer, M=1e7 pairs/layer, "
+                               "12-contract sigma x K BDP sweep",
+                   "layers": N_LAYERS, "points_per_layer": N_POINTS, "pairs_per_layer": M_PAIRS,
+                   "contracts": len(contracts), "mode": "layerwise"},
+        "forward_ms": fwd_ms,
+        "forward_pairs_per_s": pairs / (fwd_ms * 1e-3),
+        "V0_atm_sigma0.2": float(V0[contracts.index((0.2, 1.0))]),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "kernel": "fwd_layer_1d",
+                     "alg_slots_per_pair": ALG_SLOTS_PER_PAIR},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, grid, N, args.cpu_pairs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * qtree: quantization-tree transition estimation and backward dynamic
+ * programming on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Pages & Wilbertz, "GPGPUs in computational finance: Massive
+ * parallel computing for American style options" (arXiv:1101.3228).
+ *   - Sec. 2: grids Gamma_k of N_k points, Voronoi cells C_i(Gamma_k), the
+ *     nearest neighbour projection, transition weights
+ *     pi^k_ij = P(X_{k+1} in C_j(Gamma_{k+1}) | X_k in C_i(Gamma_k)) (eq. defPi,
+ *     read from layer k to k+1), and the quantized backward dynamic
+ *     programming V_k = max(phi_k, sum_j pi^k_ij V_{k+1}(j)).
+ *   - Sec. 3: the AR(1) proposition X_{k+1} = A_k X_k + T_k eps_k and the
+ *     Monte Carlo estimate of pi^k_ij by counters p^k_ij (Algorithm I,
+ *     parallel over paths as Algorithm II).
+ *   - Sec. 4: the time-layer parallel estimate that samples (X_k, eps_k)
+ *     directly from the marginal of X_k (Algorithm III).
+ *
+ * Conventions for every call:
+ *   - Host pointers are marked "host", device pointers "device".  Device
+ *     buffers are owned by the caller (for instance torch tensors); the
+ *     library never frees them.  No call allocates device memory except
+ *     where its comment says so.
+ *   - Arrays are row-major and the layers are concatenated:
+ *       grid   : float[sum_k N_k][d], layers k = 0..n
+ *       counts : int32[sum_{k<n} N_k N_{k+1}], block k is N_k x N_{k+1}
+ *       phi, V : double[n_pay][sum_k N_k]
+ *   - Layer 0 is the start point: N_0 = 1 and grid layer 0 = {x_0}.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on it unless their comment says otherwise.
+ *   - Errors are returned, never raised; qtree_status_string() names them and
+ *     qtree_last_error() gives the detail of the last failure on this thread.
+ *     Argument checks run on the host before any device work: on an error
+ *     return no device work was queued and outputs are untouched.
+ *   - Results are bitwise deterministic: counts depend only on (model, grid,
+ *     m0, M, seed, contract_id, mode), never on the launch configuration.
+ */
+#ifndef QTREE_H
+#define QTREE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QTREE_OK = 0,
+  QTREE_EINVAL = 1,      /* bad argument: shape, pointer, non-finite or unsorted grid */
+  QTREE_ENOMEM = 2,      /* workspace too small */
+  QTREE_EOVERFLOW = 3,   /* a count could exceed int32 (M >= 2^31) or m0 + M > 2^32 */
+  QTREE_EDEVICE = 4,     /* a HIP runtime call failed (detail in qtree_last_error) */
+  QTREE_EUNSUPPORTED = 5 /* valid request this build does not implement */
+} qtree_status;
+
+typedef enum {
+  QTREE_LAYERWISE = 0, /* Algorithm III: M pairs (X_k, X_{k+1}) per layer, layers in parallel */
+  QTREE_PATHWISE = 1   /* Algorithm I/II: M paths X_0 -> X_n, one thread per path */
+} qtree_mode;
+
+/* AR(1) model of the Proposition in Sec. 3, FP32, host arrays:
+ *   X_{k+1} = A_k X_k + b_k + T_k eps_k,  eps_k ~ N(0, I_d)   (k = 0..n-1)
+ *   X_k     = mu_k + L_k z,               z ~ N(0, I_d)        (k = 0..n)
+ * A, T: [n][d][d]; b: [n][d]; mu: [n+1][d]; L: [n+1][d][d]; x0: [d].
+ * The marginal form (mu, L) is what the time-layer parallel mode samples. */
+typedef struct {
+  int32_t d; /* state dimension, 1..3 */
+  int32_t n; /* number of transitions; layers 0..n */
+  const float *A, *b, *T;
+  const float *mu, *L;
+  const float *x0;
+} qtree_model;
+
+typedef struct qtree_plan qtree_plan; /* opaque host object */
+
+const char *qtree_status_string(qtree_status s);
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *qtree_last_error(void);
+/* Library version string. */
+const char *qtree_version(void);
+
+/* Bytes of device workspace a plan for this shape needs (d in 1..3,
+ * N: host [n+1]).  Pure host arithmetic. */
+qtree_status qtree_workspace_size(int32_t d, int32_t n, const int32_t *N, size_t *bytes);
+
+/* Validate a model and its grids on the host and upload the per-layer tables
+ * the kernels read (model coefficients, grid points, 1-D cell midpoints or
+ * d >= 2 half norms) into `workspace` (device, >= qtree_workspace_size bytes,
+ * owned by the caller and referenced by the plan until it is destroyed).
+ * grid: host float[sum N_k][d]; 1-D grids must be strictly increasing, all
+ * values finite; N[0] == 1.  Blocks until the upload has finished.
+ * *out receives a host object released by qtree_plan_destroy. */
+qtree_status qtree_plan_create(const qtree_model *model, const float *grid, const int32_t *N,
+                               void *workspace, size_t workspace_bytes, qtree_plan **out);
+void qtree_plan_destroy(qtree_plan *plan);
+/* Shape queries (host). */
+int32_t qtree_plan_dim(const qtree_plan *plan);
+int32_t qtree_plan_layers(const qtree_plan *plan);
+int64_t qtree_plan_count_entries(const qtree_plan *plan); /* sum_{k<n} N_k N_{k+1} */
+int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
+
+/* Launch tuning of a plan (results never depend on it).
+ *   QTREE_TUNE_CHUNK   : samples per workgroup in LAYERWISE mode (0 = automatic;
+ *                        otherwise rounded up to an even number >= 2).
+ *   QTREE_TUNE_XCD_MAP : 1 (default) deals the chunks of one layer to one XCD,
+ *                        0 uses the plain block order. */
+typedef enum { QTREE_TUNE_CHUNK = 0, QTREE_TUNE_XCD_MAP = 1 } qtree_tune_key;
+qtree_status qtree_plan_tune(qtree_plan *plan, int32_t key, int64_t value);
+
+/* Monte Carlo transition counts p^k_ij (Sec. 3 Algorithm I/II, Sec. 4
+ * Algorithm III) over samples m = m0 .. m0+M-1.
+ *   LAYERWISE: sample m of layer k draws z, eps from Philox4x32-10 with key
+ *     (seed lo, seed hi) and counter (block(m), k, contract_id, 0), sets
+ *     X_k = mu_k + L_k z, X_{k+1} = A_k X_k + b_k + T_k eps and adds one to
+ *     counts[k][cell_k(X_k)][cell_{k+1}(X_{k+1})].
+ *   PATHWISE: path m starts at x0 in cell 0 of layer 0 and for k = 0..n-1
+ *     steps X_{k+1} = A_k X_k + b_k + T_k eps_k (counter (m, k>>s, contract_id, 1))
+ *     and adds one to counts[k][i][j] for the cells i, j it leaves and enters.
+ * cell_k is the Voronoi cell of Gamma_k: in 1-D the number of FP32 midpoints
+ * (x_r + x_{r+1})/2 strictly below the point; in d >= 2 the lowest index
+ * minimising the FP32 half-norm form |g|^2/2 - <x, g> of the squared distance.
+ * counts: device int32[qtree_plan_count_entries], zeroed and overwritten.
+ * Requires M < 2^31 and m0 + M <= 2^32.  Asynchronous on `stream`. */
+qtree_status qtree_transitions(const qtree_plan *plan, uint64_t m0, uint64_t M, uint64_t seed,
+                               uint32_t contract_id, qtree_mode mode, int32_t *counts,
+                               void *stream);
+
+/* As qtree_transitions but adds to `counts` instead of overwriting them:
+ * counts over [m0, m0+M) accumulate onto earlier calls, so a run can be split
+ * into sample chunks (and resumed) with totals identical to one call. */
+qtree_status qtree_transitions_add(const qtree_plan *plan, uint64_t m0, uint64_t M, uint64_t seed,
+                                   uint32_t contract_id, qtree_mode mode, int32_t *counts,
+                                   void *stream);
+
+/* Quantized backward dynamic programming (Sec. 2), FP64, for n_pay obstacle
+ * vectors sharing one set of counts:
+ *   V_n = phi_n;  V_k(i) = max(phi_k(i), sum_j c_ij V_{k+1}(j) / p_i),
+ *   p_i = sum_j c_ij; a row no sample reached (p_i = 0) has continuation 0.
+ * counts: device int32 (as written by qtree_transitions); phi: device
+ * double[n_pay][sum N_k] (use -inf for k < n to price a European claim);
+ * V: device double[n_pay][sum N_k] output (all layers).  If V0_host is not
+ * NULL the call copies V_0 of every payoff there and synchronises `stream`
+ * before returning; otherwise it is asynchronous. */
+qtree_status qtree_bdp(const qtree_plan *plan, const int32_t *counts, const double *phi,
+                       int32_t n_pay, double *V, double *V0_host, void *stream);
+
+/* Discounted obstacle on the plan's grid points, FP64, device output
+ * phi: double[sum N_k]:  phi_k(x) = exp(-r t_k) payoff(S_{t_k}(x)),
+ * t_k = k Tm / n, S^a_t(x) = S0 exp((r - sigma_a^2/2) t + sigma_a x_a)
+ * (Sec. 2: obstacle of the optimal stopping problem on a Brownian state).
+ * kind bit 0: 0 put on S^1, 1 call on max_a S^a; bit 1: European
+ * (phi_k = -inf for k < n).  sigma: host double[d].  Asynchronous. */
+qtree_status qtree_payoff(const qtree_plan *plan, int32_t kind, double S0, double K, double r,
+                          double Tm, const double *sigma, double *phi, void *stream);
+
+/* Per-sample diagnostics, computed by the same device code as the forward
+ * kernels, so tests can compare intermediate results one by one.
+ * qtree_box_muller: z0/z1[i] = Box-Muller transform of the Philox words
+ *   (ra[i], rb[i]) (device arrays of `count` elements).
+ * qtree_layer_samples: X_k and X_{k+1} of LAYERWISE samples m0..m0+count-1
+ *   of layer k (0 <= k < n), device float[count][d] each.
+ * qtree_cells: Voronoi cell in layer k (0 <= k <= n) of `count` device points
+ *   x (float[count][d]); cell: device int32[count].
+ * All asynchronous on `stream`. */
+qtree_status qtree_box_muller(const uint32_t *ra, const uint32_t *rb, int64_t count, float *z0,
+                              float *z1, void *stream);
+qtree_status qtree_layer_samples(const qtree_plan *plan, int32_t k, uint64_t m0, int64_t count,
+                                 uint64_t seed, uint32_t contract_id, float *x, float *y,
+                                 void *stream);
+qtree_status qtree_cells(const qtree_plan *plan, int32_t k, const float *x, int64_t count,
+                         int32_t *cell, void *stream);
+
+/* Host helpers for inputs (FP64, host memory, no device work). */
+/* 1-D quadratic-optimal quantizer of N(0,1) with N points (Sec. 2,
+ * eq. Qerr): stationary grid of Lloyd's method, out: double[N], ascending. */
+qtree_status qtree_gauss_quantizer(int32_t N, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTREE_H */

@@ -263,3 +263,39 @@ def layer_pairs(model: Model, k: int, m0: int, count: int, seed: int, contract: 
 
 def pi_estimate(seed: int, rep: int, npts: int) -> float:
     return float(_bulk_setup().oracle_pi_estimate(seed, rep, npts))
+
+
+def layer_counts_one(model: Model, grid: np.ndarray, N, k: int, M: int, seed: int,
+                     contract: int = 0, m0: int = 0, nthreads: int = 1) -> np.ndarray:
+    """Counts of the single layer k -> k+1 (time-layer parallel estimate)."""
+    L = lib()
+    if not getattr(L, "_one", False):
+        P = ctypes.c_void_p
+        L.oracle_layer_counts.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                          P, ctypes.c_int32]
+        L.oracle_layer_counts.restype = ctypes.c_int
+        L._one = True
+    N = np.ascontiguousarray(N, np.int32)
+    g = np.ascontiguousarray(grid, np.float32)
+    out = np.zeros((int(N[k]), int(N[k + 1])), np.int32)
+    rc = L.oracle_layer_counts(model.cptr(), _ptr(g), _ptr(N), k, m0, M, seed, contract,
+                               _ptr(out), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle_layer_counts rejected its arguments (code {rc})")
+    return out
+
+
+def cells_bulk(grid_k: np.ndarray, d: int, x: np.ndarray) -> np.ndarray:
+    """Voronoi cells of many points (plain loop in C)."""
+    L = lib()
+    if not getattr(L, "_cells", False):
+        P = ctypes.c_void_p
+        L.oracle_cells_bulk.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, P]
+        L.oracle_cells_bulk.restype = None
+        L._cells = True
+    g = np.ascontiguousarray(grid_k, np.float32)
+    xv = np.ascontiguousarray(x, np.float32).reshape(-1, d)
+    out = np.zeros(xv.shape[0], np.int32)
+    L.oracle_cells_bulk(_ptr(g), g.size // d, d, _ptr(xv), xv.shape[0], _ptr(out))
+    return out

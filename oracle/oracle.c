@@ -528,3 +528,66 @@ double oracle_pi_estimate(uint64_t seed, uint32_t rep, uint64_t npts) {
   }
   return 4.0 * (double)inside / (double)((npts / 2) * 2);
 }
+
+/* Counts of one layer k -> k+1 of the time-layer parallel estimate over
+   samples m0 .. m0+M-1 (Algorithm III restricted to one layer), for checking
+   single layers of large problems.  counts_k: int32[N_k][N_{k+1}],
+   overwritten.  Threads split the samples and add atomically. */
+typedef struct {
+  const oracle_model *mdl;
+  const layer_grid *g0, *g1;
+  int32_t k, N1;
+  uint64_t lo, hi, seed;
+  uint32_t contract;
+  int32_t *ck;
+} layer_job;
+
+static void *run_one_layer(void *arg) {
+  layer_job *J = (layer_job *)arg;
+  for (uint64_t m = J->lo; m < J->hi; ++m) {
+    float x[3], y[3];
+    oracle_layer_pair(J->mdl, J->k, m, J->seed, J->contract, x, y);
+    int32_t i = layer_cell(J->g0, x);
+    int32_t j = layer_cell(J->g1, y);
+    __atomic_fetch_add(&J->ck[(int64_t)i * J->N1 + j], 1, __ATOMIC_RELAXED);
+  }
+  return NULL;
+}
+
+int oracle_layer_counts(const oracle_model *mdl, const float *grid, const int32_t *N, int32_t k,
+                        uint64_t m0, uint64_t M, uint64_t seed, uint32_t contract,
+                        int32_t *counts_k, int32_t nthreads) {
+  if (!mdl || !grid || !N || !counts_k || k < 0 || k >= mdl->n) return 1;
+  if (M >= (1ull << 31) || m0 + M > (1ull << 32)) return 2;
+  if (nthreads < 1) nthreads = 1;
+  int d = mdl->d;
+  int64_t off = 0;
+  for (int32_t l = 0; l < k; ++l) off += N[l];
+  layer_grid g0, g1;
+  layer_grid_init(&g0, grid + off * d, N[k], d);
+  layer_grid_init(&g1, grid + (off + N[k]) * d, N[k + 1], d);
+  memset(counts_k, 0, sizeof(int32_t) * (size_t)N[k] * (size_t)N[k + 1]);
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+  layer_job *jobs = (layer_job *)malloc(sizeof(layer_job) * (size_t)nthreads);
+  uint64_t per = (M + (uint64_t)nthreads - 1) / (uint64_t)nthreads;
+  for (int32_t t = 0; t < nthreads; ++t) {
+    uint64_t lo = m0 + per * (uint64_t)t, hi = lo + per;
+    if (lo > m0 + M) lo = m0 + M;
+    if (hi > m0 + M) hi = m0 + M;
+    layer_job J = {mdl, &g0, &g1, k, N[k + 1], lo, hi, seed, contract, counts_k};
+    jobs[t] = J;
+    pthread_create(&th[t], NULL, run_one_layer, &jobs[t]);
+  }
+  for (int32_t t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  free(g0.aux); free(g1.aux); free(th); free(jobs);
+  return 0;
+}
+
+/* Cells of `count` points x[count][d] in one grid (plain loop over oracle_cell). */
+void oracle_cells_bulk(const float *grid_k, int32_t N, int32_t d, const float *x, int64_t count,
+                       int32_t *out) {
+  layer_grid lg;
+  layer_grid_init(&lg, grid_k, N, d);
+  for (int64_t i = 0; i < count; ++i) out[i] = layer_cell(&lg, x + i * d);
+  free(lg.aux);
+}

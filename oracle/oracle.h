@@ -79,6 +79,14 @@ void oracle_philox_bulk(const uint32_t *ctr, const uint32_t key[2], int64_t coun
 void oracle_layer_pairs_bulk(const oracle_model *mdl, int32_t k, uint64_t m0, int64_t count,
                              uint64_t seed, uint32_t contract, float *xk, float *xk1);
 double oracle_pi_estimate(uint64_t seed, uint32_t rep, uint64_t npts);
+/* Cells of count points x[count][d] in one grid of N points. */
+void oracle_cells_bulk(const float *grid_k, int32_t N, int32_t d, const float *x, int64_t count,
+                       int32_t *out);
+/* Counts of the single layer k -> k+1 (Algorithm III) over samples
+   m0..m0+M-1; counts_k: int32[N_k][N_{k+1}], overwritten. */
+int oracle_layer_counts(const oracle_model *mdl, const float *grid, const int32_t *N, int32_t k,
+                        uint64_t m0, uint64_t M, uint64_t seed, uint32_t contract,
+                        int32_t *counts_k, int32_t nthreads);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,246 @@
+"""Python binding of the qtree HIP library (quantization-tree forward step and
+backward dynamic programming on MI355X, after Pages & Wilbertz,
+arXiv:1101.3228).
+
+Argument marshalling only: every step runs in libqtree.so (HIP kernels for
+gfx950 behind the C-ABI declared in include/qtree.h).  torch supplies device
+memory and the current stream.  If the library is missing this module raises
+on import of the binding -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqtree.so")
+
+LAYERWISE = 0
+PATHWISE = 1
+PUT, MAX_CALL, EUROPEAN = 0, 1, 2
+
+_STATUS = {0: "ok", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERFLOW", 4: "EDEVICE", 5: "EUNSUPPORTED"}
+
+
+class QtreeError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"qtree {_STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("T", ctypes.c_void_p),
+                ("mu", ctypes.c_void_p), ("L", ctypes.c_void_p), ("x0", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqtree.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1101_3228_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double)
+    L.qtree_status_string.argtypes = [ctypes.c_int]
+    L.qtree_status_string.restype = ctypes.c_char_p
+    L.qtree_last_error.restype = ctypes.c_char_p
+    L.qtree_version.restype = ctypes.c_char_p
+    L.qtree_workspace_size.argtypes = [i32, i32, P, P]
+    L.qtree_plan_create.argtypes = [P, P, P, P, ctypes.c_size_t, P]
+    L.qtree_plan_destroy.argtypes = [P]
+    L.qtree_plan_destroy.restype = None
+    for f in ("qtree_plan_dim", "qtree_plan_layers"):
+        getattr(L, f).argtypes = [P]
+        getattr(L, f).restype = i32
+    for f in ("qtree_plan_count_entries", "qtree_plan_points"):
+        getattr(L, f).argtypes = [P]
+        getattr(L, f).restype = i64
+    L.qtree_transitions.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
+    L.qtree_transitions_add.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
+    L.qtree_transitions_add.restype = ctypes.c_int
+    L.qtree_bdp.argtypes = [P, P, P, i32, P, P, P]
+    L.qtree_payoff.argtypes = [P, i32, f64, f64, f64, f64, P, P, P]
+    L.qtree_gauss_quantizer.argtypes = [i32, P]
+    L.qtree_box_muller.argtypes = [P, P, i64, P, P, P]
+    L.qtree_plan_tune.argtypes = [P, i32, i64]
+    L.qtree_plan_tune.restype = ctypes.c_int
+    L.qtree_layer_samples.argtypes = [P, i32, u64, i64, u64, u32, P, P, P]
+    L.qtree_cells.argtypes = [P, i32, P, i64, P, P]
+    for f in ("qtree_workspace_size", "qtree_plan_create", "qtree_transitions", "qtree_bdp",
+              "qtree_payoff", "qtree_gauss_quantizer", "qtree_box_muller",
+              "qtree_layer_samples", "qtree_cells"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise QtreeError(status, lib().qtree_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def version() -> str:
+    return lib().qtree_version().decode()
+
+
+def gauss_quantizer(N: int) -> np.ndarray:
+    """Stationary (Lloyd) quantizer of N(0,1) with N points, FP64 (host)."""
+    out = np.zeros(int(N), np.float64)
+    _check(lib().qtree_gauss_quantizer(int(N), _np_ptr(out)))
+    return out
+
+
+def workspace_size(d: int, n: int, N) -> int:
+    Nn = np.ascontiguousarray(N, np.int32)
+    b = ctypes.c_size_t(0)
+    _check(lib().qtree_workspace_size(int(d), int(n), _np_ptr(Nn), ctypes.byref(b)))
+    return int(b.value)
+
+
+class Plan:
+    """A validated model + grids resident in a device workspace (one
+    qtree_plan).  model: dict of FP32 host arrays d, n, A, b, T, mu, L, x0;
+    grid: host float32 [sum N_k, d]; N: host int32 [n+1]."""
+
+    def __init__(self, model: dict, grid: np.ndarray, N, device: str = "cuda"):
+        import torch
+        self.d, self.n = int(model["d"]), int(model["n"])
+        self.N = np.ascontiguousarray(N, np.int32)
+        keep = {k: np.ascontiguousarray(model[k], np.float32) for k in
+                ("A", "b", "T", "mu", "L", "x0")}
+        self._keep = keep
+        g = np.ascontiguousarray(grid, np.float32)
+        self.grid = g
+        cm = _Model(self.d, self.n, *(keep[k].ctypes.data for k in ("A", "b", "T", "mu", "L",
+                                                                    "x0")))
+        size = workspace_size(self.d, self.n, self.N)
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib().qtree_plan_create(ctypes.byref(cm), _np_ptr(g), _np_ptr(self.N),
+                                       self.workspace.data_ptr(), size, ctypes.byref(h)))
+        self._h = h
+        self.entries = int(lib().qtree_plan_count_entries(h))
+        self.points = int(lib().qtree_plan_points(h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qtree_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def tune(self, chunk: int | None = None, xcd_map: int | None = None):
+        """Launch tuning (QTREE_TUNE_CHUNK / QTREE_TUNE_XCD_MAP); results unchanged."""
+        if chunk is not None:
+            _check(lib().qtree_plan_tune(self._h, 0, int(chunk)))
+        if xcd_map is not None:
+            _check(lib().qtree_plan_tune(self._h, 1, int(xcd_map)))
+        return self
+
+    def count_offsets(self) -> np.ndarray:
+        N = self.N.astype(np.int64)
+        return np.concatenate([[0], np.cumsum(N[:-1] * N[1:])])
+
+    def point_offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.N.astype(np.int64))])
+
+    def new_counts(self):
+        import torch
+        return torch.empty(max(self.entries, 4), dtype=torch.int32, device=self.workspace.device)
+
+    def transitions(self, M: int, seed: int, contract: int = 0, mode: int = LAYERWISE,
+                    m0: int = 0, counts=None, stream=None):
+        """Transition counts (device int32 [entries]); asynchronous."""
+        if counts is None:
+            counts = self.new_counts()
+        _check(lib().qtree_transitions(self._h, int(m0), int(M), int(seed), int(contract),
+                                       int(mode), counts.data_ptr(), _stream_handle(stream)))
+        return counts[:self.entries]
+
+    def transitions_add(self, counts, M: int, seed: int, contract: int = 0,
+                        mode: int = LAYERWISE, m0: int = 0, stream=None):
+        """Add the counts of samples m0..m0+M-1 onto `counts`; asynchronous."""
+        _check(lib().qtree_transitions_add(self._h, int(m0), int(M), int(seed), int(contract),
+                                           int(mode), counts.data_ptr(), _stream_handle(stream)))
+        return counts
+
+    def payoff(self, kind: int, S0: float, K: float, r: float, T: float, sigma, out=None,
+               stream=None):
+        """Discounted obstacle phi on the grid points (device float64 [points])."""
+        import torch
+        sig = np.ascontiguousarray(np.resize(np.atleast_1d(np.asarray(sigma, np.float64)),
+                                             self.d), np.float64)
+        if out is None:
+            out = torch.empty(self.points, dtype=torch.float64, device=self.workspace.device)
+        _check(lib().qtree_payoff(self._h, int(kind), float(S0), float(K), float(r), float(T),
+                                  _np_ptr(sig), out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def bdp(self, counts, phi, V=None, want_v0: bool = True, stream=None):
+        """Backward dynamic programming (FP64).  phi: device float64
+        [n_pay, points] (or [points]).  Returns (V0 numpy [n_pay] or None, V)."""
+        import torch
+        phi2 = phi.reshape(-1, self.points)
+        n_pay = phi2.shape[0]
+        if V is None:
+            V = torch.empty((n_pay, self.points), dtype=torch.float64, device=phi.device)
+        V0 = np.zeros(n_pay, np.float64) if want_v0 else None
+        _check(lib().qtree_bdp(self._h, counts.data_ptr(), phi2.data_ptr(), n_pay, V.data_ptr(),
+                               _np_ptr(V0) if want_v0 else None, _stream_handle(stream)))
+        return V0, V
+
+
+def box_muller(ra, rb, stream=None):
+    """Diagnostic: Box-Muller of device uint32 word pairs (torch int32 views)."""
+    import torch
+    z0 = torch.empty(ra.numel(), dtype=torch.float32, device=ra.device)
+    z1 = torch.empty_like(z0)
+    _check(lib().qtree_box_muller(ra.data_ptr(), rb.data_ptr(), ra.numel(), z0.data_ptr(),
+                                  z1.data_ptr(), _stream_handle(stream)))
+    return z0, z1
+
+
+def layer_samples(plan: Plan, k: int, m0: int, count: int, seed: int, contract: int = 0,
+                  stream=None):
+    """Diagnostic: (X_k, X_{k+1}) of LAYERWISE samples m0..m0+count-1."""
+    import torch
+    dev = plan.workspace.device
+    x = torch.empty((max(count, 1), plan.d), dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    _check(lib().qtree_layer_samples(plan.handle, int(k), int(m0), int(count), int(seed),
+                                     int(contract), x.data_ptr(), y.data_ptr(),
+                                     _stream_handle(stream)))
+    return x[:count], y[:count]
+
+
+def cells(plan: Plan, k: int, x, stream=None):
+    """Diagnostic: Voronoi cell in layer k of device points x [count, d]."""
+    import torch
+    x = x.contiguous()
+    count = x.shape[0]
+    out = torch.empty(max(count, 1), dtype=torch.int32, device=x.device)
+    _check(lib().qtree_cells(plan.handle, int(k), x.data_ptr(), int(count), out.data_ptr(),
+                             _stream_handle(stream)))
+    return out[:count]

@@ -1,0 +1,444 @@
+// C-ABI of the qtree library: argument checks, plan/workspace layout and
+// kernel dispatch.  Declarations and contracts are in include/qtree.h.
+#include "qtree.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qtree_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qtree_status fail(qtree_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+qtree_status hip_fail(hipError_t e, const char* what) {
+  return fail(QTREE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+int log2i(int p) {
+  int l = 0;
+  while ((1 << l) < p) ++l;
+  return l;
+}
+
+// LDS limits of the kernels (160 KiB per CU; the 1-D layerwise kernel stages
+// two padded midpoint arrays, the d >= 2 kernel two point arrays of 16 B).
+constexpr int kMaxN1d = 16384;
+constexpr int kMaxNnd = 4096;
+
+}  // namespace
+
+struct qtree_plan {
+  int d = 0, n = 0;
+  std::vector<int32_t> N;
+  std::vector<int64_t> pt_off, cnt_off, aux_off;
+  std::vector<int32_t> P;
+  int64_t points = 0, entries = 0, mids_total = 0;
+  int32_t maxN = 0, maxP = 0;
+  char* ws = nullptr;
+  qtree::WsLayout lay{};
+  int64_t tune_chunk = 0;  // 0: automatic
+  int32_t tune_xcd_map = 1;
+};
+
+namespace qtree {
+
+WsLayout ws_layout(int d, int n, const int32_t* N) {
+  WsLayout l{};
+  size_t off = 0;
+  l.layers = off;
+  off = align_up(off + sizeof(LayerDev) * (size_t)(n + 1), 256);
+  int64_t pts = 0, mids = 0;
+  for (int k = 0; k <= n; ++k) {
+    pts += N[k];
+    mids += next_pow2(N[k]);
+  }
+  l.points = off;
+  off = align_up(off + (size_t)pts * (d == 1 ? sizeof(float) : sizeof(float4)), 256);
+  l.aux = off;
+  if (d == 1) off = align_up(off + (size_t)mids * sizeof(float), 256);
+  l.total = off;
+  return l;
+}
+
+}  // namespace qtree
+
+extern "C" {
+
+const char* qtree_status_string(qtree_status s) {
+  switch (s) {
+    case QTREE_OK: return "ok";
+    case QTREE_EINVAL: return "invalid argument";
+    case QTREE_ENOMEM: return "workspace too small";
+    case QTREE_EOVERFLOW: return "count overflow (M >= 2^31 or m0 + M > 2^32)";
+    case QTREE_EDEVICE: return "HIP runtime error";
+    case QTREE_EUNSUPPORTED: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+const char* qtree_last_error(void) { return g_last_error.c_str(); }
+
+const char* qtree_version(void) { return "qtree 0.1 gfx950"; }
+
+static qtree_status check_shape(int32_t d, int32_t n, const int32_t* N) {
+  if (d < 1 || d > 3) return fail(QTREE_EINVAL, "d must be 1, 2 or 3");
+  if (n < 1) return fail(QTREE_EINVAL, "n must be >= 1");
+  if (!N) return fail(QTREE_EINVAL, "N is NULL");
+  if (N[0] != 1) return fail(QTREE_EINVAL, "N[0] must be 1 (layer 0 is the start point)");
+  for (int k = 0; k <= n; ++k) {
+    if (N[k] < 1) return fail(QTREE_EINVAL, "N[k] must be >= 1 (layer " + std::to_string(k) + ")");
+    if (d == 1 && N[k] > kMaxN1d)
+      return fail(QTREE_EUNSUPPORTED, "1-D layers are limited to 16384 points");
+    if (d > 1 && N[k] > kMaxNnd)
+      return fail(QTREE_EUNSUPPORTED, "2-D/3-D layers are limited to 4096 points");
+  }
+  return QTREE_OK;
+}
+
+qtree_status qtree_workspace_size(int32_t d, int32_t n, const int32_t* N, size_t* bytes) {
+  if (!bytes) return fail(QTREE_EINVAL, "bytes is NULL");
+  qtree_status s = check_shape(d, n, N);
+  if (s != QTREE_OK) return s;
+  *bytes = qtree::ws_layout(d, n, N).total;
+  return QTREE_OK;
+}
+
+static bool all_finite(const float* p, size_t count) {
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+qtree_status qtree_plan_create(const qtree_model* model, const float* grid, const int32_t* N,
+                               void* workspace, size_t workspace_bytes, qtree_plan** out) {
+  if (!out) return fail(QTREE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!model) return fail(QTREE_EINVAL, "model is NULL");
+  const int d = model->d, n = model->n;
+  qtree_status s = check_shape(d, n, N);
+  if (s != QTREE_OK) return s;
+  if (!model->A || !model->b || !model->T || !model->mu || !model->L || !model->x0)
+    return fail(QTREE_EINVAL, "model array is NULL");
+  if (!grid) return fail(QTREE_EINVAL, "grid is NULL");
+  if (!workspace) return fail(QTREE_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 16)
+    return fail(QTREE_EINVAL, "workspace must be 16-byte aligned");
+  const size_t dd = (size_t)d * d;
+  if (!all_finite(model->A, dd * n) || !all_finite(model->b, (size_t)d * n) ||
+      !all_finite(model->T, dd * n) || !all_finite(model->mu, (size_t)d * (n + 1)) ||
+      !all_finite(model->L, dd * (n + 1)) || !all_finite(model->x0, d))
+    return fail(QTREE_EINVAL, "model coefficients must be finite");
+
+  qtree_plan p;
+  p.d = d;
+  p.n = n;
+  p.N.assign(N, N + n + 1);
+  p.pt_off.resize(n + 2);
+  p.cnt_off.resize(n + 1);
+  p.aux_off.resize(n + 2);
+  p.P.resize(n + 1);
+  p.pt_off[0] = 0;
+  p.cnt_off[0] = 0;
+  p.aux_off[0] = 0;
+  for (int k = 0; k <= n; ++k) {
+    p.pt_off[k + 1] = p.pt_off[k] + N[k];
+    p.P[k] = next_pow2(N[k]);
+    p.aux_off[k + 1] = p.aux_off[k] + p.P[k];
+    if (k < n) p.cnt_off[k + 1] = p.cnt_off[k] + (int64_t)N[k] * N[k + 1];
+    if (N[k] > p.maxN) p.maxN = N[k];
+    if (p.P[k] > p.maxP) p.maxP = p.P[k];
+  }
+  p.points = p.pt_off[n + 1];
+  p.entries = p.cnt_off[n];
+  p.mids_total = p.aux_off[n + 1];
+  if (!all_finite(grid, (size_t)p.points * d)) return fail(QTREE_EINVAL, "grid must be finite");
+  if (d == 1) {
+    for (int k = 0; k <= n; ++k) {
+      const float* g = grid + p.pt_off[k];
+      for (int r = 0; r + 1 < N[k]; ++r)
+        if (!(g[r] < g[r + 1]))
+          return fail(QTREE_EINVAL, "1-D grid of layer " + std::to_string(k) +
+                                        " must be strictly increasing");
+    }
+  }
+  p.lay = qtree::ws_layout(d, n, N);
+  if (workspace_bytes < p.lay.total)
+    return fail(QTREE_ENOMEM, "workspace needs " + std::to_string(p.lay.total) + " bytes");
+
+  // host image of the workspace
+  std::vector<char> img(p.lay.total, 0);
+  auto* layers = reinterpret_cast<qtree::LayerDev*>(img.data() + p.lay.layers);
+  for (int k = 0; k <= n; ++k) {
+    qtree::LayerDev L{};
+    L.cnt_off = k < n ? p.cnt_off[k] : 0;
+    L.N = N[k];
+    L.N1 = k < n ? N[k + 1] : 0;
+    L.pt_off = (int32_t)p.pt_off[k];
+    L.aux_off = (int32_t)p.aux_off[k];
+    L.P = p.P[k];
+    L.logP = log2i(p.P[k]);
+    if (k < n) {
+      std::memcpy(L.A, model->A + dd * k, sizeof(float) * dd);
+      std::memcpy(L.b, model->b + (size_t)d * k, sizeof(float) * d);
+      std::memcpy(L.T, model->T + dd * k, sizeof(float) * dd);
+    }
+    std::memcpy(L.mu, model->mu + (size_t)d * k, sizeof(float) * d);
+    std::memcpy(L.L, model->L + dd * k, sizeof(float) * dd);
+    std::memcpy(L.x0, model->x0, sizeof(float) * d);
+    layers[k] = L;
+  }
+  if (d == 1) {
+    std::memcpy(img.data() + p.lay.points, grid, sizeof(float) * (size_t)p.points);
+    float* mids = reinterpret_cast<float*>(img.data() + p.lay.aux);
+    for (int k = 0; k <= n; ++k) {
+      const float* g = grid + p.pt_off[k];
+      float* m = mids + p.aux_off[k];
+      // cell edges of Gamma_k: FP32 midpoints (x_r + x_{r+1}) / 2, padded with +inf
+      for (int r = 0; r < p.P[k]; ++r)
+        m[r] = (r + 1 < N[k]) ? 0.5f * (g[r] + g[r + 1]) : INFINITY;
+    }
+  } else {
+    float4* pts = reinterpret_cast<float4*>(img.data() + p.lay.points);
+    for (int64_t t = 0; t < p.points; ++t) {
+      const float* g = grid + t * d;
+      // half norm |g|^2 / 2: g0*g0, then fused g_c*g_c + t, then the exact halving
+      float h = g[0] * g[0];
+      for (int c = 1; c < d; ++c) h = std::fmaf(g[c], g[c], h);
+      h = 0.5f * h;
+      pts[t] = make_float4(g[0], d > 1 ? g[1] : 0.f, d > 2 ? g[2] : 0.f, h);
+    }
+  }
+  hipError_t e = hipMemcpy(workspace, img.data(), p.lay.total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(workspace)");
+  p.ws = static_cast<char*>(workspace);
+  *out = new qtree_plan(std::move(p));
+  return QTREE_OK;
+}
+
+void qtree_plan_destroy(qtree_plan* plan) { delete plan; }
+
+int32_t qtree_plan_dim(const qtree_plan* p) { return p ? p->d : 0; }
+int32_t qtree_plan_layers(const qtree_plan* p) { return p ? p->n : 0; }
+int64_t qtree_plan_count_entries(const qtree_plan* p) { return p ? p->entries : 0; }
+int64_t qtree_plan_points(const qtree_plan* p) { return p ? p->points : 0; }
+
+static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uint64_t seed,
+                               uint32_t contract, int32_t* counts) {
+  qtree::FwdArgs a{};
+  a.layers = reinterpret_cast<const qtree::LayerDev*>(p->ws + p->lay.layers);
+  a.mids = reinterpret_cast<const float*>(p->ws + p->lay.aux);
+  a.pts = reinterpret_cast<const float4*>(p->ws + p->lay.points);
+  a.pts1 = reinterpret_cast<const float*>(p->ws + p->lay.points);
+  a.counts = counts;
+  a.m0 = m0;
+  a.M = M;
+  a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  a.key1 = (uint32_t)(seed >> 32);
+  a.contract = contract;
+  a.n = p->n;
+  a.d = p->d;
+  a.maxP = p->maxP;
+  a.maxN = p->maxN;
+  a.mids_total = p->mids_total;
+  return a;
+}
+
+// Split each layer's M samples into chunks; one workgroup per (layer, chunk).
+static void plan_units(qtree::FwdArgs& a, const qtree_plan* p) {
+  uint64_t target;
+  if (p->tune_chunk > 0) {
+    target = (uint64_t)p->tune_chunk;
+  } else if (p->d == 1) {
+    target = 1ull << 16;
+  } else {
+    // keep the per-workgroup scan work near 2^27 point evaluations
+    const uint64_t per_sample = 2ull * (uint64_t)p->maxN + 1;
+    target = (1ull << 27) / per_sample;
+    if (target < 2048) target = 2048;
+  }
+  uint64_t chunks = (a.M + target - 1) / target;
+  if (chunks < 1) chunks = 1;
+  if (chunks > (1u << 20)) chunks = 1u << 20;
+  uint64_t len = (a.M + chunks - 1) / chunks;
+  len += len & 1;  // even, so a chunk never splits a Philox block needlessly
+  if (len == 0) len = 2;
+  chunks = (a.M + len - 1) / len;
+  if (chunks < 1) chunks = 1;
+  a.chunk_len = len;
+  a.chunks = (int32_t)chunks;
+  a.units = a.n * a.chunks;
+  a.units_per_xcd = (a.units + 7) / 8;
+  a.xcd_map = p->tune_xcd_map;
+}
+
+qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (key == QTREE_TUNE_CHUNK) {
+    if (value < 0 || value > (1ll << 31)) return fail(QTREE_EINVAL, "chunk out of range");
+    plan->tune_chunk = value;
+    return QTREE_OK;
+  }
+  if (key == QTREE_TUNE_XCD_MAP) {
+    if (value != 0 && value != 1) return fail(QTREE_EINVAL, "xcd map must be 0 or 1");
+    plan->tune_xcd_map = (int32_t)value;
+    return QTREE_OK;
+  }
+  return fail(QTREE_EINVAL, "unknown tuning key");
+}
+
+static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64_t M,
+                                     uint64_t seed, uint32_t contract_id, qtree_mode mode,
+                                     int32_t* counts, void* stream, bool zero) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (!counts) return fail(QTREE_EINVAL, "counts is NULL");
+  if (reinterpret_cast<uintptr_t>(counts) % 16)
+    return fail(QTREE_EINVAL, "counts must be 16-byte aligned");
+  if (mode != QTREE_LAYERWISE && mode != QTREE_PATHWISE)
+    return fail(QTREE_EINVAL, "unknown mode");
+  if (M >= (1ull << 31)) return fail(QTREE_EOVERFLOW, "M must be < 2^31");
+  if (m0 + M > (1ull << 32)) return fail(QTREE_EOVERFLOW, "m0 + M must be <= 2^32");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (zero) {
+    e = qtree::launch_zero_i32(counts, plan->entries, s);
+    if (e != hipSuccess) return hip_fail(e, "zero fill");
+  }
+  if (M == 0) return QTREE_OK;
+  qtree::FwdArgs a = fwd_args(plan, m0, M, seed, contract_id, counts);
+  if (mode == QTREE_PATHWISE) {
+    e = qtree::launch_fwd_path(a, s);
+  } else {
+    plan_units(a, plan);
+    e = plan->d == 1 ? qtree::launch_fwd_layer_1d(a, s) : qtree::launch_fwd_layer_nd(a, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "forward kernel launch");
+  return QTREE_OK;
+}
+
+qtree_status qtree_transitions(const qtree_plan* plan, uint64_t m0, uint64_t M, uint64_t seed,
+                               uint32_t contract_id, qtree_mode mode, int32_t* counts,
+                               void* stream) {
+  return transitions_impl(plan, m0, M, seed, contract_id, mode, counts, stream, true);
+}
+
+qtree_status qtree_transitions_add(const qtree_plan* plan, uint64_t m0, uint64_t M, uint64_t seed,
+                                   uint32_t contract_id, qtree_mode mode, int32_t* counts,
+                                   void* stream) {
+  return transitions_impl(plan, m0, M, seed, contract_id, mode, counts, stream, false);
+}
+
+qtree_status qtree_bdp(const qtree_plan* plan, const int32_t* counts, const double* phi,
+                       int32_t n_pay, double* V, double* V0_host, void* stream) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (!counts || !phi || !V) return fail(QTREE_EINVAL, "counts, phi and V must be non-NULL");
+  if (n_pay < 1) return fail(QTREE_EINVAL, "n_pay must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  qtree::BdpArgs a{};
+  a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
+  a.counts = counts;
+  a.phi = phi;
+  a.V = V;
+  a.P = plan->points;
+  a.n_pay = n_pay;
+  const int n = plan->n;
+  hipError_t e = qtree::launch_copy_last_layer(a, plan->pt_off[n], plan->N[n], s);
+  if (e != hipSuccess) return hip_fail(e, "bdp launch");
+  for (int k = n - 1; k >= 0; --k) {
+    e = qtree::launch_bdp_layer(a, k, plan->N[k], plan->N[k + 1], plan->pt_off[k],
+                                plan->pt_off[k + 1], plan->cnt_off[k], s);
+    if (e != hipSuccess) return hip_fail(e, "bdp launch");
+  }
+  if (V0_host) {
+    e = hipMemcpy2DAsync(V0_host, sizeof(double), V, sizeof(double) * (size_t)plan->points,
+                         sizeof(double), (size_t)n_pay, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "V0 copy");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  }
+  return QTREE_OK;
+}
+
+qtree_status qtree_payoff(const qtree_plan* plan, int32_t kind, double S0, double K, double r,
+                          double Tm, const double* sigma, double* phi, void* stream) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (!sigma || !phi) return fail(QTREE_EINVAL, "sigma and phi must be non-NULL");
+  if (kind < 0 || kind > 3) return fail(QTREE_EINVAL, "kind must be in 0..3");
+  if (!(Tm > 0.0) || !std::isfinite(S0) || !std::isfinite(K) || !std::isfinite(r))
+    return fail(QTREE_EINVAL, "contract parameters must be finite, Tm > 0");
+  qtree::PayoffArgs a{};
+  a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
+  a.pts1 = reinterpret_cast<const float*>(plan->ws + plan->lay.points);
+  a.pts = reinterpret_cast<const float4*>(plan->ws + plan->lay.points);
+  a.phi = phi;
+  a.n = plan->n;
+  a.d = plan->d;
+  a.kind = kind;
+  a.S0 = S0;
+  a.K = K;
+  a.r = r;
+  a.Tm = Tm;
+  for (int c = 0; c < plan->d; ++c) {
+    if (!std::isfinite(sigma[c])) return fail(QTREE_EINVAL, "sigma must be finite");
+    a.sigma[c] = sigma[c];
+  }
+  a.maxN = plan->maxN;
+  hipError_t e = qtree::launch_payoff(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "payoff launch");
+  return QTREE_OK;
+}
+
+qtree_status qtree_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,
+                              float* z1, void* stream) {
+  if (count < 0) return fail(QTREE_EINVAL, "count must be >= 0");
+  if (count == 0) return QTREE_OK;
+  if (!ra || !rb || !z0 || !z1) return fail(QTREE_EINVAL, "NULL array");
+  hipError_t e = qtree::launch_box_muller(ra, rb, count, z0, z1, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "box_muller launch");
+}
+
+qtree_status qtree_layer_samples(const qtree_plan* plan, int32_t k, uint64_t m0, int64_t count,
+                                 uint64_t seed, uint32_t contract_id, float* x, float* y,
+                                 void* stream) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (k < 0 || k >= plan->n) return fail(QTREE_EINVAL, "layer index out of range");
+  if (count < 0) return fail(QTREE_EINVAL, "count must be >= 0");
+  if (m0 + (uint64_t)count > (1ull << 32)) return fail(QTREE_EOVERFLOW, "m0 + count > 2^32");
+  if (count == 0) return QTREE_OK;
+  if (!x || !y) return fail(QTREE_EINVAL, "NULL array");
+  qtree::FwdArgs a = fwd_args(plan, m0, (uint64_t)count, seed, contract_id, nullptr);
+  hipError_t e = qtree::launch_layer_samples(a, k, count, x, y, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "layer_samples launch");
+}
+
+qtree_status qtree_cells(const qtree_plan* plan, int32_t k, const float* x, int64_t count,
+                         int32_t* cell, void* stream) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (k < 0 || k > plan->n) return fail(QTREE_EINVAL, "layer index out of range");
+  if (count < 0) return fail(QTREE_EINVAL, "count must be >= 0");
+  if (count == 0) return QTREE_OK;
+  if (!x || !cell) return fail(QTREE_EINVAL, "NULL array");
+  qtree::FwdArgs a = fwd_args(plan, 0, 0, 0, 0, nullptr);
+  hipError_t e = qtree::launch_cells(a, k, x, count, cell, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "cells launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Backward dynamic programming on the quantization tree (Sec. 2), FP64:
+//   V_n = phi_n,  V_k(i) = max(phi_k(i), sum_j c_ij V_{k+1}(j) / p_i),
+// with pi^k_ij = c_ij / p_i estimated by the forward counts.  The
+// conditional expectation on the tree is the row reduction
+// sum_j pi_ij f(x_j) of Sec. 2.  One 64-lane wave reduces one row of the
+// count block for up to kPay obstacle vectors at once, so the int32 counts
+// are read from HBM once per group of payoffs.  Also the obstacle phi_k on
+// the grid points.
+#include "qtree_internal.hpp"
+
+namespace qtree {
+
+namespace {
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kPay = 8;
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void bdp_layer_kernel(BdpArgs a, int N_k, int N_k1,
+                                                           int64_t pt_k, int64_t pt_k1,
+                                                           int64_t cnt_k, int q0, int nq) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (i >= N_k) return;
+  const int32_t* row = a.counts + cnt_k + (int64_t)i * N_k1;
+  int64_t p = 0;
+  double s[kPay];
+#pragma unroll
+  for (int q = 0; q < kPay; ++q) s[q] = 0.0;
+  for (int j = lane; j < N_k1; j += 64) {
+    const int32_t c = row[j];
+    p += c;
+    if (c != 0) {
+      const double cd = (double)c;
+#pragma unroll
+      for (int q = 0; q < kPay; ++q)
+        if (q < nq) s[q] = fma(cd, a.V[(int64_t)(q0 + q) * a.P + pt_k1 + j], s[q]);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    p += __shfl_xor(p, off, 64);
+#pragma unroll
+    for (int q = 0; q < kPay; ++q) s[q] += __shfl_xor(s[q], off, 64);
+  }
+  if (lane < nq) {
+    // lane q finalises payoff q0 + q
+    double sq = s[0];
+#pragma unroll
+    for (int q = 1; q < kPay; ++q)
+      if (lane == q) sq = s[q];
+    const double cont = p > 0 ? sq / (double)p : 0.0;
+    const int64_t at = (int64_t)(q0 + lane) * a.P + pt_k + i;
+    const double f = a.phi[at];
+    a.V[at] = f > cont ? f : cont;
+  }
+}
+
+__global__ void copy_last_layer_kernel(BdpArgs a, int64_t pt_n, int N_n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)a.n_pay * N_n;
+  if (t >= total) return;
+  const int64_t q = t / N_n, i = t - q * N_n;
+  const int64_t at = q * a.P + pt_n + i;
+  a.V[at] = a.phi[at];
+}
+
+hipError_t launch_bdp_layer(const BdpArgs& a, int k, int N_k, int N_k1, int64_t pt_k,
+                            int64_t pt_k1, int64_t cnt_k, hipStream_t s) {
+  (void)k;
+  const unsigned blocks = (unsigned)((N_k + kWaves - 1) / kWaves);
+  for (int q0 = 0; q0 < a.n_pay; q0 += kPay) {
+    const int nq = (a.n_pay - q0) < kPay ? (a.n_pay - q0) : kPay;
+    hipLaunchKernelGGL(bdp_layer_kernel, dim3(blocks), dim3(kBlock), 0, s, a, N_k, N_k1, pt_k,
+                       pt_k1, cnt_k, q0, nq);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_last_layer(const BdpArgs& a, int64_t pt_n, int N_n, hipStream_t s) {
+  const int64_t total = (int64_t)a.n_pay * N_n;
+  const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(copy_last_layer_kernel, dim3(blocks), dim3(kBlock), 0, s, a, pt_n, N_n);
+  return hipGetLastError();
+}
+
+// Discounted obstacle phi_k(x) = exp(-r t_k) payoff(S_{t_k}(x)) on every grid
+// point, S^a_t(x) = S0 exp((r - sigma_a^2 / 2) t + sigma_a x_a), FP64.
+__global__ void payoff_kernel(PayoffArgs a) {
+  const int k = blockIdx.y;
+  const LayerDev& L = a.layers[k];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  const double t = a.Tm * (double)k / (double)a.n;
+  const double disc = exp(-a.r * t);
+  const int64_t at = (int64_t)L.pt_off + i;
+  double v;
+  if (a.kind & 1) {
+    const float4 g = a.d == 1 ? make_float4(a.pts1[at], 0.f, 0.f, 0.f) : a.pts[at];
+    const float xs[3] = {g.x, g.y, g.z};
+    double smax = -__builtin_huge_val();
+    for (int c = 0; c < a.d; ++c) {
+      const double sc = a.S0 * exp((a.r - 0.5 * a.sigma[c] * a.sigma[c]) * t +
+                                   a.sigma[c] * (double)xs[c]);
+      smax = sc > smax ? sc : smax;
+    }
+    v = disc * fmax(smax - a.K, 0.0);
+  } else {
+    const float x0 = a.d == 1 ? a.pts1[at] : a.pts[at].x;
+    const double sc =
+        a.S0 * exp((a.r - 0.5 * a.sigma[0] * a.sigma[0]) * t + a.sigma[0] * (double)x0);
+    v = disc * fmax(a.K - sc, 0.0);
+  }
+  if ((a.kind & 2) && k < a.n) v = -__builtin_huge_val();
+  a.phi[at] = v;
+}
+
+hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.maxN + kBlock - 1) / kBlock), (unsigned)(a.n + 1));
+  hipLaunchKernelGGL(payoff_kernel, grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace qtree

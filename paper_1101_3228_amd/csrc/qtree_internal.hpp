@@ -1,0 +1,91 @@
+// Internal layout shared by the host side of the library and its kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qtree {
+
+constexpr int kMaxDim = 3;
+
+// One record per layer k = 0..n, stored in the plan's device workspace.
+// Model coefficients are the FP32 inputs of the AR(1) proposition (Sec. 3);
+// A, b, T are unused on the last layer.
+struct alignas(16) LayerDev {
+  int64_t cnt_off;  // first entry of counts block k (k < n)
+  int32_t N;        // N_k
+  int32_t N1;       // N_{k+1} (0 on the last layer)
+  int32_t pt_off;   // first point of layer k in the point array
+  int32_t aux_off;  // 1-D: first padded midpoint of layer k
+  int32_t P;        // 1-D: padded midpoint slots, a power of two >= N_k
+  int32_t logP;     // log2(P)
+  float A[9], b[3], T[9], mu[3], L[9];
+  float x0[3];      // start point of the pathwise mode (layer 0 record)
+};
+
+// Workspace layout (byte offsets from the workspace base).
+struct WsLayout {
+  size_t layers;   // LayerDev[n+1]
+  size_t points;   // d == 1: float[sum N]; d >= 2: float4[sum N] = (g0, g1, g2, h)
+  size_t aux;      // d == 1: float[sum P] midpoints padded with +inf
+  size_t total;
+};
+
+WsLayout ws_layout(int d, int n, const int32_t* N);
+
+struct FwdArgs {
+  const LayerDev* layers;
+  const float* mids;     // 1-D midpoints (padded per layer)
+  const float4* pts;     // d >= 2 points with half norm
+  const float* pts1;     // 1-D points
+  int32_t* counts;
+  uint64_t m0, M;
+  uint32_t key0, key1, contract;
+  int32_t n, d;
+  // launch decomposition: unit u = (layer, chunk); `chunks` per layer
+  int32_t chunks;
+  int32_t units;          // n * chunks
+  int32_t units_per_xcd;  // ceil(units / 8)
+  int32_t xcd_map;        // 1: keep a layer's chunks on one XCD
+  uint64_t chunk_len;     // samples per chunk (even)
+  int32_t maxP;           // largest padded midpoint count (1-D LDS sizing)
+  int32_t maxN;           // largest layer size (d >= 2 LDS sizing)
+  int64_t mids_total;     // 1-D: padded midpoints over all layers
+};
+
+hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s);
+hipError_t launch_fwd_layer_1d(const FwdArgs& a, hipStream_t s);
+hipError_t launch_fwd_layer_nd(const FwdArgs& a, hipStream_t s);
+hipError_t launch_fwd_path(const FwdArgs& a, hipStream_t s);
+
+struct BdpArgs {
+  const LayerDev* layers;
+  const int32_t* counts;
+  const double* phi;
+  double* V;
+  int64_t P;  // points per payoff vector (sum N_k)
+  int32_t n_pay;
+};
+hipError_t launch_bdp_layer(const BdpArgs& a, int k, int N_k, int N_k1, int64_t pt_k,
+                            int64_t pt_k1, int64_t cnt_k, hipStream_t s);
+hipError_t launch_copy_last_layer(const BdpArgs& a, int64_t pt_n, int N_n, hipStream_t s);
+
+struct PayoffArgs {
+  const LayerDev* layers;
+  const float* pts1;
+  const float4* pts;
+  double* phi;
+  int32_t n, d, kind;
+  double S0, K, r, Tm;
+  double sigma[kMaxDim];
+  int32_t maxN;
+};
+hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s);
+
+hipError_t launch_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,
+                             float* z1, hipStream_t s);
+hipError_t launch_layer_samples(const FwdArgs& a, int k, int64_t count, float* x, float* y,
+                                hipStream_t s);
+hipError_t launch_cells(const FwdArgs& a, int k, const float* x, int64_t count, int32_t* cell,
+                        hipStream_t s);
+
+}  // namespace qtree

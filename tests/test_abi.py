@@ -1,0 +1,113 @@
+"""CPU checks of the C-ABI library: it loads, exports every function declared
+in include/qtree.h, rejects bad arguments on the host before any device
+work, and its host quantizer agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1101_3228_amd as qt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(qt.LIB_PATH):
+        from paper_1101_3228_amd import build
+        build.build()
+    return qt.lib()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "qtree.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qtree_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    for s in range(6):
+        assert L.qtree_status_string(s)
+    assert b"gfx950" in L.qtree_version()
+
+
+def test_workspace_size_validation(L):
+    N = np.array([1, 10, 10], np.int32)
+    assert qt.workspace_size(1, 2, N) > 0
+    assert qt.workspace_size(2, 2, N) > qt.workspace_size(1, 2, N) // 2
+    for d, n, NN, code in ((0, 2, N, 1), (4, 2, N, 1), (1, 0, N, 1),
+                           (1, 2, np.array([2, 10, 10], np.int32), 1),
+                           (1, 2, np.array([1, 0, 10], np.int32), 1),
+                           (1, 2, np.array([1, 20000, 10], np.int32), 5),
+                           (2, 2, np.array([1, 5000, 10], np.int32), 5)):
+        with pytest.raises(qt.QtreeError) as e:
+            qt.workspace_size(d, n, NN)
+        assert e.value.status == code
+
+
+def _cmodel(d, n, arrays):
+    return qt._Model(d, n, *(arrays[k].ctypes.data for k in ("A", "b", "T", "mu", "L", "x0")))
+
+
+def test_plan_create_rejects_bad_inputs_before_device_work(L):
+    import synth
+    spec = synth.bm_model(1, 2)
+    arrays = {k: np.ascontiguousarray(spec[k], np.float32) for k in ("A", "b", "T", "mu", "L",
+                                                                     "x0")}
+    grid, N = synth.layer_grids(spec, [1, 6, 7])
+    fake_ws = ctypes.c_void_p(4096)   # never dereferenced on the error paths
+    size = qt.workspace_size(1, 2, N)
+    h = ctypes.c_void_p()
+
+    def create(g, NN=N, ws=fake_ws, nbytes=size, model=None):
+        m = model if model is not None else _cmodel(1, 2, arrays)
+        return L.qtree_plan_create(ctypes.byref(m), g.ctypes.data, NN.ctypes.data, ws, nbytes,
+                                   ctypes.byref(h))
+
+    bad = grid.copy()
+    bad[3] = np.nan
+    assert create(bad) == 1
+    unsorted = grid.copy()
+    unsorted[2], unsorted[3] = grid[3], grid[2]
+    assert create(unsorted) == 1 and b"increasing" in L.qtree_last_error()
+    assert create(grid, nbytes=size - 1) == 2
+    assert create(grid, ws=ctypes.c_void_p(4100)) == 1          # misaligned
+    assert create(grid, ws=ctypes.c_void_p(0)) == 1
+    a2 = dict(arrays)
+    a2["T"] = arrays["T"].copy()
+    a2["T"][0] = np.inf
+    assert create(grid, model=_cmodel(1, 2, a2)) == 1
+    assert L.qtree_transitions(None, 0, 10, 1, 0, 0, ctypes.c_void_p(4096), None) == 1
+    assert L.qtree_bdp(None, None, None, 1, None, None, None) == 1
+
+
+def test_library_quantizer_matches_oracle_quantizer(L):
+    from oracle.quantizer import gauss_quantizer, lloyd_step
+    for N in (1, 2, 3, 10, 50, 100):
+        lib_x = qt.gauss_quantizer(N)
+        ref = gauss_quantizer(N)
+        # the oracle's Lloyd map stops at a step of 1e-13 and contracts by
+        # about 1 - c/N^2 per sweep, so it sits within ~N^2 1e-13 of the fixed point
+        assert np.max(np.abs(lib_x - ref)) < 1e-13 * max(N, 10) ** 2, N
+        assert np.max(np.abs(lloyd_step(lib_x) - lib_x)) < 1e-12
+    x = qt.gauss_quantizer(2)
+    assert abs(x[1] - np.sqrt(2 / np.pi)) < 1e-14
+
+
+def test_library_quantizer_large_n_is_stationary(L):
+    from oracle.quantizer import distortion, lloyd_step
+    for N in (500, 2000):
+        x = qt.gauss_quantizer(N)
+        assert np.all(np.diff(x) > 0)
+        assert np.max(np.abs(lloyd_step(x) - x)) < 1e-11
+        # Bucklew-Wise: N^2 D_N -> sqrt(3) pi / 2 from below
+        assert 0.99 * np.sqrt(3) * np.pi / 2 < N * N * distortion(x) < np.sqrt(3) * np.pi / 2
