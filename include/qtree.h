@@ -103,8 +103,13 @@ int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
  *   QTREE_TUNE_CHUNK   : samples per workgroup in LAYERWISE mode (0 = automatic;
  *                        otherwise rounded up to an even number >= 2).
  *   QTREE_TUNE_XCD_MAP : 1 (default) deals the chunks of one layer to one XCD,
- *                        0 uses the plain block order. */
-typedef enum { QTREE_TUNE_CHUNK = 0, QTREE_TUNE_XCD_MAP = 1 } qtree_tune_key;
+ *                        0 uses the plain block order.
+ *   QTREE_TUNE_COUNT   : LAYERWISE counting: 0 automatic (two-pass when every
+ *                        count block has at most 256 tiles of 32768 entries),
+ *                        1 one pass with a device-scope atomic per sample,
+ *                        2 two-pass (per-chunk keys grouped by tile, then one
+ *                        LDS histogram per tile; uses the workspace scratch). */
+typedef enum { QTREE_TUNE_CHUNK = 0, QTREE_TUNE_XCD_MAP = 1, QTREE_TUNE_COUNT = 2 } qtree_tune_key;
 qtree_status qtree_plan_tune(qtree_plan *plan, int32_t key, int64_t value);
 
 /* Monte Carlo transition counts p^k_ij (Sec. 3 Algorithm I/II, Sec. 4

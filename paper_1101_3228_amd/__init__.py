@@ -151,12 +151,15 @@ class Plan:
     def handle(self):
         return self._h
 
-    def tune(self, chunk: int | None = None, xcd_map: int | None = None):
-        """Launch tuning (QTREE_TUNE_CHUNK / QTREE_TUNE_XCD_MAP); results unchanged."""
+    def tune(self, chunk: int | None = None, xcd_map: int | None = None,
+             count: int | None = None):
+        """Launch tuning (QTREE_TUNE_CHUNK / _XCD_MAP / _COUNT); results unchanged."""
         if chunk is not None:
             _check(lib().qtree_plan_tune(self._h, 0, int(chunk)))
         if xcd_map is not None:
             _check(lib().qtree_plan_tune(self._h, 1, int(xcd_map)))
+        if count is not None:
+            _check(lib().qtree_plan_tune(self._h, 2, int(count)))
         return self
 
     def count_offsets(self) -> np.ndarray:

@@ -57,9 +57,21 @@ struct qtree_plan {
   qtree::WsLayout lay{};
   int64_t tune_chunk = 0;  // 0: automatic
   int32_t tune_xcd_map = 1;
+  int32_t tune_count = 0;  // 0 automatic, 1 direct atomics, 2 two-pass
+  int32_t max_tiles = 0, total_tiles = 0;
+  bool two_pass_ok = false;
 };
 
 namespace qtree {
+
+int max_tiles_of(int n, const int32_t* N) {
+  int64_t mt = 0;
+  for (int k = 0; k < n; ++k) {
+    const int64_t t = ((int64_t)N[k] * N[k + 1] + kTile - 1) / kTile;
+    if (t > mt) mt = t;
+  }
+  return (int)(mt > (1 << 30) ? (1 << 30) : mt);
+}
 
 WsLayout ws_layout(int d, int n, const int32_t* N) {
   WsLayout l{};
@@ -75,6 +87,17 @@ WsLayout ws_layout(int d, int n, const int32_t* N) {
   off = align_up(off + (size_t)pts * (d == 1 ? sizeof(float) : sizeof(float4)), 256);
   l.aux = off;
   if (d == 1) off = align_up(off + (size_t)mids * sizeof(float), 256);
+  // scratch of the two-pass counting (only when every count block has at
+  // most kMaxTiles tiles)
+  const int mt = max_tiles_of(n, N);
+  l.keys = off;
+  if (mt <= kMaxTiles) {
+    off = align_up(off + sizeof(uint16_t) * (size_t)n * kBatchChunks * kChunk, 256);
+    l.segs = off;
+    off = align_up(off + sizeof(uint32_t) * (size_t)n * kBatchChunks * (size_t)(mt + 1), 256);
+  } else {
+    l.segs = off;
+  }
   l.total = off;
   return l;
 }
@@ -181,6 +204,8 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     }
   }
   p.lay = qtree::ws_layout(d, n, N);
+  p.max_tiles = qtree::max_tiles_of(n, N);
+  p.two_pass_ok = p.max_tiles <= qtree::kMaxTiles;
   if (workspace_bytes < p.lay.total)
     return fail(QTREE_ENOMEM, "workspace needs " + std::to_string(p.lay.total) + " bytes");
 
@@ -196,6 +221,9 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     L.aux_off = (int32_t)p.aux_off[k];
     L.P = p.P[k];
     L.logP = log2i(p.P[k]);
+    L.tiles = k < n ? (int32_t)(((int64_t)N[k] * N[k + 1] + qtree::kTile - 1) / qtree::kTile) : 0;
+    L.tile_off = p.total_tiles;
+    p.total_tiles += L.tiles;
     if (k < n) {
       std::memcpy(L.A, model->A + dd * k, sizeof(float) * dd);
       std::memcpy(L.b, model->b + (size_t)d * k, sizeof(float) * d);
@@ -259,7 +287,45 @@ static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uin
   a.maxP = p->maxP;
   a.maxN = p->maxN;
   a.mids_total = p->mids_total;
+  a.keys = reinterpret_cast<uint16_t*>(p->ws + p->lay.keys);
+  a.segs = reinterpret_cast<uint32_t*>(p->ws + p->lay.segs);
+  a.max_tiles = p->max_tiles;
+  a.seg_stride = p->max_tiles + 1;
+  a.total_tiles = p->total_tiles;
   return a;
+}
+
+// Two-pass LAYERWISE counting over [m0, m0 + M) in batches that fit the
+// scratch: pass A writes the keys of a batch, pass B folds them into counts.
+static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hipStream_t s) {
+  const uint64_t end = a.m0 + a.M;
+  const uint64_t bs = p->d == 1 ? (uint64_t)qtree::kBatchChunks * qtree::kChunk - 2
+                                : (uint64_t)qtree::kBatchChunks * qtree::kChunk;
+  bool first = zero;
+  for (uint64_t lo = a.m0; lo < end; lo += bs) {
+    const uint64_t mb = (end - lo) < bs ? (end - lo) : bs;
+    qtree::FwdArgs b = a;
+    b.m0 = lo;
+    b.M = mb;
+    uint64_t chunks;
+    if (p->d == 1) {
+      const uint64_t blocks = ((lo + mb - 1) >> 1) - (lo >> 1) + 1;
+      chunks = (blocks + qtree::kChunk / 2 - 1) / (qtree::kChunk / 2);
+    } else {
+      chunks = (mb + qtree::kChunk - 1) / qtree::kChunk;
+    }
+    b.chunks = (int32_t)chunks;
+    b.units = p->n * b.chunks;
+    b.units_per_xcd = (b.units + 7) / 8;
+    b.xcd_map = p->tune_xcd_map;
+    b.first_batch = first ? 1 : 0;
+    hipError_t e = qtree::launch_fwd_keys(b, s);
+    if (e != hipSuccess) return e;
+    e = qtree::launch_count_tiles(b, s);
+    if (e != hipSuccess) return e;
+    first = false;
+  }
+  return hipSuccess;
 }
 
 // Split each layer's M samples into chunks; one workgroup per (layer, chunk).
@@ -297,6 +363,13 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
     plan->tune_chunk = value;
     return QTREE_OK;
   }
+  if (key == QTREE_TUNE_COUNT) {
+    if (value < 0 || value > 2) return fail(QTREE_EINVAL, "count mode must be 0, 1 or 2");
+    if (value == 2 && !plan->two_pass_ok)
+      return fail(QTREE_EUNSUPPORTED, "count blocks too large for two-pass counting");
+    plan->tune_count = (int32_t)value;
+    return QTREE_OK;
+  }
   if (key == QTREE_TUNE_XCD_MAP) {
     if (value != 0 && value != 1) return fail(QTREE_EINVAL, "xcd map must be 0 or 1");
     plan->tune_xcd_map = (int32_t)value;
@@ -318,7 +391,9 @@ static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64
   if (m0 + M > (1ull << 32)) return fail(QTREE_EOVERFLOW, "m0 + M must be <= 2^32");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
-  if (zero) {
+  const bool two = mode == QTREE_LAYERWISE && M > 0 &&
+                   (plan->tune_count == 2 || (plan->tune_count == 0 && plan->two_pass_ok));
+  if (zero && !two) {
     e = qtree::launch_zero_i32(counts, plan->entries, s);
     if (e != hipSuccess) return hip_fail(e, "zero fill");
   }
@@ -326,6 +401,8 @@ static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64
   qtree::FwdArgs a = fwd_args(plan, m0, M, seed, contract_id, counts);
   if (mode == QTREE_PATHWISE) {
     e = qtree::launch_fwd_path(a, s);
+  } else if (two) {
+    e = two_pass(plan, a, zero, s);
   } else {
     plan_units(a, plan);
     e = plan->d == 1 ? qtree::launch_fwd_layer_1d(a, s) : qtree::launch_fwd_layer_nd(a, s);

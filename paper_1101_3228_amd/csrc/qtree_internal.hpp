@@ -7,6 +7,16 @@ namespace qtree {
 
 constexpr int kMaxDim = 3;
 
+// Two-pass LAYERWISE counting.  Pass A turns each chunk of kChunk samples of
+// a layer into 16-bit keys grouped by tile (kTile consecutive entries of the
+// layer's count block); pass B gives every (layer, tile) to one workgroup
+// that histograms its keys in LDS and writes the tile with plain stores.
+constexpr int kTileBits = 15;
+constexpr int kTile = 1 << kTileBits;
+constexpr int kChunk = 8192;          // samples per pass-A workgroup
+constexpr int kMaxTiles = 256;        // larger count blocks use direct atomics
+constexpr int kBatchChunks = 512;     // chunks per layer held in the scratch
+
 // One record per layer k = 0..n, stored in the plan's device workspace.
 // Model coefficients are the FP32 inputs of the AR(1) proposition (Sec. 3);
 // A, b, T are unused on the last layer.
@@ -18,6 +28,8 @@ struct alignas(16) LayerDev {
   int32_t aux_off;  // 1-D: first padded midpoint of layer k
   int32_t P;        // 1-D: padded midpoint slots, a power of two >= N_k
   int32_t logP;     // log2(P)
+  int32_t tiles;    // ceil(N_k N_{k+1} / kTile) (0 on the last layer)
+  int32_t tile_off; // tiles of the layers before k
   float A[9], b[3], T[9], mu[3], L[9];
   float x0[3];      // start point of the pathwise mode (layer 0 record)
 };
@@ -27,6 +39,8 @@ struct WsLayout {
   size_t layers;   // LayerDev[n+1]
   size_t points;   // d == 1: float[sum N]; d >= 2: float4[sum N] = (g0, g1, g2, h)
   size_t aux;      // d == 1: float[sum P] midpoints padded with +inf
+  size_t keys;     // uint16[n][kBatchChunks][kChunk] pass-A keys
+  size_t segs;     // uint32[n][kBatchChunks][max tiles + 1] segment starts
   size_t total;
 };
 
@@ -50,12 +64,21 @@ struct FwdArgs {
   int32_t maxP;           // largest padded midpoint count (1-D LDS sizing)
   int32_t maxN;           // largest layer size (d >= 2 LDS sizing)
   int64_t mids_total;     // 1-D: padded midpoints over all layers
+  // two-pass counting
+  uint16_t* keys;
+  uint32_t* segs;
+  int32_t seg_stride;     // max tiles + 1
+  int32_t max_tiles;
+  int32_t total_tiles;    // sum of tiles over layers (pass-B grid)
+  int32_t first_batch;    // pass B overwrites instead of adding
 };
 
 hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s);
 hipError_t launch_fwd_layer_1d(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd_layer_nd(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd_path(const FwdArgs& a, hipStream_t s);
+hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s);
+hipError_t launch_count_tiles(const FwdArgs& a, hipStream_t s);
 
 struct BdpArgs {
   const LayerDev* layers;

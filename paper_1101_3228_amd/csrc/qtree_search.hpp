@@ -52,11 +52,12 @@ __device__ __forceinline__ void argmin_scan(const float4* __restrict__ g, int N,
   }
   for (int p = 0; p < N; ++p) {
     const float4 q = g[p];
+    const float gc[3] = {q.x, q.y, q.z};
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      float key = fmaf(-xs[s][0], q.x, q.w);
-      key = fmaf(-xs[s][1], q.y, key);
-      if (D == 3) key = fmaf(-xs[s][2], q.z, key);
+      float key = q.w;
+#pragma unroll
+      for (int c = 0; c < D; ++c) key = fmaf(-xs[s][c], gc[c], key);
       const bool lt = key < best[s];
       best[s] = lt ? key : best[s];
       idx[s] = lt ? p : idx[s];

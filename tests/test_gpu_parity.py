@@ -134,11 +134,12 @@ def test_counts_small_bitwise_and_schedule_free(small_case, mode):
     M, m0, seed = 200_001, 7_777, 0x5EED0011
     ref = O.transitions(mdl, grid, N, M, seed=seed, contract=5, mode=mode, m0=m0,
                         nthreads=THREADS)
-    for chunk, xmap in ((0, 1), (2, 0), (4_098, 1), (65_536, 0), (333_333, 1)):
-        plan.tune(chunk=chunk, xcd_map=xmap)
+    for chunk, xmap, count in ((0, 1, 0), (0, 0, 2), (2, 0, 1), (4_098, 1, 1), (65_536, 0, 1),
+                               (333_333, 1, 1)):
+        plan.tune(chunk=chunk, xcd_map=xmap, count=count)
         got = plan.transitions(M, seed, contract=5, mode=mode, m0=m0).cpu().numpy()
-        assert np.array_equal(got, ref), (chunk, xmap)
-    plan.tune(chunk=0, xcd_map=1)
+        assert np.array_equal(got, ref), (chunk, xmap, count)
+    plan.tune(chunk=0, xcd_map=1, count=0)
 
 
 def test_counts_edge_sizes():
@@ -299,10 +300,28 @@ def test_c3_2d_full_size_sampled():
 
 def test_chunked_accumulation_equals_one_call(small_case):
     """Counts over [0, M) == counts over [0, M1) plus [M1, M) added on top
-    (resume by sample chunk)."""
+    (resume by sample chunk), in both counting schemes."""
     name, spec, grid, N, plan = small_case
-    for mode in (0, 1):
-        whole = plan.transitions(90_001, 31, mode=mode).cpu().numpy()
-        c = plan.transitions(33_333, 31, mode=mode)
-        plan.transitions_add(c, 90_001 - 33_333, 31, mode=mode, m0=33_333)
-        assert np.array_equal(c.cpu().numpy(), whole), (name, mode)
+    for count in (1, 2):
+        plan.tune(count=count)
+        for mode in (0, 1):
+            whole = plan.transitions(90_001, 31, mode=mode).cpu().numpy()
+            c = plan.transitions(33_333, 31, mode=mode)
+            plan.transitions_add(c, 90_001 - 33_333, 31, mode=mode, m0=33_333)
+            assert np.array_equal(c.cpu().numpy(), whole), (name, mode, count)
+    plan.tune(count=0)
+
+
+def test_two_pass_several_batches():
+    """More samples than one scratch batch holds (2^22 per layer): the count
+    tiles accumulate over batches; odd m0 splits a Philox pair at every batch
+    boundary."""
+    _print_case("two-pass batches")
+    spec = synth.bm_model(1, 2)
+    grid, N = synth.layer_grids(spec, [1, 300, 700])
+    plan = _plan(spec, grid, N)
+    mdl = _omodel(spec)
+    M, m0 = 9_000_001, 3
+    got = plan.transitions(M, 77, m0=m0).cpu().numpy()
+    ref = O.transitions(mdl, grid, N, M, seed=77, m0=m0, nthreads=THREADS)
+    assert np.array_equal(got, ref)
