@@ -105,7 +105,8 @@ int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
  *   QTREE_TUNE_XCD_MAP : 1 (default) deals the chunks of one layer to one XCD,
  *                        0 uses the plain block order.
  *   QTREE_TUNE_COUNT   : LAYERWISE counting: 0 automatic (two-pass when every
- *                        count block has at most 256 tiles of 32768 entries),
+ *                        count block has at most 4096 tiles of 4096 entries and
+ *                        the per-chunk sort fits in LDS),
  *                        1 one pass with a device-scope atomic per sample,
  *                        2 two-pass (per-chunk keys grouped by tile, then one
  *                        LDS histogram per tile; uses the workspace scratch). */

@@ -73,6 +73,23 @@ int max_tiles_of(int n, const int32_t* N) {
   return (int)(mt > (1 << 30) ? (1 << 30) : mt);
 }
 
+// LDS bytes of the pass-A kernel (grids or midpoints, staged keys, tile
+// counters, cursors and scan partials); two-pass counting needs it to fit.
+size_t keys_lds_bytes(int d, int n, const int32_t* N) {
+  int maxN = 0, maxP = 0;
+  for (int k = 0; k <= n; ++k) {
+    maxN = N[k] > maxN ? N[k] : maxN;
+    maxP = next_pow2(N[k]) > maxP ? next_pow2(N[k]) : maxP;
+  }
+  const size_t grids = d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)maxN;
+  return grids + sizeof(uint16_t) * kChunk +
+         sizeof(uint32_t) * (2 * (size_t)max_tiles_of(n, N) + 1 + 256);
+}
+
+bool two_pass_fits(int d, int n, const int32_t* N) {
+  return max_tiles_of(n, N) <= kMaxTiles && keys_lds_bytes(d, n, N) <= 160 * 1024;
+}
+
 WsLayout ws_layout(int d, int n, const int32_t* N) {
   WsLayout l{};
   size_t off = 0;
@@ -91,7 +108,7 @@ WsLayout ws_layout(int d, int n, const int32_t* N) {
   // most kMaxTiles tiles)
   const int mt = max_tiles_of(n, N);
   l.keys = off;
-  if (mt <= kMaxTiles) {
+  if (two_pass_fits(d, n, N)) {
     off = align_up(off + sizeof(uint16_t) * (size_t)n * kBatchChunks * kChunk, 256);
     l.segs = off;
     off = align_up(off + sizeof(uint32_t) * (size_t)n * kBatchChunks * (size_t)(mt + 1), 256);
@@ -205,7 +222,7 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
   }
   p.lay = qtree::ws_layout(d, n, N);
   p.max_tiles = qtree::max_tiles_of(n, N);
-  p.two_pass_ok = p.max_tiles <= qtree::kMaxTiles;
+  p.two_pass_ok = qtree::two_pass_fits(d, n, N);
   if (workspace_bytes < p.lay.total)
     return fail(QTREE_ENOMEM, "workspace needs " + std::to_string(p.lay.total) + " bytes");
 
@@ -221,9 +238,10 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     L.aux_off = (int32_t)p.aux_off[k];
     L.P = p.P[k];
     L.logP = log2i(p.P[k]);
-    L.tiles = k < n ? (int32_t)(((int64_t)N[k] * N[k + 1] + qtree::kTile - 1) / qtree::kTile) : 0;
+    const int64_t entries_k = k < n ? (int64_t)N[k] * N[k + 1] : 0;
+    L.tiles = (int32_t)((entries_k + qtree::kTile - 1) / qtree::kTile);
     L.tile_off = p.total_tiles;
-    p.total_tiles += L.tiles;
+    p.total_tiles += (int32_t)((entries_k + qtree::kSuper - 1) / qtree::kSuper);
     if (k < n) {
       std::memcpy(L.A, model->A + dd * k, sizeof(float) * dd);
       std::memcpy(L.b, model->b + (size_t)d * k, sizeof(float) * d);

@@ -11,11 +11,14 @@
 //    layer (Philox -> Box-Muller -> AR(1) -> two cell searches, as in the
 //    one-pass kernels), forms the flat index key = i N_{k+1} + j, and sorts
 //    the keys by tile t = key >> kTileBits with a counting sort in LDS (count
-//    per tile, scan, place).  The chunk writes its 16-bit in-tile offsets,
-//    tile by tile, with 16-byte stores, plus the segment starts.
-//  pass B (count_tiles): one workgroup per (layer, tile) walks that tile's
-//    segment in every chunk of the layer, increments a 32768-bin LDS
-//    histogram, and stores the tile into the count block.  Each count is
+//    per tile, scan, place; 4096-entry tiles keep the LDS counters of a wave
+//    apart).  The chunk writes each key as its 16-bit offset inside its
+//    32768-entry super tile, tile by tile, with 16-byte stores, plus the
+//    segment starts.
+//  pass B (count_tiles): one workgroup per (layer, super tile) walks that
+//    super tile's segment (eight consecutive tiles) in every chunk of the
+//    layer, increments a 32768-bin LDS histogram, and stores the super tile
+//    into the count block.  Each count is
 //    owned by exactly one workgroup, so the store is plain (it also replaces
 //    zeroing).  Integer counting makes the order of keys irrelevant.
 #include "qtree_internal.hpp"
@@ -57,17 +60,32 @@ __device__ __forceinline__ void count_keys(const uint32_t* key, uint32_t* tcount
     if (key[e] != 0xFFFFFFFFu) atomicAdd(&tcount[key[e] >> kTileBits], 1u);
 }
 
-__device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, int T) {
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int t = 0; t < T; ++t) {
-      const uint32_t v = tcount[t];
-      tcount[t] = run;
-      cursor[t] = run;
-      run += v;
-    }
-    tcount[T] = run;
+// Exclusive scan of tcount[0..T) in place (tcount[T] = total), copied to
+// cursor.  Each lane sums a run of consecutive counters, the lane partials
+// are scanned in LDS (Hillis-Steele), then the runs are rewritten.  `part`
+// holds kBlock entries.  Called by the whole block between barriers.
+__device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, int T,
+                                           uint32_t* part) {
+  const int per = (T + kBlock - 1) / kBlock;
+  const int t0 = (int)threadIdx.x * per;
+  uint32_t sum = 0;
+  for (int t = t0; t < t0 + per && t < T; ++t) sum += tcount[t];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
   }
+  uint32_t run = part[threadIdx.x] - sum;  // exclusive prefix of this lane's run
+  for (int t = t0; t < t0 + per && t < T; ++t) {
+    const uint32_t v = tcount[t];
+    tcount[t] = run;
+    cursor[t] = run;
+    run += v;
+  }
+  if (threadIdx.x == kBlock - 1) tcount[T] = part[kBlock - 1];
 }
 
 __device__ __forceinline__ void place_keys(const uint32_t* key, uint32_t* cursor,
@@ -76,7 +94,7 @@ __device__ __forceinline__ void place_keys(const uint32_t* key, uint32_t* cursor
   for (int e = 0; e < kKeys; ++e) {
     if (key[e] != 0xFFFFFFFFu) {
       const uint32_t pos = atomicAdd(&cursor[key[e] >> kTileBits], 1u);
-      stage[pos] = (uint16_t)(key[e] & (kTile - 1));
+      stage[pos] = (uint16_t)(key[e] & (kSuper - 1));
     }
   }
 }
@@ -110,6 +128,7 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds + ((L0.P + L1.P + 3) & ~3));
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
+  uint32_t* part = cursor + T;
   for (int i = threadIdx.x; i < L0.P; i += kBlock) mk[i] = a.mids[L0.aux_off + i];
   for (int i = threadIdx.x; i < L1.P; i += kBlock) mk1[i] = a.mids[L1.aux_off + i];
   for (int t = threadIdx.x; t <= T; t += kBlock) tcount[t] = 0;
@@ -139,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   }
   count_keys(key, tcount);
   __syncthreads();
-  scan_tiles(tcount, cursor, T);
+  scan_tiles(tcount, cursor, T, part);
   __syncthreads();
   place_keys(key, cursor, stage);
   __syncthreads();
@@ -160,6 +179,7 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + N0 + N1);
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
+  uint32_t* part = cursor + T;
   for (int i = threadIdx.x; i < N0; i += kBlock) gk[i] = a.pts[L0.pt_off + i];
   for (int i = threadIdx.x; i < N1; i += kBlock) gk1[i] = a.pts[L1.pt_off + i];
   for (int t = threadIdx.x; t <= T; t += kBlock) tcount[t] = 0;
@@ -191,16 +211,23 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
   }
   count_keys(key, tcount);
   __syncthreads();
-  scan_tiles(tcount, cursor, T);
+  scan_tiles(tcount, cursor, T, part);
   __syncthreads();
   place_keys(key, cursor, stage);
   __syncthreads();
   write_chunk(a, k, c, T, tcount, stage);
 }
 
-// Pass B: workgroup b owns tile t of layer k (b = tile_off_k + t).
+// Pass B: workgroup b owns super tile t of layer k (b = tile_off_k + t),
+// i.e. tiles [t kTilesPerSuper, (t+1) kTilesPerSuper) whose keys are one
+// contiguous segment of every chunk.  Segment bounds of kCountBlock chunks at
+// a time are fetched with one load per lane into LDS; each wave then walks
+// whole segments, 8 keys per lane per 16-byte load, adding into the
+// kSuper-bin LDS histogram.
 __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
   extern __shared__ uint32_t hist[];
+  uint32_t* sb = hist + kSuper;
+  uint32_t* se = sb + kCountBlock;
   const int b = (int)blockIdx.x;
   int lo = 0, hi = a.n - 1;  // largest k with tile_off_k <= b
   while (lo < hi) {
@@ -210,27 +237,43 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
   const int k = lo;
   const LayerDev& L0 = a.layers[k];
   const int t = b - L0.tile_off;
-  for (int i = threadIdx.x; i < kTile; i += kCountBlock) hist[i] = 0;
-  __syncthreads();
+  const int f0 = t * kTilesPerSuper;
+  const int f1 = (f0 + kTilesPerSuper) < L0.tiles ? (f0 + kTilesPerSuper) : L0.tiles;
+  for (int i = threadIdx.x; i < kSuper; i += kCountBlock) hist[i] = 0;
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  for (int c = wave; c < a.chunks; c += kCountBlock / 64) {
-    const uint32_t* seg = a.segs + ((size_t)k * a.chunks + c) * a.seg_stride;
-    const uint32_t s0 = seg[t], s1 = seg[t + 1];
-    const uint16_t* keys = a.keys + ((size_t)k * a.chunks + c) * kChunk;
-    uint32_t i = s0 + lane;
-    for (; i + 7 * 64 < s1; i += 8 * 64) {
-      uint16_t v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = keys[i + u * 64];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) atomicAdd(&hist[v[u]], 1u);
+  const uint32_t* segk = a.segs + (size_t)k * a.chunks * a.seg_stride;
+  const uint16_t* keysk = a.keys + (size_t)k * a.chunks * kChunk;
+  for (int c0 = 0; c0 < a.chunks; c0 += kCountBlock) {
+    __syncthreads();
+    const int c = c0 + (int)threadIdx.x;
+    if (c < a.chunks) {
+      sb[threadIdx.x] = segk[(size_t)c * a.seg_stride + f0];
+      se[threadIdx.x] = segk[(size_t)c * a.seg_stride + f1];
     }
-    for (; i < s1; i += 64) atomicAdd(&hist[keys[i]], 1u);
+    __syncthreads();
+    const int cn = (a.chunks - c0) < kCountBlock ? (a.chunks - c0) : kCountBlock;
+    for (int cc = wave; cc < cn; cc += kCountBlock / 64) {
+      // 16-byte loads of 8 keys each (the chunk's key block is 16-byte
+      // aligned); keys outside [s0, s1) are skipped
+      const uint32_t s0 = sb[cc], s1 = se[cc];
+      const uint4* kv = reinterpret_cast<const uint4*>(keysk + (size_t)(c0 + cc) * kChunk);
+      for (uint32_t v = (s0 >> 3) + lane; v * 8 < s1; v += 64) {
+        const uint4 w = kv[v];
+        const uint32_t q0 = v * 8;
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t q = q0 + u;
+          const uint32_t key = (words[u >> 1] >> ((u & 1) * 16)) & 0xFFFFu;
+          if (q >= s0 && q < s1) atomicAdd(&hist[key], 1u);
+        }
+      }
+    }
   }
   __syncthreads();
   const int64_t total = (int64_t)L0.N * L0.N1;
-  const int64_t base = (int64_t)t * kTile;
-  const int bins = (int)((total - base) < kTile ? (total - base) : kTile);
+  const int64_t base = (int64_t)t * kSuper;
+  const int bins = (int)((total - base) < kSuper ? (total - base) : kSuper);
   int32_t* dst = a.counts + L0.cnt_off + base;
   if (a.first_batch) {
     for (int i = threadIdx.x; i < bins; i += kCountBlock) dst[i] = (int32_t)hist[i];
@@ -251,9 +294,9 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
 }
 
 hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
-  // staged keys + tile counters + cursors
+  // staged keys + tile counters + cursors + scan partials
   const size_t tiles_bytes =
-      sizeof(uint16_t) * kChunk + sizeof(uint32_t) * (size_t)(2 * a.max_tiles + 1);
+      sizeof(uint16_t) * kChunk + sizeof(uint32_t) * (size_t)(2 * a.max_tiles + 1 + kBlock);
   hipError_t e;
   if (a.d == 1) {
     const size_t lds = sizeof(float) * (2 * (size_t)a.maxP + 4) + tiles_bytes;
@@ -272,7 +315,7 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_count_tiles(const FwdArgs& a, hipStream_t s) {
-  const size_t lds = sizeof(uint32_t) * kTile;
+  const size_t lds = sizeof(uint32_t) * (kSuper + 2 * kCountBlock);
   hipError_t e = allow_lds(count_tiles, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(count_tiles, dim3((unsigned)a.total_tiles), dim3(kCountBlock), lds, s, a);

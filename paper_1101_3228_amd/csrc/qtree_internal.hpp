@@ -7,15 +7,20 @@ namespace qtree {
 
 constexpr int kMaxDim = 3;
 
-// Two-pass LAYERWISE counting.  Pass A turns each chunk of kChunk samples of
-// a layer into 16-bit keys grouped by tile (kTile consecutive entries of the
-// layer's count block); pass B gives every (layer, tile) to one workgroup
-// that histograms its keys in LDS and writes the tile with plain stores.
-constexpr int kTileBits = 15;
+// Two-pass LAYERWISE counting.  Pass A sorts each chunk of kChunk samples of
+// a layer by tile (kTile consecutive entries of the layer's count block) and
+// stores every key as its 16-bit offset inside its super tile (kSuper
+// consecutive entries, kSuper / kTile tiles); pass B gives every (layer,
+// super tile) to one workgroup that histograms its keys in LDS and writes the
+// super tile with plain stores.
+constexpr int kTileBits = 12;
 constexpr int kTile = 1 << kTileBits;
-constexpr int kChunk = 8192;          // samples per pass-A workgroup
-constexpr int kMaxTiles = 256;        // larger count blocks use direct atomics
-constexpr int kBatchChunks = 512;     // chunks per layer held in the scratch
+constexpr int kSuperBits = 15;
+constexpr int kSuper = 1 << kSuperBits;
+constexpr int kTilesPerSuper = kSuper / kTile;
+constexpr int kChunk = 4096;          // samples per pass-A workgroup
+constexpr int kMaxTiles = 4096;       // larger count blocks use direct atomics
+constexpr int kBatchChunks = 1024;    // chunks per layer held in the scratch
 
 // One record per layer k = 0..n, stored in the plan's device workspace.
 // Model coefficients are the FP32 inputs of the AR(1) proposition (Sec. 3);
@@ -29,7 +34,7 @@ struct alignas(16) LayerDev {
   int32_t P;        // 1-D: padded midpoint slots, a power of two >= N_k
   int32_t logP;     // log2(P)
   int32_t tiles;    // ceil(N_k N_{k+1} / kTile) (0 on the last layer)
-  int32_t tile_off; // tiles of the layers before k
+  int32_t tile_off; // super tiles of the layers before k
   float A[9], b[3], T[9], mu[3], L[9];
   float x0[3];      // start point of the pathwise mode (layer 0 record)
 };
@@ -69,7 +74,7 @@ struct FwdArgs {
   uint32_t* segs;
   int32_t seg_stride;     // max tiles + 1
   int32_t max_tiles;
-  int32_t total_tiles;    // sum of tiles over layers (pass-B grid)
+  int32_t total_tiles;    // sum of super tiles over layers (pass-B grid)
   int32_t first_batch;    // pass B overwrites instead of adding
 };
 
