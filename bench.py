@@ -4,16 +4,20 @@ forward step on one MI355X, with the FP64 backward step of a contract sweep.
 Workload (one step): 1-D Brownian state (standardized log-price of the
 Black-Scholes put), n = 50 layers of N = 500 Lloyd-optimal points, M = 1e7
 pairs (X_k, X_{k+1}) per layer sampled time-layer parallel (Algorithm III),
-counts zeroed and rebuilt, then the obstacle and the quantized BDP for 12
+counts rebuilt from scratch, then the obstacles and the quantized BDP for 12
 American puts sharing the counts (sigma in {0.1, 0.2, 0.3, 0.4} x K/S0 in
-{0.8, 1.0, 1.2}).  Inputs (grids, model, payoff parameters) are resident on
-the GPU before timing starts.  The value is pairs per second of whole steps.
+{0.8, 1.0, 1.2}).  Inputs (grids, model, contract parameters) are resident on
+the GPU before timing starts.  Steps are pipelined: the obstacles and BDP of
+step s run on a second stream while step s+1 samples (counts are double
+buffered), as a stream of pricing requests would.  The value is pairs per
+second over whole steps, every step's BDP included.
 
-Prints one JSON line.  Roofline of the dominant kernel (the forward kernel):
-algorithmic VALU lane-slots per pair (the fixed arithmetic of one pair, see
-ALG_SLOTS_PER_PAIR) times pairs per launch, divided by the launch duration
-measured with HIP events on the launch stream, against the MI355X peak of
-256 CUs x 64 lanes x 2.4 GHz lane-slots per second.
+Prints one JSON line.  Roofline of the dominant kernel (the sampling pass,
+fwd_keys_1d): algorithmic VALU lane-slots per pair (the fixed arithmetic of
+one pair, see ALG_SLOTS_PER_PAIR) times pairs per launch, divided by the
+launch duration measured with HIP events on the launch stream (the library
+records a trace event between its sampling and histogram passes), against
+the MI355X peak of 256 CUs x 64 lanes x 2.4 GHz lane-slots per second.
 """
 from __future__ import annotations
 
@@ -45,8 +49,8 @@ S0, RATE, MATURITY = 100.0, 0.05, 1.0
 #   AR(1) sample: 3 fma                                                  =  3
 #   two binary searches over 512 padded midpoints: 2 x 9 steps x
 #     (address, compare, select)                                         = 54
-#   count address (mad + 64-bit add)                                     =  3
-ALG_SLOTS_PER_PAIR = 50 + 71 + 3 + 54 + 3
+#   flat count index i N_{k+1} + j                                       =  1
+ALG_SLOTS_PER_PAIR = 50 + 71 + 3 + 54 + 1
 PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
 
 
@@ -96,43 +100,67 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     spec, grid, N = _inputs()
-    plan = qt.Plan(spec, grid, N, device="cuda:0")
-    counts = plan.new_counts()
+    plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M_PAIRS)
+    assert plan.batch_samples >= M_PAIRS, "counting scratch must hold one layer's samples"
     contracts = [(s, kr) for s in SIGMAS for kr in K_RATIOS]
-    phi = torch.empty((len(contracts), plan.points), dtype=torch.float64, device=dev)
-    V = torch.empty_like(phi)
-    stream = torch.cuda.current_stream()
+    nc = len(contracts)
+    kinds = np.full(nc, qt.PUT, np.int32)
+    c_S0 = np.full(nc, S0)
+    c_K = np.array([S0 * kr for _, kr in contracts])
+    c_r = np.full(nc, RATE)
+    c_T = np.full(nc, MATURITY)
+    c_sig = np.array([[s] for s, _ in contracts])
+    counts = [plan.new_counts(), plan.new_counts()]
+    phi = [torch.empty((nc, plan.points), dtype=torch.float64, device=dev) for _ in range(2)]
+    V = [torch.empty((nc, plan.points), dtype=torch.float64, device=dev) for _ in range(2)]
+    s_fwd = torch.cuda.current_stream()
+    s_bdp = torch.cuda.Stream()
+    fwd_done = [torch.cuda.Event() for _ in range(2)]
+    bdp_done = [torch.cuda.Event() for _ in range(2)]
+    for e in bdp_done:
+        e.record(s_bdp)
 
-    def step(ev=None):
-        plan.transitions(0, 0, counts=counts)                 # zero fill only
+    def step(i, ev=None):
+        b = i % 2
+        s_fwd.wait_event(bdp_done[b])              # counts[b] free again
         if ev is not None:
-            ev[0].record(stream)
-        plan.transitions_add(counts, M_PAIRS, 0x5EED0000)
+            ev[0].record(s_fwd)
+        plan.transitions(M_PAIRS, 0x5EED0000 + i, counts=counts[b], stream=s_fwd)
         if ev is not None:
-            ev[1].record(stream)
-        for q, (s, kr) in enumerate(contracts):
-            plan.payoff(qt.PUT, S0, S0 * kr, RATE, MATURITY, s, out=phi[q])
-        plan.bdp(counts, phi, V=V, want_v0=False)
+            ev[1].record(s_fwd)
+        fwd_done[b].record(s_fwd)
+        s_bdp.wait_event(fwd_done[b])
+        plan.payoff_batch(kinds, c_S0, c_K, c_r, c_T, c_sig, out=phi[b], stream=s_bdp)
+        plan.bdp(counts[b], phi[b], V=V[b], want_v0=False, stream=s_bdp)
+        bdp_done[b].record(s_bdp)
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        step(i)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
+    # per step: start, after the sampling pass (recorded by the library), end
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
+           for _ in range(args.steps)]
+    for e in evs:
+        e[1].record(s_fwd)          # create the event so its handle can be passed down
     torch.cuda.synchronize()
-    t_start.record(stream)
+    t_start.record(s_fwd)
     for i in range(args.steps):
-        step(evs[i])
-    t_end.record(stream)
+        plan.trace(evs[i][1])
+        step(i, (evs[i][0], evs[i][2]))
+    plan.trace(None)
+    s_fwd.wait_stream(s_bdp)
+    t_end.record(s_fwd)
     torch.cuda.synchronize()
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
-    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in evs]))
+    keys_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    V = V[(args.steps - 1) % 2]
     V0 = V[:, 0].cpu().numpy()
     pairs = N_LAYERS * M_PAIRS
-    achieved = ALG_SLOTS_PER_PAIR * pairs / (fwd_ms * 1e-3)
+    achieved = ALG_SLOTS_PER_PAIR * pairs / (keys_ms * 1e-3)
     out = {
         "metric": "MC transition samples/s (cell search+count)",
         "value": pairs / (ms_step * 1e-3),
@@ -152,11 +180,13 @@ def main():
                    "layers": N_LAYERS, "points_per_layer": N_POINTS, "pairs_per_layer": M_PAIRS,
                    "contracts": len(contracts), "mode": "layerwise"},
         "forward_ms": fwd_ms,
+        "sampling_pass_ms": keys_ms,
+        "histogram_pass_ms": fwd_ms - keys_ms,
         "forward_pairs_per_s": pairs / (fwd_ms * 1e-3),
         "V0_atm_sigma0.2": float(V0[contracts.index((0.2, 1.0))]),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
-                     "kernel": "fwd_layer_1d",
+                     "kernel": "fwd_keys_1d",
                      "alg_slots_per_pair": ALG_SLOTS_PER_PAIR},
     }
     if not args.no_cpu_baseline:

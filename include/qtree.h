@@ -80,8 +80,12 @@ const char *qtree_last_error(void);
 const char *qtree_version(void);
 
 /* Bytes of device workspace a plan for this shape needs (d in 1..3,
- * N: host [n+1]).  Pure host arithmetic. */
-qtree_status qtree_workspace_size(int32_t d, int32_t n, const int32_t *N, size_t *bytes);
+ * N: host [n+1]) when its counting scratch is to hold `batch_samples`
+ * LAYERWISE samples per layer per pass (0: 2^22).  Larger M runs in several
+ * passes; a plan uses all the scratch its workspace has room for.  Pure host
+ * arithmetic. */
+qtree_status qtree_workspace_size(int32_t d, int32_t n, const int32_t *N, uint64_t batch_samples,
+                                  size_t *bytes);
 
 /* Validate a model and its grids on the host and upload the per-layer tables
  * the kernels read (model coefficients, grid points, 1-D cell midpoints or
@@ -93,6 +97,12 @@ qtree_status qtree_workspace_size(int32_t d, int32_t n, const int32_t *N, size_t
 qtree_status qtree_plan_create(const qtree_model *model, const float *grid, const int32_t *N,
                                void *workspace, size_t workspace_bytes, qtree_plan **out);
 void qtree_plan_destroy(qtree_plan *plan);
+/* Tracing: when `event_after_keys` (a hipEvent_t) is not NULL, LAYERWISE
+ * two-pass calls record it on their stream right after each sampling pass
+ * (before the histogram pass), so callers can time the two kernels apart. */
+qtree_status qtree_plan_trace(qtree_plan *plan, void *event_after_keys);
+/* LAYERWISE samples per layer one counting pass holds (0: one-pass atomics only). */
+int64_t qtree_plan_batch_samples(const qtree_plan *plan);
 /* Shape queries (host). */
 int32_t qtree_plan_dim(const qtree_plan *plan);
 int32_t qtree_plan_layers(const qtree_plan *plan);
@@ -158,6 +168,13 @@ qtree_status qtree_bdp(const qtree_plan *plan, const int32_t *counts, const doub
  * (phi_k = -inf for k < n).  sigma: host double[d].  Asynchronous. */
 qtree_status qtree_payoff(const qtree_plan *plan, int32_t kind, double S0, double K, double r,
                           double Tm, const double *sigma, double *phi, void *stream);
+/* The same for n_pay contracts in one launch per 32 contracts: host arrays
+ * kind, S0, K, r, Tm [n_pay] and sigma [n_pay][d]; phi: device
+ * double[n_pay][sum N_k]. */
+qtree_status qtree_payoff_batch(const qtree_plan *plan, int32_t n_pay, const int32_t *kind,
+                                const double *S0, const double *K, const double *r,
+                                const double *Tm, const double *sigma, double *phi,
+                                void *stream);
 
 /* Per-sample diagnostics, computed by the same device code as the forward
  * kernels, so tests can compare intermediate results one by one.

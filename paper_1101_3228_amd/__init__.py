@@ -54,7 +54,7 @@ def lib() -> ctypes.CDLL:
     L.qtree_status_string.restype = ctypes.c_char_p
     L.qtree_last_error.restype = ctypes.c_char_p
     L.qtree_version.restype = ctypes.c_char_p
-    L.qtree_workspace_size.argtypes = [i32, i32, P, P]
+    L.qtree_workspace_size.argtypes = [i32, i32, P, u64, P]
     L.qtree_plan_create.argtypes = [P, P, P, P, ctypes.c_size_t, P]
     L.qtree_plan_destroy.argtypes = [P]
     L.qtree_plan_destroy.restype = None
@@ -73,6 +73,12 @@ def lib() -> ctypes.CDLL:
     L.qtree_box_muller.argtypes = [P, P, i64, P, P, P]
     L.qtree_plan_tune.argtypes = [P, i32, i64]
     L.qtree_plan_tune.restype = ctypes.c_int
+    L.qtree_plan_trace.argtypes = [P, P]
+    L.qtree_plan_trace.restype = ctypes.c_int
+    L.qtree_plan_batch_samples.argtypes = [P]
+    L.qtree_plan_batch_samples.restype = i64
+    L.qtree_payoff_batch.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+    L.qtree_payoff_batch.restype = ctypes.c_int
     L.qtree_layer_samples.argtypes = [P, i32, u64, i64, u64, u32, P, P, P]
     L.qtree_cells.argtypes = [P, i32, P, i64, P, P]
     for f in ("qtree_workspace_size", "qtree_plan_create", "qtree_transitions", "qtree_bdp",
@@ -109,10 +115,11 @@ def gauss_quantizer(N: int) -> np.ndarray:
     return out
 
 
-def workspace_size(d: int, n: int, N) -> int:
+def workspace_size(d: int, n: int, N, batch_samples: int = 0) -> int:
     Nn = np.ascontiguousarray(N, np.int32)
     b = ctypes.c_size_t(0)
-    _check(lib().qtree_workspace_size(int(d), int(n), _np_ptr(Nn), ctypes.byref(b)))
+    _check(lib().qtree_workspace_size(int(d), int(n), _np_ptr(Nn), int(batch_samples),
+                                      ctypes.byref(b)))
     return int(b.value)
 
 
@@ -121,7 +128,8 @@ class Plan:
     qtree_plan).  model: dict of FP32 host arrays d, n, A, b, T, mu, L, x0;
     grid: host float32 [sum N_k, d]; N: host int32 [n+1]."""
 
-    def __init__(self, model: dict, grid: np.ndarray, N, device: str = "cuda"):
+    def __init__(self, model: dict, grid: np.ndarray, N, device: str = "cuda",
+                 batch_samples: int = 0):
         import torch
         self.d, self.n = int(model["d"]), int(model["n"])
         self.N = np.ascontiguousarray(N, np.int32)
@@ -132,13 +140,14 @@ class Plan:
         self.grid = g
         cm = _Model(self.d, self.n, *(keep[k].ctypes.data for k in ("A", "b", "T", "mu", "L",
                                                                     "x0")))
-        size = workspace_size(self.d, self.n, self.N)
+        size = workspace_size(self.d, self.n, self.N, batch_samples)
         self.workspace = torch.empty(size, dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
         _check(lib().qtree_plan_create(ctypes.byref(cm), _np_ptr(g), _np_ptr(self.N),
                                        self.workspace.data_ptr(), size, ctypes.byref(h)))
         self._h = h
         self.entries = int(lib().qtree_plan_count_entries(h))
+        self.batch_samples = int(lib().qtree_plan_batch_samples(h))
         self.points = int(lib().qtree_plan_points(h))
 
     def __del__(self):
@@ -188,6 +197,28 @@ class Plan:
         _check(lib().qtree_transitions_add(self._h, int(m0), int(M), int(seed), int(contract),
                                            int(mode), counts.data_ptr(), _stream_handle(stream)))
         return counts
+
+    def trace(self, event=None):
+        """Record `event` (torch.cuda.Event) after each sampling pass."""
+        if event is not None and event.cuda_event == 0:
+            event.record()  # create the underlying hipEvent_t
+        _check(lib().qtree_plan_trace(self._h, event.cuda_event if event is not None else None))
+        return self
+
+    def payoff_batch(self, kinds, S0, K, r, T, sigma, out=None, stream=None):
+        """Obstacles of n contracts in one launch: device float64 [n, points]."""
+        import torch
+        kinds = np.ascontiguousarray(np.atleast_1d(kinds), np.int32)
+        n = kinds.size
+        arr = [np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), (n,)))
+               for v in (S0, K, r, T)]
+        sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, np.float64).reshape(n, -1),
+                                                   (n, self.d)), np.float64)
+        if out is None:
+            out = torch.empty((n, self.points), dtype=torch.float64, device=self.workspace.device)
+        _check(lib().qtree_payoff_batch(self._h, n, _np_ptr(kinds), *(_np_ptr(v) for v in arr),
+                                        _np_ptr(sig), out.data_ptr(), _stream_handle(stream)))
+        return out
 
     def payoff(self, kind: int, S0: float, K: float, r: float, T: float, sigma, out=None,
                stream=None):

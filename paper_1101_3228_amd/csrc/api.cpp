@@ -59,7 +59,9 @@ struct qtree_plan {
   int32_t tune_xcd_map = 1;
   int32_t tune_count = 0;  // 0 automatic, 1 direct atomics, 2 two-pass
   int32_t max_tiles = 0, total_tiles = 0;
+  int64_t batch_chunks = 0;      // scratch chunks per layer per pass
   bool two_pass_ok = false;
+  hipEvent_t trace_keys = nullptr;
 };
 
 namespace qtree {
@@ -90,7 +92,7 @@ bool two_pass_fits(int d, int n, const int32_t* N) {
   return max_tiles_of(n, N) <= kMaxTiles && keys_lds_bytes(d, n, N) <= 160 * 1024;
 }
 
-WsLayout ws_layout(int d, int n, const int32_t* N) {
+WsLayout ws_layout(int d, int n, const int32_t* N, int64_t batch_chunks) {
   WsLayout l{};
   size_t off = 0;
   l.layers = off;
@@ -108,15 +110,24 @@ WsLayout ws_layout(int d, int n, const int32_t* N) {
   // most kMaxTiles tiles)
   const int mt = max_tiles_of(n, N);
   l.keys = off;
-  if (two_pass_fits(d, n, N)) {
-    off = align_up(off + sizeof(uint16_t) * (size_t)n * kBatchChunks * kChunk, 256);
+  if (batch_chunks > 0 && two_pass_fits(d, n, N)) {
+    off = align_up(off + sizeof(uint16_t) * (size_t)n * (size_t)batch_chunks * kChunk, 256);
     l.segs = off;
-    off = align_up(off + sizeof(uint32_t) * (size_t)n * kBatchChunks * (size_t)(mt + 1), 256);
+    off = align_up(off + sizeof(uint32_t) * (size_t)n * (size_t)batch_chunks * (size_t)(mt + 1),
+                   256);
   } else {
     l.segs = off;
   }
   l.total = off;
   return l;
+}
+
+// Chunks per layer a scratch for `samples` samples per layer needs (a d = 1
+// batch may start on an odd sample, so it spans one more Philox block).
+int64_t chunks_for(int d, uint64_t samples) {
+  if (samples == 0) return 0;
+  if (d == 1) return (int64_t)((samples / 2 + 1 + kChunk / 2 - 1) / (kChunk / 2));
+  return (int64_t)((samples + kChunk - 1) / kChunk);
 }
 
 }  // namespace qtree
@@ -154,11 +165,14 @@ static qtree_status check_shape(int32_t d, int32_t n, const int32_t* N) {
   return QTREE_OK;
 }
 
-qtree_status qtree_workspace_size(int32_t d, int32_t n, const int32_t* N, size_t* bytes) {
+qtree_status qtree_workspace_size(int32_t d, int32_t n, const int32_t* N, uint64_t batch_samples,
+                                  size_t* bytes) {
   if (!bytes) return fail(QTREE_EINVAL, "bytes is NULL");
   qtree_status s = check_shape(d, n, N);
   if (s != QTREE_OK) return s;
-  *bytes = qtree::ws_layout(d, n, N).total;
+  if (batch_samples == 0) batch_samples = qtree::kDefaultBatch;
+  if (batch_samples > (1ull << 31)) return fail(QTREE_EINVAL, "batch_samples must be <= 2^31");
+  *bytes = qtree::ws_layout(d, n, N, qtree::chunks_for(d, batch_samples)).total;
   return QTREE_OK;
 }
 
@@ -220,11 +234,21 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
                                         " must be strictly increasing");
     }
   }
-  p.lay = qtree::ws_layout(d, n, N);
+  // the scratch takes whatever the workspace holds beyond the layer tables
   p.max_tiles = qtree::max_tiles_of(n, N);
-  p.two_pass_ok = qtree::two_pass_fits(d, n, N);
-  if (workspace_bytes < p.lay.total)
-    return fail(QTREE_ENOMEM, "workspace needs " + std::to_string(p.lay.total) + " bytes");
+  const qtree::WsLayout base = qtree::ws_layout(d, n, N, 0);
+  if (workspace_bytes < base.total)
+    return fail(QTREE_ENOMEM, "workspace needs at least " + std::to_string(base.total) + " bytes");
+  p.batch_chunks = 0;
+  if (qtree::two_pass_fits(d, n, N)) {
+    const size_t per = (size_t)n * (sizeof(uint16_t) * qtree::kChunk +
+                                    sizeof(uint32_t) * (size_t)(p.max_tiles + 1));
+    int64_t c = (int64_t)((workspace_bytes - base.total) / per);
+    while (c > 0 && qtree::ws_layout(d, n, N, c).total > workspace_bytes) --c;
+    p.batch_chunks = c;
+  }
+  p.two_pass_ok = p.batch_chunks > 0;
+  p.lay = qtree::ws_layout(d, n, N, p.batch_chunks);
 
   // host image of the workspace
   std::vector<char> img(p.lay.total, 0);
@@ -317,8 +341,8 @@ static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uin
 // scratch: pass A writes the keys of a batch, pass B folds them into counts.
 static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hipStream_t s) {
   const uint64_t end = a.m0 + a.M;
-  const uint64_t bs = p->d == 1 ? (uint64_t)qtree::kBatchChunks * qtree::kChunk - 2
-                                : (uint64_t)qtree::kBatchChunks * qtree::kChunk;
+  const uint64_t bs = p->d == 1 ? (uint64_t)p->batch_chunks * qtree::kChunk - 2
+                                : (uint64_t)p->batch_chunks * qtree::kChunk;
   bool first = zero;
   for (uint64_t lo = a.m0; lo < end; lo += bs) {
     const uint64_t mb = (end - lo) < bs ? (end - lo) : bs;
@@ -339,6 +363,10 @@ static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hip
     b.first_batch = first ? 1 : 0;
     hipError_t e = qtree::launch_fwd_keys(b, s);
     if (e != hipSuccess) return e;
+    if (p->trace_keys) {
+      e = hipEventRecord(p->trace_keys, s);
+      if (e != hipSuccess) return e;
+    }
     e = qtree::launch_count_tiles(b, s);
     if (e != hipSuccess) return e;
     first = false;
@@ -372,6 +400,17 @@ static void plan_units(qtree::FwdArgs& a, const qtree_plan* p) {
   a.units = a.n * a.chunks;
   a.units_per_xcd = (a.units + 7) / 8;
   a.xcd_map = p->tune_xcd_map;
+}
+
+qtree_status qtree_plan_trace(qtree_plan* plan, void* event_after_keys) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  plan->trace_keys = static_cast<hipEvent_t>(event_after_keys);
+  return QTREE_OK;
+}
+
+int64_t qtree_plan_batch_samples(const qtree_plan* p) {
+  if (!p || !p->two_pass_ok) return 0;
+  return p->d == 1 ? p->batch_chunks * qtree::kChunk - 2 : p->batch_chunks * qtree::kChunk;
 }
 
 qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
@@ -472,33 +511,56 @@ qtree_status qtree_bdp(const qtree_plan* plan, const int32_t* counts, const doub
   return QTREE_OK;
 }
 
+qtree_status qtree_payoff_batch(const qtree_plan* plan, int32_t n_pay, const int32_t* kind,
+                                const double* S0, const double* K, const double* r,
+                                const double* Tm, const double* sigma, double* phi,
+                                void* stream) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (n_pay < 0) return fail(QTREE_EINVAL, "n_pay must be >= 0");
+  if (n_pay == 0) return QTREE_OK;
+  if (!kind || !S0 || !K || !r || !Tm || !sigma || !phi)
+    return fail(QTREE_EINVAL, "NULL array");
+  for (int q = 0; q < n_pay; ++q) {
+    if (kind[q] < 0 || kind[q] > 3) return fail(QTREE_EINVAL, "kind must be in 0..3");
+    if (!(Tm[q] > 0.0) || !std::isfinite(Tm[q]) || !std::isfinite(S0[q]) ||
+        !std::isfinite(K[q]) || !std::isfinite(r[q]))
+      return fail(QTREE_EINVAL, "contract parameters must be finite, Tm > 0");
+    for (int c = 0; c < plan->d; ++c)
+      if (!std::isfinite(sigma[(size_t)q * plan->d + c]))
+        return fail(QTREE_EINVAL, "sigma must be finite");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int q0 = 0; q0 < n_pay; q0 += qtree::kPayoffGroup) {
+    qtree::PayoffArgs a{};
+    a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
+    a.pts1 = reinterpret_cast<const float*>(plan->ws + plan->lay.points);
+    a.pts = reinterpret_cast<const float4*>(plan->ws + plan->lay.points);
+    a.phi = phi + (size_t)q0 * plan->points;
+    a.P = plan->points;
+    a.n = plan->n;
+    a.d = plan->d;
+    a.maxN = plan->maxN;
+    a.count = (n_pay - q0) < qtree::kPayoffGroup ? (n_pay - q0) : qtree::kPayoffGroup;
+    for (int q = 0; q < a.count; ++q) {
+      qtree::Contract& C = a.c[q];
+      C.kind = kind[q0 + q];
+      C.S0 = S0[q0 + q];
+      C.K = K[q0 + q];
+      C.r = r[q0 + q];
+      C.Tm = Tm[q0 + q];
+      for (int c = 0; c < plan->d; ++c) C.sigma[c] = sigma[(size_t)(q0 + q) * plan->d + c];
+    }
+    hipError_t e = qtree::launch_payoff(a, st);
+    if (e != hipSuccess) return hip_fail(e, "payoff launch");
+  }
+  return QTREE_OK;
+}
+
 qtree_status qtree_payoff(const qtree_plan* plan, int32_t kind, double S0, double K, double r,
                           double Tm, const double* sigma, double* phi, void* stream) {
   if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
-  if (!sigma || !phi) return fail(QTREE_EINVAL, "sigma and phi must be non-NULL");
-  if (kind < 0 || kind > 3) return fail(QTREE_EINVAL, "kind must be in 0..3");
-  if (!(Tm > 0.0) || !std::isfinite(S0) || !std::isfinite(K) || !std::isfinite(r))
-    return fail(QTREE_EINVAL, "contract parameters must be finite, Tm > 0");
-  qtree::PayoffArgs a{};
-  a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
-  a.pts1 = reinterpret_cast<const float*>(plan->ws + plan->lay.points);
-  a.pts = reinterpret_cast<const float4*>(plan->ws + plan->lay.points);
-  a.phi = phi;
-  a.n = plan->n;
-  a.d = plan->d;
-  a.kind = kind;
-  a.S0 = S0;
-  a.K = K;
-  a.r = r;
-  a.Tm = Tm;
-  for (int c = 0; c < plan->d; ++c) {
-    if (!std::isfinite(sigma[c])) return fail(QTREE_EINVAL, "sigma must be finite");
-    a.sigma[c] = sigma[c];
-  }
-  a.maxN = plan->maxN;
-  hipError_t e = qtree::launch_payoff(a, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "payoff launch");
-  return QTREE_OK;
+  if (!sigma) return fail(QTREE_EINVAL, "sigma is NULL");
+  return qtree_payoff_batch(plan, 1, &kind, &S0, &K, &r, &Tm, sigma, phi, stream);
 }
 
 qtree_status qtree_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,

@@ -13,7 +13,7 @@ namespace qtree {
 namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kPay = 8;
+constexpr int kPay = 16;
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void bdp_layer_kernel(BdpArgs a, int N_k, int N_k1,
@@ -85,38 +85,41 @@ hipError_t launch_copy_last_layer(const BdpArgs& a, int64_t pt_n, int N_n, hipSt
 }
 
 // Discounted obstacle phi_k(x) = exp(-r t_k) payoff(S_{t_k}(x)) on every grid
-// point, S^a_t(x) = S0 exp((r - sigma_a^2 / 2) t + sigma_a x_a), FP64.
+// point, S^a_t(x) = S0 exp((r - sigma_a^2 / 2) t + sigma_a x_a), FP64, for a
+// group of contracts (blockIdx.z).
 __global__ void payoff_kernel(PayoffArgs a) {
   const int k = blockIdx.y;
+  const Contract& C = a.c[blockIdx.z];
   const LayerDev& L = a.layers[k];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
-  const double t = a.Tm * (double)k / (double)a.n;
-  const double disc = exp(-a.r * t);
+  const double t = C.Tm * (double)k / (double)a.n;
+  const double disc = exp(-C.r * t);
   const int64_t at = (int64_t)L.pt_off + i;
   double v;
-  if (a.kind & 1) {
+  if (C.kind & 1) {
     const float4 g = a.d == 1 ? make_float4(a.pts1[at], 0.f, 0.f, 0.f) : a.pts[at];
     const float xs[3] = {g.x, g.y, g.z};
     double smax = -__builtin_huge_val();
     for (int c = 0; c < a.d; ++c) {
-      const double sc = a.S0 * exp((a.r - 0.5 * a.sigma[c] * a.sigma[c]) * t +
-                                   a.sigma[c] * (double)xs[c]);
+      const double sc = C.S0 * exp((C.r - 0.5 * C.sigma[c] * C.sigma[c]) * t +
+                                   C.sigma[c] * (double)xs[c]);
       smax = sc > smax ? sc : smax;
     }
-    v = disc * fmax(smax - a.K, 0.0);
+    v = disc * fmax(smax - C.K, 0.0);
   } else {
     const float x0 = a.d == 1 ? a.pts1[at] : a.pts[at].x;
     const double sc =
-        a.S0 * exp((a.r - 0.5 * a.sigma[0] * a.sigma[0]) * t + a.sigma[0] * (double)x0);
-    v = disc * fmax(a.K - sc, 0.0);
+        C.S0 * exp((C.r - 0.5 * C.sigma[0] * C.sigma[0]) * t + C.sigma[0] * (double)x0);
+    v = disc * fmax(C.K - sc, 0.0);
   }
-  if ((a.kind & 2) && k < a.n) v = -__builtin_huge_val();
-  a.phi[at] = v;
+  if ((C.kind & 2) && k < a.n) v = -__builtin_huge_val();
+  a.phi[(int64_t)blockIdx.z * a.P + at] = v;
 }
 
 hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.maxN + kBlock - 1) / kBlock), (unsigned)(a.n + 1));
+  const dim3 grid((unsigned)((a.maxN + kBlock - 1) / kBlock), (unsigned)(a.n + 1),
+                  (unsigned)a.count);
   hipLaunchKernelGGL(payoff_kernel, grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }

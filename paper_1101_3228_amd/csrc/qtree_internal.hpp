@@ -20,7 +20,7 @@ constexpr int kSuper = 1 << kSuperBits;
 constexpr int kTilesPerSuper = kSuper / kTile;
 constexpr int kChunk = 4096;          // samples per pass-A workgroup
 constexpr int kMaxTiles = 4096;       // larger count blocks use direct atomics
-constexpr int kBatchChunks = 1024;    // chunks per layer held in the scratch
+constexpr int kDefaultBatch = 1 << 22;  // samples per layer per pass by default
 
 // One record per layer k = 0..n, stored in the plan's device workspace.
 // Model coefficients are the FP32 inputs of the AR(1) proposition (Sec. 3);
@@ -44,12 +44,14 @@ struct WsLayout {
   size_t layers;   // LayerDev[n+1]
   size_t points;   // d == 1: float[sum N]; d >= 2: float4[sum N] = (g0, g1, g2, h)
   size_t aux;      // d == 1: float[sum P] midpoints padded with +inf
-  size_t keys;     // uint16[n][kBatchChunks][kChunk] pass-A keys
-  size_t segs;     // uint32[n][kBatchChunks][max tiles + 1] segment starts
+  size_t keys;     // uint16[n][batch chunks][kChunk] pass-A keys
+  size_t segs;     // uint32[n][batch chunks][max tiles + 1] segment starts
   size_t total;
 };
 
-WsLayout ws_layout(int d, int n, const int32_t* N);
+// Layout for a scratch that holds `batch_chunks` chunks per layer (0: none).
+WsLayout ws_layout(int d, int n, const int32_t* N, int64_t batch_chunks);
+bool two_pass_fits(int d, int n, const int32_t* N);
 
 struct FwdArgs {
   const LayerDev* layers;
@@ -97,15 +99,22 @@ hipError_t launch_bdp_layer(const BdpArgs& a, int k, int N_k, int N_k1, int64_t 
                             int64_t pt_k1, int64_t cnt_k, hipStream_t s);
 hipError_t launch_copy_last_layer(const BdpArgs& a, int64_t pt_n, int N_n, hipStream_t s);
 
+struct Contract {
+  double S0, K, r, Tm;
+  double sigma[kMaxDim];
+  int32_t kind;
+  int32_t pad_;
+};
+constexpr int kPayoffGroup = 32;  // contracts per payoff launch (kernel-argument size)
+
 struct PayoffArgs {
   const LayerDev* layers;
   const float* pts1;
   const float4* pts;
-  double* phi;
-  int32_t n, d, kind;
-  double S0, K, r, Tm;
-  double sigma[kMaxDim];
-  int32_t maxN;
+  double* phi;      // [count][P]
+  int64_t P;
+  int32_t n, d, maxN, count;
+  Contract c[kPayoffGroup];
 };
 hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s);
 

@@ -312,6 +312,43 @@ def test_chunked_accumulation_equals_one_call(small_case):
     plan.tune(count=0)
 
 
+def test_two_pass_tiny_scratch_many_passes():
+    """A plan whose workspace holds 5000 samples per layer runs a larger M in
+    many counting passes (odd m0), with identical counts; the trace event is
+    recorded after the sampling pass."""
+    _print_case("two-pass tiny scratch")
+    for d, shapes in ((1, [1, 120, 130, 40]), (2, [1, (9, 9), (10, 11), (5, 5)])):
+        spec = synth.bm_model(d, 3, rho=0.2)
+        grid, N = synth.layer_grids(spec, shapes)
+        plan = qt.Plan(spec, grid, N, batch_samples=5000)
+        assert 0 < plan.batch_samples < 20_000
+        ev = torch.cuda.Event(enable_timing=True)
+        plan.trace(ev)
+        got = plan.transitions(61_111, 5, m0=1).cpu().numpy()
+        plan.trace(None)
+        assert ev.query()
+        ref = O.transitions(_omodel(spec), grid, N, 61_111, seed=5, m0=1, nthreads=THREADS)
+        assert np.array_equal(got, ref), d
+
+
+def test_payoff_batch_matches_single():
+    spec = synth.bm_model(2, 4, rho=0.1)
+    grid, N = synth.layer_grids(spec, [1, (5, 5), (6, 6), (7, 7), (8, 8)])
+    plan = _plan(spec, grid, N)
+    rng = np.random.default_rng(2)
+    n = 40
+    kinds = rng.integers(0, 4, n)
+    S0, K = rng.uniform(80, 120, n), rng.uniform(80, 120, n)
+    r, T = rng.uniform(0, 0.1, n), rng.uniform(0.25, 2, n)
+    sig = rng.uniform(0.1, 0.4, (n, 2))
+    batch = plan.payoff_batch(kinds, S0, K, r, T, sig).cpu().numpy()
+    for q in range(n):
+        ref = O.payoff(int(kinds[q]), 2, N, grid, S0[q], K[q], r[q], T[q], sig[q])
+        fin = np.isfinite(ref)
+        assert np.array_equal(fin, np.isfinite(batch[q]))
+        assert np.allclose(batch[q][fin], ref[fin], rtol=1e-13, atol=1e-12)
+
+
 def test_two_pass_several_batches():
     """More samples than one scratch batch holds (2^22 per layer): the count
     tiles accumulate over batches; odd m0 splits a Philox pair at every batch
