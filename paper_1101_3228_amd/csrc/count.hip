@@ -13,11 +13,11 @@
 //    the keys by tile t = key >> kTileBits with a counting sort in LDS (count
 //    per tile, scan, place; 4096-entry tiles keep the LDS counters of a wave
 //    apart).  The chunk writes each key as its 16-bit offset inside its
-//    32768-entry super tile, tile by tile, with 16-byte stores, plus the
+//    16384-entry super tile, tile by tile, with 16-byte stores, plus the
 //    segment starts.
 //  pass B (count_tiles): one workgroup per (layer, super tile) walks that
-//    super tile's segment (eight consecutive tiles) in every chunk of the
-//    layer, increments a 32768-bin LDS histogram, and stores the super tile
+//    super tile's segment (four consecutive tiles) in every chunk of the
+//    layer, increments a 16384-bin LDS histogram, and stores the super tile
 //    into the count block.  Each count is
 //    owned by exactly one workgroup, so the store is plain (it also replaces
 //    zeroing).  Integer counting makes the order of keys irrelevant.
@@ -61,31 +61,30 @@ __device__ __forceinline__ void count_keys(const uint32_t* key, uint32_t* tcount
 }
 
 // Exclusive scan of tcount[0..T) in place (tcount[T] = total), copied to
-// cursor.  Each lane sums a run of consecutive counters, the lane partials
-// are scanned in LDS (Hillis-Steele), then the runs are rewritten.  `part`
-// holds kBlock entries.  Called by the whole block between barriers.
-__device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, int T,
-                                           uint32_t* part) {
-  const int per = (T + kBlock - 1) / kBlock;
-  const int t0 = (int)threadIdx.x * per;
+// cursor, by wave 0 alone: each lane sums a run of consecutive counters, the
+// 64 run sums are scanned with shuffles, then the runs are rewritten.  Must
+// sit between two barriers.
+__device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, int T) {
+  if (threadIdx.x >= 64) return;
+  const int lane = (int)threadIdx.x;
+  const int per = (T + 63) / 64;
+  const int t0 = lane * per;
   uint32_t sum = 0;
   for (int t = t0; t < t0 + per && t < T; ++t) sum += tcount[t];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  uint32_t incl = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
   }
-  uint32_t run = part[threadIdx.x] - sum;  // exclusive prefix of this lane's run
+  uint32_t run = incl - sum;
   for (int t = t0; t < t0 + per && t < T; ++t) {
     const uint32_t v = tcount[t];
     tcount[t] = run;
     cursor[t] = run;
     run += v;
   }
-  if (threadIdx.x == kBlock - 1) tcount[T] = part[kBlock - 1];
+  if (lane == 63) tcount[T] = incl;
 }
 
 __device__ __forceinline__ void place_keys(const uint32_t* key, uint32_t* cursor,
@@ -128,7 +127,6 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds + ((L0.P + L1.P + 3) & ~3));
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
-  uint32_t* part = cursor + T;
   for (int i = threadIdx.x; i < L0.P; i += kBlock) mk[i] = a.mids[L0.aux_off + i];
   for (int i = threadIdx.x; i < L1.P; i += kBlock) mk1[i] = a.mids[L1.aux_off + i];
   for (int t = threadIdx.x; t <= T; t += kBlock) tcount[t] = 0;
@@ -158,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   }
   count_keys(key, tcount);
   __syncthreads();
-  scan_tiles(tcount, cursor, T, part);
+  scan_tiles(tcount, cursor, T);
   __syncthreads();
   place_keys(key, cursor, stage);
   __syncthreads();
@@ -179,7 +177,6 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + N0 + N1);
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
-  uint32_t* part = cursor + T;
   for (int i = threadIdx.x; i < N0; i += kBlock) gk[i] = a.pts[L0.pt_off + i];
   for (int i = threadIdx.x; i < N1; i += kBlock) gk1[i] = a.pts[L1.pt_off + i];
   for (int t = threadIdx.x; t <= T; t += kBlock) tcount[t] = 0;
@@ -211,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
   }
   count_keys(key, tcount);
   __syncthreads();
-  scan_tiles(tcount, cursor, T, part);
+  scan_tiles(tcount, cursor, T);
   __syncthreads();
   place_keys(key, cursor, stage);
   __syncthreads();
@@ -252,21 +249,44 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
     }
     __syncthreads();
     const int cn = (a.chunks - c0) < kCountBlock ? (a.chunks - c0) : kCountBlock;
-    for (int cc = wave; cc < cn; cc += kCountBlock / 64) {
-      // 16-byte loads of 8 keys each (the chunk's key block is 16-byte
-      // aligned); keys outside [s0, s1) are skipped
-      const uint32_t s0 = sb[cc], s1 = se[cc];
-      const uint4* kv = reinterpret_cast<const uint4*>(keysk + (size_t)(c0 + cc) * kChunk);
-      for (uint32_t v = (s0 >> 3) + lane; v * 8 < s1; v += 64) {
-        const uint4 w = kv[v];
-        const uint32_t q0 = v * 8;
-        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    // each wave takes kInFlight chunks at a time so that several segment
+    // loads are outstanding per lane; 16-byte loads of 8 keys each (a chunk's
+    // key block is 16-byte aligned), keys outside [s0, s1) skipped
+    constexpr int kWaves = kCountBlock / 64;
+    constexpr int kInFlight = 4;
+    for (int g = wave * kInFlight; g < cn; g += kWaves * kInFlight) {
+      uint32_t s0[kInFlight], s1[kInFlight], v[kInFlight];
+      const uint4* kv[kInFlight];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const uint32_t q = q0 + u;
-          const uint32_t key = (words[u >> 1] >> ((u & 1) * 16)) & 0xFFFFu;
-          if (q >= s0 && q < s1) atomicAdd(&hist[key], 1u);
+      for (int u = 0; u < kInFlight; ++u) {
+        const int cc = g + u < cn ? g + u : g;
+        s0[u] = g + u < cn ? sb[cc] : 0u;
+        s1[u] = g + u < cn ? se[cc] : 0u;
+        kv[u] = reinterpret_cast<const uint4*>(keysk + (size_t)(c0 + cc) * kChunk);
+        v[u] = (s0[u] >> 3) + lane;
+      }
+      bool more = true;
+      while (more) {
+        uint4 w[kInFlight];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u)
+          w[u] = v[u] * 8 < s1[u] ? kv[u][v[u]] : make_uint4(0, 0, 0, 0);
+        more = false;
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+          if (v[u] * 8 < s1[u]) {
+            const uint32_t words[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const uint32_t q = v[u] * 8 + e;
+              const uint32_t key = (words[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu;
+              if (q >= s0[u] && q < s1[u]) atomicAdd(&hist[key], 1u);
+            }
+          }
+          v[u] += 64;
+          more = more || (v[u] * 8 < s1[u]);
         }
+        more = __any(more);
       }
     }
   }
@@ -296,7 +316,7 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
 hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
   // staged keys + tile counters + cursors + scan partials
   const size_t tiles_bytes =
-      sizeof(uint16_t) * kChunk + sizeof(uint32_t) * (size_t)(2 * a.max_tiles + 1 + kBlock);
+      sizeof(uint16_t) * kChunk + sizeof(uint32_t) * (size_t)(2 * a.max_tiles + 1);
   hipError_t e;
   if (a.d == 1) {
     const size_t lds = sizeof(float) * (2 * (size_t)a.maxP + 4) + tiles_bytes;

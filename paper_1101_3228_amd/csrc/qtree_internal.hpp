@@ -15,7 +15,7 @@ constexpr int kMaxDim = 3;
 // super tile with plain stores.
 constexpr int kTileBits = 12;
 constexpr int kTile = 1 << kTileBits;
-constexpr int kSuperBits = 15;
+constexpr int kSuperBits = 14;
 constexpr int kSuper = 1 << kSuperBits;
 constexpr int kTilesPerSuper = kSuper / kTile;
 constexpr int kChunk = 4096;          // samples per pass-A workgroup
