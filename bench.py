@@ -54,6 +54,22 @@ ALG_SLOTS_PER_PAIR = 50 + 71 + 3 + 54 + 1
 PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
 
 
+def _measured_traffic():
+    """HBM bytes per launch of the sampling kernel from the committed rocprofv3
+    counter runs (profiles/fwd_keys_1d_traffic.json), or None when the
+    kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fwd_keys_1d_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sha256"] else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _inputs():
     import paper_1101_3228_amd as qt
     import synth
@@ -85,9 +101,21 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=400_000,
+    ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers three times (the "
+                         "reference kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes": src.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the quantization-tree "
                                    "forward step is measured on a single MI355X "
@@ -185,7 +213,8 @@ def main():
         "forward_pairs_per_s": pairs / (fwd_ms * 1e-3),
         "V0_atm_sigma0.2": float(V0[contracts.index((0.2, 1.0))]),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS,
+                     "traffic": _measured_traffic(),
                      "kernel": "fwd_keys_1d",
                      "alg_slots_per_pair": ALG_SLOTS_PER_PAIR},
     }
