@@ -176,6 +176,56 @@ qtree_status qtree_payoff_batch(const qtree_plan *plan, int32_t n_pay, const int
                                 const double *Tm, const double *sigma, double *phi,
                                 void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many contracts with uneven n and N_k priced together.
+ * Each contract names a plan (model + grids, created as above), the samples
+ * per layer M (LAYERWISE, from sample 0), its seed and Philox contract id,
+ * its count buffer, its obstacles phi [n_pay][points] and its value buffer V
+ * [n_pay][points] (all device).  qtree_batch_plan builds a device work list
+ * of (contract, layer, chunk range) units sorted longest first; a run then
+ * issues, per scratch group, one persistent sampling launch that claims
+ * units from the list until it is empty and one histogram launch, and then
+ * one BDP launch in which each workgroup walks all layers of one contract for
+ * up to 16 of its payoffs.  Counts and values are bit-for-bit / 1e-9 the
+ * ones of qtree_transitions + qtree_bdp per contract (same Philox counters).
+ * qtree_batch_plan allocates the batch's device tables and its key scratch
+ * (`scratch_bytes`, 0 = 4 GiB; contracts are grouped so that each group
+ * fits) -- the only call besides the tuner that allocates device memory.
+ * flags bit 0: capture the run sequence into a hipGraph after the first run
+ * and replay it from then on (needs a non-NULL stream).
+ * A tuner (optional) times the candidate persistent grids on the first run
+ * and keeps the fastest per batch shape in a text cache (path given, else
+ * $QTREE_TUNE_CACHE, else memory only).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  const qtree_plan *plan;
+  uint64_t M;
+  uint64_t seed;
+  uint32_t contract_id;
+  int32_t *counts;
+  const double *phi;
+  int32_t n_pay;
+  double *V;
+} qtree_contract;
+
+typedef struct qtree_tuner qtree_tuner;
+typedef struct qtree_batch qtree_batch;
+
+qtree_status qtree_tuner_create(const char *cache_path, qtree_tuner **out);
+void qtree_tuner_destroy(qtree_tuner *tuner);
+/* Cached choice (workgroups per CU) for a batch signature, 0 if none. */
+int32_t qtree_tuner_lookup(const qtree_tuner *tuner, const char *signature);
+
+qtree_status qtree_batch_plan(const qtree_contract *contracts, int32_t n, qtree_tuner *tuner,
+                              size_t scratch_bytes, uint32_t flags, qtree_batch **out);
+/* Run the batch on `stream`; if V0_host (double[sum n_pay], contracts in
+ * order) is not NULL, copy every V_0 there and synchronise. */
+qtree_status qtree_batch_run(qtree_batch *batch, double *V0_host, void *stream);
+qtree_status qtree_batch_info(const qtree_batch *batch, int64_t *units, int64_t *tiles,
+                              int32_t *groups, int32_t *per_cu);
+const char *qtree_batch_signature(const qtree_batch *batch);
+void qtree_batch_destroy(qtree_batch *batch);
+
 /* Per-sample diagnostics, computed by the same device code as the forward
  * kernels, so tests can compare intermediate results one by one.
  * qtree_box_muller: z0/z1[i] = Box-Muller transform of the Philox words

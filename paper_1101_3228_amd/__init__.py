@@ -278,3 +278,99 @@ def cells(plan: Plan, k: int, x, stream=None):
     _check(lib().qtree_cells(plan.handle, int(k), x.data_ptr(), int(count), out.data_ptr(),
                              _stream_handle(stream)))
     return out[:count]
+
+
+class _Contract(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("M", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("contract_id", ctypes.c_uint32), ("counts", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("n_pay", ctypes.c_int32), ("V", ctypes.c_void_p)]
+
+
+def _batch_setup():
+    L = lib()
+    if getattr(L, "_batch", False):
+        return L
+    P = ctypes.c_void_p
+    L.qtree_tuner_create.argtypes = [ctypes.c_char_p, P]
+    L.qtree_tuner_create.restype = ctypes.c_int
+    L.qtree_tuner_destroy.argtypes = [P]
+    L.qtree_tuner_destroy.restype = None
+    L.qtree_tuner_lookup.argtypes = [P, ctypes.c_char_p]
+    L.qtree_tuner_lookup.restype = ctypes.c_int32
+    L.qtree_batch_plan.argtypes = [P, ctypes.c_int32, P, ctypes.c_size_t, ctypes.c_uint32, P]
+    L.qtree_batch_plan.restype = ctypes.c_int
+    L.qtree_batch_run.argtypes = [P, P, P]
+    L.qtree_batch_run.restype = ctypes.c_int
+    L.qtree_batch_info.argtypes = [P, P, P, P, P]
+    L.qtree_batch_info.restype = ctypes.c_int
+    L.qtree_batch_signature.argtypes = [P]
+    L.qtree_batch_signature.restype = ctypes.c_char_p
+    L.qtree_batch_destroy.argtypes = [P]
+    L.qtree_batch_destroy.restype = None
+    L._batch = True
+    return L
+
+
+class Tuner:
+    """Autotuner handle with an optional text cache file."""
+
+    def __init__(self, cache_path: str | None = None):
+        h = ctypes.c_void_p()
+        _check(_batch_setup().qtree_tuner_create(cache_path.encode() if cache_path else None,
+                                                 ctypes.byref(h)))
+        self._h = h
+
+    def lookup(self, signature: str) -> int:
+        return int(_batch_setup().qtree_tuner_lookup(self._h, signature.encode()))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
+            _lib.qtree_tuner_destroy(self._h)
+            self._h = None
+
+
+class Batch:
+    """Many contracts priced together (persistent sampling launch, histogram
+    launch, one BDP launch; optional hipGraph replay).  items: list of dicts
+    with plan, M, seed, contract_id, counts, phi [n_pay, points], V."""
+
+    def __init__(self, items, tuner: Tuner | None = None, scratch_bytes: int = 0,
+                 graph: bool = False):
+        L = _batch_setup()
+        self.items = items
+        arr = (_Contract * len(items))()
+        for i, it in enumerate(items):
+            plan = it["plan"]
+            phi = it["phi"].reshape(-1, plan.points)
+            arr[i] = _Contract(plan.handle.value, int(it["M"]), int(it["seed"]),
+                               int(it.get("contract_id", 0)), it["counts"].data_ptr(),
+                               phi.data_ptr(), phi.shape[0], it["V"].data_ptr())
+        self._arr = arr
+        self.n_pay = [it["phi"].reshape(-1, it["plan"].points).shape[0] for it in items]
+        h = ctypes.c_void_p()
+        _check(L.qtree_batch_plan(arr, len(items), tuner._h if tuner else None,
+                                  int(scratch_bytes), 1 if graph else 0, ctypes.byref(h)))
+        self._h = h
+        self.tuner = tuner
+
+    def run(self, want_v0: bool = True, stream=None):
+        V0 = np.zeros(sum(self.n_pay), np.float64) if want_v0 else None
+        _check(_batch_setup().qtree_batch_run(self._h, _np_ptr(V0) if want_v0 else None,
+                                              _stream_handle(stream)))
+        return V0
+
+    def info(self):
+        u, t = ctypes.c_int64(), ctypes.c_int64()
+        g, p = ctypes.c_int32(), ctypes.c_int32()
+        _check(_batch_setup().qtree_batch_info(self._h, ctypes.byref(u), ctypes.byref(t),
+                                               ctypes.byref(g), ctypes.byref(p)))
+        return {"units": u.value, "tiles": t.value, "groups": g.value, "per_cu": p.value}
+
+    @property
+    def signature(self) -> str:
+        return _batch_setup().qtree_batch_signature(self._h).decode()
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
+            _lib.qtree_batch_destroy(self._h)
+            self._h = None

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "qtree_internal.hpp"
+#include "qtree_plan.hpp"
 
 namespace {
 
@@ -20,6 +21,14 @@ qtree_status fail(qtree_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
 }
+
+}  // namespace
+
+namespace qtree {
+qtree_status set_error(qtree_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace qtree
+
+namespace {
 
 qtree_status hip_fail(hipError_t e, const char* what) {
   return fail(QTREE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -46,23 +55,6 @@ constexpr int kMaxNnd = 4096;
 
 }  // namespace
 
-struct qtree_plan {
-  int d = 0, n = 0;
-  std::vector<int32_t> N;
-  std::vector<int64_t> pt_off, cnt_off, aux_off;
-  std::vector<int32_t> P;
-  int64_t points = 0, entries = 0, mids_total = 0;
-  int32_t maxN = 0, maxP = 0;
-  char* ws = nullptr;
-  qtree::WsLayout lay{};
-  int64_t tune_chunk = 0;  // 0: automatic
-  int32_t tune_xcd_map = 1;
-  int32_t tune_count = 0;  // 0 automatic, 1 direct atomics, 2 two-pass
-  int32_t max_tiles = 0, total_tiles = 0;
-  int64_t batch_chunks = 0;      // scratch chunks per layer per pass
-  bool two_pass_ok = false;
-  hipEvent_t trace_keys = nullptr;
-};
 
 namespace qtree {
 

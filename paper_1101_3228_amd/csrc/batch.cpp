@@ -1,0 +1,455 @@
+// Batched forward step + BDP for many contracts with uneven n and N_k:
+// one persistent pass-A launch per scratch group (a device work queue of
+// (contract, layer, chunk range) units, longest first), one pass-B launch per
+// group, one BDP launch for all (contract, payoff group) pairs, captured once
+// into a hipGraph; plus the autotuner that picks the persistent grid.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "qtree.h"
+#include "qtree_batch.hpp"
+#include "qtree_plan.hpp"
+
+using qtree::set_error;
+
+struct qtree_tuner {
+  std::string path;
+  std::map<std::string, int> best;  // batch signature -> workgroups per CU
+};
+
+namespace {
+
+struct Group {
+  int unit_off = 0, n_units = 0, tile_off = 0, n_tiles = 0;
+};
+
+qtree_status hip_error(hipError_t e, const char* what) {
+  return set_error(QTREE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), sizeof(T) * src.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+void load_cache(qtree_tuner* t) {
+  if (t->path.empty()) return;
+  std::ifstream in(t->path);
+  std::string key;
+  int v;
+  while (in >> key >> v) t->best[key] = v;
+}
+
+void save_cache(const qtree_tuner* t) {
+  if (t->path.empty()) return;
+  std::ofstream out(t->path, std::ios::trunc);
+  for (const auto& kv : t->best) out << kv.first << " " << kv.second << "\n";
+}
+
+}  // namespace
+
+struct qtree_batch {
+  std::vector<qtree_contract> c;
+  std::vector<qtree::BatchContract> hc;
+  std::vector<qtree::BatchUnit> units;
+  std::vector<qtree::BatchTile> tiles;
+  std::vector<qtree::BdpJob> jobs;
+  std::vector<Group> groups;
+  std::vector<double> unit_cost;
+  qtree::BatchContract* d_contracts = nullptr;
+  qtree::BatchUnit* d_units = nullptr;
+  qtree::BatchTile* d_tiles = nullptr;
+  qtree::BdpJob* d_jobs = nullptr;
+  int* d_head = nullptr;
+  uint16_t* d_keys = nullptr;
+  uint32_t* d_segs = nullptr;
+  int64_t n_v0 = 0;
+  size_t lds = 0;
+  int dmax = 1;
+  int cus = 256;
+  int per_cu = 2;
+  int max_per_cu = 2;
+  qtree_tuner* tuner = nullptr;
+  std::string signature;
+  bool use_graph = false;
+  bool tuned = false;
+  hipGraphExec_t exec = nullptr;
+
+  ~qtree_batch() {
+    if (exec) hipGraphExecDestroy(exec);
+    for (void* p : {(void*)d_contracts, (void*)d_units, (void*)d_tiles, (void*)d_jobs,
+                    (void*)d_head, (void*)d_keys, (void*)d_segs})
+      if (p) hipFree(p);
+  }
+};
+
+namespace {
+
+qtree::BatchArgs group_args(const qtree_batch* b, const Group& g) {
+  qtree::BatchArgs a{};
+  a.contracts = b->d_contracts;
+  a.units = b->d_units + g.unit_off;
+  a.tiles = b->d_tiles + g.tile_off;
+  a.n_units = g.n_units;
+  a.n_tiles = g.n_tiles;
+  a.head = b->d_head;
+  a.keys = b->d_keys;
+  a.segs = b->d_segs;
+  return a;
+}
+
+hipError_t enqueue_forward(const qtree_batch* b, int per_cu, hipStream_t s) {
+  for (const Group& g : b->groups) {
+    hipError_t e = qtree::launch_batch_forward(group_args(b, g), b->dmax, per_cu * b->cus,
+                                               b->lds, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
+  hipError_t e = enqueue_forward(b, b->per_cu, s);
+  if (e != hipSuccess) return e;
+  return qtree::launch_bdp_batch(b->d_jobs, (int)b->jobs.size(), s);
+}
+
+// Time the forward with every candidate persistent grid and keep the best.
+qtree_status tune(qtree_batch* b, hipStream_t s) {
+  auto it = b->tuner->best.find(b->signature);
+  if (it != b->tuner->best.end()) {
+    b->per_cu = std::min(it->second, b->max_per_cu);
+    return QTREE_OK;
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return set_error(QTREE_EDEVICE, "tuner events");
+  float best_ms = 1e30f;
+  int best = b->per_cu;
+  for (int cand = 1; cand <= b->max_per_cu; cand *= 2) {
+    hipError_t e = enqueue_forward(b, cand, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = enqueue_forward(b, cand, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return hip_error(e, "tuner run");
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cand;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  b->per_cu = best;
+  b->tuner->best[b->signature] = best;
+  save_cache(b->tuner);
+  return QTREE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qtree_status qtree_tuner_create(const char* cache_path, qtree_tuner** out) {
+  if (!out) return set_error(QTREE_EINVAL, "out is NULL");
+  qtree_tuner* t = new qtree_tuner;
+  if (cache_path) t->path = cache_path;
+  else if (const char* env = std::getenv("QTREE_TUNE_CACHE")) t->path = env;
+  load_cache(t);
+  *out = t;
+  return QTREE_OK;
+}
+
+void qtree_tuner_destroy(qtree_tuner* t) { delete t; }
+
+int32_t qtree_tuner_lookup(const qtree_tuner* t, const char* signature) {
+  if (!t || !signature) return 0;
+  auto it = t->best.find(signature);
+  return it == t->best.end() ? 0 : it->second;
+}
+
+qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_tuner* tuner,
+                              size_t scratch_bytes, uint32_t flags, qtree_batch** out) {
+  if (!out) return set_error(QTREE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!contracts || n < 1) return set_error(QTREE_EINVAL, "need at least one contract");
+  if (scratch_bytes == 0) scratch_bytes = (size_t)4 << 30;
+  qtree_batch* b = new qtree_batch;
+  b->c.assign(contracts, contracts + n);
+  b->tuner = tuner;
+  b->use_graph = (flags & 1u) != 0;
+  uint64_t sig = 1469598103934665603ull;  // FNV-1a over the batch shape
+  auto mix = [&sig](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      sig ^= (v >> (8 * i)) & 0xFF;
+      sig *= 1099511628211ull;
+    }
+  };
+  int maxP = 1, maxN = 1, max_tiles = 0;
+  int64_t v0_off = 0;
+  for (int i = 0; i < n; ++i) {
+    const qtree_contract& C = contracts[i];
+    const qtree_plan* p = C.plan;
+    if (!p || !C.counts || !C.phi || !C.V) {
+      delete b;
+      return set_error(QTREE_EINVAL, "contract " + std::to_string(i) + ": NULL plan or buffer");
+    }
+    if (C.M < 1 || C.M >= (1ull << 31)) {
+      delete b;
+      return set_error(QTREE_EOVERFLOW, "contract " + std::to_string(i) + ": M out of range");
+    }
+    if (C.n_pay < 1) {
+      delete b;
+      return set_error(QTREE_EINVAL, "contract " + std::to_string(i) + ": n_pay < 1");
+    }
+    if (!qtree::two_pass_fits(p->d, p->n, p->N.data())) {
+      delete b;
+      return set_error(QTREE_EUNSUPPORTED,
+                       "contract " + std::to_string(i) + ": count blocks too large for batching");
+    }
+    mix((uint64_t)p->d);
+    mix((uint64_t)p->n);
+    mix(C.M);
+    for (int k = 0; k <= p->n; ++k) mix((uint64_t)p->N[k]);
+    b->dmax = std::max(b->dmax, (int)p->d);
+    maxP = std::max(maxP, p->maxP);
+    maxN = std::max(maxN, p->maxN);
+    max_tiles = std::max(max_tiles, p->max_tiles);
+    qtree::BatchContract bc{};
+    bc.layers = reinterpret_cast<const qtree::LayerDev*>(p->ws + p->lay.layers);
+    bc.mids = reinterpret_cast<const float*>(p->ws + p->lay.aux);
+    bc.pts = reinterpret_cast<const float4*>(p->ws + p->lay.points);
+    bc.counts = C.counts;
+    bc.key0 = (uint32_t)(C.seed & 0xFFFFFFFFu);
+    bc.key1 = (uint32_t)(C.seed >> 32);
+    bc.contract = C.contract_id;
+    bc.d = p->d;
+    bc.n = p->n;
+    bc.M = C.M;
+    bc.chunks = p->d == 1 ? (int32_t)(((C.M + 1) / 2 + qtree::kChunk / 2 - 1) / (qtree::kChunk / 2))
+                          : (int32_t)((C.M + qtree::kChunk - 1) / qtree::kChunk);
+    bc.seg_stride = p->max_tiles + 1;
+    b->hc.push_back(bc);
+    for (int q0 = 0; q0 < C.n_pay; q0 += 16) {
+      qtree::BdpJob j{};
+      j.layers = bc.layers;
+      j.counts = C.counts;
+      j.phi = C.phi;
+      j.V = C.V;
+      j.P = p->points;
+      j.n = p->n;
+      j.q0 = q0;
+      j.nq = std::min(16, C.n_pay - q0);
+      b->jobs.push_back(j);
+    }
+    v0_off += C.n_pay;
+  }
+  b->n_v0 = v0_off;
+  char sbuf[32];
+  std::snprintf(sbuf, sizeof(sbuf), "%016llx", (unsigned long long)sig);
+  b->signature = sbuf;
+  b->lds = std::max(qtree::keys_lds_1d(maxP, max_tiles),
+                    b->dmax > 1 ? qtree::keys_lds_nd(maxN, max_tiles) : (size_t)0);
+  if (b->lds > 160 * 1024) {
+    delete b;
+    return set_error(QTREE_EUNSUPPORTED, "batch needs more LDS than a workgroup has");
+  }
+  b->max_per_cu = 1;
+  while (b->max_per_cu < 8 && (size_t)(b->max_per_cu * 2) * b->lds <= 160 * 1024)
+    b->max_per_cu *= 2;
+  b->per_cu = std::min(2, b->max_per_cu);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    b->cus = prop.multiProcessorCount;
+
+  // scratch groups, then units (longest first within a group) and tiles
+  int64_t group_keys = 0, group_segs = 0;
+  const size_t per_chunk_key = sizeof(uint16_t) * qtree::kChunk;
+  std::vector<int> group_of(n);
+  Group g;
+  int gi = 0;
+  for (int i = 0; i < n; ++i) {
+    qtree::BatchContract& bc = b->hc[i];
+    const int64_t nk = (int64_t)bc.n * bc.chunks;
+    const size_t need = (size_t)nk * per_chunk_key + (size_t)nk * bc.seg_stride * 4;
+    if (need > scratch_bytes) {
+      delete b;
+      return set_error(QTREE_ENOMEM, "contract " + std::to_string(i) +
+                                         " alone exceeds the batch scratch");
+    }
+    const size_t used = (size_t)group_keys * per_chunk_key + (size_t)group_segs * 4;
+    if (i > 0 && used + need > scratch_bytes) {
+      ++gi;
+      group_keys = 0;
+      group_segs = 0;
+    }
+    bc.chunk_base = group_keys;
+    bc.seg_base = group_segs;
+    group_keys += nk;
+    group_segs += nk * bc.seg_stride;
+    group_of[i] = gi;
+  }
+  size_t scratch_keys = 0, scratch_segs = 0;
+  {
+    // size of the largest group
+    std::vector<int64_t> gk(gi + 1, 0), gs(gi + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      const qtree::BatchContract& bc = b->hc[i];
+      gk[group_of[i]] = std::max<int64_t>(gk[group_of[i]], bc.chunk_base + (int64_t)bc.n * bc.chunks);
+      gs[group_of[i]] = std::max<int64_t>(gs[group_of[i]],
+                                          bc.seg_base + (int64_t)bc.n * bc.chunks * bc.seg_stride);
+    }
+    for (int x = 0; x <= gi; ++x) {
+      scratch_keys = std::max(scratch_keys, (size_t)gk[x]);
+      scratch_segs = std::max(scratch_segs, (size_t)gs[x]);
+    }
+  }
+  for (int x = 0; x <= gi; ++x) {
+    // cost model: lane-slots per sample (1-D ~200; d >= 2 ~5 per grid point)
+    std::vector<qtree::BatchUnit> gu;
+    std::vector<double> gc;
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (group_of[i] != x) continue;
+      const qtree_plan* p = contracts[i].plan;
+      for (int k = 0; k < p->n; ++k) {
+        const double per = p->d == 1 ? 200.0 : 300.0 + 5.0 * p->d / 2.0 * (p->N[k] + p->N[k + 1]);
+        total += per * (double)contracts[i].M;
+      }
+    }
+    const double target = total / (8.0 * 2 * b->cus);  // ~8 units per workgroup slot
+    for (int i = 0; i < n; ++i) {
+      if (group_of[i] != x) continue;
+      const qtree_plan* p = contracts[i].plan;
+      const qtree::BatchContract& bc = b->hc[i];
+      for (int k = 0; k < p->n; ++k) {
+        const double per = p->d == 1 ? 200.0 : 300.0 + 5.0 * p->d / 2.0 * (p->N[k] + p->N[k + 1]);
+        const double chunk_cost = per * qtree::kChunk;
+        int step = (int)std::max(1.0, std::floor(target / chunk_cost));
+        step = std::min(step, bc.chunks);
+        for (int c0 = 0; c0 < bc.chunks; c0 += step) {
+          const int nc = std::min(step, bc.chunks - c0);
+          gu.push_back(qtree::BatchUnit{i, k, c0, nc});
+          gc.push_back(chunk_cost * nc);
+        }
+      }
+    }
+    std::vector<size_t> order(gu.size());
+    for (size_t u = 0; u < order.size(); ++u) order[u] = u;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a2, size_t b2) { return gc[a2] > gc[b2]; });
+    Group grp;
+    grp.unit_off = (int)b->units.size();
+    grp.n_units = (int)gu.size();
+    for (size_t u : order) {
+      b->units.push_back(gu[u]);
+      b->unit_cost.push_back(gc[u]);
+    }
+    grp.tile_off = (int)b->tiles.size();
+    for (int i = 0; i < n; ++i) {
+      if (group_of[i] != x) continue;
+      const qtree_plan* p = contracts[i].plan;
+      for (int k = 0; k < p->n; ++k) {
+        const int64_t entries = (int64_t)p->N[k] * p->N[k + 1];
+        const int st = (int)((entries + qtree::kSuper - 1) / qtree::kSuper);
+        for (int t = 0; t < st; ++t) b->tiles.push_back(qtree::BatchTile{i, k, t, 0});
+      }
+    }
+    grp.n_tiles = (int)b->tiles.size() - grp.tile_off;
+    b->groups.push_back(grp);
+  }
+
+  hipError_t e = upload(&b->d_contracts, b->hc);
+  if (e == hipSuccess) e = upload(&b->d_units, b->units);
+  if (e == hipSuccess) e = upload(&b->d_tiles, b->tiles);
+  if (e == hipSuccess) e = upload(&b->d_jobs, b->jobs);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_head), 256);
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&b->d_keys), scratch_keys * per_chunk_key + 16);
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&b->d_segs), scratch_segs * sizeof(uint32_t) + 16);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_error(e, "batch tables");
+  }
+  *out = b;
+  return QTREE_OK;
+}
+
+qtree_status qtree_batch_run(qtree_batch* b, double* V0_host, void* stream) {
+  if (!b) return set_error(QTREE_EINVAL, "batch is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (b->tuner && !b->tuned) {
+    qtree_status st = tune(b, s);
+    if (st != QTREE_OK) return st;
+    b->tuned = true;
+  }
+  hipError_t e;
+  if (b->exec) {
+    e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return hip_error(e, "graph launch");
+  } else {
+    e = enqueue_all(b, s);
+    if (e != hipSuccess) return hip_error(e, "batch launch");
+    if (b->use_graph && s != nullptr) {
+      // capture the same sequence for the next runs (capture does not execute)
+      hipGraph_t graph = nullptr;
+      e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t e2 = enqueue_all(b, s);
+        e = hipStreamEndCapture(s, &graph);
+        if (e2 != hipSuccess) e = e2;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+      if (graph) hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_error(e, "graph capture");
+    }
+  }
+  if (V0_host) {
+    int64_t at = 0;
+    for (const qtree_contract& C : b->c) {
+      e = hipMemcpy2DAsync(V0_host + at, sizeof(double), C.V,
+                           sizeof(double) * (size_t)C.plan->points, sizeof(double),
+                           (size_t)C.n_pay, hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return hip_error(e, "V0 copy");
+      at += C.n_pay;
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_error(e, "stream synchronize");
+  }
+  return QTREE_OK;
+}
+
+qtree_status qtree_batch_info(const qtree_batch* b, int64_t* units, int64_t* tiles,
+                              int32_t* groups, int32_t* per_cu) {
+  if (!b) return set_error(QTREE_EINVAL, "batch is NULL");
+  if (units) *units = (int64_t)b->units.size();
+  if (tiles) *tiles = (int64_t)b->tiles.size();
+  if (groups) *groups = (int32_t)b->groups.size();
+  if (per_cu) *per_cu = b->per_cu;
+  return QTREE_OK;
+}
+
+const char* qtree_batch_signature(const qtree_batch* b) { return b ? b->signature.c_str() : ""; }
+
+void qtree_batch_destroy(qtree_batch* b) { delete b; }
+
+}  // extern "C"

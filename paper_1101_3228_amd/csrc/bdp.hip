@@ -6,6 +6,7 @@
 // count block for up to kPay obstacle vectors at once, so the int32 counts
 // are read from HBM once per group of payoffs.  Also the obstacle phi_k on
 // the grid points.
+#include "qtree_batch.hpp"
 #include "qtree_internal.hpp"
 
 namespace qtree {
@@ -81,6 +82,68 @@ hipError_t launch_copy_last_layer(const BdpArgs& a, int64_t pt_n, int N_n, hipSt
   const int64_t total = (int64_t)a.n_pay * N_n;
   const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(copy_last_layer_kernel, dim3(blocks), dim3(kBlock), 0, s, a, pt_n, N_n);
+  return hipGetLastError();
+}
+
+// Batched BDP: workgroup b runs job b -- one contract and up to kPay of its
+// payoffs through all layers, a barrier between layers (the recursion is
+// sequential in k; contracts and payoff groups run in parallel).
+constexpr int kBdpBlock = 1024;
+
+__global__ __launch_bounds__(kBdpBlock) void bdp_batch_kernel(const BdpJob* jobs) {
+  const BdpJob J = jobs[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kW = kBdpBlock / 64;
+  const LayerDev& Ln = J.layers[J.n];
+  for (int t = threadIdx.x; t < J.nq * Ln.N; t += kBdpBlock) {
+    const int q = t / Ln.N, i = t - q * Ln.N;
+    const int64_t at = (int64_t)(J.q0 + q) * J.P + Ln.pt_off + i;
+    J.V[at] = J.phi[at];
+  }
+  for (int k = J.n - 1; k >= 0; --k) {
+    __syncthreads();
+    const LayerDev& L = J.layers[k];
+    const LayerDev& L1 = J.layers[k + 1];
+    const int32_t* cnt = J.counts + L.cnt_off;
+    for (int i = wave; i < L.N; i += kW) {
+      const int32_t* row = cnt + (int64_t)i * L.N1;
+      int64_t p = 0;
+      double s[kPay];
+#pragma unroll
+      for (int q = 0; q < kPay; ++q) s[q] = 0.0;
+      for (int j = lane; j < L.N1; j += 64) {
+        const int32_t c = row[j];
+        p += c;
+        if (c != 0) {
+          const double cd = (double)c;
+#pragma unroll
+          for (int q = 0; q < kPay; ++q)
+            if (q < J.nq) s[q] = fma(cd, J.V[(int64_t)(J.q0 + q) * J.P + L1.pt_off + j], s[q]);
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        p += __shfl_xor(p, off, 64);
+#pragma unroll
+        for (int q = 0; q < kPay; ++q) s[q] += __shfl_xor(s[q], off, 64);
+      }
+      if (lane < J.nq) {
+        double sq = s[0];
+#pragma unroll
+        for (int q = 1; q < kPay; ++q)
+          if (lane == q) sq = s[q];
+        const double cont = p > 0 ? sq / (double)p : 0.0;
+        const int64_t at = (int64_t)(J.q0 + lane) * J.P + L.pt_off + i;
+        const double f = J.phi[at];
+        J.V[at] = f > cont ? f : cont;
+      }
+    }
+  }
+}
+
+hipError_t launch_bdp_batch(const BdpJob* jobs, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bdp_batch_kernel, dim3((unsigned)n_jobs), dim3(kBdpBlock), 0, s, jobs);
   return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@
 // sampling and the cell searches sustain, and a count block of N_k x N_{k+1}
 // int32 (1 MB at N = 500) does not fit in LDS.  So:
 //
-//  pass A (fwd_keys_*): a workgroup draws a chunk of kChunk samples of one
+//  pass A (keys_chunk_*): a workgroup draws a chunk of kChunk samples of one
 //    layer (Philox -> Box-Muller -> AR(1) -> two cell searches, as in the
 //    one-pass kernels), forms the flat index key = i N_{k+1} + j, and sorts
 //    the keys by tile t = key >> kTileBits with a counting sort in LDS (count
@@ -15,12 +15,18 @@
 //    apart).  The chunk writes each key as its 16-bit offset inside its
 //    16384-entry super tile, tile by tile, with 16-byte stores, plus the
 //    segment starts.
-//  pass B (count_tiles): one workgroup per (layer, super tile) walks that
+//  pass B (count_tile): one workgroup per (layer, super tile) walks that
 //    super tile's segment (four consecutive tiles) in every chunk of the
 //    layer, increments a 16384-bin LDS histogram, and stores the super tile
-//    into the count block.  Each count is
-//    owned by exactly one workgroup, so the store is plain (it also replaces
-//    zeroing).  Integer counting makes the order of keys irrelevant.
+//    into the count block.  Each count is owned by exactly one workgroup, so
+//    the store is plain (it also replaces zeroing).  Integer counting makes
+//    the order of keys irrelevant.
+//
+// The same device routines serve one plan (fwd_keys_*, count_tiles) and a
+// batch of contracts (batch_keys, batch_count): the batch kernel is
+// persistent and pulls (contract, layer, chunks) units, longest first, from a
+// device work queue until it is empty.
+#include "qtree_batch.hpp"
 #include "qtree_internal.hpp"
 #include "qtree_rng.hpp"
 #include "qtree_search.hpp"
@@ -33,21 +39,30 @@ constexpr int kBlock = 256;
 constexpr int kKeys = kChunk / kBlock;  // keys per lane in pass A
 constexpr int kCountBlock = 1024;
 
-__device__ __forceinline__ bool unit_of_block_keys(const FwdArgs& a, int& k, int& chunk) {
-  int u;
-  if (a.xcd_map) {
-    const int b = (int)blockIdx.x;
-    const int slot = b >> 3;
-    if (slot >= a.units_per_xcd) return false;
-    u = (b & 7) * a.units_per_xcd + slot;
-  } else {
-    u = (int)blockIdx.x;
-  }
-  if (u >= a.units) return false;
-  k = u / a.chunks;
-  chunk = u - k * a.chunks;
-  return true;
-}
+// One pass-A job: chunk c of the samples [lo, hi) of layer k.
+struct KeysJob {
+  const LayerDev* L0;
+  const LayerDev* L1;
+  const float* mids;
+  const float4* pts;
+  uint32_t key0, key1, contract;
+  int k, c;
+  uint64_t lo, hi;
+  uint16_t* keys;  // kChunk slots of this chunk
+  uint32_t* seg;   // T + 1 segment starts of this chunk
+};
+
+// One pass-B job: super tile t of a layer whose chunks start at keys / seg.
+struct TileJob {
+  const LayerDev* L0;
+  const uint16_t* keys;
+  const uint32_t* seg;
+  int seg_stride;
+  int chunks;
+  int t;
+  int32_t* counts_k;  // count block of the layer
+  int first;
+};
 
 // Counting sort of a chunk's keys by tile, in LDS.  `tcount` holds T + 1
 // counters, `cursor` T, `stage` kChunk 16-bit slots.  Phase 1 counts keys
@@ -98,28 +113,29 @@ __device__ __forceinline__ void place_keys(const uint32_t* key, uint32_t* cursor
   }
 }
 
-__device__ __forceinline__ void write_chunk(const FwdArgs& a, int k, int c, int T,
-                                            const uint32_t* tcount, const uint16_t* stage) {
-  uint32_t* seg = a.segs + ((size_t)k * a.chunks + c) * a.seg_stride;
-  for (int t = threadIdx.x; t <= T; t += kBlock) seg[t] = tcount[t];
+__device__ __forceinline__ void sort_and_write(const KeysJob& j, const uint32_t* key, int T,
+                                               uint16_t* stage, uint32_t* tcount,
+                                               uint32_t* cursor) {
+  count_keys(key, tcount);
+  __syncthreads();
+  scan_tiles(tcount, cursor, T);
+  __syncthreads();
+  place_keys(key, cursor, stage);
+  __syncthreads();
+  for (int t = threadIdx.x; t <= T; t += kBlock) j.seg[t] = tcount[t];
   const uint32_t total = tcount[T];
-  uint4* out = reinterpret_cast<uint4*>(a.keys + ((size_t)k * a.chunks + c) * kChunk);
+  uint4* out = reinterpret_cast<uint4*>(j.keys);
   const uint4* src = reinterpret_cast<const uint4*>(stage);
   const uint32_t vecs = (total + 7) / 8;  // 8 keys per 16-byte store
   for (uint32_t v = threadIdx.x; v < vecs; v += kBlock) out[v] = src[v];
 }
 
-}  // namespace
-
-// Pass A, d = 1.  Chunk c of the batch covers the Philox blocks
+// Pass A, d = 1.  Chunk c covers the Philox blocks
 // [lo/2 + c kChunk/2, lo/2 + (c+1) kChunk/2); sample m = 2 block + h is live
-// when it lies in the batch [lo, hi).
-__global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
-  extern __shared__ float lds[];
-  int k, c;
-  if (!unit_of_block_keys(a, k, c)) return;
-  const LayerDev& L0 = a.layers[k];
-  const LayerDev& L1 = a.layers[k + 1];
+// when it lies in [lo, hi).
+__device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
+  const LayerDev& L0 = *j.L0;
+  const LayerDev& L1 = *j.L1;
   const int T = L0.tiles;
   float* mk = lds;
   float* mk1 = lds + L0.P;
@@ -127,25 +143,24 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds + ((L0.P + L1.P + 3) & ~3));
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
-  for (int i = threadIdx.x; i < L0.P; i += kBlock) mk[i] = a.mids[L0.aux_off + i];
-  for (int i = threadIdx.x; i < L1.P; i += kBlock) mk1[i] = a.mids[L1.aux_off + i];
+  for (int i = threadIdx.x; i < L0.P; i += kBlock) mk[i] = j.mids[L0.aux_off + i];
+  for (int i = threadIdx.x; i < L1.P; i += kBlock) mk1[i] = j.mids[L1.aux_off + i];
   for (int t = threadIdx.x; t <= T; t += kBlock) tcount[t] = 0;
   __syncthreads();
 
   const float mu = L0.mu[0], Lz = L0.L[0], A = L0.A[0], b = L0.b[0], Tk = L0.T[0];
   const int logP0 = L0.logP, logP1 = L1.logP;
   const uint32_t N1 = (uint32_t)L0.N1;
-  const uint64_t lo = a.m0, hi = a.m0 + a.M;
-  const uint64_t pb = (lo >> 1) + (uint64_t)c * (kChunk / 2);
+  const uint64_t pb = (j.lo >> 1) + (uint64_t)j.c * (kChunk / 2);
   uint32_t key[kKeys];
 #pragma unroll
   for (int e = 0; e < kKeys / 2; ++e) {
     const uint64_t blk = pb + (uint64_t)e * kBlock + threadIdx.x;
-    const U4 r = philox4x32_10(U4{(uint32_t)blk, (uint32_t)k, a.contract, 0u}, a.key0, a.key1);
+    const U4 r = philox4x32_10(U4{(uint32_t)blk, (uint32_t)j.k, j.contract, 0u}, j.key0, j.key1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const uint64_t m = 2 * blk + h;
-      const bool live = m >= lo && m < hi;
+      const bool live = m >= j.lo && m < j.hi;
       float z, eps;
       box_muller(h ? r.z : r.x, h ? r.w : r.y, z, eps);
       const float x = fmaf(Lz, z, mu);
@@ -154,36 +169,26 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
       key[2 * e + h] = live ? kk : 0xFFFFFFFFu;
     }
   }
-  count_keys(key, tcount);
-  __syncthreads();
-  scan_tiles(tcount, cursor, T);
-  __syncthreads();
-  place_keys(key, cursor, stage);
-  __syncthreads();
-  write_chunk(a, k, c, T, tcount, stage);
+  sort_and_write(j, key, T, stage, tcount, cursor);
 }
 
 // Pass A, d = 2, 3: S samples per lane share each LDS grid read.
 template <int D, int S>
-__global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
-  extern __shared__ float4 lds4[];
-  int k, c;
-  if (!unit_of_block_keys(a, k, c)) return;
-  const LayerDev& L0 = a.layers[k];
-  const LayerDev& L1 = a.layers[k + 1];
+__device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
+  const LayerDev& L0 = *j.L0;
+  const LayerDev& L1 = *j.L1;
   const int N0 = L0.N, N1 = L0.N1, T = L0.tiles;
   float4* gk = lds4;
   float4* gk1 = lds4 + N0;
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + N0 + N1);
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
-  for (int i = threadIdx.x; i < N0; i += kBlock) gk[i] = a.pts[L0.pt_off + i];
-  for (int i = threadIdx.x; i < N1; i += kBlock) gk1[i] = a.pts[L1.pt_off + i];
+  for (int i = threadIdx.x; i < N0; i += kBlock) gk[i] = j.pts[L0.pt_off + i];
+  for (int i = threadIdx.x; i < N1; i += kBlock) gk1[i] = j.pts[L1.pt_off + i];
   for (int t = threadIdx.x; t <= T; t += kBlock) tcount[t] = 0;
   __syncthreads();
 
-  const uint64_t lo = a.m0 + (uint64_t)c * kChunk;
-  const uint64_t hi = a.m0 + a.M;
+  const uint64_t lo = j.lo + (uint64_t)j.c * kChunk;
   uint32_t key[kKeys];
 #pragma unroll
   for (int r = 0; r < kKeys / S; ++r) {
@@ -192,9 +197,9 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const uint64_t m = lo + (uint64_t)(r * S + s) * kBlock + threadIdx.x;
-      live[s] = m < hi;
+      live[s] = m < j.hi;
       float z[D], e[D];
-      layer_normals<D>(a, k, live[s] ? m : a.m0, z, e);
+      layer_normals<D>(j.key0, j.key1, j.contract, j.k, live[s] ? m : j.lo, z, e);
       layer_pair<D>(L0, z, e, xs[s], ys[s]);
     }
     int ii[S], jj[S];
@@ -206,54 +211,33 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
       key[r * S + s] = live[s] ? kk : 0xFFFFFFFFu;
     }
   }
-  count_keys(key, tcount);
-  __syncthreads();
-  scan_tiles(tcount, cursor, T);
-  __syncthreads();
-  place_keys(key, cursor, stage);
-  __syncthreads();
-  write_chunk(a, k, c, T, tcount, stage);
+  sort_and_write(j, key, T, stage, tcount, cursor);
 }
 
-// Pass B: workgroup b owns super tile t of layer k (b = tile_off_k + t),
-// i.e. tiles [t kTilesPerSuper, (t+1) kTilesPerSuper) whose keys are one
-// contiguous segment of every chunk.  Segment bounds of kCountBlock chunks at
-// a time are fetched with one load per lane into LDS; each wave then walks
-// whole segments, 8 keys per lane per 16-byte load, adding into the
-// kSuper-bin LDS histogram.
-__global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
-  extern __shared__ uint32_t hist[];
-  uint32_t* sb = hist + kSuper;
-  uint32_t* se = sb + kCountBlock;
-  const int b = (int)blockIdx.x;
-  int lo = 0, hi = a.n - 1;  // largest k with tile_off_k <= b
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.layers[mid].tile_off <= b) lo = mid; else hi = mid - 1;
-  }
-  const int k = lo;
-  const LayerDev& L0 = a.layers[k];
-  const int t = b - L0.tile_off;
-  const int f0 = t * kTilesPerSuper;
+// Pass B for one super tile: tiles [t kTilesPerSuper, (t+1) kTilesPerSuper)
+// are one contiguous segment of every chunk.  Segment bounds of kCountBlock
+// chunks at a time are fetched with one load per lane into LDS; each wave
+// then walks kInFlight segments at once, 8 keys per lane per 16-byte load
+// (a chunk's key block is 16-byte aligned), adding into the kSuper-bin LDS
+// histogram; keys outside [s0, s1) are skipped.
+__device__ __forceinline__ void count_tile(const TileJob& j, uint32_t* hist, uint32_t* sb,
+                                           uint32_t* se) {
+  const LayerDev& L0 = *j.L0;
+  const int f0 = j.t * kTilesPerSuper;
   const int f1 = (f0 + kTilesPerSuper) < L0.tiles ? (f0 + kTilesPerSuper) : L0.tiles;
   for (int i = threadIdx.x; i < kSuper; i += kCountBlock) hist[i] = 0;
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  const uint32_t* segk = a.segs + (size_t)k * a.chunks * a.seg_stride;
-  const uint16_t* keysk = a.keys + (size_t)k * a.chunks * kChunk;
-  for (int c0 = 0; c0 < a.chunks; c0 += kCountBlock) {
+  constexpr int kWaves = kCountBlock / 64;
+  constexpr int kInFlight = 4;
+  for (int c0 = 0; c0 < j.chunks; c0 += kCountBlock) {
     __syncthreads();
     const int c = c0 + (int)threadIdx.x;
-    if (c < a.chunks) {
-      sb[threadIdx.x] = segk[(size_t)c * a.seg_stride + f0];
-      se[threadIdx.x] = segk[(size_t)c * a.seg_stride + f1];
+    if (c < j.chunks) {
+      sb[threadIdx.x] = j.seg[(size_t)c * j.seg_stride + f0];
+      se[threadIdx.x] = j.seg[(size_t)c * j.seg_stride + f1];
     }
     __syncthreads();
-    const int cn = (a.chunks - c0) < kCountBlock ? (a.chunks - c0) : kCountBlock;
-    // each wave takes kInFlight chunks at a time so that several segment
-    // loads are outstanding per lane; 16-byte loads of 8 keys each (a chunk's
-    // key block is 16-byte aligned), keys outside [s0, s1) skipped
-    constexpr int kWaves = kCountBlock / 64;
-    constexpr int kInFlight = 4;
+    const int cn = (j.chunks - c0) < kCountBlock ? (j.chunks - c0) : kCountBlock;
     for (int g = wave * kInFlight; g < cn; g += kWaves * kInFlight) {
       uint32_t s0[kInFlight], s1[kInFlight], v[kInFlight];
       const uint4* kv[kInFlight];
@@ -262,7 +246,7 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
         const int cc = g + u < cn ? g + u : g;
         s0[u] = g + u < cn ? sb[cc] : 0u;
         s1[u] = g + u < cn ? se[cc] : 0u;
-        kv[u] = reinterpret_cast<const uint4*>(keysk + (size_t)(c0 + cc) * kChunk);
+        kv[u] = reinterpret_cast<const uint4*>(j.keys + (size_t)(c0 + cc) * kChunk);
         v[u] = (s0[u] >> 3) + lane;
       }
       bool more = true;
@@ -292,15 +276,151 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
   }
   __syncthreads();
   const int64_t total = (int64_t)L0.N * L0.N1;
-  const int64_t base = (int64_t)t * kSuper;
+  const int64_t base = (int64_t)j.t * kSuper;
   const int bins = (int)((total - base) < kSuper ? (total - base) : kSuper);
-  int32_t* dst = a.counts + L0.cnt_off + base;
-  if (a.first_batch) {
+  int32_t* dst = j.counts_k + base;
+  if (j.first) {
     for (int i = threadIdx.x; i < bins; i += kCountBlock) dst[i] = (int32_t)hist[i];
   } else {
     for (int i = threadIdx.x; i < bins; i += kCountBlock) dst[i] += (int32_t)hist[i];
   }
 }
+
+__device__ __forceinline__ bool unit_of_block_keys(const FwdArgs& a, int& k, int& chunk) {
+  int u;
+  if (a.xcd_map) {
+    const int b = (int)blockIdx.x;
+    const int slot = b >> 3;
+    if (slot >= a.units_per_xcd) return false;
+    u = (b & 7) * a.units_per_xcd + slot;
+  } else {
+    u = (int)blockIdx.x;
+  }
+  if (u >= a.units) return false;
+  k = u / a.chunks;
+  chunk = u - k * a.chunks;
+  return true;
+}
+
+__device__ __forceinline__ KeysJob plan_job(const FwdArgs& a, int k, int c) {
+  KeysJob j;
+  j.L0 = &a.layers[k];
+  j.L1 = &a.layers[k + 1];
+  j.mids = a.mids;
+  j.pts = a.pts;
+  j.key0 = a.key0;
+  j.key1 = a.key1;
+  j.contract = a.contract;
+  j.k = k;
+  j.c = c;
+  j.lo = a.m0;
+  j.hi = a.m0 + a.M;
+  j.keys = a.keys + ((size_t)k * a.chunks + c) * kChunk;
+  j.seg = a.segs + ((size_t)k * a.chunks + c) * a.seg_stride;
+  return j;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- one plan
+
+__global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
+  extern __shared__ float lds[];
+  int k, c;
+  if (!unit_of_block_keys(a, k, c)) return;
+  keys_chunk_1d(plan_job(a, k, c), lds);
+}
+
+template <int D, int S>
+__global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
+  extern __shared__ float4 lds4[];
+  int k, c;
+  if (!unit_of_block_keys(a, k, c)) return;
+  keys_chunk_nd<D, S>(plan_job(a, k, c), lds4);
+}
+
+// Workgroup b owns super tile t of layer k (b = tile_off_k + t).
+__global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
+  extern __shared__ uint32_t hist[];
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = a.n - 1;  // largest k with tile_off_k <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.layers[mid].tile_off <= b) lo = mid; else hi = mid - 1;
+  }
+  const int k = lo;
+  TileJob j;
+  j.L0 = &a.layers[k];
+  j.keys = a.keys + (size_t)k * a.chunks * kChunk;
+  j.seg = a.segs + (size_t)k * a.chunks * a.seg_stride;
+  j.seg_stride = a.seg_stride;
+  j.chunks = a.chunks;
+  j.t = b - a.layers[k].tile_off;
+  j.counts_k = a.counts + a.layers[k].cnt_off;
+  j.first = a.first_batch;
+  count_tile(j, hist, hist + kSuper, hist + kSuper + kCountBlock);
+}
+
+// ------------------------------------------------------------- a batch
+
+// Persistent pass A over a work list of (contract, layer, chunk range)
+// units sorted by decreasing cost; each workgroup claims the next unit until
+// the list is exhausted (the claim counter is reset by batch_reset first).
+template <int DMAX>
+__global__ __launch_bounds__(kBlock) void batch_keys(BatchArgs a) {
+  extern __shared__ float4 lds4[];
+  __shared__ int unit_sh;
+  for (;;) {
+    if (threadIdx.x == 0) unit_sh = atomicAdd(a.head, 1);
+    __syncthreads();
+    const int u = unit_sh;
+    __syncthreads();
+    if (u >= a.n_units) return;
+    const BatchUnit U = a.units[u];
+    const BatchContract& C = a.contracts[U.c];
+    for (int c = U.chunk0; c < U.chunk0 + U.nchunks; ++c) {
+      KeysJob j;
+      j.L0 = &C.layers[U.k];
+      j.L1 = &C.layers[U.k + 1];
+      j.mids = C.mids;
+      j.pts = C.pts;
+      j.key0 = C.key0;
+      j.key1 = C.key1;
+      j.contract = C.contract;
+      j.k = U.k;
+      j.c = c;
+      j.lo = 0;
+      j.hi = C.M;
+      j.keys = a.keys + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
+      j.seg = a.segs + (size_t)C.seg_base + ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
+      if (C.d == 1) keys_chunk_1d(j, reinterpret_cast<float*>(lds4));
+      else if (DMAX >= 2 && C.d == 2) keys_chunk_nd<2, 4>(j, lds4);
+      else if (DMAX >= 3) keys_chunk_nd<3, 4>(j, lds4);
+      __syncthreads();
+    }
+  }
+}
+
+// Pass B of a batch: workgroup b handles tile record b.
+__global__ __launch_bounds__(kCountBlock) void batch_count(BatchArgs a) {
+  extern __shared__ uint32_t hist[];
+  const BatchTile T = a.tiles[blockIdx.x];
+  const BatchContract& C = a.contracts[T.c];
+  TileJob j;
+  j.L0 = &C.layers[T.k];
+  j.keys = a.keys + ((size_t)C.chunk_base + (size_t)T.k * C.chunks) * kChunk;
+  j.seg = a.segs + (size_t)C.seg_base + (size_t)T.k * C.chunks * (size_t)C.seg_stride;
+  j.seg_stride = C.seg_stride;
+  j.chunks = C.chunks;
+  j.t = T.t;
+  j.counts_k = C.counts + C.layers[T.k].cnt_off;
+  j.first = 1;
+  count_tile(j, hist, hist + kSuper, hist + kSuper + kCountBlock);
+}
+
+__global__ void batch_reset(int* head) { *head = 0; }
+
+// ------------------------------------------------------------- launchers
 
 static dim3 keys_grid(const FwdArgs& a) {
   return a.xcd_map ? dim3((unsigned)(8 * a.units_per_xcd)) : dim3((unsigned)a.units);
@@ -313,21 +433,28 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+size_t keys_lds_1d(int maxP, int max_tiles) {
+  return sizeof(float) * (2 * (size_t)maxP + 4) + sizeof(uint16_t) * kChunk +
+         sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
+}
+
+size_t keys_lds_nd(int maxN, int max_tiles) {
+  return sizeof(float4) * 2 * (size_t)maxN + sizeof(uint16_t) * kChunk +
+         sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
+}
+
 hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
-  // staged keys + tile counters + cursors + scan partials
-  const size_t tiles_bytes =
-      sizeof(uint16_t) * kChunk + sizeof(uint32_t) * (size_t)(2 * a.max_tiles + 1);
   hipError_t e;
   if (a.d == 1) {
-    const size_t lds = sizeof(float) * (2 * (size_t)a.maxP + 4) + tiles_bytes;
+    const size_t lds = keys_lds_1d(a.maxP, a.max_tiles);
     if ((e = allow_lds(fwd_keys_1d, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(fwd_keys_1d, keys_grid(a), dim3(kBlock), lds, s, a);
   } else if (a.d == 2) {
-    const size_t lds = sizeof(float4) * 2 * (size_t)a.maxN + tiles_bytes;
+    const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
     if ((e = allow_lds(fwd_keys_nd<2, 4>, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL((fwd_keys_nd<2, 4>), keys_grid(a), dim3(kBlock), lds, s, a);
   } else {
-    const size_t lds = sizeof(float4) * 2 * (size_t)a.maxN + tiles_bytes;
+    const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
     if ((e = allow_lds(fwd_keys_nd<3, 4>, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL((fwd_keys_nd<3, 4>), keys_grid(a), dim3(kBlock), lds, s, a);
   }
@@ -339,6 +466,27 @@ hipError_t launch_count_tiles(const FwdArgs& a, hipStream_t s) {
   hipError_t e = allow_lds(count_tiles, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(count_tiles, dim3((unsigned)a.total_tiles), dim3(kCountBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_forward(const BatchArgs& a, int dmax, int grid, size_t lds,
+                                hipStream_t s) {
+  hipError_t e;
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, a.head);
+  if (dmax <= 1) {
+    if ((e = allow_lds(batch_keys<1>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_keys<1>, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+  } else if (dmax == 2) {
+    if ((e = allow_lds(batch_keys<2>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_keys<2>, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+  } else {
+    if ((e = allow_lds(batch_keys<3>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_keys<3>, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t lds_b = sizeof(uint32_t) * (kSuper + 2 * kCountBlock);
+  if ((e = allow_lds(batch_count, lds_b)) != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_count, dim3((unsigned)a.n_tiles), dim3(kCountBlock), lds_b, s, a);
   return hipGetLastError();
 }
 

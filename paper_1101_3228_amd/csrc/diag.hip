@@ -28,7 +28,7 @@ __global__ void layer_samples_kernel(FwdArgs a, int k, int64_t count, float* x, 
   if (i >= count) return;
   const uint64_t m = a.m0 + (uint64_t)i;
   float z[D], e[D], xs[D], ys[D];
-  layer_normals<D>(a, k, m, z, e);
+  layer_normals<D>(a.key0, a.key1, a.contract, k, m, z, e);
   layer_pair<D>(a.layers[k], z, e, xs, ys);
 #pragma unroll
   for (int c = 0; c < D; ++c) {

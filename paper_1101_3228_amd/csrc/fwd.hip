@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void fwd_layer_nd(FwdArgs a) {
       const uint64_t m = base + (uint64_t)s * kBlock + threadIdx.x;
       live[s] = m < hi;
       float z[D], e[D];
-      layer_normals<D>(a, k, (uint32_t)(live[s] ? m : lo), z, e);
+      layer_normals<D>(a.key0, a.key1, a.contract, k, live[s] ? m : lo, z, e);
       layer_pair<D>(L0, z, e, xs[s], ys[s]);
     }
     int ii[S], jj[S];

@@ -1,0 +1,64 @@
+// Device tables of a batch of contracts (many plans in one launch).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qtree_internal.hpp"
+
+namespace qtree {
+
+// One contract: its plan tables, its counts and where its pass-A keys live
+// in the batch scratch of its group.
+struct BatchContract {
+  const LayerDev* layers;
+  const float* mids;
+  const float4* pts;
+  int32_t* counts;
+  uint32_t key0, key1, contract;
+  int32_t d, n;
+  uint64_t M;            // samples per layer, from sample 0
+  int64_t chunk_base;    // first chunk slot of layer 0 in the group scratch
+  int64_t seg_base;      // first segment word of layer 0 in the group scratch
+  int32_t chunks;        // chunks per layer
+  int32_t seg_stride;    // tiles of the contract's largest count block + 1
+};
+
+// Pass-A work unit: chunks [chunk0, chunk0 + nchunks) of layer k of contract c.
+struct BatchUnit {
+  int32_t c, k, chunk0, nchunks;
+};
+
+// Pass-B job: super tile t of layer k of contract c.
+struct BatchTile {
+  int32_t c, k, t, pad_;
+};
+
+struct BatchArgs {
+  const BatchContract* contracts;
+  const BatchUnit* units;  // this group's units (longest first)
+  const BatchTile* tiles;  // this group's tiles
+  int32_t n_units, n_tiles;
+  int* head;               // claim counter of the persistent pass A
+  uint16_t* keys;
+  uint32_t* segs;
+};
+
+hipError_t launch_batch_forward(const BatchArgs& a, int dmax, int grid, size_t lds,
+                                hipStream_t s);
+size_t keys_lds_1d(int maxP, int max_tiles);
+size_t keys_lds_nd(int maxN, int max_tiles);
+
+// BDP of one contract for payoffs [q0, q0 + nq) (nq <= 16), all layers, in
+// one workgroup.
+struct BdpJob {
+  const LayerDev* layers;
+  const int32_t* counts;
+  const double* phi;
+  double* V;
+  int64_t P;
+  int32_t n, q0, nq, pad_;
+};
+
+hipError_t launch_bdp_batch(const BdpJob* jobs, int n_jobs, hipStream_t s);
+
+}  // namespace qtree

@@ -1,0 +1,32 @@
+// Host-side plan object shared by the C-ABI implementation files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "qtree.h"
+#include "qtree_internal.hpp"
+
+struct qtree_plan {
+  int d = 0, n = 0;
+  std::vector<int32_t> N;
+  std::vector<int64_t> pt_off, cnt_off, aux_off;
+  std::vector<int32_t> P;
+  int64_t points = 0, entries = 0, mids_total = 0;
+  int32_t maxN = 0, maxP = 0;
+  char* ws = nullptr;
+  qtree::WsLayout lay{};
+  int64_t tune_chunk = 0;  // 0: automatic
+  int32_t tune_xcd_map = 1;
+  int32_t tune_count = 0;  // 0 automatic, 1 direct atomics, 2 two-pass
+  int32_t max_tiles = 0, total_tiles = 0;
+  int64_t batch_chunks = 0;      // scratch chunks per layer per pass
+  bool two_pass_ok = false;
+  hipEvent_t trace_keys = nullptr;
+};
+
+namespace qtree {
+// Record a failure for qtree_last_error and return its status.
+qtree_status set_error(qtree_status s, const std::string& msg);
+}  // namespace qtree

@@ -70,21 +70,21 @@ __device__ __forceinline__ void argmin_scan(const float4* __restrict__ g, int N,
 // block m >> 1 and the Box-Muller pair m & 1; d = 2 block m; d = 3 blocks
 // (m, tag 0) and (m, tag 16).
 template <int D>
-__device__ __forceinline__ void layer_normals(const FwdArgs& a, int k, uint64_t m, float* z,
-                                              float* e) {
+__device__ __forceinline__ void layer_normals(uint32_t key0, uint32_t key1, uint32_t contract,
+                                              int k, uint64_t m, float* z, float* e) {
   if (D == 1) {
-    const U4 r = philox4x32_10(U4{(uint32_t)(m >> 1), (uint32_t)k, a.contract, 0u}, a.key0, a.key1);
+    const U4 r = philox4x32_10(U4{(uint32_t)(m >> 1), (uint32_t)k, contract, 0u}, key0, key1);
     if (m & 1) box_muller(r.z, r.w, z[0], e[0]);
     else box_muller(r.x, r.y, z[0], e[0]);
   } else if (D == 2) {
-    const U4 r = philox4x32_10(U4{(uint32_t)m, (uint32_t)k, a.contract, 0u}, a.key0, a.key1);
+    const U4 r = philox4x32_10(U4{(uint32_t)m, (uint32_t)k, contract, 0u}, key0, key1);
     box_muller(r.x, r.y, z[0], z[1]);
     box_muller(r.z, r.w, e[0], e[1]);
   } else {
-    const U4 r = philox4x32_10(U4{(uint32_t)m, (uint32_t)k, a.contract, 0u}, a.key0, a.key1);
+    const U4 r = philox4x32_10(U4{(uint32_t)m, (uint32_t)k, contract, 0u}, key0, key1);
     box_muller(r.x, r.y, z[0], z[1]);
     box_muller(r.z, r.w, z[2], e[0]);
-    const U4 r2 = philox4x32_10(U4{(uint32_t)m, (uint32_t)k, a.contract, 16u}, a.key0, a.key1);
+    const U4 r2 = philox4x32_10(U4{(uint32_t)m, (uint32_t)k, contract, 16u}, key0, key1);
     box_muller(r2.x, r2.y, e[1], e[2]);
   }
 }

@@ -145,3 +145,33 @@ def contract_box(rng: np.random.Generator, count: int, d: int = 1):
         n=rng.integers(10, 101, count),
         rho=(rng.uniform(-0.5, 0.9, count) if d > 1 else np.zeros(count)),
     )
+
+
+def batch_contracts(count: int, seed: int = 0x5EED0000, n_range=(10, 100),
+                    N_range=(50, 2000), M: int = 1_000_000, shrink: float = 1.0):
+    """Uneven contracts: per contract d alternating 1 / 2, n uniform in
+    n_range, N_max log-uniform in N_range, per-layer sizes
+    N_k = round(N_min + (N_max - N_min) sqrt(k/n)) with N_min = max(10, N_max/10)
+    (2-D: near-square product shapes).  `shrink` scales n and N down for tests."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(count):
+        d = 1 + (c % 2)
+        n = max(2, int(round(rng.integers(n_range[0], n_range[1] + 1) * shrink)))
+        Nmax = int(round(np.exp(rng.uniform(np.log(N_range[0]), np.log(N_range[1]))) * shrink))
+        Nmax = max(Nmax, 4)
+        Nmin = max(2, int(round(max(10 * shrink, Nmax / 10))))
+        sizes = [1]
+        for k in range(1, n + 1):
+            Nk = int(round(Nmin + (Nmax - Nmin) * np.sqrt(k / n)))
+            if d == 1:
+                sizes.append(max(Nk, 1))
+            else:
+                a = max(1, int(np.floor(np.sqrt(Nk))))
+                sizes.append((a, max(1, Nk // a)))
+        T = float(rng.uniform(0.25, 2.0))
+        rho = float(rng.uniform(-0.5, 0.9)) if d == 2 else 0.0
+        out.append(dict(d=d, n=n, sizes=sizes, T=T, rho=rho, M=M,
+                        sigma=float(rng.uniform(0.1, 0.4)), K_over_S0=float(rng.uniform(0.8, 1.2)),
+                        r=float(rng.uniform(0.0, 0.1))))
+    return out

@@ -1,0 +1,86 @@
+"""GPU checks of the batched path: many uneven contracts in one persistent
+launch give the same counts (bit-exact) and values as one plan at a time;
+graph replays reproduce the eager run; scratch groups and the tuner cache."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1101_3228_amd as qt  # noqa: E402
+
+
+def _contracts(count, shrink, M, seed=7):
+    specs = synth.batch_contracts(count, seed=seed, M=M, shrink=shrink)
+    items = []
+    for i, sp in enumerate(specs):
+        model = synth.bm_model(sp["d"], sp["n"], T=sp["T"], rho=sp["rho"])
+        grid, N = synth.layer_grids(model, sp["sizes"])
+        plan = qt.Plan(model, grid, N, batch_samples=1)
+        kinds = [qt.PUT, qt.PUT | qt.EUROPEAN] if sp["d"] == 1 else [qt.MAX_CALL]
+        phi = torch.stack([plan.payoff(k, 100.0, 100.0 * sp["K_over_S0"], sp["r"], sp["T"],
+                                       [sp["sigma"], sp["sigma"] * 1.2]) for k in kinds])
+        items.append(dict(plan=plan, M=sp["M"], seed=synth.SEED_BASE + i, contract_id=i,
+                          counts=plan.new_counts(), phi=phi, V=torch.empty_like(phi),
+                          model=model, grid=grid, N=N))
+    return items
+
+
+def _single(items):
+    ref_counts, ref_v0 = [], []
+    for it in items:
+        plan = it["plan"]
+        c = plan.transitions(it["M"], it["seed"], contract=it["contract_id"])
+        V0, _ = plan.bdp(c, it["phi"])
+        ref_counts.append(c.cpu().numpy().copy())
+        ref_v0.append(V0)
+    return ref_counts, np.concatenate(ref_v0)
+
+
+def test_batch_equals_one_plan_at_a_time():
+    print("[gpu-case] batch vs single", flush=True)
+    items = _contracts(12, shrink=0.12, M=60_001)
+    ref_counts, ref_v0 = _single(items)
+    batch = qt.Batch(items)
+    info = batch.info()
+    assert info["units"] >= sum(it["plan"].n for it in items)
+    V0 = batch.run()
+    for it, rc in zip(items, ref_counts):
+        assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), rc)
+    assert np.allclose(V0, ref_v0, rtol=1e-12, atol=0)
+    # and against the oracle for two contracts (one 1-D, one 2-D)
+    for it in items[:2]:
+        sp = it["model"]
+        mdl = O.Model(sp["d"], sp["n"], sp["A"], sp["b"], sp["T"], sp["mu"], sp["L"], sp["x0"])
+        ref = O.transitions(mdl, it["grid"], it["N"], it["M"], seed=it["seed"],
+                            contract=it["contract_id"], nthreads=8)
+        assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), ref)
+
+
+def test_batch_scratch_groups_and_graph_replay(tmp_path):
+    print("[gpu-case] batch groups + graph", flush=True)
+    items = _contracts(9, shrink=0.1, M=40_000, seed=11)
+    ref_counts, ref_v0 = _single(items)
+    tuner = qt.Tuner(str(tmp_path / "tune.txt"))
+    stream = torch.cuda.Stream()
+    batch = qt.Batch(items, tuner=tuner, scratch_bytes=3 << 20, graph=True)
+    assert batch.info()["groups"] > 1
+    for rep in range(4):
+        for it in items:                      # eager work between replays
+            it["counts"].fill_(-1)
+            it["V"].fill_(0.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            V0 = batch.run(stream=stream)
+        for it, rc in zip(items, ref_counts):
+            assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), rc), rep
+        assert np.allclose(V0, ref_v0, rtol=1e-12, atol=0), rep
+    assert tuner.lookup(batch.signature) >= 1
+    assert os.path.exists(tmp_path / "tune.txt")
+    again = qt.Tuner(str(tmp_path / "tune.txt"))
+    assert again.lookup(batch.signature) == tuner.lookup(batch.signature)
