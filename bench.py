@@ -29,6 +29,12 @@ import time
 
 import numpy as np
 
+
+def log(msg: str) -> None:
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -103,6 +109,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
+    ap.add_argument("--workload", choices=("c2", "c3", "batch"), default="c2",
+                    help="c2 (default): the 1-D time-layer workload of the headline metric; "
+                         "c3: 2-D max-call, n=30, N=2000, M=1e7; batch: 256 uneven "
+                         "1-D/2-D contracts, M=1e6 each, one batched run per step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -121,6 +131,11 @@ def main():
                                    "forward step is measured on a single MI355X "
                                    "(multi-GPU sharding is a design note only)"}))
         sys.exit(2)
+
+    if args.workload == "c3":
+        return run_c3(args)
+    if args.workload == "batch":
+        return run_batch(args)
 
     import torch
     import paper_1101_3228_amd as qt
@@ -220,6 +235,152 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, grid, N, args.cpu_pairs)
+    print(json.dumps(out), flush=True)
+
+
+# Algorithmic VALU lane-slots of one d = 2 pair, excluding the searches:
+# Philox 100, two Box-Muller 142, AR(1) 12 FMA; each grid point of the two
+# searches costs 2 FMA + 1/2 of a 3-input min = 2.5 lane-slots.
+ALG_SLOTS_2D_PAIR = 100 + 142 + 12
+ALG_SLOTS_2D_POINT = 2.5
+
+
+def run_c3(args):
+    """2-D max-call state, n = 30, N = 2000 (40 x 50 product of Lloyd grids
+    mapped by sqrt(t_k) chol(R)), rho = 0.3, M = 1e7 pairs per layer; BDP of
+    the American and European max-call (sigma 0.2 / 0.3)."""
+    import torch
+    import paper_1101_3228_amd as qt
+    import synth
+    torch.cuda.set_device(0)
+    n, M = 30, 10_000_000
+    spec = synth.bm_model(2, n, T=MATURITY, rho=0.3)
+    grid, N = synth.layer_grids(spec, [1] + [(40, 50)] * n, base=qt.gauss_quantizer)
+    plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M)
+    counts = plan.new_counts()
+    s_fwd = torch.cuda.current_stream()
+    ev_keys = torch.cuda.Event(enable_timing=True)
+    ev_keys.record(s_fwd)
+
+    def step(i, ev=None):
+        if ev is not None:
+            ev[0].record(s_fwd)
+        plan.transitions(M, 0x5EED0000 + i, counts=counts, stream=s_fwd)
+        if ev is not None:
+            ev[1].record(s_fwd)
+        phi = plan.payoff_batch([qt.MAX_CALL, qt.MAX_CALL | qt.EUROPEAN], S0, S0, RATE,
+                                MATURITY, [[0.2, 0.3], [0.2, 0.3]], stream=s_fwd)
+        return plan.bdp(counts, phi, want_v0=False, stream=s_fwd)[1]
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
+    for e in evs:
+        e[1].record(s_fwd)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(s_fwd)
+    for i in range(args.steps):
+        plan.trace(evs[i][1])
+        V = step(i, (evs[i][0], evs[i][2]))
+    plan.trace(None)
+    t1.record(s_fwd)
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+    keys_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in evs]))
+    pairs = n * M
+    points = sum(int(N[k]) + int(N[k + 1]) for k in range(n)) * M
+    alg = ALG_SLOTS_2D_PAIR * pairs + ALG_SLOTS_2D_POINT * points
+    achieved = alg / (keys_ms * 1e-3)
+    V0 = V[:, 0].cpu().numpy()
+    out = {
+        "metric": "MC transition samples/s (cell search+count)",
+        "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, int32 counts, f64 BDP", "data": "synthetic",
+        "config": {"workload": "2-D max-call tree, time-layer parallel: n=30 layers, "
+                               "N=2000 (40x50 Lloyd product) points/layer, M=1e7 pairs/layer",
+                   "layers": n, "points_per_layer": 2000, "pairs_per_layer": M},
+        "forward_ms": fwd_ms, "sampling_pass_ms": keys_ms,
+        "paper_convention_gflops": 6.0 * points / (keys_ms * 1e-3) / 1e9,
+        "V0_american_european": [float(V0[0]), float(V0[1])],
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "kernel": "fwd_keys_nd<2,4>"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(args):
+    """256 contracts with uneven n in [10, 100] and N_k in [50, 2000], d
+    alternating 1 / 2, M = 1e6 pairs per layer each, two payoffs per contract;
+    one batched run (persistent sampling launch, histogram launch, BDP launch,
+    replayed as a hipGraph) per step."""
+    import torch
+    import paper_1101_3228_amd as qt
+    import synth
+    torch.cuda.set_device(0)
+    t_prep = time.perf_counter()
+    specs = synth.batch_contracts(256, M=1_000_000)
+    qcache = {}
+
+    def q(Nv):
+        if Nv not in qcache:
+            qcache[Nv] = qt.gauss_quantizer(Nv)
+        return qcache[Nv]
+    items = []
+    for i, sp in enumerate(specs):
+        model = synth.bm_model(sp["d"], sp["n"], T=sp["T"], rho=sp["rho"])
+        grid, N = synth.layer_grids(model, sp["sizes"], base=q)
+        plan = qt.Plan(model, grid, N, device="cuda:0", batch_samples=1)
+        kinds = [qt.PUT, qt.PUT | qt.EUROPEAN] if sp["d"] == 1 else \
+            [qt.MAX_CALL, qt.MAX_CALL | qt.EUROPEAN]
+        phi = plan.payoff_batch(kinds, S0, S0 * sp["K_over_S0"], sp["r"], sp["T"],
+                                [[sp["sigma"], sp["sigma"] * 1.2]] * 2)
+        items.append(dict(plan=plan, M=sp["M"], seed=0x5EED0000 + i, contract_id=i,
+                          counts=plan.new_counts(), phi=phi, V=torch.empty_like(phi)))
+        if (i + 1) % 32 == 0:
+            log(f"prepared {i + 1}/{len(specs)} contracts ({time.perf_counter() - t_prep:.1f} s)")
+    tuner = qt.Tuner(os.environ.get("QTREE_TUNE_CACHE"))
+    stream = torch.cuda.Stream()
+    batch = qt.Batch(items, tuner=tuner, scratch_bytes=40 << 30, graph=True)
+    prep_s = time.perf_counter() - t_prep
+    log(f"batch planned ({prep_s:.1f} s)")
+    with torch.cuda.stream(stream):
+        for w in range(max(args.warmup, 2)):     # first run tunes and captures the graph
+            batch.run(want_v0=False, stream=stream)
+            torch.cuda.synchronize()
+            log(f"warm-up run {w + 1} done")
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(args.steps):
+            batch.run(want_v0=False, stream=stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        V0 = batch.run(want_v0=True, stream=stream)
+    ms_step = t0.elapsed_time(t1) / args.steps
+    pairs = sum(sp["n"] * sp["M"] for sp in specs)
+    options = sum(it["phi"].shape[0] for it in items)
+    info = batch.info()
+    out = {
+        "metric": "MC transition samples/s (cell search+count); options/s (tree)",
+        "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, int32 counts, f64 BDP", "data": "synthetic",
+        "config": {"workload": "batch of 256 contracts, d alternating 1/2, n in [10,100], "
+                               "N_k in [50,2000], M=1e6 pairs/layer each, 2 payoffs each",
+                   "contracts": len(items), "pairs": pairs, "options": options},
+        "options_per_s": options / (ms_step * 1e-3),
+        "batch": info, "prep_s": prep_s,
+        "V0_mean": float(np.mean(V0)),
+    }
     print(json.dumps(out), flush=True)
 
 

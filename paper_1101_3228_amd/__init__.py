@@ -212,8 +212,9 @@ class Plan:
         n = kinds.size
         arr = [np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), (n,)))
                for v in (S0, K, r, T)]
-        sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, np.float64).reshape(n, -1),
-                                                   (n, self.d)), np.float64)
+        sig = np.asarray(sigma, np.float64).reshape(n, -1)
+        sig = np.ascontiguousarray(np.broadcast_to(sig[:, :self.d] if sig.shape[1] >= self.d
+                                                   else sig, (n, self.d)), np.float64)
         if out is None:
             out = torch.empty((n, self.points), dtype=torch.float64, device=self.workspace.device)
         _check(lib().qtree_payoff_batch(self._h, n, _np_ptr(kinds), *(_np_ptr(v) for v in arr),

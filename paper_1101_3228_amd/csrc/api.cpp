@@ -75,8 +75,10 @@ size_t keys_lds_bytes(int d, int n, const int32_t* N) {
     maxN = N[k] > maxN ? N[k] : maxN;
     maxP = next_pow2(N[k]) > maxP ? next_pow2(N[k]) : maxP;
   }
-  const size_t grids = d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)maxN;
-  return grids + sizeof(uint16_t) * kChunk +
+  const size_t grids =
+      d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)(maxN + kScanTile);
+  // d >= 2 keeps a chunk's 32-bit keys in LDS (reused as the 16-bit staging)
+  return grids + (d == 1 ? sizeof(uint16_t) : sizeof(uint32_t)) * kChunk +
          sizeof(uint32_t) * (2 * (size_t)max_tiles_of(n, N) + 1 + 256);
 }
 

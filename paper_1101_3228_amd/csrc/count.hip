@@ -35,8 +35,8 @@ namespace qtree {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kKeys = kChunk / kBlock;  // keys per lane in pass A
+constexpr int kBlock = 256;      // pass-A workgroup, d = 1
+constexpr int kBlockNd = 512;    // pass-A workgroup, d >= 2 (two waves per SIMD under one grid pair)
 constexpr int kCountBlock = 1024;
 
 // One pass-A job: chunk c of the samples [lo, hi) of layer k.
@@ -69,9 +69,10 @@ struct TileJob {
 // per tile; the exclusive scan gives each tile's segment start; phase 2
 // places every key at its tile's cursor; the staged chunk is then copied to
 // its scratch slot with wide stores, and the segment starts with it.
+template <int KB>
 __device__ __forceinline__ void count_keys(const uint32_t* key, uint32_t* tcount) {
 #pragma unroll
-  for (int e = 0; e < kKeys; ++e)
+  for (int e = 0; e < kChunk / KB; ++e)
     if (key[e] != 0xFFFFFFFFu) atomicAdd(&tcount[key[e] >> kTileBits], 1u);
 }
 
@@ -102,10 +103,11 @@ __device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, i
   if (lane == 63) tcount[T] = incl;
 }
 
+template <int KB>
 __device__ __forceinline__ void place_keys(const uint32_t* key, uint32_t* cursor,
                                            uint16_t* stage) {
 #pragma unroll
-  for (int e = 0; e < kKeys; ++e) {
+  for (int e = 0; e < kChunk / KB; ++e) {
     if (key[e] != 0xFFFFFFFFu) {
       const uint32_t pos = atomicAdd(&cursor[key[e] >> kTileBits], 1u);
       stage[pos] = (uint16_t)(key[e] & (kSuper - 1));
@@ -113,27 +115,30 @@ __device__ __forceinline__ void place_keys(const uint32_t* key, uint32_t* cursor
   }
 }
 
+template <int KB>
 __device__ __forceinline__ void sort_and_write(const KeysJob& j, const uint32_t* key, int T,
                                                uint16_t* stage, uint32_t* tcount,
                                                uint32_t* cursor) {
-  count_keys(key, tcount);
+  count_keys<KB>(key, tcount);
   __syncthreads();
   scan_tiles(tcount, cursor, T);
   __syncthreads();
-  place_keys(key, cursor, stage);
+  place_keys<KB>(key, cursor, stage);
   __syncthreads();
-  for (int t = threadIdx.x; t <= T; t += kBlock) j.seg[t] = tcount[t];
+  for (int t = threadIdx.x; t <= T; t += KB) j.seg[t] = tcount[t];
   const uint32_t total = tcount[T];
   uint4* out = reinterpret_cast<uint4*>(j.keys);
   const uint4* src = reinterpret_cast<const uint4*>(stage);
   const uint32_t vecs = (total + 7) / 8;  // 8 keys per 16-byte store
-  for (uint32_t v = threadIdx.x; v < vecs; v += kBlock) out[v] = src[v];
+  for (uint32_t v = threadIdx.x; v < vecs; v += KB) out[v] = src[v];
 }
 
 // Pass A, d = 1.  Chunk c covers the Philox blocks
 // [lo/2 + c kChunk/2, lo/2 + (c+1) kChunk/2); sample m = 2 block + h is live
 // when it lies in [lo, hi).
+template <int KB>
 __device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
+  constexpr int kKeys = kChunk / KB;
   const LayerDev& L0 = *j.L0;
   const LayerDev& L1 = *j.L1;
   const int T = L0.tiles;
@@ -143,9 +148,9 @@ __device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds + ((L0.P + L1.P + 3) & ~3));
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
-  for (int i = threadIdx.x; i < L0.P; i += kBlock) mk[i] = j.mids[L0.aux_off + i];
-  for (int i = threadIdx.x; i < L1.P; i += kBlock) mk1[i] = j.mids[L1.aux_off + i];
-  for (int t = threadIdx.x; t <= T; t += kBlock) tcount[t] = 0;
+  for (int i = threadIdx.x; i < L0.P; i += KB) mk[i] = j.mids[L0.aux_off + i];
+  for (int i = threadIdx.x; i < L1.P; i += KB) mk1[i] = j.mids[L1.aux_off + i];
+  for (int t = threadIdx.x; t <= T; t += KB) tcount[t] = 0;
   __syncthreads();
 
   const float mu = L0.mu[0], Lz = L0.L[0], A = L0.A[0], b = L0.b[0], Tk = L0.T[0];
@@ -155,7 +160,7 @@ __device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
   uint32_t key[kKeys];
 #pragma unroll
   for (int e = 0; e < kKeys / 2; ++e) {
-    const uint64_t blk = pb + (uint64_t)e * kBlock + threadIdx.x;
+    const uint64_t blk = pb + (uint64_t)e * KB + threadIdx.x;
     const U4 r = philox4x32_10(U4{(uint32_t)blk, (uint32_t)j.k, j.contract, 0u}, j.key0, j.key1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -169,49 +174,61 @@ __device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
       key[2 * e + h] = live ? kk : 0xFFFFFFFFu;
     }
   }
-  sort_and_write(j, key, T, stage, tcount, cursor);
+  sort_and_write<KB>(j, key, T, stage, tcount, cursor);
 }
 
-// Pass A, d = 2, 3: S samples per lane share each LDS grid read.
-template <int D, int S>
+// Pass A, d = 2, 3: S samples per lane share each LDS grid read.  The rounds
+// are not unrolled (their search state stays in registers); each round's
+// keys go to an LDS buffer that becomes the sort's staging area once the
+// keys are back in registers.
+template <int D, int S, int KB>
 __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
+  constexpr int kKeys = kChunk / KB;
   const LayerDev& L0 = *j.L0;
   const LayerDev& L1 = *j.L1;
   const int N0 = L0.N, N1 = L0.N1, T = L0.tiles;
+  // both grids padded to whole scan tiles with records whose key is +inf
+  const int P0 = (N0 + kScanTile - 1) / kScanTile * kScanTile;
+  const int P1 = (N1 + kScanTile - 1) / kScanTile * kScanTile;
   float4* gk = lds4;
-  float4* gk1 = lds4 + N0;
-  uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + N0 + N1);
-  uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
+  float4* gk1 = lds4 + P0;
+  uint32_t* kbuf = reinterpret_cast<uint32_t*>(lds4 + P0 + P1);  // kChunk keys
+  uint16_t* stage = reinterpret_cast<uint16_t*>(kbuf);           // reused after the reload
+  uint32_t* tcount = kbuf + kChunk;
   uint32_t* cursor = tcount + (T + 1);
-  for (int i = threadIdx.x; i < N0; i += kBlock) gk[i] = j.pts[L0.pt_off + i];
-  for (int i = threadIdx.x; i < N1; i += kBlock) gk1[i] = j.pts[L1.pt_off + i];
-  for (int t = threadIdx.x; t <= T; t += kBlock) tcount[t] = 0;
+  const float4 pad = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
+  for (int i = threadIdx.x; i < P0; i += KB) gk[i] = i < N0 ? j.pts[L0.pt_off + i] : pad;
+  for (int i = threadIdx.x; i < P1; i += KB) gk1[i] = i < N1 ? j.pts[L1.pt_off + i] : pad;
+  for (int t = threadIdx.x; t <= T; t += KB) tcount[t] = 0;
   __syncthreads();
 
   const uint64_t lo = j.lo + (uint64_t)j.c * kChunk;
-  uint32_t key[kKeys];
-#pragma unroll
+#pragma unroll 1
   for (int r = 0; r < kKeys / S; ++r) {
     float xs[S][D], ys[S][D];
     bool live[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const uint64_t m = lo + (uint64_t)(r * S + s) * kBlock + threadIdx.x;
+      const uint64_t m = lo + (uint64_t)(r * S + s) * KB + threadIdx.x;
       live[s] = m < j.hi;
       float z[D], e[D];
       layer_normals<D>(j.key0, j.key1, j.contract, j.k, live[s] ? m : j.lo, z, e);
       layer_pair<D>(L0, z, e, xs[s], ys[s]);
     }
     int ii[S], jj[S];
-    argmin_scan<D, S>(gk, N0, xs, ii);
-    argmin_scan<D, S>(gk1, N1, ys, jj);
+    argmin_scan_tiled<D, S, kScanTile>(gk, P0, xs, ii);
+    argmin_scan_tiled<D, S, kScanTile>(gk1, P1, ys, jj);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const uint32_t kk = (uint32_t)ii[s] * (uint32_t)N1 + (uint32_t)jj[s];
-      key[r * S + s] = live[s] ? kk : 0xFFFFFFFFu;
+      kbuf[(r * S + s) * KB + threadIdx.x] = live[s] ? kk : 0xFFFFFFFFu;
     }
   }
-  sort_and_write(j, key, T, stage, tcount, cursor);
+  uint32_t key[kKeys];
+#pragma unroll
+  for (int e = 0; e < kKeys; ++e) key[e] = kbuf[e * KB + threadIdx.x];
+  __syncthreads();  // kbuf is the staging area from here on
+  sort_and_write<KB>(j, key, T, stage, tcount, cursor);
 }
 
 // Pass B for one super tile: tiles [t kTilesPerSuper, (t+1) kTilesPerSuper)
@@ -328,15 +345,15 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   extern __shared__ float lds[];
   int k, c;
   if (!unit_of_block_keys(a, k, c)) return;
-  keys_chunk_1d(plan_job(a, k, c), lds);
+  keys_chunk_1d<kBlock>(plan_job(a, k, c), lds);
 }
 
 template <int D, int S>
-__global__ __launch_bounds__(kBlock) void fwd_keys_nd(FwdArgs a) {
+__global__ __launch_bounds__(kBlockNd) void fwd_keys_nd(FwdArgs a) {
   extern __shared__ float4 lds4[];
   int k, c;
   if (!unit_of_block_keys(a, k, c)) return;
-  keys_chunk_nd<D, S>(plan_job(a, k, c), lds4);
+  keys_chunk_nd<D, S, kBlockNd>(plan_job(a, k, c), lds4);
 }
 
 // Workgroup b owns super tile t of layer k (b = tile_off_k + t).
@@ -367,7 +384,7 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
 // units sorted by decreasing cost; each workgroup claims the next unit until
 // the list is exhausted (the claim counter is reset by batch_reset first).
 template <int DMAX>
-__global__ __launch_bounds__(kBlock) void batch_keys(BatchArgs a) {
+__global__ __launch_bounds__(kBlockNd) void batch_keys(BatchArgs a) {
   extern __shared__ float4 lds4[];
   __shared__ int unit_sh;
   for (;;) {
@@ -393,9 +410,9 @@ __global__ __launch_bounds__(kBlock) void batch_keys(BatchArgs a) {
       j.hi = C.M;
       j.keys = a.keys + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
       j.seg = a.segs + (size_t)C.seg_base + ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
-      if (C.d == 1) keys_chunk_1d(j, reinterpret_cast<float*>(lds4));
-      else if (DMAX >= 2 && C.d == 2) keys_chunk_nd<2, 4>(j, lds4);
-      else if (DMAX >= 3) keys_chunk_nd<3, 4>(j, lds4);
+      if (C.d == 1) keys_chunk_1d<kBlockNd>(j, reinterpret_cast<float*>(lds4));
+      else if (DMAX >= 2 && C.d == 2) keys_chunk_nd<2, 4, kBlockNd>(j, lds4);
+      else if (DMAX >= 3) keys_chunk_nd<3, 4, kBlockNd>(j, lds4);
       __syncthreads();
     }
   }
@@ -439,7 +456,7 @@ size_t keys_lds_1d(int maxP, int max_tiles) {
 }
 
 size_t keys_lds_nd(int maxN, int max_tiles) {
-  return sizeof(float4) * 2 * (size_t)maxN + sizeof(uint16_t) * kChunk +
+  return sizeof(float4) * 2 * (size_t)(maxN + kScanTile) + sizeof(uint32_t) * kChunk +
          sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
 }
 
@@ -452,11 +469,11 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
   } else if (a.d == 2) {
     const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
     if ((e = allow_lds(fwd_keys_nd<2, 4>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL((fwd_keys_nd<2, 4>), keys_grid(a), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((fwd_keys_nd<2, 4>), keys_grid(a), dim3(kBlockNd), lds, s, a);
   } else {
     const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
     if ((e = allow_lds(fwd_keys_nd<3, 4>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL((fwd_keys_nd<3, 4>), keys_grid(a), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((fwd_keys_nd<3, 4>), keys_grid(a), dim3(kBlockNd), lds, s, a);
   }
   return hipGetLastError();
 }
@@ -475,13 +492,13 @@ hipError_t launch_batch_forward(const BatchArgs& a, int dmax, int grid, size_t l
   hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, a.head);
   if (dmax <= 1) {
     if ((e = allow_lds(batch_keys<1>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys<1>, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(batch_keys<1>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
   } else if (dmax == 2) {
     if ((e = allow_lds(batch_keys<2>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys<2>, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(batch_keys<2>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
   } else {
     if ((e = allow_lds(batch_keys<3>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys<3>, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(batch_keys<3>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t lds_b = sizeof(uint32_t) * (kSuper + 2 * kCountBlock);

@@ -21,6 +21,7 @@ constexpr int kTilesPerSuper = kSuper / kTile;
 constexpr int kChunk = 4096;          // samples per pass-A workgroup
 constexpr int kMaxTiles = 4096;       // larger count blocks use direct atomics
 constexpr int kDefaultBatch = 1 << 22;  // samples per layer per pass by default
+constexpr int kScanTile = 8;            // records per tile of the d >= 2 argmin scan
 
 // One record per layer k = 0..n, stored in the plan's device workspace.
 // Model coefficients are the FP32 inputs of the AR(1) proposition (Sec. 3);

@@ -65,6 +65,62 @@ __device__ __forceinline__ void argmin_scan(const float4* __restrict__ g, int N,
   }
 }
 
+// The same argmin, by tiles of TL records: a running minimum per tile
+// (fminf chains -> v_min3_f32) and only the index of the first tile whose
+// minimum is strictly smaller than the best so far; the winning tile is then
+// rescanned for the first record whose key equals the minimum.  Bit-identical
+// to argmin_scan (same keys, lowest index among the minimal ones).  The
+// record array must be padded to a multiple of TL with records whose key is
+// +inf for every x (g = 0, h = +inf).
+template <int D, int S, int TL>
+__device__ __forceinline__ void argmin_scan_tiled(const float4* __restrict__ g, int Npad,
+                                                  const float (*xs)[D], int* idx) {
+  float best[S];
+  int tile[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    best[s] = __builtin_huge_valf();
+    tile[s] = 0;
+  }
+  for (int p0 = 0; p0 < Npad; p0 += TL) {
+    float m[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) m[s] = __builtin_huge_valf();
+#pragma unroll
+    for (int q = 0; q < TL; ++q) {
+      const float4 r = g[p0 + q];
+      const float gc[3] = {r.x, r.y, r.z};
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        float key = r.w;
+#pragma unroll
+        for (int c = 0; c < D; ++c) key = fmaf(-xs[s][c], gc[c], key);
+        m[s] = fminf(m[s], key);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const bool lt = m[s] < best[s];
+      best[s] = lt ? m[s] : best[s];
+      tile[s] = lt ? p0 : tile[s];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    int found = tile[s] + TL - 1;
+#pragma unroll
+    for (int q = TL - 1; q >= 0; --q) {
+      const float4 r = g[tile[s] + q];
+      const float gc[3] = {r.x, r.y, r.z};
+      float key = r.w;
+#pragma unroll
+      for (int c = 0; c < D; ++c) key = fmaf(-xs[s][c], gc[c], key);
+      found = key == best[s] ? tile[s] + q : found;
+    }
+    idx[s] = found;
+  }
+}
+
 // Standard normals z (for X_k) and eps (for the innovation) of LAYERWISE
 // sample m of layer k.  Philox counter (block, k, contract, tag): d = 1 uses
 // block m >> 1 and the Box-Muller pair m & 1; d = 2 block m; d = 3 blocks

@@ -83,7 +83,13 @@ extern "C" qtree_status qtree_gauss_quantizer(int32_t N, double* out) {
   std::vector<double> x(N), F(N), lo(N), di(N), up(N), dx(N), c(N), g(N), cen(N), trial(N);
   for (int i = 0; i < N; ++i) x[i] = std::sqrt(3.0) * normal_quantile((i + 0.5) / N);
   double gap = lloyd_gap(x, &cen);
-  for (int it = 0; it < 10000 && gap > 1e-14; ++it) {
+  // Newton converges quadratically down to the rounding floor of the
+  // residual (~1e-13); below 1e-9 the loop stops once the gap has not halved
+  // for four steps and keeps the best grid seen.
+  std::vector<double> best = x;
+  double best_gap = gap;
+  int stall = 0;
+  for (int it = 0; it < 10000 && gap > 1e-14 && stall < 4; ++it) {
     residual(x, F, lo, di, up);
     // Thomas algorithm for J dx = -F
     c[0] = up[0] / di[0];
@@ -110,7 +116,13 @@ extern "C" qtree_status qtree_gauss_quantizer(int32_t N, double* out) {
     }
     if (!taken) x = cen;
     gap = lloyd_gap(x, &cen);
+    stall = (gap < 1e-9 && !(gap < 0.5 * best_gap)) ? stall + 1 : 0;
+    if (gap < best_gap) {
+      best_gap = gap;
+      best = x;
+    }
   }
+  x.swap(best);
   // symmetrise (the law is symmetric; removes the last rounding asymmetry)
   for (int i = 0; i < N / 2; ++i) {
     const double v = 0.5 * (x[N - 1 - i] - x[i]);
