@@ -162,19 +162,23 @@ qtree_status qtree_bdp(const qtree_plan *plan, const int32_t *counts, const doub
 
 /* Discounted obstacle on the plan's grid points, FP64, device output
  * phi: double[sum N_k]:  phi_k(x) = exp(-r t_k) payoff(S_{t_k}(x)),
- * t_k = k Tm / n, S^a_t(x) = S0 exp((r - sigma_a^2/2) t + sigma_a x_a)
- * (Sec. 2: obstacle of the optimal stopping problem on a Brownian state).
- * kind bit 0: 0 put on S^1, 1 call on max_a S^a; bit 1: European
+ * t_k = k Tm / n, S^a_t(x) = S0 exp((r - sigma_a^2/2) t + sigma_a y_a) with
+ * the Brownian factors y = mix x (Sec. 2: obstacle of the optimal stopping
+ * problem on a Brownian state).  mix: host double[d][d] row-major, or NULL
+ * for the identity; sqrt(T) I prices maturity T on the grid of a unit-time
+ * Brownian motion, sqrt(T) chol(R) adds a correlation R to independent
+ * factors.  kind bit 0: 0 put on S^1, 1 call on max_a S^a; bit 1: European
  * (phi_k = -inf for k < n).  sigma: host double[d].  Asynchronous. */
 qtree_status qtree_payoff(const qtree_plan *plan, int32_t kind, double S0, double K, double r,
-                          double Tm, const double *sigma, double *phi, void *stream);
-/* The same for n_pay contracts in one launch per 32 contracts: host arrays
- * kind, S0, K, r, Tm [n_pay] and sigma [n_pay][d]; phi: device
- * double[n_pay][sum N_k]. */
+                          double Tm, const double *sigma, const double *mix, double *phi,
+                          void *stream);
+/* The same for n_pay contracts in one launch per 16 contracts: host arrays
+ * kind, S0, K, r, Tm [n_pay], sigma [n_pay][d] and mix [n_pay][d][d] (or
+ * NULL); phi: device double[n_pay][sum N_k]. */
 qtree_status qtree_payoff_batch(const qtree_plan *plan, int32_t n_pay, const int32_t *kind,
                                 const double *S0, const double *K, const double *r,
-                                const double *Tm, const double *sigma, double *phi,
-                                void *stream);
+                                const double *Tm, const double *sigma, const double *mix,
+                                double *phi, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batches: many contracts with uneven n and N_k priced together.
@@ -183,8 +187,9 @@ qtree_status qtree_payoff_batch(const qtree_plan *plan, int32_t n_pay, const int
  * its count buffer, its obstacles phi [n_pay][points] and its value buffer V
  * [n_pay][points] (all device).  qtree_batch_plan builds a device work list
  * of (contract, layer, chunk range) units sorted longest first; a run then
- * issues, per scratch group, one persistent sampling launch that claims
- * units from the list until it is empty and one histogram launch, and then
+ * issues, per scratch group, two persistent sampling launches (the d >= 2
+ * units, then the 1-D units) that claim units from their list until it is
+ * empty and one histogram launch, and then
  * one BDP launch in which each workgroup walks all layers of one contract for
  * up to 16 of its payoffs.  Counts and values are bit-for-bit / 1e-9 the
  * ones of qtree_transitions + qtree_bdp per contract (same Philox counters).
@@ -213,7 +218,8 @@ typedef struct qtree_batch qtree_batch;
 
 qtree_status qtree_tuner_create(const char *cache_path, qtree_tuner **out);
 void qtree_tuner_destroy(qtree_tuner *tuner);
-/* Cached choice (workgroups per CU) for a batch signature, 0 if none. */
+/* Cached choice for a batch signature, 0 if none: workgroups per CU of the
+ * 1-D sampling launch in bits 0-7, of the d >= 2 launch in bits 8-15. */
 int32_t qtree_tuner_lookup(const qtree_tuner *tuner, const char *signature);
 
 qtree_status qtree_batch_plan(const qtree_contract *contracts, int32_t n, qtree_tuner *tuner,
@@ -221,8 +227,11 @@ qtree_status qtree_batch_plan(const qtree_contract *contracts, int32_t n, qtree_
 /* Run the batch on `stream`; if V0_host (double[sum n_pay], contracts in
  * order) is not NULL, copy every V_0 there and synchronise. */
 qtree_status qtree_batch_run(qtree_batch *batch, double *V0_host, void *stream);
+/* Work units, histogram tiles, scratch groups, and the persistent workgroups
+ * per CU of the 1-D and of the d >= 2 sampling launch (any pointer may be
+ * NULL). */
 qtree_status qtree_batch_info(const qtree_batch *batch, int64_t *units, int64_t *tiles,
-                              int32_t *groups, int32_t *per_cu);
+                              int32_t *groups, int32_t *per_cu_1d, int32_t *per_cu_nd);
 const char *qtree_batch_signature(const qtree_batch *batch);
 void qtree_batch_destroy(qtree_batch *batch);
 

@@ -71,7 +71,7 @@ def lib():
         L.oracle_bdp.restype = ctypes.c_int64
         L.oracle_payoff.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_double, P, P]
+                                    ctypes.c_double, P, P, P]
         _lib = L
     return _lib
 
@@ -194,15 +194,19 @@ PUT, MAX_CALL, EUROPEAN = 0, 1, 2
 
 
 def payoff(kind: int, d: int, N, grid: np.ndarray, S0: float, K: float, r: float, T: float,
-           sigma) -> np.ndarray:
+           sigma, mix=None) -> np.ndarray:
+    """mix: optional [d][d] map from the grid state to the Brownian factors
+    of the log-prices (None: identity)."""
     N = np.ascontiguousarray(N, np.int32)
     n = N.size - 1
     g = np.ascontiguousarray(grid, np.float32)
     sig = np.ascontiguousarray(np.atleast_1d(sigma), np.float64)
     if sig.size < d:
         sig = np.resize(sig, d)
+    mx = None if mix is None else np.ascontiguousarray(np.asarray(mix, np.float64).reshape(d, d))
     phi = np.zeros(int(point_offsets(N)[-1]), np.float64)
-    lib().oracle_payoff(kind, d, n, _ptr(N), _ptr(g), S0, K, r, T, _ptr(sig), _ptr(phi))
+    lib().oracle_payoff(kind, d, n, _ptr(N), _ptr(g), S0, K, r, T, _ptr(sig),
+                        None if mx is None else _ptr(mx), _ptr(phi))
     return phi
 
 

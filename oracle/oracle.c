@@ -455,7 +455,7 @@ int64_t oracle_bdp(const int32_t *counts, const int32_t *N, int32_t n, const dou
 
 void oracle_payoff(int32_t kind, int32_t d, int32_t n, const int32_t *N, const float *grid,
                    double S0, double K, double r, double Tm, const double *sigma,
-                   double *phi) {
+                   const double *mix, double *phi) {
   int max_call = kind & 1, european = kind & 2;
   int64_t off = 0;
   for (int32_t k = 0; k <= n; ++k) {
@@ -463,16 +463,25 @@ void oracle_payoff(int32_t kind, int32_t d, int32_t n, const int32_t *N, const f
     double disc = exp(-r * t);
     for (int32_t i = 0; i < N[k]; ++i) {
       const float *x = grid + (off + i) * d;
+      double y[3];
+      for (int a = 0; a < d; ++a) {
+        if (!mix) {
+          y[a] = (double)x[a];
+          continue;
+        }
+        y[a] = 0.0;
+        for (int b = 0; b < d; ++b) y[a] += mix[a * d + b] * (double)x[b];
+      }
       double v;
       if (max_call) {
         double smax = -INFINITY;
         for (int a = 0; a < d; ++a) {
-          double s = S0 * exp((r - 0.5 * sigma[a] * sigma[a]) * t + sigma[a] * (double)x[a]);
+          double s = S0 * exp((r - 0.5 * sigma[a] * sigma[a]) * t + sigma[a] * y[a]);
           if (s > smax) smax = s;
         }
         v = disc * fmax(smax - K, 0.0);
       } else {
-        double s = S0 * exp((r - 0.5 * sigma[0] * sigma[0]) * t + sigma[0] * (double)x[0]);
+        double s = S0 * exp((r - 0.5 * sigma[0] * sigma[0]) * t + sigma[0] * y[0]);
         v = disc * fmax(K - s, 0.0);
       }
       if (european && k < n) v = -INFINITY;

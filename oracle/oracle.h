@@ -61,13 +61,15 @@ int oracle_transitions(const oracle_model *mdl, const float *grid, const int32_t
 int64_t oracle_bdp(const int32_t *counts, const int32_t *N, int32_t n, const double *phi,
                    int32_t n_pay, double *V_all, double *V0);
 /* Discounted obstacle phi_k(x) = exp(-r t_k) * payoff(S_{t_k}(x)), t_k = k*Tm/n.
-   kind bit 0 clear: put (K - S)^+ on S = S0 exp((r - sigma^2/2) t + sigma x_0).
-   kind bit 0 set  : call on the max of d assets S^a = S0 exp((r - sigma_a^2/2) t + sigma_a x_a).
+   The Brownian factors are y = mix x (mix: [d][d] row-major, FP64; NULL is
+   the identity), y_a = sum_b mix[a][b] x_b summed in order of b.
+   kind bit 0 clear: put (K - S)^+ on S = S0 exp((r - sigma^2/2) t + sigma y_0).
+   kind bit 0 set  : call on the max of d assets S^a = S0 exp((r - sigma_a^2/2) t + sigma_a y_a).
    kind bit 1 set  : European, phi_k = -inf for k < n (the max in the BDP then
                      always takes the continuation value). */
 void oracle_payoff(int32_t kind, int32_t d, int32_t n, const int32_t *N, const float *grid,
                    double S0, double K, double r, double Tm, const double *sigma,
-                   double *phi);
+                   const double *mix, double *phi);
 
 /* Bulk helpers for tests. */
 void oracle_ln_u24_bulk(uint32_t K0, int64_t count, float *out);

@@ -68,7 +68,7 @@ def lib() -> ctypes.CDLL:
     L.qtree_transitions_add.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
     L.qtree_transitions_add.restype = ctypes.c_int
     L.qtree_bdp.argtypes = [P, P, P, i32, P, P, P]
-    L.qtree_payoff.argtypes = [P, i32, f64, f64, f64, f64, P, P, P]
+    L.qtree_payoff.argtypes = [P, i32, f64, f64, f64, f64, P, P, P, P]
     L.qtree_gauss_quantizer.argtypes = [i32, P]
     L.qtree_box_muller.argtypes = [P, P, i64, P, P, P]
     L.qtree_plan_tune.argtypes = [P, i32, i64]
@@ -77,7 +77,7 @@ def lib() -> ctypes.CDLL:
     L.qtree_plan_trace.restype = ctypes.c_int
     L.qtree_plan_batch_samples.argtypes = [P]
     L.qtree_plan_batch_samples.restype = i64
-    L.qtree_payoff_batch.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+    L.qtree_payoff_batch.argtypes = [P, i32, P, P, P, P, P, P, P, P, P]
     L.qtree_payoff_batch.restype = ctypes.c_int
     L.qtree_layer_samples.argtypes = [P, i32, u64, i64, u64, u32, P, P, P]
     L.qtree_cells.argtypes = [P, i32, P, i64, P, P]
@@ -205,8 +205,10 @@ class Plan:
         _check(lib().qtree_plan_trace(self._h, event.cuda_event if event is not None else None))
         return self
 
-    def payoff_batch(self, kinds, S0, K, r, T, sigma, out=None, stream=None):
-        """Obstacles of n contracts in one launch: device float64 [n, points]."""
+    def payoff_batch(self, kinds, S0, K, r, T, sigma, mix=None, out=None, stream=None):
+        """Obstacles of n contracts in one launch: device float64 [n, points].
+        sigma: [n, d] (or broadcastable); mix: optional [n, d, d] map from the
+        grid state to the log-price factors (None: identity)."""
         import torch
         kinds = np.ascontiguousarray(np.atleast_1d(kinds), np.int32)
         n = kinds.size
@@ -215,22 +217,30 @@ class Plan:
         sig = np.asarray(sigma, np.float64).reshape(n, -1)
         sig = np.ascontiguousarray(np.broadcast_to(sig[:, :self.d] if sig.shape[1] >= self.d
                                                    else sig, (n, self.d)), np.float64)
+        mx = None
+        if mix is not None:
+            mx = np.ascontiguousarray(np.broadcast_to(
+                np.asarray(mix, np.float64).reshape(-1, self.d, self.d), (n, self.d, self.d)))
         if out is None:
             out = torch.empty((n, self.points), dtype=torch.float64, device=self.workspace.device)
         _check(lib().qtree_payoff_batch(self._h, n, _np_ptr(kinds), *(_np_ptr(v) for v in arr),
-                                        _np_ptr(sig), out.data_ptr(), _stream_handle(stream)))
+                                        _np_ptr(sig), None if mx is None else _np_ptr(mx),
+                                        out.data_ptr(), _stream_handle(stream)))
         return out
 
-    def payoff(self, kind: int, S0: float, K: float, r: float, T: float, sigma, out=None,
-               stream=None):
+    def payoff(self, kind: int, S0: float, K: float, r: float, T: float, sigma, mix=None,
+               out=None, stream=None):
         """Discounted obstacle phi on the grid points (device float64 [points])."""
         import torch
         sig = np.ascontiguousarray(np.resize(np.atleast_1d(np.asarray(sigma, np.float64)),
                                              self.d), np.float64)
+        mx = None if mix is None else np.ascontiguousarray(
+            np.asarray(mix, np.float64).reshape(self.d, self.d))
         if out is None:
             out = torch.empty(self.points, dtype=torch.float64, device=self.workspace.device)
         _check(lib().qtree_payoff(self._h, int(kind), float(S0), float(K), float(r), float(T),
-                                  _np_ptr(sig), out.data_ptr(), _stream_handle(stream)))
+                                  _np_ptr(sig), None if mx is None else _np_ptr(mx),
+                                  out.data_ptr(), _stream_handle(stream)))
         return out
 
     def bdp(self, counts, phi, V=None, want_v0: bool = True, stream=None):
@@ -302,7 +312,7 @@ def _batch_setup():
     L.qtree_batch_plan.restype = ctypes.c_int
     L.qtree_batch_run.argtypes = [P, P, P]
     L.qtree_batch_run.restype = ctypes.c_int
-    L.qtree_batch_info.argtypes = [P, P, P, P, P]
+    L.qtree_batch_info.argtypes = [P, P, P, P, P, P]
     L.qtree_batch_info.restype = ctypes.c_int
     L.qtree_batch_signature.argtypes = [P]
     L.qtree_batch_signature.restype = ctypes.c_char_p
@@ -362,10 +372,12 @@ class Batch:
 
     def info(self):
         u, t = ctypes.c_int64(), ctypes.c_int64()
-        g, p = ctypes.c_int32(), ctypes.c_int32()
+        g, p1, pn = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(_batch_setup().qtree_batch_info(self._h, ctypes.byref(u), ctypes.byref(t),
-                                               ctypes.byref(g), ctypes.byref(p)))
-        return {"units": u.value, "tiles": t.value, "groups": g.value, "per_cu": p.value}
+                                               ctypes.byref(g), ctypes.byref(p1),
+                                               ctypes.byref(pn)))
+        return {"units": u.value, "tiles": t.value, "groups": g.value,
+                "per_cu_1d": p1.value, "per_cu_nd": pn.value}
 
     @property
     def signature(self) -> str:

@@ -507,8 +507,8 @@ qtree_status qtree_bdp(const qtree_plan* plan, const int32_t* counts, const doub
 
 qtree_status qtree_payoff_batch(const qtree_plan* plan, int32_t n_pay, const int32_t* kind,
                                 const double* S0, const double* K, const double* r,
-                                const double* Tm, const double* sigma, double* phi,
-                                void* stream) {
+                                const double* Tm, const double* sigma, const double* mix,
+                                double* phi, void* stream) {
   if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
   if (n_pay < 0) return fail(QTREE_EINVAL, "n_pay must be >= 0");
   if (n_pay == 0) return QTREE_OK;
@@ -522,6 +522,10 @@ qtree_status qtree_payoff_batch(const qtree_plan* plan, int32_t n_pay, const int
     for (int c = 0; c < plan->d; ++c)
       if (!std::isfinite(sigma[(size_t)q * plan->d + c]))
         return fail(QTREE_EINVAL, "sigma must be finite");
+    if (mix)
+      for (int c = 0; c < plan->d * plan->d; ++c)
+        if (!std::isfinite(mix[(size_t)q * plan->d * plan->d + c]))
+          return fail(QTREE_EINVAL, "mix must be finite");
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   for (int q0 = 0; q0 < n_pay; q0 += qtree::kPayoffGroup) {
@@ -543,6 +547,9 @@ qtree_status qtree_payoff_batch(const qtree_plan* plan, int32_t n_pay, const int
       C.r = r[q0 + q];
       C.Tm = Tm[q0 + q];
       for (int c = 0; c < plan->d; ++c) C.sigma[c] = sigma[(size_t)(q0 + q) * plan->d + c];
+      C.has_mix = mix ? 1 : 0;
+      const int dd = plan->d * plan->d;
+      for (int c = 0; c < dd; ++c) C.mix[c] = mix ? mix[(size_t)(q0 + q) * dd + c] : 0.0;
     }
     hipError_t e = qtree::launch_payoff(a, st);
     if (e != hipSuccess) return hip_fail(e, "payoff launch");
@@ -551,10 +558,11 @@ qtree_status qtree_payoff_batch(const qtree_plan* plan, int32_t n_pay, const int
 }
 
 qtree_status qtree_payoff(const qtree_plan* plan, int32_t kind, double S0, double K, double r,
-                          double Tm, const double* sigma, double* phi, void* stream) {
+                          double Tm, const double* sigma, const double* mix, double* phi,
+                          void* stream) {
   if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
   if (!sigma) return fail(QTREE_EINVAL, "sigma is NULL");
-  return qtree_payoff_batch(plan, 1, &kind, &S0, &K, &r, &Tm, sigma, phi, stream);
+  return qtree_payoff_batch(plan, 1, &kind, &S0, &K, &r, &Tm, sigma, mix, phi, stream);
 }
 
 qtree_status qtree_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,

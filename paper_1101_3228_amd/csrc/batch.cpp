@@ -1,8 +1,9 @@
 // Batched forward step + BDP for many contracts with uneven n and N_k:
-// one persistent pass-A launch per scratch group (a device work queue of
-// (contract, layer, chunk range) units, longest first), one pass-B launch per
-// group, one BDP launch for all (contract, payoff group) pairs, captured once
-// into a hipGraph; plus the autotuner that picks the persistent grid.
+// per scratch group, two persistent pass-A launches (device work queues of
+// (contract, layer, chunk range) units, longest first: one for the d >= 2
+// contracts, one for the 1-D ones) and one pass-B launch; then one BDP
+// launch for all (contract, payoff group) pairs, captured once into a
+// hipGraph; plus the autotuner that picks each persistent grid.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,13 +24,17 @@ using qtree::set_error;
 
 struct qtree_tuner {
   std::string path;
-  std::map<std::string, int> best;  // batch signature -> workgroups per CU
+  // batch signature -> workgroups per CU: 1-D launch in the low byte, d >= 2
+  // launch in the next
+  std::map<std::string, int> best;
 };
 
 namespace {
 
+// Units [off[x], off[x] + cnt[x]) of a group: x = 0 the 1-D list, x = 1 the
+// d >= 2 list.
 struct Group {
-  int unit_off = 0, n_units = 0, tile_off = 0, n_tiles = 0;
+  int unit_off[2] = {0, 0}, n_units[2] = {0, 0}, tile_off = 0, n_tiles = 0;
 };
 
 qtree_status hip_error(hipError_t e, const char* what) {
@@ -77,11 +82,11 @@ struct qtree_batch {
   uint16_t* d_keys = nullptr;
   uint32_t* d_segs = nullptr;
   int64_t n_v0 = 0;
-  size_t lds = 0;
-  int dmax = 1;
+  size_t lds[2] = {0, 0};     // dynamic LDS of the 1-D and d >= 2 launches
+  int dmax = 1;               // largest d among the d >= 2 contracts (1: none)
   int cus = 256;
-  int per_cu = 2;
-  int max_per_cu = 2;
+  int per_cu[2] = {1, 1};     // persistent workgroups per CU of each launch
+  int max_per_cu[2] = {1, 1};
   qtree_tuner* tuner = nullptr;
   std::string signature;
   bool use_graph = false;
@@ -98,68 +103,88 @@ struct qtree_batch {
 
 namespace {
 
-qtree::BatchArgs group_args(const qtree_batch* b, const Group& g) {
+// Arguments of launch x (0: 1-D pass A, 1: d >= 2 pass A) of group g; the two
+// launches claim from separate counters.
+qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x) {
   qtree::BatchArgs a{};
   a.contracts = b->d_contracts;
-  a.units = b->d_units + g.unit_off;
+  a.units = b->d_units + g.unit_off[x];
   a.tiles = b->d_tiles + g.tile_off;
-  a.n_units = g.n_units;
+  a.n_units = g.n_units[x];
   a.n_tiles = g.n_tiles;
-  a.head = b->d_head;
+  a.head = b->d_head + 32 * x;
   a.keys = b->d_keys;
   a.segs = b->d_segs;
   return a;
 }
 
-hipError_t enqueue_forward(const qtree_batch* b, int per_cu, hipStream_t s) {
+// Pass A of launch class x with `per_cu` workgroups per CU, for every group.
+hipError_t enqueue_keys(const qtree_batch* b, int x, int per_cu, hipStream_t s) {
   for (const Group& g : b->groups) {
-    hipError_t e = qtree::launch_batch_forward(group_args(b, g), b->dmax, per_cu * b->cus,
-                                               b->lds, s);
+    hipError_t e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax,
+                                            per_cu * b->cus, b->lds[x], s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
-  hipError_t e = enqueue_forward(b, b->per_cu, s);
-  if (e != hipSuccess) return e;
+  for (const Group& g : b->groups) {
+    hipError_t e = hipSuccess;
+    for (int x = 1; x >= 0 && e == hipSuccess; --x)  // the heavier d >= 2 list first
+      e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax,
+                                   b->per_cu[x] * b->cus, b->lds[x], s);
+    if (e == hipSuccess) e = qtree::launch_batch_count(group_args(b, g, 0), s);
+    if (e != hipSuccess) return e;
+  }
   return qtree::launch_bdp_batch(b->d_jobs, (int)b->jobs.size(), s);
 }
 
-// Time the forward with every candidate persistent grid and keep the best.
+bool has_units(const qtree_batch* b, int x) {
+  for (const Group& g : b->groups)
+    if (g.n_units[x] > 0) return true;
+  return false;
+}
+
+// Time each pass-A launch class with every candidate persistent grid (powers
+// of two up to the occupancy limit) and keep the fastest.
 qtree_status tune(qtree_batch* b, hipStream_t s) {
   auto it = b->tuner->best.find(b->signature);
   if (it != b->tuner->best.end()) {
-    b->per_cu = std::min(it->second, b->max_per_cu);
+    for (int x = 0; x < 2; ++x)
+      b->per_cu[x] = std::max(1, std::min((it->second >> (8 * x)) & 0xFF, b->max_per_cu[x]));
     return QTREE_OK;
   }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return set_error(QTREE_EDEVICE, "tuner events");
-  float best_ms = 1e30f;
-  int best = b->per_cu;
-  for (int cand = 1; cand <= b->max_per_cu; cand *= 2) {
-    hipError_t e = enqueue_forward(b, cand, s);  // warm-up
-    if (e == hipSuccess) e = hipEventRecord(e0, s);
-    if (e == hipSuccess) e = enqueue_forward(b, cand, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e != hipSuccess) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      return hip_error(e, "tuner run");
+  for (int x = 0; x < 2; ++x) {
+    if (!has_units(b, x)) continue;
+    float best_ms = 1e30f;
+    int best = b->per_cu[x];
+    for (int cand = 1; cand <= b->max_per_cu[x]; cand *= 2) {
+      hipError_t e = enqueue_keys(b, x, cand, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = enqueue_keys(b, x, cand, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return hip_error(e, "tuner run");
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+      }
     }
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = cand;
-    }
+    b->per_cu[x] = best;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  b->per_cu = best;
-  b->tuner->best[b->signature] = best;
+  b->tuner->best[b->signature] = b->per_cu[0] | (b->per_cu[1] << 8);
   save_cache(b->tuner);
   return QTREE_OK;
 }
@@ -203,7 +228,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
       sig *= 1099511628211ull;
     }
   };
-  int maxP = 1, maxN = 1, max_tiles = 0;
+  int maxP = 1, maxN = 1, max_tiles1 = 0, max_tilesn = 0;
   int64_t v0_off = 0;
   for (int i = 0; i < n; ++i) {
     const qtree_contract& C = contracts[i];
@@ -230,9 +255,13 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     mix(C.M);
     for (int k = 0; k <= p->n; ++k) mix((uint64_t)p->N[k]);
     b->dmax = std::max(b->dmax, (int)p->d);
-    maxP = std::max(maxP, p->maxP);
-    maxN = std::max(maxN, p->maxN);
-    max_tiles = std::max(max_tiles, p->max_tiles);
+    if (p->d == 1) {
+      maxP = std::max(maxP, p->maxP);
+      max_tiles1 = std::max(max_tiles1, p->max_tiles);
+    } else {
+      maxN = std::max(maxN, p->maxN);
+      max_tilesn = std::max(max_tilesn, p->max_tiles);
+    }
     qtree::BatchContract bc{};
     bc.layers = reinterpret_cast<const qtree::LayerDev*>(p->ws + p->lay.layers);
     bc.mids = reinterpret_cast<const float*>(p->ws + p->lay.aux);
@@ -266,16 +295,17 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
   char sbuf[32];
   std::snprintf(sbuf, sizeof(sbuf), "%016llx", (unsigned long long)sig);
   b->signature = sbuf;
-  b->lds = std::max(qtree::keys_lds_1d(maxP, max_tiles),
-                    b->dmax > 1 ? qtree::keys_lds_nd(maxN, max_tiles) : (size_t)0);
-  if (b->lds > 160 * 1024) {
+  b->lds[0] = qtree::keys_lds_1d(maxP, max_tiles1);
+  b->lds[1] = qtree::keys_lds_nd(maxN, max_tilesn);
+  if (b->lds[0] > 160 * 1024 || (b->dmax > 1 && b->lds[1] > 160 * 1024)) {
     delete b;
     return set_error(QTREE_EUNSUPPORTED, "batch needs more LDS than a workgroup has");
   }
-  b->max_per_cu = 1;
-  while (b->max_per_cu < 8 && (size_t)(b->max_per_cu * 2) * b->lds <= 160 * 1024)
-    b->max_per_cu *= 2;
-  b->per_cu = std::min(2, b->max_per_cu);
+  for (int x = 0; x < 2; ++x) {
+    if (x == 1 && b->dmax == 1) continue;
+    b->max_per_cu[x] = std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lds[x]));
+    b->per_cu[x] = std::min(2, b->max_per_cu[x]);
+  }
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
@@ -337,31 +367,37 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
       }
     }
     const double target = total / (8.0 * 2 * b->cus);  // ~8 units per workgroup slot
-    for (int i = 0; i < n; ++i) {
-      if (group_of[i] != x) continue;
-      const qtree_plan* p = contracts[i].plan;
-      const qtree::BatchContract& bc = b->hc[i];
-      for (int k = 0; k < p->n; ++k) {
-        const double per = p->d == 1 ? 200.0 : 300.0 + 5.0 * p->d / 2.0 * (p->N[k] + p->N[k + 1]);
-        const double chunk_cost = per * qtree::kChunk;
-        int step = (int)std::max(1.0, std::floor(target / chunk_cost));
-        step = std::min(step, bc.chunks);
-        for (int c0 = 0; c0 < bc.chunks; c0 += step) {
-          const int nc = std::min(step, bc.chunks - c0);
-          gu.push_back(qtree::BatchUnit{i, k, c0, nc});
-          gc.push_back(chunk_cost * nc);
+    Group grp;
+    for (int cls = 0; cls < 2; ++cls) {
+      gu.clear();
+      gc.clear();
+      for (int i = 0; i < n; ++i) {
+        const qtree_plan* p = contracts[i].plan;
+        if (group_of[i] != x || (p->d > 1) != (cls == 1)) continue;
+        const qtree::BatchContract& bc = b->hc[i];
+        for (int k = 0; k < p->n; ++k) {
+          const double per =
+              p->d == 1 ? 200.0 : 300.0 + 5.0 * p->d / 2.0 * (p->N[k] + p->N[k + 1]);
+          const double chunk_cost = per * qtree::kChunk;
+          int step = (int)std::max(1.0, std::floor(target / chunk_cost));
+          step = std::min(step, bc.chunks);
+          for (int c0 = 0; c0 < bc.chunks; c0 += step) {
+            const int nc = std::min(step, bc.chunks - c0);
+            gu.push_back(qtree::BatchUnit{i, k, c0, nc});
+            gc.push_back(chunk_cost * nc);
+          }
         }
       }
-    }
-    std::vector<size_t> order(gu.size());
-    for (size_t u = 0; u < order.size(); ++u) order[u] = u;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a2, size_t b2) { return gc[a2] > gc[b2]; });
-    Group grp;
-    grp.unit_off = (int)b->units.size();
-    grp.n_units = (int)gu.size();
-    for (size_t u : order) {
-      b->units.push_back(gu[u]);
-      b->unit_cost.push_back(gc[u]);
+      std::vector<size_t> order(gu.size());
+      for (size_t u = 0; u < order.size(); ++u) order[u] = u;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](size_t a2, size_t b2) { return gc[a2] > gc[b2]; });
+      grp.unit_off[cls] = (int)b->units.size();
+      grp.n_units[cls] = (int)gu.size();
+      for (size_t u : order) {
+        b->units.push_back(gu[u]);
+        b->unit_cost.push_back(gc[u]);
+      }
     }
     grp.tile_off = (int)b->tiles.size();
     for (int i = 0; i < n; ++i) {
@@ -439,12 +475,13 @@ qtree_status qtree_batch_run(qtree_batch* b, double* V0_host, void* stream) {
 }
 
 qtree_status qtree_batch_info(const qtree_batch* b, int64_t* units, int64_t* tiles,
-                              int32_t* groups, int32_t* per_cu) {
+                              int32_t* groups, int32_t* per_cu_1d, int32_t* per_cu_nd) {
   if (!b) return set_error(QTREE_EINVAL, "batch is NULL");
   if (units) *units = (int64_t)b->units.size();
   if (tiles) *tiles = (int64_t)b->tiles.size();
   if (groups) *groups = (int32_t)b->groups.size();
-  if (per_cu) *per_cu = b->per_cu;
+  if (per_cu_1d) *per_cu_1d = b->per_cu[0];
+  if (per_cu_nd) *per_cu_nd = b->per_cu[1];
   return QTREE_OK;
 }
 

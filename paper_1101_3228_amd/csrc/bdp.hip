@@ -159,21 +159,28 @@ __global__ void payoff_kernel(PayoffArgs a) {
   const double t = C.Tm * (double)k / (double)a.n;
   const double disc = exp(-C.r * t);
   const int64_t at = (int64_t)L.pt_off + i;
+  const float4 g = a.d == 1 ? make_float4(a.pts1[at], 0.f, 0.f, 0.f) : a.pts[at];
+  const float xs[3] = {g.x, g.y, g.z};
+  double y[3];
+  for (int c = 0; c < a.d; ++c) {
+    if (!C.has_mix) {
+      y[c] = (double)xs[c];
+      continue;
+    }
+    y[c] = 0.0;
+    for (int e = 0; e < a.d; ++e) y[c] += C.mix[c * a.d + e] * (double)xs[e];
+  }
   double v;
   if (C.kind & 1) {
-    const float4 g = a.d == 1 ? make_float4(a.pts1[at], 0.f, 0.f, 0.f) : a.pts[at];
-    const float xs[3] = {g.x, g.y, g.z};
     double smax = -__builtin_huge_val();
     for (int c = 0; c < a.d; ++c) {
-      const double sc = C.S0 * exp((C.r - 0.5 * C.sigma[c] * C.sigma[c]) * t +
-                                   C.sigma[c] * (double)xs[c]);
+      const double sc = C.S0 * exp((C.r - 0.5 * C.sigma[c] * C.sigma[c]) * t + C.sigma[c] * y[c]);
       smax = sc > smax ? sc : smax;
     }
     v = disc * fmax(smax - C.K, 0.0);
   } else {
-    const float x0 = a.d == 1 ? a.pts1[at] : a.pts[at].x;
     const double sc =
-        C.S0 * exp((C.r - 0.5 * C.sigma[0] * C.sigma[0]) * t + C.sigma[0] * (double)x0);
+        C.S0 * exp((C.r - 0.5 * C.sigma[0] * C.sigma[0]) * t + C.sigma[0] * y[0]);
     v = disc * fmax(C.K - sc, 0.0);
   }
   if ((C.kind & 2) && k < a.n) v = -__builtin_huge_val();

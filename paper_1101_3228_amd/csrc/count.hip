@@ -383,9 +383,10 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
 // Persistent pass A over a work list of (contract, layer, chunk range)
 // units sorted by decreasing cost; each workgroup claims the next unit until
 // the list is exhausted (the claim counter is reset by batch_reset first).
-template <int DMAX>
-__global__ __launch_bounds__(kBlockNd) void batch_keys(BatchArgs a) {
-  extern __shared__ float4 lds4[];
+// One launch takes the 1-D units (256 lanes, a few registers, several
+// workgroups per CU), another the d >= 2 units (512 lanes under one grid pair).
+template <int KB, typename Body>
+__device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
   __shared__ int unit_sh;
   for (;;) {
     if (threadIdx.x == 0) unit_sh = atomicAdd(a.head, 1);
@@ -410,12 +411,26 @@ __global__ __launch_bounds__(kBlockNd) void batch_keys(BatchArgs a) {
       j.hi = C.M;
       j.keys = a.keys + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
       j.seg = a.segs + (size_t)C.seg_base + ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
-      if (C.d == 1) keys_chunk_1d<kBlockNd>(j, reinterpret_cast<float*>(lds4));
-      else if (DMAX >= 2 && C.d == 2) keys_chunk_nd<2, 4, kBlockNd>(j, lds4);
-      else if (DMAX >= 3) keys_chunk_nd<3, 4, kBlockNd>(j, lds4);
+      body(C, j);
       __syncthreads();
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void batch_keys_1d(BatchArgs a) {
+  extern __shared__ float lds[];
+  batch_loop<kBlock>(a, [&](const BatchContract&, const KeysJob& j) {
+    keys_chunk_1d<kBlock>(j, lds);
+  });
+}
+
+template <int DMAX>
+__global__ __launch_bounds__(kBlockNd) void batch_keys_nd(BatchArgs a) {
+  extern __shared__ float4 lds4[];
+  batch_loop<kBlockNd>(a, [&](const BatchContract& C, const KeysJob& j) {
+    if (DMAX < 3 || C.d == 2) keys_chunk_nd<2, 4, kBlockNd>(j, lds4);
+    else keys_chunk_nd<3, 4, kBlockNd>(j, lds4);
+  });
 }
 
 // Pass B of a batch: workgroup b handles tile record b.
@@ -486,23 +501,47 @@ hipError_t launch_count_tiles(const FwdArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_forward(const BatchArgs& a, int dmax, int grid, size_t lds,
-                                hipStream_t s) {
+hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int grid, size_t lds, hipStream_t s) {
   hipError_t e;
+  if (a.n_units == 0) return hipSuccess;
   hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, a.head);
   if (dmax <= 1) {
-    if ((e = allow_lds(batch_keys<1>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys<1>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
+    if ((e = allow_lds(batch_keys_1d, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_keys_1d, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
   } else if (dmax == 2) {
-    if ((e = allow_lds(batch_keys<2>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys<2>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
+    if ((e = allow_lds(batch_keys_nd<2>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_keys_nd<2>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
   } else {
-    if ((e = allow_lds(batch_keys<3>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys<3>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
+    if ((e = allow_lds(batch_keys_nd<3>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_keys_nd<3>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
   }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+int batch_keys_occupancy(int dmax, size_t lds) {
+  int blocks = 0;
+  hipError_t e;
+  if (dmax <= 1) {
+    e = allow_lds(batch_keys_1d, lds);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_1d, kBlock, lds);
+  } else if (dmax == 2) {
+    e = allow_lds(batch_keys_nd<2>, lds);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_nd<2>, kBlockNd, lds);
+  } else {
+    e = allow_lds(batch_keys_nd<3>, lds);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_nd<3>, kBlockNd, lds);
+  }
+  return (e == hipSuccess && blocks > 0) ? blocks : 1;
+}
+
+hipError_t launch_batch_count(const BatchArgs& a, hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
   const size_t lds_b = sizeof(uint32_t) * (kSuper + 2 * kCountBlock);
-  if ((e = allow_lds(batch_count, lds_b)) != hipSuccess) return e;
+  hipError_t e = allow_lds(batch_count, lds_b);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batch_count, dim3((unsigned)a.n_tiles), dim3(kCountBlock), lds_b, s, a);
   return hipGetLastError();
 }

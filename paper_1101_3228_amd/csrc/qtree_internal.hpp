@@ -103,10 +103,11 @@ hipError_t launch_copy_last_layer(const BdpArgs& a, int64_t pt_n, int N_n, hipSt
 struct Contract {
   double S0, K, r, Tm;
   double sigma[kMaxDim];
+  double mix[kMaxDim * kMaxDim];  // Brownian factors y = mix x (row-major d x d)
   int32_t kind;
-  int32_t pad_;
+  int32_t has_mix;                // 0: y = x
 };
-constexpr int kPayoffGroup = 32;  // contracts per payoff launch (kernel-argument size)
+constexpr int kPayoffGroup = 16;  // contracts per payoff launch (kernel-argument size)
 
 struct PayoffArgs {
   const LayerDev* layers;

@@ -53,6 +53,18 @@ def test_batch_equals_one_plan_at_a_time():
     for it, rc in zip(items, ref_counts):
         assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), rc)
     assert np.allclose(V0, ref_v0, rtol=1e-12, atol=0)
+    assert info["per_cu_1d"] >= 1 and info["per_cu_nd"] >= 1
+    # batches of one dimension only (the other sampling launch is empty)
+    for sub in (slice(0, None, 2), slice(1, None, 2)):
+        part = items[sub]
+        for it in part:
+            it["counts"].fill_(-1)
+        V0p = qt.Batch(part).run()
+        for it, rc in zip(part, ref_counts[sub]):
+            assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), rc)
+        off = np.cumsum([0] + [it["phi"].shape[0] for it in items])
+        want = np.concatenate([ref_v0[off[i]:off[i + 1]] for i in range(len(items))[sub]])
+        assert np.allclose(V0p, want, rtol=1e-12, atol=0)
     # and against the oracle for two contracts (one 1-D, one 2-D)
     for it in items[:2]:
         sp = it["model"]

@@ -182,13 +182,15 @@ def test_counts_largest_layers():
 def test_payoff_matches_oracle(small_case):
     name, spec, grid, N, plan = small_case
     d = spec["d"]
+    mix = np.tril(np.random.default_rng(5).uniform(0.5, 1.5, (d, d)))
     for kind in (0, 1, 2, 3):
         sig = [0.2, 0.3, 0.25][:d]
-        got = plan.payoff(kind, 100.0, 95.0, 0.04, 1.3, sig).cpu().numpy()
-        ref = O.payoff(kind, d, N, grid, 100.0, 95.0, 0.04, 1.3, sig)
-        fin = np.isfinite(ref)
-        assert np.array_equal(fin, np.isfinite(got))
-        assert np.allclose(got[fin], ref[fin], rtol=1e-13, atol=1e-12)
+        for mx in (None, mix):
+            got = plan.payoff(kind, 100.0, 95.0, 0.04, 1.3, sig, mix=mx).cpu().numpy()
+            ref = O.payoff(kind, d, N, grid, 100.0, 95.0, 0.04, 1.3, sig, mix=mx)
+            fin = np.isfinite(ref)
+            assert np.array_equal(fin, np.isfinite(got))
+            assert np.allclose(got[fin], ref[fin], rtol=1e-13, atol=1e-12)
 
 
 def test_bdp_matches_oracle_with_edge_rows():
@@ -341,12 +343,15 @@ def test_payoff_batch_matches_single():
     S0, K = rng.uniform(80, 120, n), rng.uniform(80, 120, n)
     r, T = rng.uniform(0, 0.1, n), rng.uniform(0.25, 2, n)
     sig = rng.uniform(0.1, 0.4, (n, 2))
-    batch = plan.payoff_batch(kinds, S0, K, r, T, sig).cpu().numpy()
-    for q in range(n):
-        ref = O.payoff(int(kinds[q]), 2, N, grid, S0[q], K[q], r[q], T[q], sig[q])
-        fin = np.isfinite(ref)
-        assert np.array_equal(fin, np.isfinite(batch[q]))
-        assert np.allclose(batch[q][fin], ref[fin], rtol=1e-13, atol=1e-12)
+    mix = np.tril(rng.uniform(-1.0, 1.5, (n, 2, 2)))
+    for mx in (None, mix):
+        batch = plan.payoff_batch(kinds, S0, K, r, T, sig, mix=mx).cpu().numpy()
+        for q in range(n):
+            ref = O.payoff(int(kinds[q]), 2, N, grid, S0[q], K[q], r[q], T[q], sig[q],
+                           mix=None if mx is None else mx[q])
+            fin = np.isfinite(ref)
+            assert np.array_equal(fin, np.isfinite(batch[q]))
+            assert np.allclose(batch[q][fin], ref[fin], rtol=1e-13, atol=1e-12)
 
 
 def test_two_pass_several_batches():

@@ -71,6 +71,50 @@ def _lloyd_grids(spec, Nn):
 S0, K, R, SIG, TM = 100.0, 100.0, 0.05, 0.2, 1.0
 
 
+def test_brownian_scaling_mix_prices_maturity_T_on_the_unit_grid(oracle_lib):
+    """The log-price factor y = mix x: with mix = sqrt(T) the tree of the
+    unit-time Brownian motion prices maturity T (W_{sT} has the law of
+    sqrt(T) W_s), the same as the tree built on the maturity-T grid up to the
+    FP32 rounding of the two grids, and both converge to Black-Scholes."""
+    n, Nn, T = 4, 200, 1.7
+    unit = synth.bm_model(1, n, T=1.0)
+    direct = synth.bm_model(1, n, T=T)
+    gu, N = _lloyd_grids(unit, Nn)
+    gd, _ = _lloyd_grids(direct, Nn)
+    kind = oracle_lib.PUT | oracle_lib.EUROPEAN
+    v_unit = oracle_lib.bdp(_exact_counts_bm(unit, gu, N), N,
+                            oracle_lib.payoff(kind, 1, N, gu, S0, K, R, T, SIG,
+                                              mix=[[math.sqrt(T)]]))[0][0]
+    v_direct = oracle_lib.bdp(_exact_counts_bm(direct, gd, N), N,
+                              oracle_lib.payoff(kind, 1, N, gd, S0, K, R, T, SIG))[0][0]
+    assert v_unit == pytest.approx(v_direct, rel=2e-6)
+    bs = _exact.black_scholes_put(S0, K, R, SIG, T)
+    assert abs(v_unit - bs) < 1e-4 * bs
+    # a wrong scale (mix = 1, i.e. maturity 1 paths with maturity-T discounting) is far off
+    v_wrong = oracle_lib.bdp(_exact_counts_bm(unit, gu, N), N,
+                             oracle_lib.payoff(kind, 1, N, gu, S0, K, R, T, SIG))[0][0]
+    assert abs(v_wrong - bs) > 1e-2 * bs
+
+
+def test_mix_correlates_independent_factors(oracle_lib):
+    """2-D: mix = chol(R) on a grid of independent factors gives the payoff
+    of the grid C g of correlated factors (pointwise, up to FP32 rounding of
+    the correlated grid)."""
+    rho = 0.6
+    C = np.linalg.cholesky(np.array([[1.0, rho], [rho, 1.0]]))
+    indep = synth.bm_model(2, 3)
+    g, N = synth.layer_grids(indep, [1, (4, 5), (5, 6), (6, 7)])
+    gc = (g.astype(np.float64) @ C.T).astype(np.float32)
+    for kind in (oracle_lib.MAX_CALL, oracle_lib.PUT):
+        a = oracle_lib.payoff(kind, 2, N, g, S0, K, R, TM, [0.2, 0.3], mix=C)
+        b = oracle_lib.payoff(kind, 2, N, gc, S0, K, R, TM, [0.2, 0.3])
+        assert np.allclose(a, b, rtol=1e-6, atol=1e-9)
+    # the max-call sees the correlation (the put, on factor 0 = x_0, does not)
+    a = oracle_lib.payoff(oracle_lib.MAX_CALL, 2, N, g, S0, K, R, TM, [0.2, 0.3], mix=C)
+    assert not np.allclose(a, oracle_lib.payoff(oracle_lib.MAX_CALL, 2, N, g, S0, K, R, TM,
+                                                [0.2, 0.3]), rtol=1e-3, atol=1e-3)
+
+
 def test_european_put_exact_tree_is_quantized_expectation_and_converges(oracle_lib):
     n = 4
     spec = synth.bm_model(1, n, T=TM)
