@@ -175,3 +175,47 @@ def batch_contracts(count: int, seed: int = 0x5EED0000, n_range=(10, 100),
                         sigma=float(rng.uniform(0.1, 0.4)), K_over_S0=float(rng.uniform(0.8, 1.2)),
                         r=float(rng.uniform(0.0, 0.1))))
     return out
+
+
+# --------------------------------------------------------------- surrogate
+
+#: Training box of the put surrogate: (S0/K, sigma, r, T, n, rho); rho is
+#: fixed at 0 for a one-factor contract.
+PUT_BOX_LO = np.array([1 / 1.2, 0.1, 0.0, 0.25, 10.0, 0.0], np.float32)
+PUT_BOX_HI = np.array([1 / 0.8, 0.4, 0.1, 2.0, 100.0, 0.0], np.float32)
+
+
+def mlp_init(seed: int, n_in: int = 6, n_hid: int = 256) -> np.ndarray:
+    """Initial FP32 parameters of the 6-256-256-256-1 network, packed
+    (W1, b1, W2, b2, W3, b3, w4, b4; rows = output units): weights
+    N(0, 1/fan_in), biases 0, head N(0, 1/(4 fan_in))."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((n_in, n_hid), (n_hid, n_hid), (n_hid, n_hid)):
+        parts.append(rng.standard_normal((fan_out, fan_in)).ravel() / np.sqrt(fan_in))
+        parts.append(np.zeros(fan_out))
+    parts.append(rng.standard_normal(n_hid) / np.sqrt(4.0 * n_hid))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def box_queries(count: int, seed: int, lo=PUT_BOX_LO, hi=PUT_BOX_HI, frac_out: float = 0.0):
+    """Contract parameters uniform in the box (n integer), FP32 [count][6];
+    the last round(frac_out * count) of them leave the box in one random
+    coordinate that is not fixed, by 5-50 % of its span, and stay valid
+    contracts (above the box, or below it for S0/K and r only)."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    x = lo + rng.random((count, lo.size)) * (hi - lo)
+    x[:, 4] = rng.integers(int(lo[4]), int(hi[4]) + 1, count)
+    n_out = int(round(frac_out * count))
+    free = np.flatnonzero(hi > lo)
+    for q in range(count - n_out, count):
+        c = int(rng.choice(free))
+        step = rng.uniform(0.05, 0.5) * (hi[c] - lo[c])
+        below = c in (0, 2) and rng.random() < 0.5
+        x[q, c] = lo[c] - step if below else hi[c] + step
+        if c == 4:
+            x[q, c] = np.ceil(x[q, c])
+    return x.astype(np.float32)
