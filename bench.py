@@ -60,12 +60,12 @@ ALG_SLOTS_PER_PAIR = 50 + 71 + 3 + 54 + 1
 PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
 
 
-def _measured_traffic():
-    """HBM bytes per launch of the sampling kernel from the committed rocprofv3
-    counter runs (profiles/fwd_keys_1d_traffic.json), or None when the
-    kernel's sources changed since the counters were taken."""
+def _measured_traffic(kernel: str = "fwd_keys_1d"):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    runs (profiles/<kernel>_traffic.json), or None when the kernel's sources
+    changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "fwd_keys_1d_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     try:
         rec = json.load(open(path))
         h = hashlib.sha256()
@@ -109,10 +109,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
-    ap.add_argument("--workload", choices=("c2", "c3", "batch"), default="c2",
+    ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1"),
+                    default="c2",
                     help="c2 (default): the 1-D time-layer workload of the headline metric; "
                          "c3: 2-D max-call, n=30, N=2000, M=1e7; batch: 256 uneven "
-                         "1-D/2-D contracts, M=1e6 each, one batched run per step")
+                         "1-D/2-D contracts, M=1e6 each, one batched run per step; c5: the "
+                         "put surrogate, 1e6 queries per step after training on 1e5 tree "
+                         "prices; c1: 1-D pathwise put, n=10, N=100, M=1e5 paths (latency); "
+                         "p1: the paper's 2-D shape, n=365, N=100/250/500, M=1e5, both "
+                         "algorithms, counts copied to the host")
+    ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -136,6 +142,12 @@ def main():
         return run_c3(args)
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "c5":
+        return run_c5(args)
+    if args.workload == "c1":
+        return run_c1(args)
+    if args.workload == "p1":
+        return run_p1(args)
 
     import torch
     import paper_1101_3228_amd as qt
@@ -309,7 +321,8 @@ def run_c3(args):
         "paper_convention_gflops": 6.0 * points / (keys_ms * 1e-3) / 1e9,
         "V0_american_european": [float(V0[0]), float(V0[1])],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS,
+                     "traffic": _measured_traffic("fwd_keys_nd"),
                      "kernel": "fwd_keys_nd<2,4>"},
     }
     print(json.dumps(out), flush=True)
@@ -382,6 +395,195 @@ def run_batch(args):
         "V0_mean": float(np.mean(V0)),
     }
     print(json.dumps(out), flush=True)
+
+
+def run_c5(args):
+    """The put surrogate (6-256-256-256-1, BF16 weights, two activation
+    terms): labels from the tree (N = 100 optimal points per layer, counts
+    shared per n, M = 2e6 pairs per layer), training on 1e5 of them (not
+    timed), then one step = inference of 1e6 queries of which 5 % lie
+    outside the box.  Reported beside it: the tree's options/s on the same
+    queries (counts cached), the rate with the out-of-box 5 % sent to the
+    tree, and the held-out accuracy."""
+    import torch
+    import synth
+    from paper_1101_3228_amd import surrogate as S
+    torch.cuda.set_device(0)
+    lo, hi = synth.PUT_BOX_LO, synth.PUT_BOX_HI
+    t_prep = time.perf_counter()
+    pricer = S.PutTreePricer(N=100, M=2_000_000, device="cuda:0")
+    xtr = synth.box_queries(100_000, 0x5EED0000)
+    ytr = pricer.price(xtr)
+    log(f"labels: {time.perf_counter() - t_prep:.1f} s")
+    sur = S.Surrogate(pricer, lo, hi, synth.mlp_init(0x5EED0001), out_scale=0.05,
+                      act_terms=2, max_batch=4096, baseline=1, device="cuda:0")
+    t_fit = time.perf_counter()
+    hist = sur.fit(xtr, ytr, epochs=args.epochs, lr=2e-3, lr_final=1e-6,
+                   log=lambda e, l: e % 500 == 0 and log(f"epoch {e}: loss {l:.3e}"))
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t_fit
+    xte = synth.box_queries(20_000, 0x5EED0002)
+    yte = pricer.price(xte)
+    yp, _ = sur.price(xte)
+    err = np.abs(yp - yte) / np.maximum(yte, 1e-2)
+
+    Q = 1_000_000
+    xq = synth.box_queries(Q, 0x5EED0003, frac_out=0.05)
+    xd = torch.from_numpy(xq).cuda()
+    y = torch.empty(Q, dtype=torch.float32, device="cuda:0")
+    mask = torch.empty(Q, dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        sur.net.forward(xd, y, mask, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        sur.net.forward(xd, y, mask, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    value = Q / (ms * 1e-3)
+    alg_flop = 2.0 * (6 * 256 + 2 * 256 * 256 + 256)      # per query
+    achieved = alg_flop * Q / (ms * 1e-3) / 1e12
+
+    # the tree on a sample of the same queries (counts cached; payoff + BDP)
+    inside = mask.cpu().numpy().astype(bool)
+    sample = xq[:20_000]
+    pricer.price(sample[:2000])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pricer.price(sample)
+    torch.cuda.synchronize()
+    tree_rate = sample.shape[0] / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    pricer.price(xq[~inside])
+    torch.cuda.synchronize()
+    fallback_s = time.perf_counter() - t0
+    blended = Q / (ms * 1e-3 + fallback_s)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import mlp as OM
+        p = sur.net.params()
+        xs = xq[:20_000]
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 10.0:
+            OM.forward(p, xs, lo, hi, 0.05, terms=2, baseline=1)
+            reps += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": reps * xs.shape[0] / el, "unit": "options/s",
+               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+               "kind": "oracle",
+               "sample": f"FP64 numpy network on 20000 of the queries, {reps} passes"}
+    out = {
+        "metric": "options/s surrogate vs tree", "value": value, "unit": "options/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 weights, f32 accumulation", "data": "synthetic",
+        "config": {"workload": "put surrogate 6-256-256-256-1 (Black-Scholes control "
+                               "variate): 1e6 queries (5 % outside the training box) per "
+                               "step; trained on 1e5 tree prices (N = 100, M = 2e6 "
+                               "pairs/layer, n in [10, 100])",
+                   "queries": Q, "act_terms": 2, "train_rows": int(xtr.shape[0]),
+                   "epochs": args.epochs},
+        "tree_options_per_s": tree_rate,
+        "with_fallback_options_per_s": blended,
+        "speedup_vs_tree": value / tree_rate,
+        "accuracy_r19": {"mean": float(err.mean()), "median": float(np.median(err)),
+                         "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
+                         "frac_le_1e-3": float(np.mean(err <= 1e-3))},
+        "train_s": fit_s, "final_loss": hist[-1],
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None,
+                     "kernel": "mlp_forward<2,false>"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_c1(args):
+    """1-D put, n = 10, N = 100 Lloyd points per layer, M = 1e5 paths
+    (pathwise, Algorithm II), S0 = K = 100, sigma = 0.2, r = 0.05, T = 1; one
+    step = forward + obstacle + BDP with V_0 on the host (a latency figure)."""
+    import torch
+    import paper_1101_3228_amd as qt
+    import synth
+    torch.cuda.set_device(0)
+    n, Nn, M = 10, 100, 100_000
+    spec = synth.bm_model(1, n, T=1.0)
+    grid, N = synth.layer_grids(spec, [1] + [Nn] * n, base=qt.gauss_quantizer)
+    plan = qt.Plan(spec, grid, N, device="cuda:0")
+    counts = plan.new_counts()
+    phi = plan.payoff(qt.PUT, S0, 100.0, RATE, 1.0, 0.2)
+
+    def step(i):
+        plan.transitions(M, 0x5EED0000 + i, mode=qt.PATHWISE, counts=counts)
+        return plan.bdp(counts, phi)[0]
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        V0 = step(i)
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / args.steps
+    print(json.dumps({
+        "metric": "MC transition samples/s (cell search+count)", "value": M * n / (ms * 1e-3),
+        "unit": "transitions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, int32 counts, f64 BDP", "data": "synthetic",
+        "config": {"workload": "1-D American put, pathwise: n=10, N=100, M=1e5 paths; "
+                               "forward + BDP + V0 to host per step (latency bound)"},
+        "V0": float(V0[0]), "roofline": None,
+        "roofline_note": "1e6 transitions per step: launch latency, not a throughput bound",
+    }), flush=True)
+
+
+def run_p1(args):
+    """The paper's own shape (context): 2-D Ornstein-Uhlenbeck state,
+    n = 365, N = 100 / 250 / 500 per layer, M = 1e5; time-layer parallel
+    (Algorithm III, pairs per layer) and pathwise (Algorithm II); each run
+    includes copying the counts to the host, as the paper's timings do."""
+    import torch
+    import paper_1101_3228_amd as qt
+    import synth
+    torch.cuda.set_device(0)
+    n, M = 365, 100_000
+    spec = synth.ou_model(n)
+    res = {}
+    for Nn in (100, 250, 500):
+        grid, N = synth.layer_grids(spec, [1] + [Nn] * n, base=qt.gauss_quantizer)
+        plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M)
+        counts = plan.new_counts()
+        host = torch.empty(counts.shape, dtype=counts.dtype, pin_memory=True)
+        for mode, name in ((qt.LAYERWISE, "alg3"), (qt.PATHWISE, "alg2")):
+            for i in range(args.warmup):
+                plan.transitions(M, 7 + i, mode=mode, counts=counts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                plan.transitions(M, 7 + i, mode=mode, counts=counts)
+                host.copy_(counts)
+            torch.cuda.synchronize()
+            s_run = (time.perf_counter() - t0) / args.steps
+            res[f"{name}_N{Nn}"] = {"s": s_run, "transitions_per_s": M * n / s_run}
+        log(f"N={Nn} done")
+    print(json.dumps({
+        "metric": "MC transition samples/s (cell search+count)",
+        "value": res["alg3_N500"]["transitions_per_s"], "unit": "transitions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["alg3_N500"]["s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, int32 counts", "data": "synthetic",
+        "config": {"workload": "paper shape (context): 2-D OU, n=365, N=100/250/500, M=1e5, "
+                               "Algorithms III and II, counts copied to the host per run"},
+        "runs": res,
+        "paper_context_gtx480_s": {"alg3": {"N100": 0.21, "N250": 0.50, "N500": 0.99},
+                                   "alg2": {"N100": 0.11, "N250": 0.30, "N500": 0.63}},
+        "roofline": None,
+    }), flush=True)
 
 
 if __name__ == "__main__":

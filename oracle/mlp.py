@@ -16,9 +16,12 @@ Network (parameters packed in one FP32 vector, rows = output units):
     z1  = W1 u + b1,            h1 = silu(z1)            W1: [256][6]
     z2  = W2 q(h1) + b2,        h2 = silu(z2)            W2: [256][256]
     z3  = W3 q(h2) + b3,        h3 = silu(z3)            W3: [256][256]
-    y   = s (w4 . h3 + b4)                               w4: [256], b4: scalar
-with silu(z) = z / (1 + e^-z).  The weight matrices W1, W2, W3, w4 take BF16
-values (the FP32 master copy rounded to nearest even); biases stay FP32.
+    y   = s (w4 . h3 + b4) + base(x)                     w4: [256], b4: scalar
+with silu(z) = z / (1 + e^-z); base(x) = 0, or with baseline = 1 the
+Black-Scholes European put per unit strike on the raw inputs (S0/K, sigma,
+r, T): e^{-rT} Phi(-d2) - (S0/K) Phi(-d1) (a control variate, inside the
+box).  The weight matrices W1, W2, W3, w4 take BF16 values (the FP32 master
+copy rounded to nearest even); biases stay FP32.
 q(h) is the activation as the matrix cores see it: the sum of `terms` BF16
 numbers (hi = bf16(h); with two terms also lo = bf16(h - hi)).  Layer 1 and
 the head are not matrix products (6 inputs, 1 output) and use h unrounded.
@@ -107,7 +110,18 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(p, x, lo, hi, out_scale: float, terms: int = 2, quantize: bool = True):
+def bs_put(x) -> np.ndarray:
+    """Black-Scholes European put per unit strike, rows (S0/K, sigma, r, T, ...)."""
+    from scipy.special import ndtr
+    x = np.asarray(x, np.float64)
+    s, sig, r, T = x[:, 0], x[:, 1], x[:, 2], x[:, 3]
+    v = sig * np.sqrt(T)
+    d1 = (np.log(s) + (r + 0.5 * sig * sig) * T) / v
+    return np.exp(-r * T) * ndtr(-(d1 - v)) - s * ndtr(-d1)
+
+
+def forward(p, x, lo, hi, out_scale: float, terms: int = 2, quantize: bool = True,
+            baseline: int = 0):
     """y [B] and the cache the backward needs."""
     W1, b1, W2, b2, W3, b3, w4, b4 = unpack(p)
     if quantize:
@@ -125,6 +139,9 @@ def forward(p, x, lo, hi, out_scale: float, terms: int = 2, quantize: bool = Tru
     z3 = a2 @ W3.T + b3
     h3 = silu(z3)
     y = out_scale * (h3 @ w4 + b4)
+    if baseline:
+        inside = in_range(x, lo, hi)
+        y = y + np.where(inside, bs_put(np.where(inside[:, None], x, 1.0)), 0.0)
     cache = dict(u=u, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3, h3=h3, W2=W2, W3=W3, w4=w4,
                  out_scale=out_scale)
     return y, cache
@@ -149,9 +166,10 @@ def backward(cache, dy) -> np.ndarray:
     return pack(dW1, db1, dW2, db2, dW3, db3, dw4, db4)
 
 
-def loss_and_grad(p, x, t, w, lo, hi, out_scale: float, terms: int = 2, quantize: bool = True):
+def loss_and_grad(p, x, t, w, lo, hi, out_scale: float, terms: int = 2, quantize: bool = True,
+                  baseline: int = 0):
     """(L, dL/dp, y) for L = sum_b w_b (y_b - t_b)^2 / B."""
-    y, cache = forward(p, x, lo, hi, out_scale, terms, quantize)
+    y, cache = forward(p, x, lo, hi, out_scale, terms, quantize, baseline)
     t = np.asarray(t, np.float64)
     w = np.ones_like(t) if w is None else np.asarray(w, np.float64)
     B = t.size

@@ -1,6 +1,6 @@
 """CPU checks of the C-ABI library: it loads, exports every function declared
-in include/qtree.h, rejects bad arguments on the host before any device
-work, and its host quantizer agrees with the oracle's."""
+in include/*.h, rejects bad arguments on the host before any device work,
+and its host quantizer agrees with the oracle's."""
 import ctypes
 import os
 import re
@@ -22,14 +22,19 @@ def L():
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "qtree.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(qtree_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for h in sorted(os.listdir(inc)):
+        if h.endswith(".h"):
+            src = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
+            names.update(re.findall(r"\b(qtree_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported(L):
     names = _declared()
     assert len(names) >= 15
+    assert "qtree_mlp_train_step" in names
     for name in names:
         assert hasattr(L, name), name
 
@@ -113,3 +118,40 @@ def test_library_quantizer_large_n_is_stationary(L):
         assert np.max(np.abs(lloyd_step(x) - x)) < 1e-11
         # Bucklew-Wise: N^2 D_N -> sqrt(3) pi / 2 from below
         assert 0.99 * np.sqrt(3) * np.pi / 2 < N * N * distortion(x) < np.sqrt(3) * np.pi / 2
+
+
+def test_mlp_validation_before_device_work(L):
+    from paper_1101_3228_amd import surrogate as S
+    S._setup()
+    nb = ctypes.c_size_t()
+    assert L.qtree_mlp_workspace_size(0, ctypes.byref(nb)) == 0
+    inference = nb.value
+    assert L.qtree_mlp_workspace_size(4096, ctypes.byref(nb)) == 0
+    assert nb.value > inference + 256 * 4096 * 4 * 6          # the training activations
+    assert L.qtree_mlp_workspace_size(-1, ctypes.byref(nb)) == 1
+    assert L.qtree_mlp_workspace_size((1 << 24) + 1, ctypes.byref(nb)) == 1
+    p = np.zeros(S.N_PARAMS, np.float32)
+    lo = np.zeros(6, np.float32)
+    hi = np.ones(6, np.float32)
+    h = ctypes.c_void_p()
+    fake = 1 << 20                                           # never dereferenced
+    args = dict(p=p.ctypes.data, lo=lo.ctypes.data, hi=hi.ctypes.data, s=0.1, terms=2,
+                base=0, mb=0, ws=fake, nb=inference)
+
+    def create(**kw):
+        a = dict(args, **kw)
+        return L.qtree_mlp_create(a["p"], a["lo"], a["hi"], a["s"], a["terms"], a["base"],
+                                  a["mb"], a["ws"], a["nb"], ctypes.byref(h))
+    assert create(terms=3) == 1
+    assert create(base=2) == 1
+    assert create(base=1) == 1                               # sigma_min = 0 in this box
+    assert create(s=0.0) == 1
+    assert create(mb=-5) == 1
+    assert create(ws=fake + 4) == 1                          # misaligned
+    assert create(p=None) == 1
+    bad = hi.copy()
+    bad[2] = -1.0                                            # lo > hi
+    assert create(hi=bad.ctypes.data) == 1
+    assert create(nb=inference - 1) == 2                     # ENOMEM
+    assert b"workspace" in L.qtree_last_error()
+    assert L.qtree_mlp_forward(None, None, 4, None, None, None) == 1

@@ -1,0 +1,222 @@
+"""GPU checks of the pricing surrogate (include/qtree_mlp.h) against the FP64
+oracle network (oracle/mlp.py) and the tree.
+
+Tolerances (derived from the arithmetic, see the design notes):
+* forward, two activation terms: the kernels round at the same points as the
+  oracle; what remains is FP32 arithmetic (fast exp / reciprocal in SiLU,
+  ~1e-7 relative per activation) and FP32 MFMA sums of 256 products, and
+  the split hi + lo carries 16 bits, so |y - y_ref| <= 1e-4 rms(y);
+* forward, one term: an FP32 activation within ~1e-7 of a BF16 rounding
+  boundary may round the other way than the FP64 one (one BF16 ulp, 2^-8
+  relative, on a fraction ~1e-4 of the activations), so
+  |y - y_ref| <= 3e-3 rms(y) and the mean <= 3e-4 rms(y);
+* gradients: the backward pass feeds BF16 activation gradients and BF16
+  layer inputs (one term) to the MFMA, ~2^-9 relative noise per product, so
+  per tensor ||g - g_ref|| <= 1e-2 ||g_ref|| and cosine >= 0.999;
+* the box mask is a comparison of the same FP32 numbers: exact.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from oracle import mlp as M
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1101_3228_amd as qt  # noqa: E402
+from paper_1101_3228_amd import surrogate as S  # noqa: E402
+
+LO, HI = synth.PUT_BOX_LO, synth.PUT_BOX_HI
+TENSORS = (("W1", M.OFF_W1, M.OFF_B1), ("b1", M.OFF_B1, M.OFF_W2), ("W2", M.OFF_W2, M.OFF_B2),
+           ("b2", M.OFF_B2, M.OFF_W3), ("W3", M.OFF_W3, M.OFF_B3), ("b3", M.OFF_B3, M.OFF_W4),
+           ("w4", M.OFF_W4, M.OFF_B4), ("b4", M.OFF_B4, M.N_PARAMS))
+
+
+def _case(name):
+    print(f"[gpu-case] {name}", flush=True)
+
+
+def _params(seed=1):
+    p = synth.mlp_init(seed)
+    rng = np.random.default_rng(seed + 100)
+    p[M.OFF_B1:M.OFF_W2] = rng.uniform(-0.5, 0.5, 256)
+    p[M.OFF_B2:M.OFF_W3] = rng.uniform(-0.5, 0.5, 256)
+    p[M.OFF_B3:M.OFF_W4] = rng.uniform(-0.5, 0.5, 256)
+    p[M.OFF_B4] = 0.3
+    return p
+
+
+@pytest.mark.parametrize("terms", [1, 2])
+@pytest.mark.parametrize("B", [1, 31, 1000, 4099])
+def test_forward_matches_oracle(terms, B):
+    _case(f"mlp forward terms={terms} B={B}")
+    p = _params()
+    x = synth.box_queries(B, 5 + B, frac_out=0.05)
+    net = S.MLP(p, LO, HI, out_scale=0.1, act_terms=terms)
+    y, m = net.forward(torch.from_numpy(x).cuda())
+    y = y.cpu().numpy().astype(np.float64)
+    yr, _ = M.forward(p, x, LO, HI, 0.1, terms=terms)
+    assert np.array_equal(m.cpu().numpy().astype(bool), M.in_range(x, LO, HI))
+    sc = np.sqrt(np.mean(yr ** 2))
+    d = np.abs(y - yr)
+    if terms == 2:
+        assert d.max() <= 1e-4 * sc
+    else:
+        assert d.max() <= 3e-3 * sc and d.mean() <= 3e-4 * sc
+    # the rounding points matter at these tolerances (the plain network differs)
+    if terms == 1 and B >= 1000:
+        y0, _ = M.forward(p, x, LO, HI, 0.1, quantize=False)
+        assert np.abs(y0 - yr).max() > 1e-3 * sc
+
+
+def test_forward_with_black_scholes_baseline():
+    """baseline = 1 adds the Black-Scholes put inside the box (FP32 erfc/log/
+    exp on the GPU, FP64 ndtr in the oracle; its two terms, each up to ~0.6,
+    cancel, so 2e-6 absolute on top of the network's tolerance)."""
+    _case("mlp forward baseline")
+    p = _params(3)
+    x = synth.box_queries(4099, 77, frac_out=0.05)
+    net = S.MLP(p, LO, HI, out_scale=0.1, act_terms=2, baseline=1)
+    y, m = net.forward(torch.from_numpy(x).cuda())
+    y = y.cpu().numpy().astype(np.float64)
+    inside = m.cpu().numpy().astype(bool)
+    yr, _ = M.forward(p, x, LO, HI, 0.1, terms=2, baseline=1)
+    sc = np.sqrt(np.mean(yr ** 2))
+    assert np.abs(y - yr)[inside].max() <= 1e-4 * sc + 2e-6
+    y0, _ = M.forward(p, x, LO, HI, 0.1, terms=2)
+    assert np.abs(y - y0)[~inside].max() <= 1e-4 * sc      # outside: no baseline
+
+
+def test_forward_empty_batch_and_mask_edges():
+    _case("mlp forward edges")
+    net = S.MLP(_params(), LO, HI, act_terms=2)
+    y, m = net.forward(torch.empty((0, 6), dtype=torch.float32, device="cuda"))
+    assert y.numel() == 0 and m.numel() == 0
+    x = np.tile(LO, (4, 1)).astype(np.float32)
+    x[1] = HI
+    x[2, 1] = np.nextafter(LO[1], np.float32(0))
+    x[3, 5] = 1e-7
+    _, m = net.forward(torch.from_numpy(x).cuda())
+    assert m.cpu().numpy().tolist() == [1, 1, 0, 0]
+
+
+@pytest.mark.parametrize("terms", [1, 2])
+@pytest.mark.parametrize("B", [300, 4096])
+def test_gradient_matches_oracle(terms, B):
+    _case(f"mlp grad terms={terms} B={B}")
+    p = _params(2)
+    rows = 5000
+    x = synth.box_queries(rows, 17)
+    rng = np.random.default_rng(3)
+    t = rng.uniform(0.0, 0.3, rows).astype(np.float32)
+    w = rng.uniform(0.5, 2.0, rows).astype(np.float32)
+    idx = rng.permutation(rows)[:B].astype(np.int32)
+    net = S.MLP(p, LO, HI, out_scale=0.1, act_terms=terms, max_batch=4096)
+    g, loss = net.grad(*(torch.from_numpy(a).cuda() for a in (x, t, w, idx)))
+    g = g.cpu().numpy().astype(np.float64)
+    L, gr, _ = M.loss_and_grad(p, x[idx], t[idx], w[idx], LO, HI, 0.1, terms=terms)
+    assert float(loss.item()) == pytest.approx(L, rel=2e-3 if terms == 1 else 1e-4)
+    for name, a, b in TENSORS:
+        ga, gb = g[a:b], gr[a:b]
+        nb = np.linalg.norm(gb)
+        assert np.linalg.norm(ga - gb) <= 1e-2 * nb, name
+        assert ga @ gb >= 0.999 * np.linalg.norm(ga) * nb, name
+
+
+def test_adam_steps_follow_oracle():
+    """Three Adam steps: at step t the update is lr m^/(sqrt(v^) + eps), a
+    sign-like step of size ~lr, so the GPU and oracle trajectories agree to a
+    small fraction of lr wherever the two gradients agree in sign."""
+    _case("mlp adam")
+    p = _params(4)
+    x = synth.box_queries(600, 19)
+    rng = np.random.default_rng(5)
+    t = rng.uniform(0.0, 0.3, 600).astype(np.float32)
+    net = S.MLP(p, LO, HI, out_scale=0.1, act_terms=2, max_batch=600)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    pr, mr, vr = p.astype(np.float64), np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS)
+    lr = 1e-3
+    for step in range(1, 4):
+        net.train_step(xd, td, None, None, 600, lr)
+        _, g, _ = M.loss_and_grad(pr, x, t, None, LO, HI, 0.1, terms=2)
+        pr, mr, vr = M.adam(pr, mr, vr, g, step, lr)
+    d = np.abs(net.params().astype(np.float64) - pr)
+    assert np.mean(d <= 0.05 * lr) >= 0.99
+    assert d.max() <= 6 * lr
+    # the parameters moved, and set_params restores them exactly
+    assert np.abs(net.params() - p).max() > 0.5 * lr
+    net.set_params(p)
+    assert np.array_equal(net.params(), p)
+
+
+def test_tree_labels_match_oracle():
+    """The label pricer's counts (unit-time Brownian tree, shared contract id) are
+    the oracle's bit for bit, and its Brownian-scaled put prices match the
+    oracle BDP on the oracle payoff with mix = sqrt(T) to 1e-9."""
+    _case("surrogate labels vs oracle")
+    pricer = S.PutTreePricer(N=60, M=300_001)
+    x = synth.box_queries(40, 23)
+    for n in (10, 13):
+        x[:, 4] = n
+        plan, counts = pricer.tree(n)
+        model = S.unit_bm_model(n)
+        grid, N = S.unit_bm_grid(n, 60)
+        mdl = O.Model(1, n, model["A"], model["b"], model["T"], model["mu"], model["L"],
+                      model["x0"])
+        ref = O.transitions(mdl, grid, N, 300_001, seed=pricer.seed, contract=pricer.contract,
+                            nthreads=8)
+        assert np.array_equal(counts.cpu().numpy(), ref)
+        got = pricer.price(x)
+        for q in range(0, 40, 7):
+            phi = O.payoff(O.PUT, 1, N, grid, float(x[q, 0]), 1.0, float(x[q, 2]),
+                           float(x[q, 3]), float(x[q, 1]), mix=[[np.sqrt(float(x[q, 3]))]])
+            V0, _, _ = O.bdp(ref, N, phi)
+            assert got[q] == pytest.approx(V0[0], rel=1e-9, abs=1e-15)
+
+
+def _r19(y, t):
+    return np.abs(y - t) / np.maximum(t, 1e-2)
+
+
+def test_surrogate_learns_tree_prices_and_falls_back():
+    """Trained on 2e4 tree solves, the network reproduces held-out in-box
+    prices; out-of-box queries are priced by the tree itself (bit-identical
+    to a direct tree solve)."""
+    _case("surrogate training + fallback")
+    pricer = S.PutTreePricer(N=60, M=400_000)
+    lo, hi = LO.copy(), HI.copy()
+    lo[4], hi[4] = 10, 16                       # few trees keep the test short
+    xtr = synth.box_queries(20_000, 31, lo, hi)
+    ytr = pricer.price(xtr)
+    sur = S.Surrogate(pricer, lo, hi, synth.mlp_init(7), out_scale=0.1, act_terms=2,
+                      max_batch=2048)
+    hist = sur.fit(xtr, ytr, epochs=60, lr=2e-3, lr_final=1e-5)
+    assert hist[-1] < 0.05 * hist[0]
+    xte = synth.box_queries(2000, 32, lo, hi, frac_out=0.05)
+    yte = pricer.price(xte)
+    yp, used = sur.price(xte)
+    inside = M.in_range(xte, lo, hi)
+    assert np.array_equal(used, ~inside)
+    assert np.array_equal(yp[~inside], yte[~inside])           # the tree, exactly
+    err = _r19(yp[inside], yte[inside])
+    print(f"R19 error: mean {err.mean():.2e} p99 {np.quantile(err, 0.99):.2e}", flush=True)
+    assert np.median(err) < 1e-2
+    # what the network gains: the same in-box queries, network against tree
+    import time
+    xin = torch.from_numpy(xte[inside]).cuda()
+    sur.net.forward(xin)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        sur.net.forward(xin)
+    torch.cuda.synchronize()
+    t_net = (time.perf_counter() - t0) / 10
+    t0 = time.perf_counter()
+    pricer.price(xte[inside])
+    torch.cuda.synchronize()
+    t_tree = time.perf_counter() - t0
+    print(f"options/s: network {inside.sum() / t_net:.3e}, tree {inside.sum() / t_tree:.3e}",
+          flush=True)
+    assert t_tree > 10 * t_net

@@ -164,6 +164,33 @@ def test_constant_network_closed_form():
     assert np.allclose(y, 0.5 * (np.sum(w4 * b3 / (1 + np.exp(-b3))) + 0.25), rtol=1e-14)
 
 
+def test_black_scholes_baseline():
+    """The control variate: the Black-Scholes put per unit strike against the
+    test helper's own formula, put-call parity, and its limits."""
+    from tests import _exact
+    x = synth.box_queries(200, 41)
+    b = M.bs_put(x)
+    for q in range(0, 200, 23):
+        s, sig, r, T = (float(v) for v in x[q, :4])
+        assert b[q] == pytest.approx(_exact.black_scholes_put(s, 1.0, r, sig, T), rel=1e-12)
+    # put-call parity with the call from the same d1, d2: C - P = S/K - e^{-rT}
+    from scipy.special import ndtr
+    s, sig, r, T = (x[:, c].astype(np.float64) for c in range(4))
+    v = sig * np.sqrt(T)
+    d1 = (np.log(s) + (r + 0.5 * sig ** 2) * T) / v
+    call = s * ndtr(d1) - np.exp(-r * T) * ndtr(d1 - v)
+    assert np.allclose(call - b, s - np.exp(-r * T), atol=1e-14)
+    assert np.all(b > 0) and np.all(b >= np.exp(-r * T) - s - 1e-15)
+    # the network adds it inside the box only
+    p = synth.mlp_init(12).astype(np.float64)
+    xb = synth.box_queries(50, 42, frac_out=0.2)
+    y0, _ = M.forward(p, xb, LO, HI, 0.1)
+    y1, _ = M.forward(p, xb, LO, HI, 0.1, baseline=1)
+    inside = M.in_range(xb, LO, HI)
+    assert np.allclose((y1 - y0)[inside], M.bs_put(xb[inside]), rtol=1e-12)
+    assert np.array_equal(y1[~inside], y0[~inside])
+
+
 def test_box_edges_and_fixed_slot():
     x = np.tile(LO, (6, 1)).astype(np.float32)
     x[1] = HI
