@@ -59,6 +59,12 @@ S0, RATE, MATURITY = 100.0, 0.05, 1.0
 ALG_SLOTS_PER_PAIR = 50 + 71 + 3 + 54 + 1
 PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
 
+# Algorithmic VALU lane-slots of one surrogate query (the matrix products run
+# on the MFMA units): 768 SiLU = 768 x (3 full-rate ops + exp and reciprocal
+# at quarter rate, 4 each) = 8448; 512 bias adds (layers 2, 3); 256 head FMAs;
+# 256 packed BF16 conversions of the 512 MFMA-layer inputs.
+MLP_SLOTS_PER_QUERY = 768 * 11 + 512 + 256 + 256
+
 
 def _measured_traffic(kernel: str = "fwd_keys_1d"):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
@@ -119,6 +125,8 @@ def main():
                          "p1: the paper's 2-D shape, n=365, N=100/250/500, M=1e5, both "
                          "algorithms, counts copied to the host")
     ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
+    ap.add_argument("--act-terms", type=int, default=1, choices=(1, 2),
+                    help="c5: BF16 terms per activation entering the MFMA layers")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -257,6 +265,16 @@ ALG_SLOTS_2D_PAIR = 100 + 142 + 12
 ALG_SLOTS_2D_POINT = 2.5
 
 
+def alg_slots_pair(d: int, Nk: int, Nk1: int) -> float:
+    """Algorithmic lane-slots of one pair from layer k (Nk points) to k+1:
+    1-D as ALG_SLOTS_PER_PAIR with the two search depths of these sizes,
+    d = 2 as ALG_SLOTS_2D_PAIR plus 2.5 per grid point of both layers."""
+    if d == 1:
+        depth = sum(max(0, int(np.ceil(np.log2(max(Nv, 1))))) for Nv in (Nk, Nk1))
+        return 50 + 71 + 3 + 1 + 3 * depth
+    return ALG_SLOTS_2D_PAIR + ALG_SLOTS_2D_POINT * (Nk + Nk1)
+
+
 def run_c3(args):
     """2-D max-call state, n = 30, N = 2000 (40 x 50 product of Lloyd grids
     mapped by sqrt(t_k) chol(R)), rho = 0.3, M = 1e7 pairs per layer; BDP of
@@ -381,6 +399,11 @@ def run_batch(args):
     pairs = sum(sp["n"] * sp["M"] for sp in specs)
     options = sum(it["phi"].shape[0] for it in items)
     info = batch.info()
+    alg = 0.0
+    for sp in specs:
+        Ns = [int(np.prod(v)) for v in sp["sizes"]]
+        alg += sp["M"] * sum(alg_slots_pair(sp["d"], Ns[k], Ns[k + 1]) for k in range(sp["n"]))
+    achieved = alg / (ms_step * 1e-3)
     out = {
         "metric": "MC transition samples/s (cell search+count); options/s (tree)",
         "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
@@ -393,6 +416,10 @@ def run_batch(args):
         "options_per_s": options / (ms_step * 1e-3),
         "batch": info, "prep_s": prep_s,
         "V0_mean": float(np.mean(V0)),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "kernel": "whole step (batch_keys_nd + batch_keys_1d + batch_count + "
+                               "bdp_batch_kernel); the per-kernel split is in the profile"},
     }
     print(json.dumps(out), flush=True)
 
@@ -416,7 +443,7 @@ def run_c5(args):
     ytr = pricer.price(xtr)
     log(f"labels: {time.perf_counter() - t_prep:.1f} s")
     sur = S.Surrogate(pricer, lo, hi, synth.mlp_init(0x5EED0001), out_scale=0.05,
-                      act_terms=2, max_batch=4096, baseline=1, device="cuda:0")
+                      act_terms=args.act_terms, max_batch=4096, baseline=1, device="cuda:0")
     t_fit = time.perf_counter()
     hist = sur.fit(xtr, ytr, epochs=args.epochs, lr=2e-3, lr_final=1e-6,
                    log=lambda e, l: e % 500 == 0 and log(f"epoch {e}: loss {l:.3e}"))
@@ -470,7 +497,7 @@ def run_c5(args):
         t0 = time.perf_counter()
         reps = 0
         while time.perf_counter() - t0 < 10.0:
-            OM.forward(p, xs, lo, hi, 0.05, terms=2, baseline=1)
+            OM.forward(p, xs, lo, hi, 0.05, terms=args.act_terms, baseline=1)
             reps += 1
         el = time.perf_counter() - t0
         cpu = {"value": reps * xs.shape[0] / el, "unit": "options/s",
@@ -486,7 +513,7 @@ def run_c5(args):
                                "variate): 1e6 queries (5 % outside the training box) per "
                                "step; trained on 1e5 tree prices (N = 100, M = 2e6 "
                                "pairs/layer, n in [10, 100])",
-                   "queries": Q, "act_terms": 2, "train_rows": int(xtr.shape[0]),
+                   "queries": Q, "act_terms": args.act_terms, "train_rows": int(xtr.shape[0]),
                    "epochs": args.epochs},
         "tree_options_per_s": tree_rate,
         "with_fallback_options_per_s": blended,
@@ -497,7 +524,12 @@ def run_c5(args):
         "train_s": fit_s, "final_loss": hist[-1],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": achieved / 2500.0, "traffic": None,
-                     "kernel": "mlp_forward<2,false>"},
+                     "kernel": f"mlp_forward<{args.act_terms},false>"},
+        # what binds this kernel in practice: SiLU on the vector ALUs
+        "valu_view": {"alg_slots_per_query": MLP_SLOTS_PER_QUERY,
+                      "achieved": MLP_SLOTS_PER_QUERY * value / 1e12,
+                      "peak": PEAK_SLOTS / 1e12, "unit": "Tlane-slot/s",
+                      "frac": MLP_SLOTS_PER_QUERY * value / PEAK_SLOTS},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

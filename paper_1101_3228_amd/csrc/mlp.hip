@@ -16,6 +16,11 @@
 // leaving the registers.  The weights are stored pre-permuted to match
 // (fragment (ib, t) of lane l = W[32 ib + l % 32][unit(t, l / 32, e)],
 // e = 0..7, 16 contiguous bytes per lane).
+//
+// Layer 1 (6 inputs) is one K-step per output block as well: the 16 K-slots
+// hold the normalised inputs as two BF16 terms, (u_hi[0..5], u_lo[0..5], 0 x4)
+// for lane halves h = 0 (slots 0..7) and h = 1 (slots 8..15), against
+// (W1[i][0..5], W1[i][0..5], 0 x4); the accumulators start from the biases.
 #include <hip/hip_runtime.h>
 
 #include "qtree_mlp_internal.hpp"
@@ -41,6 +46,12 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 
 __device__ __forceinline__ float bf16_float(uint16_t b) {
   return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+// Position of W1[i][c] in the layer-1 fragments: K-slot c (hi term) and
+// K-slot 6 + c (lo term); slot s lives in lane half s / 8, element s % 8.
+__host__ __device__ __forceinline__ int frag1_index(int i, int slot) {
+  return (((i >> 5) * 64) + 32 * (slot >> 3) + (i & 31)) * 8 + (slot & 7);
 }
 
 // Index of W[i][k] in the fragment layout described at the top.
@@ -77,14 +88,23 @@ __device__ __forceinline__ void to_operand(const float (&v)[16], bf16x8 (&op)[TE
   }
 }
 
-// acc[ib] = sum over the 16 K-steps of fragment(ib, t) x op[.][t].
+__device__ __forceinline__ int unit_of(int jb, int r, int h) {
+  return 32 * jb + 8 * (r >> 2) + 4 * h + (r & 3);
+}
+
+// acc[ib] = bias + sum over the 16 K-steps of fragment(ib, t) x op[.][t]
+// (bias: per-unit LDS array, or NULL for zero).
 template <int TERMS>
 __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ frags,
                                            const bf16x8 (&op)[TERMS][16], int lane,
-                                           f32x16 (&acc)[8]) {
+                                           const float* bias, f32x16 (&acc)[8]) {
   const bf16x8* wf = reinterpret_cast<const bf16x8*>(frags);
+  const int h = lane >> 5;
 #pragma unroll
-  for (int ib = 0; ib < 8; ++ib) acc[ib] = f32x16{};
+  for (int ib = 0; ib < 8; ++ib) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[ib][r] = bias ? bias[unit_of(ib, r, h)] : 0.0f;
+  }
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
 #pragma unroll
@@ -95,10 +115,6 @@ __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ frags,
         acc[ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, op[TERMS - 1][t], acc[ib], 0, 0, 0);
     }
   }
-}
-
-__device__ __forceinline__ int unit_of(int jb, int r, int h) {
-  return 32 * jb + 8 * (r >> 2) + 4 * h + (r & 3);
 }
 
 // Offset of accumulator r of block jb of a lane inside its wave's tile of a
@@ -134,10 +150,8 @@ struct FwdIO {
 // backward pass, and the loss gradient dL/dy replaces y.
 template <int TERMS, bool TRAIN>
 __global__ __launch_bounds__(kBlock) void mlp_forward(Weights W, FwdIO io, Train T) {
-  __shared__ float sw1[kHid * kIn];
   __shared__ float sb[3][kHid];
   __shared__ float sw4[kHid];
-  for (int i = threadIdx.x; i < kHid * kIn; i += kBlock) sw1[i] = bf16_float(W.w1[i]);
   for (int i = threadIdx.x; i < kHid; i += kBlock) {
     sb[0][i] = W.master[kOffB1 + i];
     sb[1][i] = W.master[kOffB2 + i];
@@ -172,16 +186,34 @@ __global__ __launch_bounds__(kBlock) void mlp_forward(Weights W, FwdIO io, Train
 
   bf16x8 op[TERMS][16];
   f32x16 acc[8];
-  // layer 1 (VALU): z1 = W1 u + b1, straight into the operand layout
+  {
+    // layer 1 (MFMA): z1 = b1 + W1 (u_hi + u_lo), one K-step per block
+    float q[16];
+#pragma unroll
+    for (int c = 0; c < kIn; ++c) {
+      const __bf16 a = (__bf16)u[c];
+      q[c] = (float)a;
+      q[kIn + c] = (float)(__bf16)(u[c] - (float)a);
+    }
+#pragma unroll
+    for (int c = 2 * kIn; c < 16; ++c) q[c] = 0.0f;
+    bf16x8 ub;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ub[e] = (__bf16)(h ? q[8 + e] : q[e]);
+    const bf16x8* w1f = reinterpret_cast<const bf16x8*>(W.w1);
+#pragma unroll
+    for (int ib = 0; ib < 8; ++ib) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[ib][r] = sb[0][unit_of(ib, r, h)];
+      acc[ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1f[ib * 64 + lane], ub, acc[ib], 0, 0, 0);
+    }
+  }
 #pragma unroll
   for (int jb = 0; jb < 8; ++jb) {
     float v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int unit = unit_of(jb, r, h);
-      float z = sb[0][unit];
-#pragma unroll
-      for (int c = 0; c < kIn; ++c) z = fmaf(sw1[unit * kIn + c], u[c], z);
+      const float z = acc[jb][r];
       v[r] = silu(z);
       if (TRAIN) {
         T.z1[tb + tile_off(jb, r)] = z;
@@ -191,14 +223,13 @@ __global__ __launch_bounds__(kBlock) void mlp_forward(Weights W, FwdIO io, Train
     to_operand<TERMS>(v, op, jb);
   }
   // layer 2 (MFMA)
-  mfma_layer<TERMS>(W.w2f, op, lane, acc);
+  mfma_layer<TERMS>(W.w2f, op, lane, nullptr, acc);
 #pragma unroll
   for (int jb = 0; jb < 8; ++jb) {
     float v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int unit = unit_of(jb, r, h);
-      const float z = acc[jb][r] + sb[1][unit];
+      const float z = acc[jb][r] + sb[1][unit_of(jb, r, h)];
       v[r] = silu(z);
       if (TRAIN) {
         T.z2[tb + tile_off(jb, r)] = z;
@@ -208,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void mlp_forward(Weights W, FwdIO io, Train
     to_operand<TERMS>(v, op, jb);
   }
   // layer 3 (MFMA) and the head
-  mfma_layer<TERMS>(W.w3f, op, lane, acc);
+  mfma_layer<TERMS>(W.w3f, op, lane, nullptr, acc);
   float part = 0.0f;
 #pragma unroll
   for (int jb = 0; jb < 8; ++jb) {
@@ -273,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void mlp_backward(Weights W, Train T) {
     }
     to_operand<1>(v, op, jb);
   }
-  mfma_layer<1>(W.w3t, op, lane, acc);  // dh2 = W3^T dz3
+  mfma_layer<1>(W.w3t, op, lane, nullptr, acc);  // dh2 = W3^T dz3
 #pragma unroll
   for (int jb = 0; jb < 8; ++jb) {
     float v[16];
@@ -285,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void mlp_backward(Weights W, Train T) {
     }
     to_operand<1>(v, op, jb);
   }
-  mfma_layer<1>(W.w2t, op, lane, acc);  // dh1 = W2^T dz2
+  mfma_layer<1>(W.w2t, op, lane, nullptr, acc);  // dh1 = W2^T dz2
 #pragma unroll
   for (int jb = 0; jb < 8; ++jb) {
 #pragma unroll
@@ -417,7 +448,11 @@ __global__ __launch_bounds__(kBlock) void mlp_adam(AdamArgs a) {
   }
   const uint16_t bits = bf16_bits(v);
   if (p < kOffB1) {
-    a.w1[p] = bits;
+    const int i = p / kIn, c = p % kIn;
+    a.w1[frag1_index(i, c)] = bits;
+    a.w1[frag1_index(i, kIn + c)] = bits;
+    if (c == 0)
+      for (int z = 2 * kIn; z < 16; ++z) a.w1[frag1_index(i, z)] = 0;
   } else if (p >= kOffW2 && p < kOffB2) {
     const int i = (p - kOffW2) >> 8, k = (p - kOffW2) & 255;
     a.w2f[frag_index(i, k)] = bits;

@@ -40,7 +40,7 @@ MlpLayout mlp_layout(int64_t max_batch) {
   L.mom = take(4 * P);
   L.vel = take(4 * P);
   L.grad = take(4 * P);
-  L.w1 = take(2 * M::kHid * M::kIn);
+  L.w1 = take(2 * M::kHid * 16);  // layer-1 fragments: 16 K-slots per row
   L.w4 = take(2 * M::kHid);
   L.w2f = take(2 * M::kHid * M::kHid);
   L.w3f = take(2 * M::kHid * M::kHid);

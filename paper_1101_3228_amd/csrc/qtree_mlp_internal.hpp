@@ -23,11 +23,11 @@ constexpr int kBlockRows = kBlock / 64 * kWaveRows;
 constexpr int kChunk = 256;          // samples per weight-gradient partial; training rows pad to it
 
 // Network as the kernels read it.  Matrix weights are BF16 (raw bits);
-// w2f / w3f hold W2, W3 as MFMA A-operand fragments (see mlp.hip), w2t / w3t
-// the same for the transposes.
+// w1f holds W1 as the A operand of one K-step (see mlp.hip), w2f / w3f hold
+// W2, W3 as MFMA A-operand fragments, w2t / w3t the same for the transposes.
 struct Weights {
   const float* master;  // FP32 packed parameters (biases are read from here)
-  const uint16_t* w1;   // [256][6]
+  const uint16_t* w1;   // [8][64][8] fragments of W1
   const uint16_t* w4;   // [256]
   const uint16_t* w2f;
   const uint16_t* w3f;
