@@ -72,12 +72,16 @@ struct qtree_batch {
   std::vector<qtree::BatchUnit> units;
   std::vector<qtree::BatchTile> tiles;
   std::vector<qtree::BdpJob> jobs;
+  std::vector<qtree::BdpTask> bdp_tasks;  // all backward steps, step by step
+  std::vector<int> step_off;              // tasks of step j: [step_off[j], step_off[j + 1])
+  int max_last = 0;                       // largest n_pay x N_n of a job
   std::vector<Group> groups;
   std::vector<double> unit_cost;
   qtree::BatchContract* d_contracts = nullptr;
   qtree::BatchUnit* d_units = nullptr;
   qtree::BatchTile* d_tiles = nullptr;
   qtree::BdpJob* d_jobs = nullptr;
+  qtree::BdpTask* d_bdp_tasks = nullptr;
   int* d_head = nullptr;
   uint16_t* d_keys = nullptr;
   uint32_t* d_segs = nullptr;
@@ -96,6 +100,7 @@ struct qtree_batch {
   ~qtree_batch() {
     if (exec) hipGraphExecDestroy(exec);
     for (void* p : {(void*)d_contracts, (void*)d_units, (void*)d_tiles, (void*)d_jobs,
+                    (void*)d_bdp_tasks,
                     (void*)d_head, (void*)d_keys, (void*)d_segs})
       if (p) hipFree(p);
   }
@@ -137,7 +142,8 @@ hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
     if (e == hipSuccess) e = qtree::launch_batch_count(group_args(b, g, 0), s);
     if (e != hipSuccess) return e;
   }
-  return qtree::launch_bdp_batch(b->d_jobs, (int)b->jobs.size(), s);
+  return qtree::launch_bdp_steps(b->d_jobs, (int)b->jobs.size(), b->max_last, b->d_bdp_tasks,
+                                 b->step_off.data(), (int)b->step_off.size() - 1, s);
 }
 
 bool has_units(const qtree_batch* b, int x) {
@@ -228,6 +234,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
       sig *= 1099511628211ull;
     }
   };
+  std::vector<int> job_contract;  // contract of every BDP job
   int maxP = 1, maxN = 1, max_tiles1 = 0, max_tilesn = 0;
   int64_t v0_off = 0;
   for (int i = 0; i < n; ++i) {
@@ -288,6 +295,8 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
       j.q0 = q0;
       j.nq = std::min(16, C.n_pay - q0);
       b->jobs.push_back(j);
+      job_contract.push_back(i);
+      b->max_last = std::max(b->max_last, j.nq * p->N[p->n]);
     }
     v0_off += C.n_pay;
   }
@@ -413,10 +422,27 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     b->groups.push_back(grp);
   }
 
+  // backward steps: step j is layer n - 1 - j of every job with n > j
+  int max_n = 0;
+  for (const qtree::BdpJob& j : b->jobs) max_n = std::max(max_n, (int)j.n);
+  b->step_off.assign(1, 0);
+  for (int step = 0; step < max_n; ++step) {
+    for (size_t jb = 0; jb < b->jobs.size(); ++jb) {
+      const qtree::BdpJob& J = b->jobs[jb];
+      if (J.n <= step) continue;
+      const int k = J.n - 1 - step;
+      const int rows = contracts[job_contract[jb]].plan->N[k];
+      for (int r0 = 0; r0 < rows; r0 += qtree::kBdpTaskRows)
+        b->bdp_tasks.push_back(qtree::BdpTask{(int32_t)jb, k, r0,
+                                              std::min(qtree::kBdpTaskRows, rows - r0)});
+    }
+    b->step_off.push_back((int)b->bdp_tasks.size());
+  }
   hipError_t e = upload(&b->d_contracts, b->hc);
   if (e == hipSuccess) e = upload(&b->d_units, b->units);
   if (e == hipSuccess) e = upload(&b->d_tiles, b->tiles);
   if (e == hipSuccess) e = upload(&b->d_jobs, b->jobs);
+  if (e == hipSuccess) e = upload(&b->d_bdp_tasks, b->bdp_tasks);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_head), 256);
   if (e == hipSuccess)
     e = hipMalloc(reinterpret_cast<void**>(&b->d_keys), scratch_keys * per_chunk_key + 16);

@@ -85,65 +85,78 @@ hipError_t launch_copy_last_layer(const BdpArgs& a, int64_t pt_n, int N_n, hipSt
   return hipGetLastError();
 }
 
-// Batched BDP: workgroup b runs job b -- one contract and up to kPay of its
-// payoffs through all layers, a barrier between layers (the recursion is
-// sequential in k; contracts and payoff groups run in parallel).
-constexpr int kBdpBlock = 1024;
+// Batched BDP.  The recursion is sequential in k, so it runs as backward
+// steps: step j takes layer n - 1 - j of every contract with n > j, its rows
+// cut into tasks of up to kBdpTaskRows rows, one wave per row (as
+// bdp_layer_kernel) for the job's up to kPay payoffs; a launch boundary
+// separates the steps.  Every contract's work is spread over the whole chip
+// at every step.
+constexpr int kBdpBlock = 64 * kBdpTaskRows;
 
-__global__ __launch_bounds__(kBdpBlock) void bdp_batch_kernel(const BdpJob* jobs) {
-  const BdpJob J = jobs[blockIdx.x];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int kW = kBdpBlock / 64;
+__global__ void bdp_batch_copy_kernel(const BdpJob* jobs) {
+  const BdpJob J = jobs[blockIdx.y];
   const LayerDev& Ln = J.layers[J.n];
-  for (int t = threadIdx.x; t < J.nq * Ln.N; t += kBdpBlock) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < J.nq * Ln.N; t += gridDim.x * blockDim.x) {
     const int q = t / Ln.N, i = t - q * Ln.N;
     const int64_t at = (int64_t)(J.q0 + q) * J.P + Ln.pt_off + i;
     J.V[at] = J.phi[at];
   }
-  for (int k = J.n - 1; k >= 0; --k) {
-    __syncthreads();
-    const LayerDev& L = J.layers[k];
-    const LayerDev& L1 = J.layers[k + 1];
-    const int32_t* cnt = J.counts + L.cnt_off;
-    for (int i = wave; i < L.N; i += kW) {
-      const int32_t* row = cnt + (int64_t)i * L.N1;
-      int64_t p = 0;
-      double s[kPay];
+}
+
+__global__ __launch_bounds__(kBdpBlock) void bdp_step_kernel(const BdpJob* jobs,
+                                                             const BdpTask* tasks) {
+  const BdpTask T = tasks[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave >= T.nrows) return;
+  const BdpJob& J = jobs[T.job];
+  const LayerDev& L = J.layers[T.k];
+  const LayerDev& L1 = J.layers[T.k + 1];
+  const int i = T.row0 + wave;
+  const int32_t* row = J.counts + L.cnt_off + (int64_t)i * L.N1;
+  int64_t p = 0;
+  double s[kPay];
 #pragma unroll
-      for (int q = 0; q < kPay; ++q) s[q] = 0.0;
-      for (int j = lane; j < L.N1; j += 64) {
-        const int32_t c = row[j];
-        p += c;
-        if (c != 0) {
-          const double cd = (double)c;
+  for (int q = 0; q < kPay; ++q) s[q] = 0.0;
+  for (int j = lane; j < L.N1; j += 64) {
+    const int32_t c = row[j];
+    p += c;
+    if (c != 0) {
+      const double cd = (double)c;
 #pragma unroll
-          for (int q = 0; q < kPay; ++q)
-            if (q < J.nq) s[q] = fma(cd, J.V[(int64_t)(J.q0 + q) * J.P + L1.pt_off + j], s[q]);
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        p += __shfl_xor(p, off, 64);
-#pragma unroll
-        for (int q = 0; q < kPay; ++q) s[q] += __shfl_xor(s[q], off, 64);
-      }
-      if (lane < J.nq) {
-        double sq = s[0];
-#pragma unroll
-        for (int q = 1; q < kPay; ++q)
-          if (lane == q) sq = s[q];
-        const double cont = p > 0 ? sq / (double)p : 0.0;
-        const int64_t at = (int64_t)(J.q0 + lane) * J.P + L.pt_off + i;
-        const double f = J.phi[at];
-        J.V[at] = f > cont ? f : cont;
-      }
+      for (int q = 0; q < kPay; ++q)
+        if (q < J.nq) s[q] = fma(cd, J.V[(int64_t)(J.q0 + q) * J.P + L1.pt_off + j], s[q]);
     }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    p += __shfl_xor(p, off, 64);
+#pragma unroll
+    for (int q = 0; q < kPay; ++q) s[q] += __shfl_xor(s[q], off, 64);
+  }
+  if (lane < J.nq) {
+    double sq = s[0];
+#pragma unroll
+    for (int q = 1; q < kPay; ++q)
+      if (lane == q) sq = s[q];
+    const double cont = p > 0 ? sq / (double)p : 0.0;
+    const int64_t at = (int64_t)(J.q0 + lane) * J.P + L.pt_off + i;
+    const double f = J.phi[at];
+    J.V[at] = f > cont ? f : cont;
   }
 }
 
-hipError_t launch_bdp_batch(const BdpJob* jobs, int n_jobs, hipStream_t s) {
+hipError_t launch_bdp_steps(const BdpJob* jobs, int n_jobs, int max_last, const BdpTask* tasks,
+                            const int* step_off, int n_steps, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bdp_batch_kernel, dim3((unsigned)n_jobs), dim3(kBdpBlock), 0, s, jobs);
+  const unsigned cx = (unsigned)((max_last + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(bdp_batch_copy_kernel, dim3(cx < 1 ? 1 : cx, (unsigned)n_jobs), dim3(kBlock),
+                     0, s, jobs);
+  for (int j = 0; j < n_steps; ++j) {
+    const int cnt = step_off[j + 1] - step_off[j];
+    if (cnt > 0)
+      hipLaunchKernelGGL(bdp_step_kernel, dim3((unsigned)cnt), dim3(kBdpBlock), 0, s, jobs,
+                         tasks + step_off[j]);
+  }
   return hipGetLastError();
 }
 

@@ -54,8 +54,7 @@ int batch_keys_occupancy(int dmax, size_t lds);
 size_t keys_lds_1d(int maxP, int max_tiles);
 size_t keys_lds_nd(int maxN, int max_tiles);
 
-// BDP of one contract for payoffs [q0, q0 + nq) (nq <= 16), all layers, in
-// one workgroup.
+// BDP of one contract for payoffs [q0, q0 + nq) (nq <= 16).
 struct BdpJob {
   const LayerDev* layers;
   const int32_t* counts;
@@ -65,6 +64,16 @@ struct BdpJob {
   int32_t n, q0, nq, pad_;
 };
 
-hipError_t launch_bdp_batch(const BdpJob* jobs, int n_jobs, hipStream_t s);
+// Rows [row0, row0 + nrows) of layer k of job `job` (nrows <= kBdpTaskRows).
+struct BdpTask {
+  int32_t job, k, row0, nrows;
+};
+constexpr int kBdpTaskRows = 16;
+
+// Backward steps of a batch: V_n = phi_n for every job (grid over jobs),
+// then step j = 0, 1, ... runs tasks [step_off[j], step_off[j + 1]) -- layer
+// n - 1 - j of every job with n > j -- one launch per step.
+hipError_t launch_bdp_steps(const BdpJob* jobs, int n_jobs, int max_last, const BdpTask* tasks,
+                            const int* step_off, int n_steps, hipStream_t s);
 
 }  // namespace qtree
