@@ -125,6 +125,8 @@ def main():
                          "p1: the paper's 2-D shape, n=365, N=100/250/500, M=1e5, both "
                          "algorithms, counts copied to the host")
     ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="c2/c3: layer groups of the two-pass forward (0: library default)")
     ap.add_argument("--act-terms", type=int, default=1, choices=(1, 2),
                     help="c5: BF16 terms per activation entering the MFMA layers")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -165,6 +167,8 @@ def main():
     spec, grid, N = _inputs()
     plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M_PAIRS)
     assert plan.batch_samples >= M_PAIRS, "counting scratch must hold one layer's samples"
+    if args.groups:
+        plan.tune(groups=args.groups)
     contracts = [(s, kr) for s in SIGMAS for kr in K_RATIOS]
     nc = len(contracts)
     kinds = np.full(nc, qt.PUT, np.int32)
@@ -287,6 +291,8 @@ def run_c3(args):
     spec = synth.bm_model(2, n, T=MATURITY, rho=0.3)
     grid, N = synth.layer_grids(spec, [1] + [(40, 50)] * n, base=qt.gauss_quantizer)
     plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M)
+    if args.groups:
+        plan.tune(groups=args.groups)
     counts = plan.new_counts()
     s_fwd = torch.cuda.current_stream()
     ev_keys = torch.cuda.Event(enable_timing=True)
@@ -476,7 +482,7 @@ def run_c5(args):
 
     # the tree on a sample of the same queries (counts cached; payoff + BDP)
     inside = mask.cpu().numpy().astype(bool)
-    sample = xq[:20_000]
+    sample = xq[:100_000]
     pricer.price(sample[:2000])
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -119,8 +119,20 @@ int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
  *                        the per-chunk sort fits in LDS),
  *                        1 one pass with a device-scope atomic per sample,
  *                        2 two-pass (per-chunk keys grouped by tile, then one
- *                        LDS histogram per tile; uses the workspace scratch). */
-typedef enum { QTREE_TUNE_CHUNK = 0, QTREE_TUNE_XCD_MAP = 1, QTREE_TUNE_COUNT = 2 } qtree_tune_key;
+ *                        LDS histogram per tile; uses the workspace scratch).
+ *   QTREE_TUNE_GROUPS  : two-pass only: the layers are split into this many
+ *                        groups (1..8, default 4); the histogram pass of a
+ *                        group runs on a stream of the plan, concurrently with
+ *                        the sampling pass of the next group.  The call still
+ *                        completes in order on `stream` (which waits for it).
+ *                        A plan used with groups > 1 must not be used from
+ *                        two host threads at once. */
+typedef enum {
+  QTREE_TUNE_CHUNK = 0,
+  QTREE_TUNE_XCD_MAP = 1,
+  QTREE_TUNE_COUNT = 2,
+  QTREE_TUNE_GROUPS = 3
+} qtree_tune_key;
 qtree_status qtree_plan_tune(qtree_plan *plan, int32_t key, int64_t value);
 
 /* Monte Carlo transition counts p^k_ij (Sec. 3 Algorithm I/II, Sec. 4
@@ -154,7 +166,8 @@ qtree_status qtree_transitions_add(const qtree_plan *plan, uint64_t m0, uint64_t
  *   p_i = sum_j c_ij; a row no sample reached (p_i = 0) has continuation 0.
  * counts: device int32 (as written by qtree_transitions); phi: device
  * double[n_pay][sum N_k] (use -inf for k < n to price a European claim);
- * V: device double[n_pay][sum N_k] output (all layers).  If V0_host is not
+ * V: device double[n_pay][sum N_k] output (all layers); 1 <= n_pay <= 2^20,
+ * one launch per layer for all payoffs.  If V0_host is not
  * NULL the call copies V_0 of every payoff there and synchronises `stream`
  * before returning; otherwise it is asynchronous. */
 qtree_status qtree_bdp(const qtree_plan *plan, const int32_t *counts, const double *phi,

@@ -161,14 +161,16 @@ class Plan:
         return self._h
 
     def tune(self, chunk: int | None = None, xcd_map: int | None = None,
-             count: int | None = None):
-        """Launch tuning (QTREE_TUNE_CHUNK / _XCD_MAP / _COUNT); results unchanged."""
+             count: int | None = None, groups: int | None = None):
+        """Launch tuning (QTREE_TUNE_CHUNK / _XCD_MAP / _COUNT / _GROUPS); results unchanged."""
         if chunk is not None:
             _check(lib().qtree_plan_tune(self._h, 0, int(chunk)))
         if xcd_map is not None:
             _check(lib().qtree_plan_tune(self._h, 1, int(xcd_map)))
         if count is not None:
             _check(lib().qtree_plan_tune(self._h, 2, int(count)))
+        if groups is not None:
+            _check(lib().qtree_plan_tune(self._h, 3, int(groups)))
         return self
 
     def count_offsets(self) -> np.ndarray:

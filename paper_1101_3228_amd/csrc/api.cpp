@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -259,6 +260,7 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     const int64_t entries_k = k < n ? (int64_t)N[k] * N[k + 1] : 0;
     L.tiles = (int32_t)((entries_k + qtree::kTile - 1) / qtree::kTile);
     L.tile_off = p.total_tiles;
+    p.tile_off.push_back(p.total_tiles);
     p.total_tiles += (int32_t)((entries_k + qtree::kSuper - 1) / qtree::kSuper);
     if (k < n) {
       std::memcpy(L.A, model->A + dd * k, sizeof(float) * dd);
@@ -333,10 +335,30 @@ static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uin
 
 // Two-pass LAYERWISE counting over [m0, m0 + M) in batches that fit the
 // scratch: pass A writes the keys of a batch, pass B folds them into counts.
+// The plan's stream and events for overlapped histogram passes.
+static hipError_t ensure_aux(const qtree_plan* p, int groups) {
+  hipError_t e = hipSuccess;
+  if (!p->aux) e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking);
+  for (int g = 0; g < groups && e == hipSuccess; ++g)
+    if (!p->fork[g]) e = hipEventCreateWithFlags(&p->fork[g], hipEventDisableTiming);
+  if (e == hipSuccess && !p->join) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+  return e;
+}
+
+// Two-pass forward over sample batches that fit the scratch.  The layers are
+// split into `groups`; with more than one, the histogram pass of group g runs
+// on the plan's stream while the sampling pass of group g + 1 runs on `s`
+// (the passes of different layers touch disjoint scratch), and `s` waits for
+// the histograms before the scratch is reused and before returning.
 static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hipStream_t s) {
   const uint64_t end = a.m0 + a.M;
   const uint64_t bs = p->d == 1 ? (uint64_t)p->batch_chunks * qtree::kChunk - 2
                                 : (uint64_t)p->batch_chunks * qtree::kChunk;
+  const int groups = std::max(1, std::min(p->tune_groups, p->n));
+  if (groups > 1) {
+    hipError_t e = ensure_aux(p, groups);
+    if (e != hipSuccess) return e;
+  }
   bool first = zero;
   for (uint64_t lo = a.m0; lo < end; lo += bs) {
     const uint64_t mb = (end - lo) < bs ? (end - lo) : bs;
@@ -351,20 +373,36 @@ static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hip
       chunks = (mb + qtree::kChunk - 1) / qtree::kChunk;
     }
     b.chunks = (int32_t)chunks;
-    b.units = p->n * b.chunks;
-    b.units_per_xcd = (b.units + 7) / 8;
     b.xcd_map = p->tune_xcd_map;
     b.first_batch = first ? 1 : 0;
-    hipError_t e = qtree::launch_fwd_keys(b, s);
-    if (e != hipSuccess) return e;
-    if (p->trace_keys) {
-      e = hipEventRecord(p->trace_keys, s);
-      if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (groups > 1 && lo > a.m0) e = hipStreamWaitEvent(s, p->join, 0);  // scratch reuse
+    for (int g = 0; g < groups && e == hipSuccess; ++g) {
+      const int k0 = (int)((int64_t)p->n * g / groups);
+      const int k1 = (int)((int64_t)p->n * (g + 1) / groups);
+      qtree::FwdArgs c = b;
+      c.layer0 = k0;
+      c.units = (k1 - k0) * b.chunks;
+      c.units_per_xcd = (c.units + 7) / 8;
+      c.tile0 = p->tile_off[k0];
+      c.total_tiles = p->tile_off[k1] - p->tile_off[k0];
+      e = qtree::launch_fwd_keys(c, s);
+      if (e != hipSuccess) break;
+      if (g == groups - 1 && p->trace_keys) e = hipEventRecord(p->trace_keys, s);
+      if (e != hipSuccess) break;
+      if (groups == 1) {
+        e = qtree::launch_count_tiles(c, s);
+      } else {
+        e = hipEventRecord(p->fork[g], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->aux, p->fork[g], 0);
+        if (e == hipSuccess) e = qtree::launch_count_tiles(c, p->aux);
+      }
     }
-    e = qtree::launch_count_tiles(b, s);
+    if (e == hipSuccess && groups > 1) e = hipEventRecord(p->join, p->aux);
     if (e != hipSuccess) return e;
     first = false;
   }
+  if (groups > 1) return hipStreamWaitEvent(s, p->join, 0);
   return hipSuccess;
 }
 
@@ -419,6 +457,12 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
     if (value == 2 && !plan->two_pass_ok)
       return fail(QTREE_EUNSUPPORTED, "count blocks too large for two-pass counting");
     plan->tune_count = (int32_t)value;
+    return QTREE_OK;
+  }
+  if (key == QTREE_TUNE_GROUPS) {
+    if (value < 1 || value > qtree_plan::kMaxGroups)
+      return fail(QTREE_EINVAL, "groups must be in 1..8");
+    plan->tune_groups = (int32_t)value;
     return QTREE_OK;
   }
   if (key == QTREE_TUNE_XCD_MAP) {
@@ -479,6 +523,7 @@ qtree_status qtree_bdp(const qtree_plan* plan, const int32_t* counts, const doub
   if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
   if (!counts || !phi || !V) return fail(QTREE_EINVAL, "counts, phi and V must be non-NULL");
   if (n_pay < 1) return fail(QTREE_EINVAL, "n_pay must be >= 1");
+  if (n_pay > (1 << 20)) return fail(QTREE_EINVAL, "n_pay must be <= 2^20");
   hipStream_t s = static_cast<hipStream_t>(stream);
   qtree::BdpArgs a{};
   a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);

@@ -17,12 +17,16 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kPay = 16;
 }  // namespace
 
+// One layer for every payoff: blockIdx.y selects the group of kPay payoffs
+// (the count row is re-read per group, from L2 for all but the first).
 __global__ __launch_bounds__(kBlock) void bdp_layer_kernel(BdpArgs a, int N_k, int N_k1,
                                                            int64_t pt_k, int64_t pt_k1,
-                                                           int64_t cnt_k, int q0, int nq) {
+                                                           int64_t cnt_k) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (i >= N_k) return;
+  const int q0 = blockIdx.y * kPay;
+  const int nq = (a.n_pay - q0) < kPay ? (a.n_pay - q0) : kPay;
   const int32_t* row = a.counts + cnt_k + (int64_t)i * N_k1;
   int64_t p = 0;
   double s[kPay];
@@ -70,11 +74,9 @@ hipError_t launch_bdp_layer(const BdpArgs& a, int k, int N_k, int N_k1, int64_t 
                             int64_t pt_k1, int64_t cnt_k, hipStream_t s) {
   (void)k;
   const unsigned blocks = (unsigned)((N_k + kWaves - 1) / kWaves);
-  for (int q0 = 0; q0 < a.n_pay; q0 += kPay) {
-    const int nq = (a.n_pay - q0) < kPay ? (a.n_pay - q0) : kPay;
-    hipLaunchKernelGGL(bdp_layer_kernel, dim3(blocks), dim3(kBlock), 0, s, a, N_k, N_k1, pt_k,
-                       pt_k1, cnt_k, q0, nq);
-  }
+  const unsigned groups = (unsigned)((a.n_pay + kPay - 1) / kPay);
+  hipLaunchKernelGGL(bdp_layer_kernel, dim3(blocks, groups), dim3(kBlock), 0, s, a, N_k, N_k1,
+                     pt_k, pt_k1, cnt_k);
   return hipGetLastError();
 }
 

@@ -314,8 +314,9 @@ __device__ __forceinline__ bool unit_of_block_keys(const FwdArgs& a, int& k, int
     u = (int)blockIdx.x;
   }
   if (u >= a.units) return false;
-  k = u / a.chunks;
-  chunk = u - k * a.chunks;
+  const int kl = u / a.chunks;
+  chunk = u - kl * a.chunks;
+  k = a.layer0 + kl;
   return true;
 }
 
@@ -356,10 +357,10 @@ __global__ __launch_bounds__(kBlockNd) void fwd_keys_nd(FwdArgs a) {
   keys_chunk_nd<D, S, kBlockNd>(plan_job(a, k, c), lds4);
 }
 
-// Workgroup b owns super tile t of layer k (b = tile_off_k + t).
+// Workgroup b owns super tile t of layer k (tile0 + b = tile_off_k + t).
 __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
   extern __shared__ uint32_t hist[];
-  const int b = (int)blockIdx.x;
+  const int b = a.tile0 + (int)blockIdx.x;
   int lo = 0, hi = a.n - 1;  // largest k with tile_off_k <= b
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;

@@ -77,8 +77,10 @@ struct FwdArgs {
   uint32_t* segs;
   int32_t seg_stride;     // max tiles + 1
   int32_t max_tiles;
-  int32_t total_tiles;    // sum of super tiles over layers (pass-B grid)
+  int32_t total_tiles;    // super tiles of this launch (pass-B grid)
   int32_t first_batch;    // pass B overwrites instead of adding
+  int32_t layer0;         // first layer of this launch (units and tiles)
+  int32_t tile0;          // first super tile of this launch
 };
 
 hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s);

@@ -20,10 +20,24 @@ struct qtree_plan {
   int64_t tune_chunk = 0;  // 0: automatic
   int32_t tune_xcd_map = 1;
   int32_t tune_count = 0;  // 0 automatic, 1 direct atomics, 2 two-pass
+  int32_t tune_groups = 4;  // layer groups of the two-pass forward
   int32_t max_tiles = 0, total_tiles = 0;
+  std::vector<int32_t> tile_off;  // first super tile of every layer (host copy)
   int64_t batch_chunks = 0;      // scratch chunks per layer per pass
   bool two_pass_ok = false;
   hipEvent_t trace_keys = nullptr;
+  // stream and events of the overlapped histogram passes (made on first use)
+  static constexpr int kMaxGroups = 8;
+  mutable hipStream_t aux = nullptr;
+  mutable hipEvent_t fork[kMaxGroups] = {};
+  mutable hipEvent_t join = nullptr;
+
+  ~qtree_plan() {
+    for (hipEvent_t& e : fork)
+      if (e) hipEventDestroy(e);
+    if (join) hipEventDestroy(join);
+    if (aux) hipStreamDestroy(aux);
+  }
 };
 
 namespace qtree {

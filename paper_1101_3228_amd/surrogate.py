@@ -176,7 +176,7 @@ class PutTreePricer:
     independent Monte Carlo draws."""
 
     def __init__(self, N: int = 100, M: int = 10_000_000, seed: int = 0x5EED0000,
-                 american: bool = True, device: str = "cuda", chunk: int = 2048,
+                 american: bool = True, device: str = "cuda", chunk: int = 8192,
                  contract: int = 0):
         self.N, self.M, self.seed, self.american = int(N), int(M), int(seed), bool(american)
         self.device, self.chunk, self.contract = device, int(chunk), int(contract)

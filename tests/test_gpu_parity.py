@@ -134,12 +134,13 @@ def test_counts_small_bitwise_and_schedule_free(small_case, mode):
     M, m0, seed = 200_001, 7_777, 0x5EED0011
     ref = O.transitions(mdl, grid, N, M, seed=seed, contract=5, mode=mode, m0=m0,
                         nthreads=THREADS)
-    for chunk, xmap, count in ((0, 1, 0), (0, 0, 2), (2, 0, 1), (4_098, 1, 1), (65_536, 0, 1),
-                               (333_333, 1, 1)):
-        plan.tune(chunk=chunk, xcd_map=xmap, count=count)
+    for chunk, xmap, count, groups in ((0, 1, 0, 2), (0, 0, 2, 1), (2, 0, 1, 2), (4_098, 1, 1, 2),
+                                       (65_536, 0, 1, 2), (333_333, 1, 1, 2), (0, 1, 2, 3),
+                                       (0, 1, 2, 8)):
+        plan.tune(chunk=chunk, xcd_map=xmap, count=count, groups=groups)
         got = plan.transitions(M, seed, contract=5, mode=mode, m0=m0).cpu().numpy()
-        assert np.array_equal(got, ref), (chunk, xmap, count)
-    plan.tune(chunk=0, xcd_map=1, count=0)
+        assert np.array_equal(got, ref), (chunk, xmap, count, groups)
+    plan.tune(chunk=0, xcd_map=1, count=0, groups=4)
 
 
 def test_counts_edge_sizes():
@@ -324,13 +325,15 @@ def test_two_pass_tiny_scratch_many_passes():
         grid, N = synth.layer_grids(spec, shapes)
         plan = qt.Plan(spec, grid, N, batch_samples=5000)
         assert 0 < plan.batch_samples < 20_000
-        ev = torch.cuda.Event(enable_timing=True)
-        plan.trace(ev)
-        got = plan.transitions(61_111, 5, m0=1).cpu().numpy()
-        plan.trace(None)
-        assert ev.query()
         ref = O.transitions(_omodel(spec), grid, N, 61_111, seed=5, m0=1, nthreads=THREADS)
-        assert np.array_equal(got, ref), d
+        for groups in (1, 3):                # histograms on the plan's stream when 3
+            plan.tune(groups=groups)
+            ev = torch.cuda.Event(enable_timing=True)
+            plan.trace(ev)
+            got = plan.transitions(61_111, 5, m0=1).cpu().numpy()
+            plan.trace(None)
+            assert ev.query()
+            assert np.array_equal(got, ref), (d, groups)
 
 
 def test_payoff_batch_matches_single():
