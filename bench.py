@@ -14,10 +14,14 @@ second over whole steps, every step's BDP included.
 
 Prints one JSON line.  Roofline of the dominant kernel (the sampling pass,
 fwd_keys_1d): algorithmic VALU lane-slots per pair (the fixed arithmetic of
-one pair, see ALG_SLOTS_PER_PAIR) times pairs per launch, divided by the
-launch duration measured with HIP events on the launch stream (the library
-records a trace event between its sampling and histogram passes), against
-the MI355X peak of 256 CUs x 64 lanes x 2.4 GHz lane-slots per second.
+one pair, see ALG_SLOTS_PER_PAIR) times the pairs of one step, divided by the
+time of the step's sampling launches measured with HIP events on their
+stream (from the start of the step to a trace event the library records
+after the last of them; the 1-D forward runs its layers in 4 groups, one
+sampling launch each, back to back on that stream, with the histogram
+passes on a second stream), against the MI355X peak of 256 CUs x 64 lanes x
+2.4 GHz lane-slots per second.  `traffic` is the HBM bytes of the same
+launches per step from the committed counter profile.
 """
 from __future__ import annotations
 

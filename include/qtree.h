@@ -121,7 +121,8 @@ int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
  *                        2 two-pass (per-chunk keys grouped by tile, then one
  *                        LDS histogram per tile; uses the workspace scratch).
  *   QTREE_TUNE_GROUPS  : two-pass only: the layers are split into this many
- *                        groups (1..8, default 4); the histogram pass of a
+ *                        groups (1..8; 0 = automatic, the default: 4 for
+ *                        d = 1, 1 for d >= 2); the histogram pass of a
  *                        group runs on a stream of the plan, concurrently with
  *                        the sampling pass of the next group.  The call still
  *                        completes in order on `stream` (which waits for it).

@@ -354,7 +354,10 @@ static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hip
   const uint64_t end = a.m0 + a.M;
   const uint64_t bs = p->d == 1 ? (uint64_t)p->batch_chunks * qtree::kChunk - 2
                                 : (uint64_t)p->batch_chunks * qtree::kChunk;
-  const int groups = std::max(1, std::min(p->tune_groups, p->n));
+  // automatic: four groups hide most of the 1-D histogram pass; for d >= 2
+  // that pass is ~1 % of the forward and more launches only add tails
+  const int want = p->tune_groups > 0 ? p->tune_groups : (p->d == 1 ? 4 : 1);
+  const int groups = std::max(1, std::min(want, p->n));
   if (groups > 1) {
     hipError_t e = ensure_aux(p, groups);
     if (e != hipSuccess) return e;
@@ -460,8 +463,8 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
     return QTREE_OK;
   }
   if (key == QTREE_TUNE_GROUPS) {
-    if (value < 1 || value > qtree_plan::kMaxGroups)
-      return fail(QTREE_EINVAL, "groups must be in 1..8");
+    if (value < 0 || value > qtree_plan::kMaxGroups)
+      return fail(QTREE_EINVAL, "groups must be in 0..8");
     plan->tune_groups = (int32_t)value;
     return QTREE_OK;
   }

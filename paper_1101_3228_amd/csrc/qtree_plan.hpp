@@ -20,7 +20,7 @@ struct qtree_plan {
   int64_t tune_chunk = 0;  // 0: automatic
   int32_t tune_xcd_map = 1;
   int32_t tune_count = 0;  // 0 automatic, 1 direct atomics, 2 two-pass
-  int32_t tune_groups = 4;  // layer groups of the two-pass forward
+  int32_t tune_groups = 0;  // layer groups of the two-pass forward (0: automatic)
   int32_t max_tiles = 0, total_tiles = 0;
   std::vector<int32_t> tile_off;  // first super tile of every layer (host copy)
   int64_t batch_chunks = 0;      // scratch chunks per layer per pass

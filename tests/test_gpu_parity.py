@@ -140,7 +140,7 @@ def test_counts_small_bitwise_and_schedule_free(small_case, mode):
         plan.tune(chunk=chunk, xcd_map=xmap, count=count, groups=groups)
         got = plan.transitions(M, seed, contract=5, mode=mode, m0=m0).cpu().numpy()
         assert np.array_equal(got, ref), (chunk, xmap, count, groups)
-    plan.tune(chunk=0, xcd_map=1, count=0, groups=4)
+    plan.tune(chunk=0, xcd_map=1, count=0, groups=0)
 
 
 def test_counts_edge_sizes():
