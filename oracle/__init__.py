@@ -72,6 +72,11 @@ def lib():
         L.oracle_payoff.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, P, P, P]
+        L.oracle_forward_payoff.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, P, P, P]
+        L.oracle_swing.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, P]
+        L.oracle_swing.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -191,6 +196,36 @@ def bdp(counts: np.ndarray, N, phi: np.ndarray, want_all: bool = False):
 
 
 PUT, MAX_CALL, EUROPEAN = 0, 1, 2
+
+
+def forward_payoff(model: dict, N, grid: np.ndarray, S0: float, K: float, r: float, T: float,
+                   sigma, mix=None) -> np.ndarray:
+    """v_k(x) = e^{-r t_k} (S0 exp(sigma . mix (x - mu_k) - var_k / 2) - K) on the grid."""
+    d = int(model["d"])
+    N = np.ascontiguousarray(N, np.int32)
+    n = N.size - 1
+    g = np.ascontiguousarray(grid, np.float32)
+    mu = np.ascontiguousarray(model["mu"], np.float32)
+    L = np.ascontiguousarray(model["L"], np.float32)
+    sig = np.ascontiguousarray(np.resize(np.atleast_1d(np.asarray(sigma, np.float64)), d))
+    mx = None if mix is None else np.ascontiguousarray(np.asarray(mix, np.float64).reshape(d, d))
+    v = np.zeros(int(point_offsets(N)[-1]), np.float64)
+    lib().oracle_forward_payoff(d, n, _ptr(N), _ptr(g), _ptr(mu), _ptr(L), S0, K, r, T,
+                                _ptr(sig), None if mx is None else _ptr(mx), _ptr(v))
+    return v
+
+
+def swing(counts: np.ndarray, N, v: np.ndarray, Qmin: int, Qmax: int, want_all: bool = False):
+    """Swing option by the bang-bang BDP in FP64: (P0, P_all [Qmax+1][points] or None)."""
+    N = np.ascontiguousarray(N, np.int32)
+    n = N.size - 1
+    P = int(point_offsets(N)[-1])
+    c = np.ascontiguousarray(counts, np.int32)
+    vv = np.ascontiguousarray(v, np.float64)
+    P_all = np.zeros((Qmax + 1, P), np.float64) if want_all else None
+    P0 = lib().oracle_swing(_ptr(c), _ptr(N), n, _ptr(vv), int(Qmin), int(Qmax),
+                            _ptr(P_all) if want_all else None)
+    return float(P0), P_all
 
 
 def payoff(kind: int, d: int, N, grid: np.ndarray, S0: float, K: float, r: float, T: float,

@@ -491,6 +491,83 @@ void oracle_payoff(int32_t kind, int32_t d, int32_t n, const int32_t *N, const f
   }
 }
 
+void oracle_forward_payoff(int32_t d, int32_t n, const int32_t *N, const float *grid,
+                           const float *mu, const float *L, double S0, double K, double r,
+                           double Tm, const double *sigma, const double *mix, double *v) {
+  int64_t off = 0;
+  for (int32_t k = 0; k <= n; ++k) {
+    const double t = Tm * (double)k / (double)n;
+    const double disc = exp(-r * t);
+    /* w = mix' sigma: s_k = w . x */
+    double w[3];
+    for (int b = 0; b < d; ++b) {
+      w[b] = 0.0;
+      for (int a = 0; a < d; ++a) w[b] += sigma[a] * (mix ? mix[a * d + b] : (a == b ? 1.0 : 0.0));
+    }
+    /* var_k = |L_k' w|^2, mean term w . mu_k */
+    const float *Lk = L + (size_t)k * d * d;
+    double var = 0.0, wm = 0.0;
+    for (int c = 0; c < d; ++c) {
+      double u = 0.0;
+      for (int b = 0; b < d; ++b) u += w[b] * (double)Lk[b * d + c];
+      var += u * u;
+    }
+    for (int b = 0; b < d; ++b) wm += w[b] * (double)mu[(size_t)k * d + b];
+    for (int32_t i = 0; i < N[k]; ++i) {
+      const float *x = grid + (off + i) * d;
+      double s = 0.0;
+      for (int b = 0; b < d; ++b) s += w[b] * (double)x[b];
+      v[off + i] = disc * (S0 * exp(s - wm - 0.5 * var) - K);
+    }
+    off += N[k];
+  }
+}
+
+double oracle_swing(const int32_t *counts, const int32_t *N, int32_t n, const double *v,
+                    int32_t Qmin, int32_t Qmax, double *P_all) {
+  const int32_t C = Qmax + 1;
+  int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 2));
+  int64_t *coff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  poff[0] = 0;
+  coff[0] = 0;
+  for (int32_t k = 0; k <= n; ++k) poff[k + 1] = poff[k] + N[k];
+  for (int32_t k = 0; k < n; ++k) coff[k + 1] = coff[k] + (int64_t)N[k] * N[k + 1];
+  const int64_t P = poff[n + 1];
+  double *V = (double *)malloc(sizeof(double) * (size_t)P * (size_t)C);  /* [c][P] */
+  for (int32_t c = 0; c < C; ++c)
+    for (int32_t i = 0; i < N[n]; ++i)
+      V[(size_t)c * P + poff[n] + i] = (c >= Qmin && c <= Qmax) ? 0.0 : -INFINITY;
+  double *cont = (double *)malloc(sizeof(double) * (size_t)(C + 1));
+  for (int32_t k = n - 1; k >= 0; --k) {
+    const int32_t *ck = counts + coff[k];
+    for (int32_t i = 0; i < N[k]; ++i) {
+      int64_t p = 0;
+      for (int32_t j = 0; j < N[k + 1]; ++j) p += ck[(int64_t)i * N[k + 1] + j];
+      for (int32_t c = 0; c < C; ++c) {
+        double s = 0.0;
+        for (int32_t j = 0; j < N[k + 1]; ++j) {
+          const int32_t cij = ck[(int64_t)i * N[k + 1] + j];
+          if (cij) s += (double)cij * V[(size_t)c * P + poff[k + 1] + j];
+        }
+        cont[c] = p > 0 ? s / (double)p : 0.0;
+      }
+      for (int32_t c = 0; c < C; ++c) {
+        double best = -INFINITY;
+        for (int x = 0; x <= 1; ++x) {
+          if (c + x > Qmax || c + x + (n - k - 1) < Qmin) continue;
+          const double val = (x ? v[poff[k] + i] : 0.0) + cont[c + x];
+          if (val > best) best = val;
+        }
+        V[(size_t)c * P + poff[k] + i] = best;
+      }
+    }
+  }
+  const double P0 = V[0];
+  if (P_all) memcpy(P_all, V, sizeof(double) * (size_t)P * (size_t)C);
+  free(cont); free(V); free(poff); free(coff);
+  return P0;
+}
+
 /* Bulk helpers for the exhaustive and statistical tests (plain loops). */
 void oracle_ln_u24_bulk(uint32_t K0, int64_t count, float *out) {
   for (int64_t i = 0; i < count; ++i) out[i] = oracle_ln_u24(K0 + (uint32_t)i);

@@ -71,6 +71,30 @@ void oracle_payoff(int32_t kind, int32_t d, int32_t n, const int32_t *N, const f
                    double S0, double K, double r, double Tm, const double *sigma,
                    const double *mix, double *phi);
 
+/* Forward on the sum of the factors (obstacle of the swing contract on the
+   2-factor model, Sec. 3): with y = mix x (mix NULL: identity) and
+   s_k = sum_a sigma_a y_a,
+     v_k(x) = exp(-r t_k) (S0 exp(s_k - sigma' mix mu_k - var_k / 2) - K),
+   var_k = |L_k' mix' sigma|^2 the variance of s_k under the marginal law
+   X_k = mu_k + L_k z, so that E S_k = S0.  mu: [n+1][d], L: [n+1][d][d]
+   (FP32 model inputs), t_k = k Tm / n.  No positive part. */
+void oracle_forward_payoff(int32_t d, int32_t n, const int32_t *N, const float *grid,
+                           const float *mu, const float *L, double S0, double K, double r,
+                           double Tm, const double *sigma, const double *mix, double *v);
+
+/* Swing option on the tree (Sec. 2: the stochastic control problem with a
+   bang-bang control): exercise dates k = 0..n-1, q_k in {0, 1}, total
+   consumption in [Qmin, Qmax] (0 <= Qmin <= Qmax <= n).  The state is the
+   consumption c used before date k; x in {0, 1} is feasible at (k, c) when
+   c + x <= Qmax and c + x + (n - k - 1) >= Qmin.
+     P_n(c)   = 0 for Qmin <= c <= Qmax, -inf otherwise,
+     P_k(i,c) = max over feasible x of  x v_k(i) + cont_k(i, c + x),
+     cont_k(i, c') = sum_j c_ij P_{k+1}(j, c') / p_i   (0 for an empty row),
+   -inf where no x is feasible.  v: [sum N_k] (layer n unused).  P_all
+   (optional): [Qmax + 1][sum N_k].  Returns P_0(0, 0). */
+double oracle_swing(const int32_t *counts, const int32_t *N, int32_t n, const double *v,
+                    int32_t Qmin, int32_t Qmax, double *P_all);
+
 /* Bulk helpers for tests. */
 void oracle_ln_u24_bulk(uint32_t K0, int64_t count, float *out);
 void oracle_sincos_bulk(uint32_t J0, int64_t count, float *s, float *c);
