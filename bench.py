@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
-    ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1"),
+    ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1", "swing"),
                     default="c2",
                     help="c2 (default): the 1-D time-layer workload of the headline metric; "
                          "c3: 2-D max-call, n=30, N=2000, M=1e7; batch: 256 uneven "
@@ -127,7 +127,9 @@ def main():
                          "put surrogate, 1e6 queries per step after training on 1e5 tree "
                          "prices; c1: 1-D pathwise put, n=10, N=100, M=1e5 paths (latency); "
                          "p1: the paper's 2-D shape, n=365, N=100/250/500, M=1e5, both "
-                         "algorithms, counts copied to the host")
+                         "algorithms, counts copied to the host; swing: the paper's swing "
+                         "contract shape, 2-D OU, n=365, N=100 and 500, M=1e5, volume "
+                         "constraints (100, 250)")
     ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
     ap.add_argument("--groups", type=int, default=0,
                     help="c2/c3: layer groups of the two-pass forward (0: library default)")
@@ -162,6 +164,8 @@ def main():
         return run_c1(args)
     if args.workload == "p1":
         return run_p1(args)
+    if args.workload == "swing":
+        return run_swing(args)
 
     import torch
     import paper_1101_3228_amd as qt
@@ -625,6 +629,79 @@ def run_p1(args):
         "paper_context_gtx480_s": {"alg3": {"N100": 0.21, "N250": 0.50, "N500": 0.99},
                                    "alg2": {"N100": 0.11, "N250": 0.30, "N500": 0.63}},
         "roofline": None,
+    }), flush=True)
+
+
+PEAK_FP64 = 78.6e12  # MI355X FP64 vector FLOP/s
+
+
+def run_swing(args):
+    """The swing contract of the paper's own workload shape (Sec. 3): 2-D
+    Ornstein-Uhlenbeck factors (alpha = 1 and 5, rho = -0.4), n = 365 daily
+    dates, N = 100 (10 x 10) and 500 (20 x 25) points per layer, M = 1e5
+    pairs per layer (time-layer parallel), forward on the factor sum
+    (sigma = 0.7 / 1.4, S0 = K = 20), volume in [100, 250].  One step =
+    forward step + obstacle + swing BDP with P0 on the host."""
+    import torch
+    import paper_1101_3228_amd as qt
+    import synth
+    torch.cuda.set_device(0)
+    n, M, Qmin, Qmax = 365, 100_000, 100, 250
+    spec = synth.ou_model(n, alpha=(1.0, 5.0), sig=(1.0, 1.0), rho=-0.4)
+    runs = {}
+    for Nn, side in ((100, (10, 10)), (500, (20, 25))):
+        grid, N = synth.layer_grids(spec, [1] + [side] * n, base=qt.gauss_quantizer)
+        plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M)
+        counts = plan.new_counts()
+        v = torch.empty(plan.points, dtype=torch.float64, device="cuda:0")
+        P = torch.empty((plan.points, Qmax + 1), dtype=torch.float64, device="cuda:0")
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+        def step(i, timed=False):
+            if timed:
+                ev[0].record(stream)
+            plan.transitions(M, 0x5EED0000 + i, counts=counts)
+            plan.payoff_forward(20.0, 20.0, 0.0, 1.0, [0.7, 1.4], out=v)
+            if timed:
+                ev[1].record(stream)
+            p0, _ = plan.swing(counts, v, Qmin, Qmax, P=P, want_p0=False)
+            if timed:
+                ev[2].record(stream)
+        for i in range(args.warmup):
+            step(i)
+        torch.cuda.synchronize()
+        fwd_ms = bdp_ms = 0.0
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(i, timed=True)
+            torch.cuda.synchronize()
+            fwd_ms += ev[0].elapsed_time(ev[1])
+            bdp_ms += ev[1].elapsed_time(ev[2])
+        wall = (time.perf_counter() - t0) / args.steps
+        P0, _ = plan.swing(counts, v, Qmin, Qmax, P=P)
+        nnz = int((counts != 0).sum().item())
+        flop = 2.0 * nnz * (Qmax + 1)
+        runs[f"N{Nn}"] = {"fwd_ms": fwd_ms / args.steps, "swing_bdp_ms": bdp_ms / args.steps,
+                          "step_ms": wall * 1e3, "transitions_per_s": M * n / (fwd_ms / args.steps * 1e-3),
+                          "P0": P0, "nnz_counts": nnz,
+                          "swing_fp64_frac": flop / (bdp_ms / args.steps * 1e-3) / PEAK_FP64}
+        log(f"N={Nn} done")
+    r5 = runs["N500"]
+    print(json.dumps({
+        "metric": "MC transition samples/s (cell search+count)",
+        "value": r5["transitions_per_s"], "unit": "transitions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r5["step_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, int32 counts, f64 swing BDP", "data": "synthetic",
+        "config": {"workload": "swing contract, paper shape: 2-D OU, n=365, N=100/500, M=1e5 "
+                               "pairs/layer, volume in [100, 250]; forward + obstacle + swing BDP"},
+        "runs": runs,
+        "roofline": {"bound": "alu", "achieved": 2.0 * r5["nnz_counts"] * (Qmax + 1)
+                     / (r5["swing_bdp_ms"] * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s (FP64)", "frac": r5["swing_fp64_frac"], "traffic": None,
+                     "kernel": "swing_layer_kernel (2 FLOP per nonzero count and volume level)"},
+        "paper_context_gtx480_s": {"alg3_estimation": {"N100": 0.21, "N500": 0.99}},
     }), flush=True)
 
 

@@ -194,6 +194,35 @@ qtree_status qtree_payoff_batch(const qtree_plan *plan, int32_t n_pay, const int
                                 const double *Tm, const double *sigma, const double *mix,
                                 double *phi, void *stream);
 
+/* Forward on the sum of the factors, the obstacle of the swing contract on
+ * the Gaussian factor model (Sec. 3: S_t = s0 exp(sum_a sigma_a X^a_t -
+ * mu_t / 2)), FP64, device output v: double[sum N_k]:
+ *   v_k(x) = exp(-r t_k) (S0 exp(s_k(x) - w . mu_k - var_k / 2) - K),
+ *   s_k(x) = w . x,  w = mix' sigma,  var_k = |L_k' w|^2,
+ * with the plan's marginal X_k = mu_k + L_k z, so that E S_k = S0 (no
+ * positive part).  sigma: host double[d]; mix: host double[d][d] or NULL
+ * (identity).  t_k = k Tm / n.  Asynchronous. */
+qtree_status qtree_payoff_forward(const qtree_plan *plan, double S0, double K, double r,
+                                  double Tm, const double *sigma, const double *mix, double *v,
+                                  void *stream);
+
+/* Swing option on the tree (Sec. 2: the stochastic control problem with
+ * volume constraints, whose optimal control is bang-bang), FP64.  Dates
+ * k = 0..n-1, q_k in {0, 1}, sum_k q_k in [Qmin, Qmax] (0 <= Qmin <= Qmax
+ * <= n, Qmax <= 2046).  State: the volume c consumed before date k;
+ *   P_n(c) = 0 for Qmin <= c <= Qmax, -inf otherwise,
+ *   P_k(i, c) = max over x in {0, 1} with c + x <= Qmax and
+ *               c + x + (n - k - 1) >= Qmin of x v_k(i) + cont_k(i, c + x),
+ *   cont_k(i, c') = sum_j c_ij P_{k+1}(j, c') / p_i (0 for a row no sample
+ *   reached), -inf where no x is feasible.
+ * counts: as written by qtree_transitions; v: device double[sum N_k]
+ * (layer n unused), e.g. from qtree_payoff_forward; P: device
+ * double[sum N_k][Qmax + 1] output (grid point major: the volume levels
+ * of a point are contiguous; all layers).  If P0_host is not NULL the call
+ * copies P_0(0, 0) there and synchronises `stream`.  One launch per layer. */
+qtree_status qtree_swing(const qtree_plan *plan, const int32_t *counts, const double *v,
+                         int32_t Qmin, int32_t Qmax, double *P, double *P0_host, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches: many contracts with uneven n and N_k priced together.
  * Each contract names a plan (model + grids, created as above), the samples

@@ -79,6 +79,10 @@ def lib() -> ctypes.CDLL:
     L.qtree_plan_batch_samples.restype = i64
     L.qtree_payoff_batch.argtypes = [P, i32, P, P, P, P, P, P, P, P, P]
     L.qtree_payoff_batch.restype = ctypes.c_int
+    L.qtree_payoff_forward.argtypes = [P, f64, f64, f64, f64, P, P, P, P]
+    L.qtree_payoff_forward.restype = ctypes.c_int
+    L.qtree_swing.argtypes = [P, P, P, i32, i32, P, P, P]
+    L.qtree_swing.restype = ctypes.c_int
     L.qtree_layer_samples.argtypes = [P, i32, u64, i64, u64, u32, P, P, P]
     L.qtree_cells.argtypes = [P, i32, P, i64, P, P]
     for f in ("qtree_workspace_size", "qtree_plan_create", "qtree_transitions", "qtree_bdp",
@@ -244,6 +248,36 @@ class Plan:
                                   _np_ptr(sig), None if mx is None else _np_ptr(mx),
                                   out.data_ptr(), _stream_handle(stream)))
         return out
+
+    def payoff_forward(self, S0: float, K: float, r: float, T: float, sigma, mix=None,
+                       out=None, stream=None):
+        """Forward on the sum of the factors, e^{-r t_k}(S_k - K), on the grid
+        points (device float64 [points])."""
+        import torch
+        sig = np.ascontiguousarray(np.resize(np.atleast_1d(np.asarray(sigma, np.float64)),
+                                             self.d), np.float64)
+        mx = None if mix is None else np.ascontiguousarray(
+            np.asarray(mix, np.float64).reshape(self.d, self.d))
+        if out is None:
+            out = torch.empty(self.points, dtype=torch.float64, device=self.workspace.device)
+        _check(lib().qtree_payoff_forward(self._h, float(S0), float(K), float(r), float(T),
+                                          _np_ptr(sig), None if mx is None else _np_ptr(mx),
+                                          out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def swing(self, counts, v, Qmin: int, Qmax: int, P=None, want_p0: bool = True,
+              stream=None):
+        """Swing option (bang-bang BDP over the consumed volume): returns
+        (P0 or None, P device float64 [points, Qmax + 1])."""
+        import torch
+        if P is None:
+            P = torch.empty((self.points, int(Qmax) + 1), dtype=torch.float64,
+                            device=v.device)
+        p0 = np.zeros(1, np.float64)
+        _check(lib().qtree_swing(self._h, counts.data_ptr(), v.data_ptr(), int(Qmin), int(Qmax),
+                                 P.data_ptr(), _np_ptr(p0) if want_p0 else None,
+                                 _stream_handle(stream)))
+        return (float(p0[0]) if want_p0 else None), P
 
     def bdp(self, counts, phi, V=None, want_v0: bool = True, stream=None):
         """Backward dynamic programming (FP64).  phi: device float64

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqtree.so")
 
 SOURCES = ["api.cpp", "batch.cpp", "quantizer.cpp", "mlp_api.cpp", "fwd.hip", "count.hip",
-           "bdp.hip", "diag.hip", "mlp.hip"]
+           "bdp.hip", "diag.hip", "mlp.hip", "swing.hip"]
 
 # -ffp-contract=off: the sample arithmetic is a fixed sequence of IEEE
 # operations (explicit fmaf only); packed FP32 instructions are disabled.

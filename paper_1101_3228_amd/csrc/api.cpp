@@ -613,6 +613,67 @@ qtree_status qtree_payoff(const qtree_plan* plan, int32_t kind, double S0, doubl
   return qtree_payoff_batch(plan, 1, &kind, &S0, &K, &r, &Tm, sigma, mix, phi, stream);
 }
 
+qtree_status qtree_payoff_forward(const qtree_plan* plan, double S0, double K, double r,
+                                  double Tm, const double* sigma, const double* mix, double* v,
+                                  void* stream) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (!sigma || !v) return fail(QTREE_EINVAL, "sigma and v must be non-NULL");
+  if (!(Tm > 0.0) || !std::isfinite(Tm) || !std::isfinite(S0) || !std::isfinite(K) ||
+      !std::isfinite(r))
+    return fail(QTREE_EINVAL, "contract parameters must be finite, Tm > 0");
+  const int d = plan->d;
+  for (int c = 0; c < d; ++c)
+    if (!std::isfinite(sigma[c])) return fail(QTREE_EINVAL, "sigma must be finite");
+  if (mix)
+    for (int c = 0; c < d * d; ++c)
+      if (!std::isfinite(mix[c])) return fail(QTREE_EINVAL, "mix must be finite");
+  qtree::ForwardArgs a{};
+  a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
+  a.pts1 = reinterpret_cast<const float*>(plan->ws + plan->lay.points);
+  a.pts = reinterpret_cast<const float4*>(plan->ws + plan->lay.points);
+  a.v = v;
+  a.n = plan->n;
+  a.d = d;
+  a.maxN = plan->maxN;
+  a.S0 = S0;
+  a.K = K;
+  a.r = r;
+  a.Tm = Tm;
+  for (int b = 0; b < d; ++b) {  // w = mix' sigma, summed over a in order
+    a.w[b] = 0.0;
+    for (int c = 0; c < d; ++c) a.w[b] += sigma[c] * (mix ? mix[c * d + b] : (c == b ? 1.0 : 0.0));
+  }
+  const hipError_t e = qtree::launch_forward_payoff(a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "forward payoff launch");
+}
+
+qtree_status qtree_swing(const qtree_plan* plan, const int32_t* counts, const double* v,
+                         int32_t Qmin, int32_t Qmax, double* P, double* P0_host, void* stream) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (!counts || !v || !P) return fail(QTREE_EINVAL, "counts, v and P must be non-NULL");
+  if (Qmin < 0 || Qmin > Qmax || Qmax > plan->n)
+    return fail(QTREE_EINVAL, "need 0 <= Qmin <= Qmax <= n");
+  if (Qmax > qtree::kSwingMaxQ) return fail(QTREE_EUNSUPPORTED, "Qmax above 2046");
+  qtree::SwingArgs a{};
+  a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
+  a.counts = counts;
+  a.v = v;
+  a.P = P;
+  a.Pts = plan->points;
+  a.n = plan->n;
+  a.Qmin = Qmin;
+  a.Qmax = Qmax;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = qtree::launch_swing(a, plan->N.data(), s);
+  if (e != hipSuccess) return hip_fail(e, "swing launch");
+  if (P0_host) {
+    e = hipMemcpyAsync(P0_host, P, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "swing P0 copy");
+  }
+  return QTREE_OK;
+}
+
 qtree_status qtree_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,
                               float* z1, void* stream) {
   if (count < 0) return fail(QTREE_EINVAL, "count must be >= 0");

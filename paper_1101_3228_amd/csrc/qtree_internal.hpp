@@ -83,6 +83,32 @@ struct FwdArgs {
   int32_t tile0;          // first super tile of this launch
 };
 
+// Forward obstacle on the sum of the factors (see qtree_payoff_forward).
+struct ForwardArgs {
+  const LayerDev* layers;
+  const float* pts1;
+  const float4* pts;
+  double* v;
+  int32_t n, d, maxN;
+  double S0, K, r, Tm;
+  double w[kMaxDim];  // mix' sigma
+};
+
+// Swing BDP: P is [Pts][Qmax + 1] (point major, the levels of a point
+// contiguous).
+constexpr int kSwingMaxQ = 2046;
+struct SwingArgs {
+  const LayerDev* layers;
+  const int32_t* counts;
+  const double* v;
+  double* P;
+  int64_t Pts;
+  int32_t n, Qmin, Qmax;
+};
+
+hipError_t launch_forward_payoff(const ForwardArgs& a, hipStream_t s);
+hipError_t launch_swing(const SwingArgs& a, const int32_t* N_host, hipStream_t s);
+
 hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s);
 hipError_t launch_fwd_layer_1d(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd_layer_nd(const FwdArgs& a, hipStream_t s);

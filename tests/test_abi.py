@@ -155,3 +155,12 @@ def test_mlp_validation_before_device_work(L):
     assert create(nb=inference - 1) == 2                     # ENOMEM
     assert b"workspace" in L.qtree_last_error()
     assert L.qtree_mlp_forward(None, None, 4, None, None, None) == 1
+
+
+def test_swing_and_forward_validation_before_device_work(L):
+    qt.lib()
+    assert L.qtree_swing(None, None, None, 0, 1, None, None, None) == 1
+    sig = np.array([0.2], np.float64)
+    assert L.qtree_payoff_forward(None, ctypes.c_double(1.0), ctypes.c_double(1.0),
+                                  ctypes.c_double(0.0), ctypes.c_double(1.0), sig.ctypes.data,
+                                  None, None, None) == 1
