@@ -19,8 +19,9 @@ time of the step's sampling launches measured with HIP events on their
 stream (from the start of the step to a trace event the library records
 after the last of them; the 1-D forward runs its layers in 4 groups, one
 sampling launch each, back to back on that stream, with the histogram
-passes on a second stream), against the MI355X peak of 256 CUs x 64 lanes x
-2.4 GHz lane-slots per second.  `traffic` is the HBM bytes of the same
+passes on a second stream), against the MI355X VALU peak of 256 CUs x 128
+lanes x 2.4 GHz lane-slots per second (the FP32 vector rate of 157.3 TFLOP/s
+at 2 flops per FMA lane).  `traffic` is the HBM bytes of the same
 launches per step from the committed counter profile.
 """
 from __future__ import annotations
@@ -47,10 +48,17 @@ SIGMAS = (0.1, 0.2, 0.3, 0.4)
 K_RATIOS = (0.8, 1.0, 1.2)
 S0, RATE, MATURITY = 100.0, 0.05, 1.0
 
-# Algorithmic VALU lane-slots of one 1-D pair at N = 500 (issue cost: full-rate
-# ops 1, quarter-rate ops 4):
-#   Philox4x32-10, half a call per pair: 10 rounds x (2 x 32x32->64 mad [4] +
-#     2 x 3-input xor [1]) / 2                                          = 50
+# VALU peak: 128 lanes per clock per CU.  gfx950 issues all-VGPR FP32
+# fma/add/mul, integer add/sub, bitwise ops and right shifts at up to 128
+# lanes/clock/CU (measured 105-121); every other VALU op (compares, selects,
+# min/max, 32x32 multiplies, conversions, any op with an SGPR operand) at 64,
+# and those pair with the former (min + add: 118); FP32 transcendentals at
+# 32.  Algorithmic lane-slots therefore price every op 1 and a transcendental
+# 4 against the 128-lane peak (profiles/valu_op_rates.md).
+#
+# Algorithmic VALU lane-slots of one 1-D pair at N = 500:
+#   Philox4x32-10, half a call per pair: 10 rounds x (2 x 32x32->64 mad +
+#     4 xor) / 2                                                         = 30
 #   Box-Muller, one per pair: word->integer split 2, convert 1, exponent and
 #     mantissa split 3, fold 3, t 1, Mercator series 13 fma + 2, Cody-Waite
 #     3 + 2, scale 1, correctly rounded sqrt 12 (v_sqrt [4] + 2 fma + 2 cmp
@@ -60,12 +68,12 @@ S0, RATE, MATURITY = 100.0, 0.05, 1.0
 #   two binary searches over 512 padded midpoints: 2 x 9 steps x
 #     (address, compare, select)                                         = 54
 #   flat count index i N_{k+1} + j                                       =  1
-ALG_SLOTS_PER_PAIR = 50 + 71 + 3 + 54 + 1
-PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
+ALG_SLOTS_PER_PAIR = 30 + 71 + 3 + 54 + 1
+PEAK_SLOTS = 256 * 128 * 2.4e9         # lane-slots per second
 
 # Algorithmic VALU lane-slots of one surrogate query (the matrix products run
-# on the MFMA units): 768 SiLU = 768 x (3 full-rate ops + exp and reciprocal
-# at quarter rate, 4 each) = 8448; 512 bias adds (layers 2, 3); 256 head FMAs;
+# on the MFMA units): 768 SiLU = 768 x (3 ops + exp and reciprocal, 4 each)
+# = 8448; 512 bias adds (layers 2, 3); 256 head FMAs;
 # 256 packed BF16 conversions of the 512 MFMA-layer inputs.
 MLP_SLOTS_PER_QUERY = 768 * 11 + 512 + 256 + 256
 
@@ -119,7 +127,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
-    ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1", "swing"),
+    ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1", "swing",
+                                           "rng", "nn"),
                     default="c2",
                     help="c2 (default): the 1-D time-layer workload of the headline metric; "
                          "c3: 2-D max-call, n=30, N=2000, M=1e7; batch: 256 uneven "
@@ -129,7 +138,8 @@ def main():
                          "p1: the paper's 2-D shape, n=365, N=100/250/500, M=1e5, both "
                          "algorithms, counts copied to the host; swing: the paper's swing "
                          "contract shape, 2-D OU, n=365, N=100 and 500, M=1e5, volume "
-                         "constraints (100, 250)")
+                         "constraints (100, 250); rng: the quarter-disc experiment, 500 x "
+                         "1e9 Philox points; nn: 36.5M brute-force 2-D searches, N=100/250/500")
     ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
     ap.add_argument("--groups", type=int, default=0,
                     help="c2/c3: layer groups of the two-pass forward (0: library default)")
@@ -166,6 +176,10 @@ def main():
         return run_p1(args)
     if args.workload == "swing":
         return run_swing(args)
+    if args.workload == "rng":
+        return run_rng(args)
+    if args.workload == "nn":
+        return run_nn(args)
 
     import torch
     import paper_1101_3228_amd as qt
@@ -271,9 +285,9 @@ def main():
 
 
 # Algorithmic VALU lane-slots of one d = 2 pair, excluding the searches:
-# Philox 100, two Box-Muller 142, AR(1) 12 FMA; each grid point of the two
+# one Philox call 60, two Box-Muller 142, AR(1) 12 FMA; each grid point of the two
 # searches costs 2 FMA + 1/2 of a 3-input min = 2.5 lane-slots.
-ALG_SLOTS_2D_PAIR = 100 + 142 + 12
+ALG_SLOTS_2D_PAIR = 60 + 142 + 12
 ALG_SLOTS_2D_POINT = 2.5
 
 
@@ -283,7 +297,7 @@ def alg_slots_pair(d: int, Nk: int, Nk1: int) -> float:
     d = 2 as ALG_SLOTS_2D_PAIR plus 2.5 per grid point of both layers."""
     if d == 1:
         depth = sum(max(0, int(np.ceil(np.log2(max(Nv, 1))))) for Nv in (Nk, Nk1))
-        return 50 + 71 + 3 + 1 + 3 * depth
+        return 30 + 71 + 3 + 1 + 3 * depth
     return ALG_SLOTS_2D_PAIR + ALG_SLOTS_2D_POINT * (Nk + Nk1)
 
 
@@ -702,6 +716,88 @@ def run_swing(args):
                      "unit": "TFLOP/s (FP64)", "frac": r5["swing_fp64_frac"], "traffic": None,
                      "kernel": "swing_layer_kernel (2 FLOP per nonzero count and volume level)"},
         "paper_context_gtx480_s": {"alg3_estimation": {"N100": 0.21, "N500": 0.99}},
+    }), flush=True)
+
+
+def run_rng(args):
+    """The generator comparison of the paper (Table rngs): estimate pi from
+    1e9 points in the unit square, 500 repetitions, Philox4x32-10 uniforms."""
+    import torch
+    import paper_1101_3228_amd as qt
+    torch.cuda.set_device(0)
+    npts, reps = 1_000_000_000, 500
+    inside = torch.zeros(reps, dtype=torch.int64, device="cuda:0")
+    qt.pi_quarter_disc(0x5EED0000, 0, 4, npts, inside=inside[:4])     # warm-up
+    inside.zero_()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    qt.pi_quarter_disc(0x5EED0000, 0, reps, npts, inside=inside)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    est = 4.0 * inside.cpu().numpy().astype(np.float64) / npts
+    # Philox call (10 rounds x (2 mad + 4 xor)) + two points x (2 shifts, 2
+    # 48-bit squares, 64-bit add, compare, count)
+    slots = 60 + 2 * 7
+    achieved = slots * (npts / 2) * reps / (ms * 1e-3)
+    print(json.dumps({
+        "metric": "Philox points/s (quarter-disc experiment)", "value": npts * reps / (ms * 1e-3),
+        "unit": "points/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "pi from 1e9 points in the unit square, 500 repetitions"},
+        "ms_per_1e9_points": ms / reps, "mean": float(est.mean()),
+        "std": float(est.std(ddof=1)), "std_theory": float(4 * np.sqrt(np.pi / 4 * (1 - np.pi / 4) / npts)),
+        "paper_context_gtx480_s_per_1e9": {"drand48": 0.2562, "MRG32k3a": 0.2573, "XORWOW": 0.2085},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "kernel": "pi_quarter_disc_kernel (74 lane-slots per Philox block)"},
+    }), flush=True)
+
+
+def run_nn(args):
+    """The search benchmark of the paper (Table nn): 36.5e6 brute-force
+    nearest-neighbour searches of N(0, I_2) points in 2-D grids of N = 100,
+    250, 500 points (products of Lloyd quantizers), exact lowest-index argmin."""
+    import torch
+    import paper_1101_3228_amd as qt
+    import synth
+    torch.cuda.set_device(0)
+    Q = 36_500_000
+    rng = np.random.default_rng(0x5EED0000)
+    x = torch.from_numpy(rng.standard_normal((Q, 2)).astype(np.float32)).cuda()
+    cell = torch.empty(Q, dtype=torch.int32, device="cuda:0")
+    out = {}
+    for Nn in (100, 250, 500):
+        spec = synth.bm_model(2, 1, T=1.0)
+        grid, N = synth.layer_grids(spec, [1, Nn], base=qt.gauss_quantizer)
+        plan = qt.Plan(spec, grid, N, device="cuda:0")
+        qt.cells(plan, 1, x[:1000])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            lib_cells = qt.lib().qtree_cells(plan.handle, 1, x.data_ptr(), Q, cell.data_ptr(),
+                                             qt._stream_handle(None))
+            assert lib_cells == 0
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out[f"N{Nn}"] = {"ms": ms, "searches_per_s": Q / (ms * 1e-3),
+                         "paper_convention_gflops": 6.0 * Q * Nn / (ms * 1e-3) / 1e9}
+        slots = ALG_SLOTS_2D_POINT * Q * Nn / (ms * 1e-3)
+    print(json.dumps({
+        "metric": "brute-force 2-D nearest-neighbour searches/s", "value": out["N500"]["searches_per_s"],
+        "unit": "searches/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": out["N500"]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "36.5e6 searches of N(0, I) points, grids of N = 100 / 250 / 500"},
+        "runs": out, "paper_context_gtx480_s": {"N100": 0.09, "N250": 0.23, "N500": 0.41},
+        "roofline": {"bound": "alu", "achieved": slots / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tlane-slot/s", "frac": slots / PEAK_SLOTS, "traffic": None,
+                     "kernel": "cells_kernel<2> at N = 500 (2.5 lane-slots per query and "
+                               "grid point: 2 FMA + half of a 3-input min)"},
     }), flush=True)
 
 

@@ -295,6 +295,16 @@ qtree_status qtree_layer_samples(const qtree_plan *plan, int32_t k, uint64_t m0,
 qtree_status qtree_cells(const qtree_plan *plan, int32_t k, const float *x, int64_t count,
                          int32_t *cell, void *stream);
 
+/* The quarter-disc experiment of the generator comparison (Sec. 3, Table
+ * rngs) on the library's Philox4x32-10: for repetitions rep0 .. rep0+reps-1
+ * adds to inside[rep - rep0] (device uint64, caller-zeroed) the number of
+ * the npts points (npts even, <= 2^33) of that repetition with
+ * u^2 + v^2 <= 1, point h of block i being u = (r_{2h} >> 8) 2^-24,
+ * v = (r_{2h+1} >> 8) 2^-24 of Philox(counter (i, rep, 0, 3), key = seed).
+ * The estimate is 4 inside / npts.  Asynchronous. */
+qtree_status qtree_pi_quarter_disc(uint64_t seed, uint32_t rep0, int32_t reps, uint64_t npts,
+                                   uint64_t *inside, void *stream);
+
 /* Host helpers for inputs (FP64, host memory, no device work). */
 /* 1-D quadratic-optimal quantizer of N(0,1) with N points (Sec. 2,
  * eq. Qerr): stationary grid of Lloyd's method, out: double[N], ascending. */

@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
     L.qtree_payoff_forward.restype = ctypes.c_int
     L.qtree_swing.argtypes = [P, P, P, i32, i32, P, P, P]
     L.qtree_swing.restype = ctypes.c_int
+    L.qtree_pi_quarter_disc.argtypes = [u64, u32, i32, u64, P, P]
+    L.qtree_pi_quarter_disc.restype = ctypes.c_int
     L.qtree_layer_samples.argtypes = [P, i32, u64, i64, u64, u32, P, P, P]
     L.qtree_cells.argtypes = [P, i32, P, i64, P, P]
     for f in ("qtree_workspace_size", "qtree_plan_create", "qtree_transitions", "qtree_bdp",
@@ -301,6 +303,17 @@ def box_muller(ra, rb, stream=None):
     _check(lib().qtree_box_muller(ra.data_ptr(), rb.data_ptr(), ra.numel(), z0.data_ptr(),
                                   z1.data_ptr(), _stream_handle(stream)))
     return z0, z1
+
+
+def pi_quarter_disc(seed: int, rep0: int, reps: int, npts: int, inside=None, stream=None):
+    """Quarter-disc counts of `reps` repetitions of npts Philox points
+    (device uint64 tensor [reps], as int64)."""
+    import torch
+    if inside is None:
+        inside = torch.zeros(reps, dtype=torch.int64, device="cuda")
+    _check(lib().qtree_pi_quarter_disc(int(seed), int(rep0), int(reps), int(npts),
+                                       inside.data_ptr(), _stream_handle(stream)))
+    return inside
 
 
 def layer_samples(plan: Plan, k: int, m0: int, count: int, seed: int, contract: int = 0,

@@ -9,6 +9,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqtree.so")
+# calibration program of the ALU rooflines (VALU issue rate per opcode)
+RATES_SRC = os.path.join(CSRC, "valu_rates.hip")
+RATES_BIN = os.path.join(PKG, "valu_rates")
 
 SOURCES = ["api.cpp", "batch.cpp", "quantizer.cpp", "mlp_api.cpp", "fwd.hip", "count.hip",
            "bdp.hip", "diag.hip", "mlp.hip", "swing.hip"]
@@ -39,7 +42,22 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libqtree.so")
     os.replace(tmp, LIB)
+    build_rates(verbose)
     return LIB
+
+
+def build_rates(verbose: bool = False) -> str:
+    flags = [f for f in FLAGS if f not in ("-shared", "-fPIC")]
+    tmp = RATES_BIN + ".tmp"
+    cmd = [hipcc(), *flags, "-o", tmp, RATES_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building valu_rates")
+    os.replace(tmp, RATES_BIN)
+    return RATES_BIN
 
 
 if __name__ == "__main__":

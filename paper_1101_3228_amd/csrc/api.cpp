@@ -674,6 +674,18 @@ qtree_status qtree_swing(const qtree_plan* plan, const int32_t* counts, const do
   return QTREE_OK;
 }
 
+qtree_status qtree_pi_quarter_disc(uint64_t seed, uint32_t rep0, int32_t reps, uint64_t npts,
+                                   uint64_t* inside, void* stream) {
+  if (!inside) return fail(QTREE_EINVAL, "inside is NULL");
+  if (reps < 1 || reps > 65535) return fail(QTREE_EINVAL, "reps must be in 1..65535");
+  if (npts == 0 || (npts & 1) || npts > (1ull << 33))
+    return fail(QTREE_EINVAL, "npts must be even, in 2..2^33");
+  const hipError_t e = qtree::launch_pi_quarter_disc(
+      (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), rep0, reps, npts / 2,
+      reinterpret_cast<unsigned long long*>(inside), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "pi launch");
+}
+
 qtree_status qtree_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,
                               float* z1, void* stream) {
   if (count < 0) return fail(QTREE_EINVAL, "count must be >= 0");

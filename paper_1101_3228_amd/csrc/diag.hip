@@ -54,6 +54,44 @@ __global__ void cells_kernel(FwdArgs a, int k, const float* x, int64_t count, in
   }
 }
 
+// Quarter-disc experiment of the generator comparison (Sec. 3, Table rngs):
+// point h of Philox block i of repetition rep (counter (i, rep, 0, 3)) is
+// (U, V) = (r_{2h} >> 8, r_{2h+1} >> 8) 2^-24, inside when U^2 + V^2 <= 2^48
+// (integers, exact).  Blocks of a repetition are dealt over the grid's x
+// dimension; every workgroup adds its count to inside[rep] once.
+__global__ __launch_bounds__(kBlock) void pi_quarter_disc_kernel(uint32_t key0, uint32_t key1,
+                                                                 uint32_t rep0, uint64_t blocks,
+                                                                 unsigned long long* inside) {
+  __shared__ unsigned long long part[kBlock / 64];
+  const uint32_t rep = rep0 + blockIdx.y;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  uint64_t n = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < blocks; i += stride) {
+    const U4 r = philox4x32_10(U4{(uint32_t)i, rep, 0u, 3u}, key0, key1);
+    const uint64_t u0 = r.x >> 8, v0 = r.y >> 8, u1 = r.z >> 8, v1 = r.w >> 8;
+    n += (u0 * u0 + v0 * v0 <= (1ull << 48)) ? 1u : 0u;
+    n += (u1 * u1 + v1 * v1 <= (1ull << 48)) ? 1u : 0u;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+    atomicAdd(&inside[blockIdx.y], t);
+  }
+}
+
+hipError_t launch_pi_quarter_disc(uint32_t key0, uint32_t key1, uint32_t rep0, int reps,
+                                  uint64_t blocks, unsigned long long* inside, hipStream_t s) {
+  const uint64_t want = (blocks + kBlock - 1) / kBlock;
+  const unsigned gx = (unsigned)(want < 2048 ? (want < 1 ? 1 : want) : 2048);
+  hipLaunchKernelGGL(pi_quarter_disc_kernel, dim3(gx, (unsigned)reps), dim3(kBlock), 0, s, key0,
+                     key1, rep0, blocks, inside);
+  return hipGetLastError();
+}
+
 hipError_t launch_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,
                              float* z1, hipStream_t s) {
   const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);

@@ -148,6 +148,8 @@ struct PayoffArgs {
 };
 hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s);
 
+hipError_t launch_pi_quarter_disc(uint32_t key0, uint32_t key1, uint32_t rep0, int reps,
+                                  uint64_t blocks, unsigned long long* inside, hipStream_t s);
 hipError_t launch_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,
                              float* z1, hipStream_t s);
 hipError_t launch_layer_samples(const FwdArgs& a, int k, int64_t count, float* x, float* y,

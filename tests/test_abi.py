@@ -164,3 +164,13 @@ def test_swing_and_forward_validation_before_device_work(L):
     assert L.qtree_payoff_forward(None, ctypes.c_double(1.0), ctypes.c_double(1.0),
                                   ctypes.c_double(0.0), ctypes.c_double(1.0), sig.ctypes.data,
                                   None, None, None) == 1
+
+
+def test_pi_quarter_disc_validation_before_device_work(L):
+    qt.lib()
+    buf = ctypes.c_uint64(0)
+    ptr = ctypes.addressof(buf)
+    assert L.qtree_pi_quarter_disc(1, 0, 1, 2, None, None) == 1          # inside NULL
+    for reps, npts in ((0, 2), (65536, 2), (1, 0), (1, 3), (1, (1 << 33) + 2)):
+        assert L.qtree_pi_quarter_disc(1, 0, reps, npts, ptr, None) == 1, (reps, npts)
+    assert buf.value == 0

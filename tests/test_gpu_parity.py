@@ -370,3 +370,18 @@ def test_two_pass_several_batches():
     got = plan.transitions(M, 77, m0=m0).cpu().numpy()
     ref = O.transitions(mdl, grid, N, M, seed=77, m0=m0, nthreads=THREADS)
     assert np.array_equal(got, ref)
+
+
+def test_pi_quarter_disc_counts_match_oracle():
+    """The generator experiment of Table rngs: the GPU count of points in the
+    quarter disc equals the oracle's, repetition by repetition (integers)."""
+    _print_case("pi quarter disc")
+    npts = 2_000_000
+    got = qt.pi_quarter_disc(0x5EED0000, 3, 4, npts).cpu().numpy()
+    for r in range(4):
+        ref = O.pi_estimate(0x5EED0000, 3 + r, npts) * npts / 4.0
+        assert got[r] == int(round(ref)), r
+    small = qt.pi_quarter_disc(7, 0, 1, 2).cpu().numpy()
+    assert small[0] == int(round(O.pi_estimate(7, 0, 2) * 2 / 4.0))
+    with pytest.raises(qt.QtreeError):
+        qt.pi_quarter_disc(7, 0, 1, 3)                    # odd count of points
