@@ -78,8 +78,7 @@ size_t keys_lds_bytes(int d, int n, const int32_t* N) {
   }
   const size_t grids =
       d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)(maxN + kScanTile);
-  // d >= 2 keeps a chunk's 32-bit keys in LDS (reused as the 16-bit staging)
-  return grids + (d == 1 ? sizeof(uint16_t) : sizeof(uint32_t)) * kChunk +
+  return grids + sizeof(uint16_t) * kChunk +
          sizeof(uint32_t) * (2 * (size_t)max_tiles_of(n, N) + 1 + 256);
 }
 
@@ -278,9 +277,14 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     for (int k = 0; k <= n; ++k) {
       const float* g = grid + p.pt_off[k];
       float* m = mids + p.aux_off[k];
-      // cell edges of Gamma_k: FP32 midpoints (x_r + x_{r+1}) / 2, padded with +inf
-      for (int r = 0; r < p.P[k]; ++r)
-        m[r] = (r + 1 < N[k]) ? 0.5f * (g[r] + g[r + 1]) : INFINITY;
+      // cell edges of Gamma_k: FP32 midpoints (x_r + x_{r+1}) / 2, padded with
+      // +inf; a zero midpoint is stored as +0 (the device search reads the
+      // sign bit of m - x, and -0 < x is the same comparison as +0 < x)
+      for (int r = 0; r < p.P[k]; ++r) {
+        float v = (r + 1 < N[k]) ? 0.5f * (g[r] + g[r + 1]) : INFINITY;
+        if (v == 0.0f) v = 0.0f;
+        m[r] = v;
+      }
     }
   } else {
     float4* pts = reinterpret_cast<float4*>(img.data() + p.lay.points);

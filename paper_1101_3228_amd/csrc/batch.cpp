@@ -88,6 +88,7 @@ struct qtree_batch {
   int64_t n_v0 = 0;
   size_t lds[2] = {0, 0};     // dynamic LDS of the 1-D and d >= 2 launches
   int dmax = 1;               // largest d among the d >= 2 contracts (1: none)
+  int lg1 = 0;                // search depth of the 1-D launch class (log2 of its largest P)
   int cus = 256;
   int per_cu[2] = {1, 1};     // persistent workgroups per CU of each launch
   int max_per_cu[2] = {1, 1};
@@ -126,7 +127,7 @@ qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x) {
 // Pass A of launch class x with `per_cu` workgroups per CU, for every group.
 hipError_t enqueue_keys(const qtree_batch* b, int x, int per_cu, hipStream_t s) {
   for (const Group& g : b->groups) {
-    hipError_t e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax,
+    hipError_t e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax, b->lg1,
                                             per_cu * b->cus, b->lds[x], s);
     if (e != hipSuccess) return e;
   }
@@ -137,7 +138,7 @@ hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
   for (const Group& g : b->groups) {
     hipError_t e = hipSuccess;
     for (int x = 1; x >= 0 && e == hipSuccess; --x)  // the heavier d >= 2 list first
-      e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax,
+      e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax, b->lg1,
                                    b->per_cu[x] * b->cus, b->lds[x], s);
     if (e == hipSuccess) e = qtree::launch_batch_count(group_args(b, g, 0), s);
     if (e != hipSuccess) return e;
@@ -304,6 +305,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
   char sbuf[32];
   std::snprintf(sbuf, sizeof(sbuf), "%016llx", (unsigned long long)sig);
   b->signature = sbuf;
+  while ((1 << b->lg1) < maxP) ++b->lg1;
   b->lds[0] = qtree::keys_lds_1d(maxP, max_tiles1);
   b->lds[1] = qtree::keys_lds_nd(maxN, max_tilesn);
   if (b->lds[0] > 160 * 1024 || (b->dmax > 1 && b->lds[1] > 160 * 1024)) {
@@ -312,7 +314,8 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
   }
   for (int x = 0; x < 2; ++x) {
     if (x == 1 && b->dmax == 1) continue;
-    b->max_per_cu[x] = std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lds[x]));
+    b->max_per_cu[x] =
+        std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lg1, b->lds[x]));
     b->per_cu[x] = std::min(2, b->max_per_cu[x]);
   }
   int dev = 0;

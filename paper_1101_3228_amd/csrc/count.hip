@@ -135,25 +135,52 @@ __device__ __forceinline__ void sort_and_write(const KeysJob& j, const uint32_t*
 
 // Pass A, d = 1.  Chunk c covers the Philox blocks
 // [lo/2 + c kChunk/2, lo/2 + (c+1) kChunk/2); sample m = 2 block + h is live
-// when it lies in [lo, hi).
-template <int KB>
+// when it lies in [lo, hi).  LOGP > 0: both layers' midpoints are staged in
+// breadth-first order, padded with +inf to 2^LOGP entries (LOGP >= the
+// layers' own logP), and searched at that fixed depth; the uniform model coefficients and the
+// Philox key are kept in vector registers.  LOGP = 0: searches of each
+// layer's own depth.
+template <int KB, int LOGP>
 __device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
   constexpr int kKeys = kChunk / KB;
   const LayerDev& L0 = *j.L0;
   const LayerDev& L1 = *j.L1;
   const int T = L0.tiles;
+  const int P0 = LOGP > 0 ? (1 << LOGP) : L0.P;
+  const int P1 = LOGP > 0 ? (1 << LOGP) : L1.P;
   float* mk = lds;
-  float* mk1 = lds + L0.P;
+  float* mk1 = lds + P0;
   // 16-byte aligned staging (it is copied out with 16-byte accesses)
-  uint16_t* stage = reinterpret_cast<uint16_t*>(lds + ((L0.P + L1.P + 3) & ~3));
+  uint16_t* stage = reinterpret_cast<uint16_t*>(lds + ((P0 + P1 + 3) & ~3));
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
-  for (int i = threadIdx.x; i < L0.P; i += KB) mk[i] = j.mids[L0.aux_off + i];
-  for (int i = threadIdx.x; i < L1.P; i += KB) mk1[i] = j.mids[L1.aux_off + i];
+  if (LOGP > 0) {
+    // breadth-first order, padded with +inf beyond each layer's own midpoints
+    constexpr int LG = LOGP > 0 ? LOGP : 1;
+    const float inf = __builtin_huge_valf();
+    for (int i = threadIdx.x; i < P0; i += KB) {
+      const int src = i > 0 ? bfs_source<LG>(i) : 0;
+      mk[i] = (i > 0 && src < L0.P) ? j.mids[L0.aux_off + src] : inf;
+    }
+    for (int i = threadIdx.x; i < P1; i += KB) {
+      const int src = i > 0 ? bfs_source<LG>(i) : 0;
+      mk1[i] = (i > 0 && src < L1.P) ? j.mids[L1.aux_off + src] : inf;
+    }
+  } else {
+    for (int i = threadIdx.x; i < P0; i += KB) mk[i] = j.mids[L0.aux_off + i];
+    for (int i = threadIdx.x; i < P1; i += KB) mk1[i] = j.mids[L1.aux_off + i];
+  }
   for (int t = threadIdx.x; t <= T; t += KB) tcount[t] = 0;
   __syncthreads();
 
-  const float mu = L0.mu[0], Lz = L0.L[0], A = L0.A[0], b = L0.b[0], Tk = L0.T[0];
+  float mu = L0.mu[0], Lz = L0.L[0], A = L0.A[0], b = L0.b[0], Tk = L0.T[0];
+  if (LOGP > 0) {
+    mu = vgpr_copy(mu);
+    Lz = vgpr_copy(Lz);
+    A = vgpr_copy(A);
+    b = vgpr_copy(b);
+    Tk = vgpr_copy(Tk);
+  }
   const int logP0 = L0.logP, logP1 = L1.logP;
   const uint32_t N1 = (uint32_t)L0.N1;
   const uint64_t pb = (j.lo >> 1) + (uint64_t)j.c * (kChunk / 2);
@@ -161,7 +188,9 @@ __device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
 #pragma unroll
   for (int e = 0; e < kKeys / 2; ++e) {
     const uint64_t blk = pb + (uint64_t)e * KB + threadIdx.x;
-    const U4 r = philox4x32_10(U4{(uint32_t)blk, (uint32_t)j.k, j.contract, 0u}, j.key0, j.key1);
+    const U4 ctr = U4{(uint32_t)blk, (uint32_t)j.k, j.contract, 0u};
+    const U4 r = LOGP > 0 ? philox4x32_10_vk(ctr, j.key0, j.key1)
+                          : philox4x32_10(ctr, j.key0, j.key1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const uint64_t m = 2 * blk + h;
@@ -170,20 +199,30 @@ __device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
       box_muller(h ? r.z : r.x, h ? r.w : r.y, z, eps);
       const float x = fmaf(Lz, z, mu);
       const float y = fmaf(Tk, eps, fmaf(A, x, b));
-      const uint32_t kk = (uint32_t)cell_1d(mk, logP0, x) * N1 + (uint32_t)cell_1d(mk1, logP1, y);
+      int c0, c1;
+      if (LOGP > 0) {
+        c0 = cell_1d_bfs<(LOGP > 0 ? LOGP : 1)>(mk, x);
+        c1 = cell_1d_bfs<(LOGP > 0 ? LOGP : 1)>(mk1, y);
+      } else {
+        c0 = cell_1d(mk, logP0, x);
+        c1 = cell_1d(mk1, logP1, y);
+      }
+      const uint32_t kk = (uint32_t)c0 * N1 + (uint32_t)c1;
       key[2 * e + h] = live ? kk : 0xFFFFFFFFu;
     }
   }
   sort_and_write<KB>(j, key, T, stage, tcount, cursor);
 }
 
-// Pass A, d = 2, 3: S samples per lane share each LDS grid read.  The rounds
-// are not unrolled (their search state stays in registers); each round's
-// keys go to an LDS buffer that becomes the sort's staging area once the
-// keys are back in registers.
+// Pass A, d = 2, 3: S samples per lane share each LDS grid read, in
+// kChunk / (KB S) rounds whose keys stay in registers.  The grid
+// scans take tiles of kNdTile records (a smaller tile than the padding unit
+// keeps the kernel within 128 VGPRs, four waves per SIMD).
 template <int D, int S, int KB>
 __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   constexpr int kKeys = kChunk / KB;
+  constexpr int kNdTile = 4;
+  static_assert(kScanTile % kNdTile == 0, "scan tile must divide the padding unit");
   const LayerDev& L0 = *j.L0;
   const LayerDev& L1 = *j.L1;
   const int N0 = L0.N, N1 = L0.N1, T = L0.tiles;
@@ -192,9 +231,8 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   const int P1 = (N1 + kScanTile - 1) / kScanTile * kScanTile;
   float4* gk = lds4;
   float4* gk1 = lds4 + P0;
-  uint32_t* kbuf = reinterpret_cast<uint32_t*>(lds4 + P0 + P1);  // kChunk keys
-  uint16_t* stage = reinterpret_cast<uint16_t*>(kbuf);           // reused after the reload
-  uint32_t* tcount = kbuf + kChunk;
+  uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + P0 + P1);
+  uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
   const float4 pad = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
   for (int i = threadIdx.x; i < P0; i += KB) gk[i] = i < N0 ? j.pts[L0.pt_off + i] : pad;
@@ -203,6 +241,9 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   __syncthreads();
 
   const uint64_t lo = j.lo + (uint64_t)j.c * kChunk;
+  uint32_t key[kKeys];
+#pragma unroll
+  for (int e = 0; e < kKeys; ++e) key[e] = 0xFFFFFFFFu;
 #pragma unroll 1
   for (int r = 0; r < kKeys / S; ++r) {
     float xs[S][D], ys[S][D];
@@ -216,18 +257,18 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
       layer_pair<D>(L0, z, e, xs[s], ys[s]);
     }
     int ii[S], jj[S];
-    argmin_scan_tiled<D, S, kScanTile>(gk, P0, xs, ii);
-    argmin_scan_tiled<D, S, kScanTile>(gk1, P1, ys, jj);
+    argmin_scan_tiled<D, S, kNdTile>(gk, P0, xs, ii);
+    argmin_scan_tiled<D, S, kNdTile>(gk1, P1, ys, jj);
+    // the round is not unrolled, so its keys go to fixed registers by a
+    // uniform select (a dynamic index would put the array in scratch)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const uint32_t kk = (uint32_t)ii[s] * (uint32_t)N1 + (uint32_t)jj[s];
-      kbuf[(r * S + s) * KB + threadIdx.x] = live[s] ? kk : 0xFFFFFFFFu;
+      const uint32_t v = live[s] ? kk : 0xFFFFFFFFu;
+#pragma unroll
+      for (int q = 0; q < kKeys / S; ++q) key[q * S + s] = q == r ? v : key[q * S + s];
     }
   }
-  uint32_t key[kKeys];
-#pragma unroll
-  for (int e = 0; e < kKeys; ++e) key[e] = kbuf[e * KB + threadIdx.x];
-  __syncthreads();  // kbuf is the staging area from here on
   sort_and_write<KB>(j, key, T, stage, tcount, cursor);
 }
 
@@ -342,11 +383,12 @@ __device__ __forceinline__ KeysJob plan_job(const FwdArgs& a, int k, int c) {
 
 // ------------------------------------------------------------- one plan
 
+template <int LOGP>
 __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   extern __shared__ float lds[];
   int k, c;
   if (!unit_of_block_keys(a, k, c)) return;
-  keys_chunk_1d<kBlock>(plan_job(a, k, c), lds);
+  keys_chunk_1d<kBlock, LOGP>(plan_job(a, k, c), lds);
 }
 
 template <int D, int S>
@@ -418,10 +460,15 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
   }
 }
 
+// LG > 0: every unit is searched at depth LG (the largest padded midpoint
+// count of the batch's 1-D contracts; shallower layers are padded with +inf).
+// One depth per launch: instances switched inside one kernel would share one
+// register allocation (the union of their live ranges).
+template <int LG>
 __global__ __launch_bounds__(kBlock) void batch_keys_1d(BatchArgs a) {
   extern __shared__ float lds[];
   batch_loop<kBlock>(a, [&](const BatchContract&, const KeysJob& j) {
-    keys_chunk_1d<kBlock>(j, lds);
+    keys_chunk_1d<kBlock, LG>(j, lds);
   });
 }
 
@@ -472,16 +519,29 @@ size_t keys_lds_1d(int maxP, int max_tiles) {
 }
 
 size_t keys_lds_nd(int maxN, int max_tiles) {
-  return sizeof(float4) * 2 * (size_t)(maxN + kScanTile) + sizeof(uint32_t) * kChunk +
+  return sizeof(float4) * 2 * (size_t)(maxN + kScanTile) + sizeof(uint16_t) * kChunk +
          sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
 }
 
 hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
   hipError_t e;
   if (a.d == 1) {
+    // one instance per search depth: the plan's largest padded midpoint count
     const size_t lds = keys_lds_1d(a.maxP, a.max_tiles);
-    if ((e = allow_lds(fwd_keys_1d, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(fwd_keys_1d, keys_grid(a), dim3(kBlock), lds, s, a);
+    switch (a.maxP) {
+#define QTREE_KEYS_1D(LG)                                                              \
+  case 1 << LG:                                                                        \
+    if ((e = allow_lds(fwd_keys_1d<LG>, lds)) != hipSuccess) return e;                 \
+    hipLaunchKernelGGL(fwd_keys_1d<LG>, keys_grid(a), dim3(kBlock), lds, s, a);        \
+    break;
+      QTREE_KEYS_1D(1) QTREE_KEYS_1D(2) QTREE_KEYS_1D(3) QTREE_KEYS_1D(4) QTREE_KEYS_1D(5)
+      QTREE_KEYS_1D(6) QTREE_KEYS_1D(7) QTREE_KEYS_1D(8) QTREE_KEYS_1D(9) QTREE_KEYS_1D(10)
+      QTREE_KEYS_1D(11) QTREE_KEYS_1D(12) QTREE_KEYS_1D(13)
+#undef QTREE_KEYS_1D
+      default:
+        if ((e = allow_lds(fwd_keys_1d<0>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(fwd_keys_1d<0>, keys_grid(a), dim3(kBlock), lds, s, a);
+    }
   } else if (a.d == 2) {
     const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
     if ((e = allow_lds(fwd_keys_nd<2, 4>, lds)) != hipSuccess) return e;
@@ -502,13 +562,37 @@ hipError_t launch_count_tiles(const FwdArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int grid, size_t lds, hipStream_t s) {
-  hipError_t e;
+// The kernel instance of a 1-D search depth (0: each layer's own depth).
+#define QTREE_BATCH_1D_SWITCH(LG, CALL) \
+  switch (LG) {                         \
+    case 1: CALL(1); break;             \
+    case 2: CALL(2); break;             \
+    case 3: CALL(3); break;             \
+    case 4: CALL(4); break;             \
+    case 5: CALL(5); break;             \
+    case 6: CALL(6); break;             \
+    case 7: CALL(7); break;             \
+    case 8: CALL(8); break;             \
+    case 9: CALL(9); break;             \
+    case 10: CALL(10); break;           \
+    case 11: CALL(11); break;           \
+    case 12: CALL(12); break;           \
+    case 13: CALL(13); break;           \
+    default: CALL(0);                   \
+  }
+
+hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, size_t lds,
+                             hipStream_t s) {
+  hipError_t e = hipSuccess;
   if (a.n_units == 0) return hipSuccess;
   hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, a.head);
   if (dmax <= 1) {
-    if ((e = allow_lds(batch_keys_1d, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys_1d, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+#define QTREE_LAUNCH_1D(LG)                                                                 \
+  if ((e = allow_lds(batch_keys_1d<LG>, lds)) == hipSuccess)                                \
+    hipLaunchKernelGGL(batch_keys_1d<LG>, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+    QTREE_BATCH_1D_SWITCH(lg1, QTREE_LAUNCH_1D)
+#undef QTREE_LAUNCH_1D
+    if (e != hipSuccess) return e;
   } else if (dmax == 2) {
     if ((e = allow_lds(batch_keys_nd<2>, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(batch_keys_nd<2>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
@@ -519,13 +603,15 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int grid, size_t lds,
   return hipGetLastError();
 }
 
-int batch_keys_occupancy(int dmax, size_t lds) {
+int batch_keys_occupancy(int dmax, int lg1, size_t lds) {
   int blocks = 0;
-  hipError_t e;
+  hipError_t e = hipSuccess;
   if (dmax <= 1) {
-    e = allow_lds(batch_keys_1d, lds);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_1d, kBlock, lds);
+#define QTREE_OCC_1D(LG)                                                                   \
+  if ((e = allow_lds(batch_keys_1d<LG>, lds)) == hipSuccess)                               \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_1d<LG>, kBlock, lds);
+    QTREE_BATCH_1D_SWITCH(lg1, QTREE_OCC_1D)
+#undef QTREE_OCC_1D
   } else if (dmax == 2) {
     e = allow_lds(batch_keys_nd<2>, lds);
     if (e == hipSuccess)

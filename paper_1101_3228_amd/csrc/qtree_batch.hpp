@@ -45,12 +45,13 @@ struct BatchArgs {
 
 // Persistent pass A over a.units: dmax 1 runs the 1-D kernel (every unit
 // must be 1-D), 2 or 3 the d >= 2 kernel.  Resets a.head first.
-hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int grid, size_t lds, hipStream_t s);
+hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, size_t lds,
+                             hipStream_t s);
 // Pass B over a.tiles.
 hipError_t launch_batch_count(const BatchArgs& a, hipStream_t s);
 // Workgroups of the pass-A kernel (dmax as above) that fit on one CU with
 // `lds` bytes of dynamic LDS each.
-int batch_keys_occupancy(int dmax, size_t lds);
+int batch_keys_occupancy(int dmax, int lg1, size_t lds);
 size_t keys_lds_1d(int maxP, int max_tiles);
 size_t keys_lds_nd(int maxN, int max_tiles);
 

@@ -16,6 +16,52 @@ __device__ __forceinline__ int cell_1d(const float* mids, int logP, float x) {
   return c;
 }
 
+// Breadth-first (Eytzinger) order of the 2^LOGP padded midpoints of a layer:
+// node i (1 <= i < 2^LOGP) at depth t = floor(log2 i) holds the sorted
+// midpoint (2 (i - 2^t) + 1) 2^(LOGP-t-1) - 1, so binary lifting from the
+// root visits the same midpoints as cell_1d.  Nodes of one depth are
+// adjacent in LDS: the lanes of a wave at a shallow depth read a few
+// consecutive words instead of words one power of two apart (which share a
+// bank).  Slot 0 is unused.
+template <int LOGP>
+__device__ __forceinline__ int bfs_source(int i) {
+  const int t = 31 - __clz(i);
+  return ((2 * (i - (1 << t)) + 1) << (LOGP - t - 1)) - 1;
+}
+
+// cell_1d over a breadth-first LDS copy, the depth fixed at compile time:
+// i <- 2 i + (e_i < x) from the root, count = i - 2^LOGP.  The comparison is
+// the sign bit of e_i - x, which equals (e_i < x) for every finite x and
+// every midpoint that is +inf or finite and not -0 (zero midpoints are stored
+// as +0): with denormals kept the difference of two distinct floats never
+// rounds to zero, and m - m = +0.  A step after the load is six full-rate
+// vector operations (subtract, arithmetic shift, and, three adds: r = 4 i is
+// doubled, the bit added, the LDS base added) instead of a compare and a
+// select; they form one asm block so that the compiler keeps these forms
+// (it would fuse them into a left shift and an and-or, both half rate) and
+// puts no wait states between them (plain VALU dependences interlock).
+template <int LOGP>
+__device__ __forceinline__ int cell_1d_bfs(const float* e, float x) {
+  typedef __attribute__((address_space(3))) const float lds_float;
+  const uint32_t base = (uint32_t)(uintptr_t)(lds_float*)e;
+  const uint32_t basev = vgpr_copy(base);
+  uint32_t r = 4, addr = base + 4;
+#pragma unroll
+  for (int t = 0; t < LOGP; ++t) {
+    const float m = *(lds_float*)(uintptr_t)addr;
+    uint32_t tmp;
+    asm("v_sub_f32_e32 %[t], %[m], %[x]\n\t"
+        "v_ashrrev_i32_e32 %[t], 31, %[t]\n\t"
+        "v_and_b32_e32 %[t], 4, %[t]\n\t"
+        "v_add_u32_e32 %[r], %[r], %[r]\n\t"
+        "v_add_u32_e32 %[r], %[r], %[t]\n\t"
+        "v_add_u32_e32 %[a], %[r], %[b]"
+        : [r] "+v"(r), [a] "=v"(addr), [t] "=&v"(tmp)
+        : [m] "v"(m), [x] "v"(x), [b] "v"(basev));
+  }
+  return (int)(r >> 2) - (1 << LOGP);
+}
+
 // X_k = mu + L z and X_{k+1} = b + A X_k + T eps, row by row, left-to-right
 // chains of fused multiply-adds (the AR(1) proposition of Sec. 3).
 template <int D>
@@ -82,13 +128,22 @@ __device__ __forceinline__ void argmin_scan_tiled(const float4* __restrict__ g, 
     best[s] = __builtin_huge_valf();
     tile[s] = 0;
   }
+  // the records of the next tile are loaded while the current one is
+  // scanned (the last iteration reloads its own tile, which stays in bounds)
+  float4 cur[TL];
+#pragma unroll
+  for (int q = 0; q < TL; ++q) cur[q] = g[q];
   for (int p0 = 0; p0 < Npad; p0 += TL) {
+    float4 nxt[TL];
+    const int pn = p0 + TL < Npad ? p0 + TL : p0;
+#pragma unroll
+    for (int q = 0; q < TL; ++q) nxt[q] = g[pn + q];
     float m[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) m[s] = __builtin_huge_valf();
 #pragma unroll
     for (int q = 0; q < TL; ++q) {
-      const float4 r = g[p0 + q];
+      const float4 r = cur[q];
       const float gc[3] = {r.x, r.y, r.z};
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -104,6 +159,8 @@ __device__ __forceinline__ void argmin_scan_tiled(const float4* __restrict__ g, 
       best[s] = lt ? m[s] : best[s];
       tile[s] = lt ? p0 : tile[s];
     }
+#pragma unroll
+    for (int q = 0; q < TL; ++q) cur[q] = nxt[q];
   }
 #pragma unroll
   for (int s = 0; s < S; ++s) {

@@ -385,3 +385,30 @@ def test_pi_quarter_disc_counts_match_oracle():
     assert small[0] == int(round(O.pi_estimate(7, 0, 2) * 2 / 4.0))
     with pytest.raises(qt.QtreeError):
         qt.pi_quarter_disc(7, 0, 1, 3)                    # odd count of points
+
+
+def test_zero_midpoint_and_signed_zero_samples():
+    """A midpoint that rounds to -0 (grid point -2^-149 next to 0) and samples
+    that are exactly +0 or -0 (no noise, mean 0): the search counts the
+    midpoints strictly below the sample, so a signed zero never counts as
+    below the other zero."""
+    _print_case("zero midpoint / signed zero samples")
+    n = 3
+    spec = synth.bm_model(1, n, T=1.0)
+    spec["L"] = np.zeros_like(spec["L"])
+    spec["T"] = np.zeros_like(spec["T"])
+    # mean -0: fma(0, z, -0) is -0 for z < 0 and +0 for z > 0
+    spec["mu"] = np.full_like(spec["mu"], -0.0)
+    spec["b"] = np.full_like(spec["b"], -0.0)
+    tiny = np.float32(np.ldexp(1.0, -149))
+    layer = np.array([-tiny, 0.0, 1.0], np.float32)
+    assert np.float32(0.5) * (layer[0] + layer[1]) == 0.0
+    assert np.signbit(np.float32(0.5) * (layer[0] + layer[1]))
+    grid = np.concatenate([[0.0], layer, layer, layer]).astype(np.float32).reshape(-1, 1)
+    N = np.array([1, 3, 3, 3], np.int32)
+    plan = qt.Plan(spec, grid, N)
+    counts = plan.transitions(40_001, 0x5EED0011).cpu().numpy()
+    ref = O.transitions(_omodel(spec), grid, N, 40_001, seed=0x5EED0011)
+    assert np.array_equal(counts, ref)
+    # every sample sits at a zero, below no midpoint: all mass in cell 0 -> 0
+    assert counts[0] == 40_001 and counts[1:3].sum() == 0
