@@ -338,3 +338,38 @@ def cells_bulk(grid_k: np.ndarray, d: int, x: np.ndarray) -> np.ndarray:
     out = np.zeros(xv.shape[0], np.int32)
     L.oracle_cells_bulk(_ptr(g), g.size // d, d, _ptr(xv), xv.shape[0], _ptr(out))
     return out
+
+
+def lloyd(d: int, grid: np.ndarray, L, M: int, iters: int, seed: int, fresh: bool = True):
+    """Randomized Lloyd iteration for the quadratic quantization error of
+    X = L z (Sec. 2, eq. Qerr).  Returns (grid float32 [N][d], distortion
+    float64 [iters])."""
+    Lib = lib()
+    P = ctypes.c_void_p
+    Lib.oracle_lloyd.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_uint64,
+                                 ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, P]
+    Lib.oracle_lloyd.restype = ctypes.c_int
+    g = np.ascontiguousarray(np.asarray(grid, np.float32).reshape(-1, d)).copy()
+    Lm = np.ascontiguousarray(np.asarray(L, np.float32).reshape(d, d))
+    dist = np.zeros(max(iters, 1), np.float64)
+    rc = Lib.oracle_lloyd(d, g.shape[0], _ptr(Lm), _ptr(g), M, iters, seed, int(bool(fresh)),
+                          _ptr(dist))
+    if rc != 0:
+        raise MemoryError("oracle_lloyd")
+    return g, dist[:iters]
+
+
+def lloyd_samples(d: int, L, seed: int, it: int, count: int, fresh: bool = True) -> np.ndarray:
+    """The samples X = L z of one Lloyd iteration (m = 0 .. count-1)."""
+    Lib = lib()
+    P = ctypes.c_void_p
+    Lib.oracle_lloyd_sample.argtypes = [ctypes.c_int32, P, ctypes.c_uint64, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_uint64, P]
+    Lib.oracle_lloyd_sample.restype = None
+    Lm = np.ascontiguousarray(np.asarray(L, np.float32).reshape(d, d))
+    out = np.zeros((count, d), np.float32)
+    x = np.zeros(3, np.float32)
+    for m in range(count):
+        Lib.oracle_lloyd_sample(d, _ptr(Lm), seed, int(bool(fresh)), it, m, _ptr(x))
+        out[m] = x[:d]
+    return out

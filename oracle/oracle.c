@@ -677,3 +677,76 @@ void oracle_cells_bulk(const float *grid_k, int32_t N, int32_t d, const float *x
   for (int64_t i = 0; i < count; ++i) out[i] = layer_cell(&lg, x + i * d);
   free(lg.aux);
 }
+
+/* ------------------------------------------------------------------ */
+/* Grid optimization (Sec. 2, eq. Qerr): randomized Lloyd iteration for  */
+/* the quadratic quantization error of X = L z, z ~ N(0, I_d).           */
+/* ------------------------------------------------------------------ */
+/* Sample m of iteration `it` draws one Philox block, counter
+   (m, fresh ? it : 0, 0, 2), and takes z_0, z_1 from Box-Muller of
+   (r0, r1) and z_2 from (r2, r3); X_r = sum_c L[r][c] z_c as a chain of
+   fused multiply-adds from 0.  Each sample is assigned to its cell by the
+   tree's own rule (oracle_cell).  A Lloyd step replaces every grid point
+   by the mean of the samples of its cell (a cell without samples keeps its
+   point): the fixed points of this map are the stationary grids of
+   eq. Qerr.  The cell sums are kept exactly as integers: coordinate x
+   contributes rint(x 2^24), the squared distance to the cell's point
+   rint(|x - g|^2 2^16) (both in FP64), so the result does not depend on
+   the order in which samples are added.  New point: (sum 2^-24) / count in
+   FP64, rounded once to FP32.  distortion[it] = (sum of the squared
+   distances) / M before the update of iteration it. */
+static int64_t fixed_scaled(double v, double scale) { return (int64_t)rint(v * scale); }
+
+void oracle_lloyd_sample(int32_t d, const float *L, uint64_t seed, int32_t fresh, int32_t it,
+                         uint64_t m, float *x) {
+  uint32_t key[2], r[4], ctr[4] = {(uint32_t)m, fresh ? (uint32_t)it : 0u, 0u, 2u};
+  float z[4];
+  seed_key(seed, key);
+  oracle_philox4x32_10(ctr, key, r);
+  oracle_box_muller(r[0], r[1], &z[0], &z[1]);
+  oracle_box_muller(r[2], r[3], &z[2], &z[3]);
+  for (int row = 0; row < d; ++row) {
+    float v = 0.0f;
+    for (int c = 0; c < d; ++c) v = fmaf(L[row * d + c], z[c], v);
+    x[row] = v;
+  }
+}
+
+int oracle_lloyd(int32_t d, int32_t N, const float *L, float *grid, uint64_t M, int32_t iters,
+                 uint64_t seed, int32_t fresh, double *distortion) {
+  int64_t *sum = (int64_t *)calloc((size_t)N * d, sizeof(int64_t));
+  int64_t *cnt = (int64_t *)calloc((size_t)N, sizeof(int64_t));
+  if (!sum || !cnt) { free(sum); free(cnt); return -1; }
+  for (int32_t it = 0; it < iters; ++it) {
+    memset(sum, 0, sizeof(int64_t) * (size_t)N * d);
+    memset(cnt, 0, sizeof(int64_t) * (size_t)N);
+    int64_t dist = 0;
+    layer_grid lg;
+    layer_grid_init(&lg, grid, N, d);
+    for (uint64_t m = 0; m < M; ++m) {
+      float x[3];
+      oracle_lloyd_sample(d, L, seed, fresh, it, m, x);
+      const int32_t i = layer_cell(&lg, x);
+      const float *g = grid + (size_t)i * d;
+      double d2 = 0.0;
+      for (int c = 0; c < d; ++c) {
+        const double dx = (double)x[c] - (double)g[c];
+        d2 = d2 + dx * dx;
+        sum[(size_t)i * d + c] += fixed_scaled((double)x[c], 0x1p24);
+      }
+      cnt[i] += 1;
+      dist += fixed_scaled(d2, 0x1p16);
+    }
+    free(lg.aux);
+    if (distortion) distortion[it] = ((double)dist * 0x1p-16) / (double)M;
+    for (int32_t i = 0; i < N; ++i) {
+      if (cnt[i] == 0) continue;
+      for (int c = 0; c < d; ++c)
+        grid[(size_t)i * d + c] =
+            (float)(((double)sum[(size_t)i * d + c] * 0x1p-24) / (double)cnt[i]);
+    }
+  }
+  free(sum);
+  free(cnt);
+  return 0;
+}

@@ -114,6 +114,15 @@ int oracle_layer_counts(const oracle_model *mdl, const float *grid, const int32_
                         uint64_t m0, uint64_t M, uint64_t seed, uint32_t contract,
                         int32_t *counts_k, int32_t nthreads);
 
+/* Randomized Lloyd iteration for eq. Qerr of X = L z (Sec. 2): `iters`
+   steps of M samples each over grid[N][d] (in: start, out: result);
+   distortion[iters] (optional) = the mean squared distance before each
+   step.  Returns 0, or -1 when memory runs out. */
+void oracle_lloyd_sample(int32_t d, const float *L, uint64_t seed, int32_t fresh, int32_t it,
+                         uint64_t m, float *x);
+int oracle_lloyd(int32_t d, int32_t N, const float *L, float *grid, uint64_t M, int32_t iters,
+                 uint64_t seed, int32_t fresh, double *distortion);
+
 #ifdef __cplusplus
 }
 #endif
