@@ -128,7 +128,7 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
     ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1", "swing",
-                                           "rng", "nn"),
+                                           "rng", "nn", "lloyd"),
                     default="c2",
                     help="c2 (default): the 1-D time-layer workload of the headline metric; "
                          "c3: 2-D max-call, n=30, N=2000, M=1e7; batch: 256 uneven "
@@ -139,7 +139,9 @@ def main():
                          "algorithms, counts copied to the host; swing: the paper's swing "
                          "contract shape, 2-D OU, n=365, N=100 and 500, M=1e5, volume "
                          "constraints (100, 250); rng: the quarter-disc experiment, 500 x "
-                         "1e9 Philox points; nn: 36.5M brute-force 2-D searches, N=100/250/500")
+                         "1e9 Philox points; nn: 36.5M brute-force 2-D searches, N=100/250/500; "
+                         "lloyd: randomized Lloyd grid optimization, d=2, N=500, 1e6 samples "
+                         "x 20 steps")
     ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
     ap.add_argument("--groups", type=int, default=0,
                     help="c2/c3: layer groups of the two-pass forward (0: library default)")
@@ -180,6 +182,8 @@ def main():
         return run_rng(args)
     if args.workload == "nn":
         return run_nn(args)
+    if args.workload == "lloyd":
+        return run_lloyd(args)
 
     import torch
     import paper_1101_3228_amd as qt
@@ -799,6 +803,58 @@ def run_nn(args):
                      "kernel": "cells_kernel<2> at N = 500 (2.5 lane-slots per query and "
                                "grid point: 2 FMA + half of a 3-input min)"},
     }), flush=True)
+
+
+def run_lloyd(args):
+    """Grid optimization (Sec. 2, eq. Qerr): randomized Lloyd steps for the
+    2-D Gaussian N(0, L L^T), L = chol([[1, 0.3], [0.3, 1]]) (the correlation
+    of the 2-D max-call workload), N = 500 points from a 20 x 25 product of
+    N(0, 1) quantile grids, 1e6 fresh samples per step, 20 steps."""
+    import torch
+    import oracle as O
+    import paper_1101_3228_amd as qt
+    import synth
+    torch.cuda.set_device(0)
+    d, N, M, steps = 2, 500, 1_000_000, 20
+    L = np.linalg.cholesky(np.array([[1.0, 0.3], [0.3, 1.0]]))
+    a, b = synth.quantile_grid_1d(20), synth.quantile_grid_1d(25)
+    g0 = (np.stack(np.meshgrid(a, b, indexing="ij"), axis=-1).reshape(-1, 2) @ L.T)
+    g0 = g0.astype(np.float32)
+    grid = torch.empty((N, d), dtype=torch.float32, device="cuda:0")
+    dist = torch.zeros(steps, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(qt.lib().qtree_lloyd_workspace_size(d, N), dtype=torch.uint8, device="cuda:0")
+    qt.lloyd(d, g0, L, M, 2, 0x5EED0000, grid=grid, distortion=dist, workspace=ws)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    qt.lloyd(d, g0, L, M, steps, 0x5EED0000, grid=grid, distortion=dist, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    dd = dist.cpu().numpy()
+    value = M * steps / (ms * 1e-3)
+    alg = ALG_SLOTS_2D_POINT * N + 60 + 142 + 4      # search + Philox + two Box-Muller + L z
+    out = {
+        "metric": "Lloyd samples/s (grid optimization, eq. Qerr)", "value": value,
+        "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, int64 cell sums", "data": "synthetic",
+        "config": {"workload": "randomized Lloyd, d=2, N=500, N(0, [[1,0.3],[0.3,1]]), "
+                               "1e6 samples/step, 20 steps"},
+        "distortion_first_last": [float(dd[0]), float(dd[-1])],
+        "roofline": {"bound": "alu", "achieved": alg * value / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tlane-slot/s", "frac": alg * value / PEAK_SLOTS, "traffic": None,
+                     "kernel": "lloyd_accum_kernel<2> (2.5 lane-slots per sample and grid "
+                               "point + 206 per sample)"},
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        Mc = 200_000
+        O.lloyd(d, g0, L, Mc, 1, 0x5EED0000)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": Mc / dt, "unit": "samples/s", "cores": 1,
+                               "kind": "oracle", "sample": f"one step of {Mc} samples ({dt:.1f} s)"}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

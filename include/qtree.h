@@ -305,6 +305,40 @@ qtree_status qtree_cells(const qtree_plan *plan, int32_t k, const float *x, int6
 qtree_status qtree_pi_quarter_disc(uint64_t seed, uint32_t rep0, int32_t reps, uint64_t npts,
                                    uint64_t *inside, void *stream);
 
+/* Grid optimization (Sec. 2, eq. Qerr): `steps` randomized Lloyd steps that
+ * lower the quadratic quantization error E min_i |X - x_i|^2 of X = L z,
+ * z ~ N(0, I_d).  A step draws M samples (sample m of step t: Philox counter
+ * (m, fresh ? t : 0, 0, 2), key = seed; z_0, z_1 from Box-Muller of words
+ * (0, 1), z_2 from words (2, 3); X_r = sum_c L[r][c] z_c as a chain of fused
+ * multiply-adds from 0), assigns each to its cell by the tree's rule (d = 1:
+ * the number of FP32 midpoints strictly below; d >= 2: the lowest-index
+ * minimum of |g|^2/2 - <X, g>), and moves every point to the mean of its
+ * cell's samples (a cell without samples keeps its point).  Cell sums are
+ * exact integers (rint(x 2^24) per coordinate), so the result does not
+ * depend on the order of summation; new point = (sum 2^-24) / count in
+ * FP64, rounded to FP32.
+ *   d: 1..3; N: 1..8192 (d = 1) or 1..2048 (d = 2, 3).
+ *   L: host float[d][d], row-major; every row's absolute sum <= 64 / 5.77.
+ *   grid0: host float[N][d], the start grid, coordinates within [-64, 64]
+ *     (d = 1: strictly increasing).
+ *   grid: device float[N][d], receives the result (written from grid0 first).
+ *   M: samples per step, 1 .. 2^31 - 1.  steps >= 1.
+ *   fresh: nonzero draws new samples every step; zero reuses the samples of
+ *     step 0 (Lloyd's method on a fixed empirical measure: the distortion
+ *     does not increase).
+ *   distortion: device double[steps] or NULL: entry t = the mean squared
+ *     distance of step t's samples to their cell's point before the move.
+ *   workspace: device, qtree_lloyd_workspace_size(d, N) bytes, caller-owned.
+ * Errors (before any device work): EINVAL (bad d, NULL, non-finite or
+ * unsorted grid0, steps < 1), EOVERFLOW (M, L or grid0 out of range),
+ * ENOMEM (workspace too small), EUNSUPPORTED (N above the limit).
+ * Asynchronous on `stream` (grid0 is copied before the call returns). */
+size_t qtree_lloyd_workspace_size(int32_t d, int32_t N);
+qtree_status qtree_lloyd(int32_t d, int32_t N, const float *L, const float *grid0, float *grid,
+                         uint64_t M, int32_t steps, uint64_t seed, int32_t fresh,
+                         double *distortion, void *workspace, size_t workspace_bytes,
+                         void *stream);
+
 /* Host helpers for inputs (FP64, host memory, no device work). */
 /* 1-D quadratic-optimal quantizer of N(0,1) with N points (Sec. 2,
  * eq. Qerr): stationary grid of Lloyd's method, out: double[N], ascending. */

@@ -85,6 +85,10 @@ def lib() -> ctypes.CDLL:
     L.qtree_swing.restype = ctypes.c_int
     L.qtree_pi_quarter_disc.argtypes = [u64, u32, i32, u64, P, P]
     L.qtree_pi_quarter_disc.restype = ctypes.c_int
+    L.qtree_lloyd_workspace_size.argtypes = [i32, i32]
+    L.qtree_lloyd_workspace_size.restype = ctypes.c_size_t
+    L.qtree_lloyd.argtypes = [i32, i32, P, P, P, u64, i32, u64, i32, P, P, ctypes.c_size_t, P]
+    L.qtree_lloyd.restype = ctypes.c_int
     L.qtree_layer_samples.argtypes = [P, i32, u64, i64, u64, u32, P, P, P]
     L.qtree_cells.argtypes = [P, i32, P, i64, P, P]
     for f in ("qtree_workspace_size", "qtree_plan_create", "qtree_transitions", "qtree_bdp",
@@ -314,6 +318,28 @@ def pi_quarter_disc(seed: int, rep0: int, reps: int, npts: int, inside=None, str
     _check(lib().qtree_pi_quarter_disc(int(seed), int(rep0), int(reps), int(npts),
                                        inside.data_ptr(), _stream_handle(stream)))
     return inside
+
+
+def lloyd(d: int, grid0, L, M: int, steps: int, seed: int, fresh: bool = True, grid=None,
+          distortion=None, workspace=None, device="cuda", stream=None):
+    """Grid optimization (Sec. 2, eq. Qerr): `steps` randomized Lloyd steps of
+    M samples of X = L z from the host start grid grid0 [N][d].  Returns
+    (grid, distortion): device float32 [N, d] and float64 [steps]."""
+    import torch
+    g0 = np.ascontiguousarray(np.asarray(grid0, np.float32).reshape(-1, d))
+    Lm = np.ascontiguousarray(np.asarray(L, np.float32).reshape(d, d))
+    N = g0.shape[0]
+    if grid is None:
+        grid = torch.empty((N, d), dtype=torch.float32, device=device)
+    if distortion is None:
+        distortion = torch.zeros(max(steps, 1), dtype=torch.float64, device=grid.device)
+    ws_bytes = lib().qtree_lloyd_workspace_size(int(d), int(N))
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=grid.device)
+    _check(lib().qtree_lloyd(int(d), int(N), _np_ptr(Lm), _np_ptr(g0), grid.data_ptr(), int(M),
+                             int(steps), int(seed), int(bool(fresh)), distortion.data_ptr(),
+                             workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
+    return grid, distortion
 
 
 def layer_samples(plan: Plan, k: int, m0: int, count: int, seed: int, contract: int = 0,

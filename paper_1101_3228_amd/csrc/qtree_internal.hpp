@@ -148,6 +148,28 @@ struct PayoffArgs {
 };
 hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s);
 
+// Randomized Lloyd iteration (Sec. 2, eq. Qerr) on a device grid.
+struct LloydArgs {
+  int d, N;
+  int Npad;                  // d >= 2: records padded to whole scan tiles
+  int P, logP;               // d = 1: midpoint slots (power of two >= N)
+  float L[9];                // X = L z, row-major [d][d]
+  uint32_t key0, key1;       // Philox key (seed)
+  uint32_t it_ctr;           // counter word 1 of the step (the step, or 0)
+  int it;                    // step index (distortion slot)
+  uint64_t M;                // samples per step
+  float* grid;               // [N][d], updated in place
+  float4* recs;              // d >= 2: [Npad] (g, |g|^2 / 2)
+  float* mids;               // d = 1: [P] midpoints padded with +inf
+  unsigned int* cnt;         // [N]
+  unsigned long long* sum;   // [N][d] two's complement sums of rint(x 2^24)
+  unsigned long long* dist;  // sum of rint(|x - g|^2 2^16)
+  double* distortion;        // [steps] or null
+};
+size_t lloyd_lds_bytes(int d, int N, int Npad, int P);
+hipError_t launch_lloyd_prepare(const LloydArgs& a, hipStream_t s);
+hipError_t launch_lloyd_step(const LloydArgs& a, int blocks, hipStream_t s);
+
 hipError_t launch_pi_quarter_disc(uint32_t key0, uint32_t key1, uint32_t rep0, int reps,
                                   uint64_t blocks, unsigned long long* inside, hipStream_t s);
 hipError_t launch_box_muller(const uint32_t* ra, const uint32_t* rb, int64_t count, float* z0,

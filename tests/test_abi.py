@@ -174,3 +174,34 @@ def test_pi_quarter_disc_validation_before_device_work(L):
     for reps, npts in ((0, 2), (65536, 2), (1, 0), (1, 3), (1, (1 << 33) + 2)):
         assert L.qtree_pi_quarter_disc(1, 0, reps, npts, ptr, None) == 1, (reps, npts)
     assert buf.value == 0
+
+
+def test_lloyd_validation_before_device_work(L):
+    qt.lib()
+    P = ctypes.c_void_p
+
+    def call(d, N, Lm, g0, M=1000, steps=2, ws_bytes=1 << 20, ws=1):
+        Lm = np.ascontiguousarray(np.asarray(Lm, np.float32))
+        g0 = np.ascontiguousarray(np.asarray(g0, np.float32))
+        return L.qtree_lloyd(d, N, Lm.ctypes.data, g0.ctypes.data, P(1), M, steps, 5, 1, None,
+                             P(ws), ws_bytes, None)
+
+    eye2 = np.eye(2)
+    g2 = np.zeros((4, 2))
+    assert call(0, 4, eye2, g2) == 1                          # d
+    assert call(4, 4, np.eye(4), np.zeros((4, 4))) == 1
+    assert call(2, 0, eye2, g2) == 1                          # N
+    assert call(2, 2049, eye2, np.zeros((2049, 2))) == 5      # above the limit
+    assert call(2, 4, eye2, g2, M=0) == 3                     # M
+    assert call(2, 4, eye2, g2, M=1 << 31) == 3
+    assert call(2, 4, eye2, g2, steps=0) == 1
+    assert call(2, 4, 20 * eye2, g2) == 3                     # |X| could exceed 64
+    bad = g2.copy()
+    bad[1, 1] = np.nan
+    assert call(2, 4, eye2, bad) == 1
+    assert call(2, 4, eye2, g2 + 100.0) == 3
+    assert call(1, 3, [[1.0]], [0.0, 0.0, 1.0]) == 1          # 1-D not increasing
+    need = L.qtree_lloyd_workspace_size(2, 4)
+    assert need > 0 and L.qtree_lloyd_workspace_size(2, 0) == 0
+    assert call(2, 4, eye2, g2, ws_bytes=need - 1) == 2       # workspace
+    assert L.qtree_lloyd(2, 4, None, None, None, 10, 1, 0, 1, None, None, 0, None) == 1

@@ -14,8 +14,6 @@ import numpy as np
 import pytest
 from scipy.stats import norm
 
-import oracle as O
-
 
 def exact_lloyd_1d(N, iters=2000):
     """Optimal N-point quantizer of N(0, 1) by deterministic Lloyd steps with
