@@ -34,18 +34,18 @@ __device__ __forceinline__ int bfs_source(int i) {
 // the sign bit of e_i - x, which equals (e_i < x) for every finite x and
 // every midpoint that is +inf or finite and not -0 (zero midpoints are stored
 // as +0): with denormals kept the difference of two distinct floats never
-// rounds to zero, and m - m = +0.  A step after the load is six full-rate
-// vector operations (subtract, arithmetic shift, and, three adds: r = 4 i is
-// doubled, the bit added, the LDS base added) instead of a compare and a
-// select; they form one asm block so that the compiler keeps these forms
-// (it would fuse them into a left shift and an and-or, both half rate) and
+// rounds to zero, and m - m = +0.  The LDS address a = base + 4 i is carried:
+// the child's address is 2 a + (4 b - base), b the sign bit.  A step after
+// the load is five vector operations (subtract, arithmetic shift, and, add,
+// and one shift-add, the only half-rate one) instead of a compare and a
+// select; they form one asm block so that the compiler keeps these forms and
 // puts no wait states between them (plain VALU dependences interlock).
 template <int LOGP>
 __device__ __forceinline__ int cell_1d_bfs(const float* e, float x) {
   typedef __attribute__((address_space(3))) const float lds_float;
   const uint32_t base = (uint32_t)(uintptr_t)(lds_float*)e;
-  const uint32_t basev = vgpr_copy(base);
-  uint32_t r = 4, addr = base + 4;
+  const uint32_t nbase = vgpr_copy(0u - base);
+  uint32_t addr = base + 4;
 #pragma unroll
   for (int t = 0; t < LOGP; ++t) {
     const float m = *(lds_float*)(uintptr_t)addr;
@@ -53,13 +53,12 @@ __device__ __forceinline__ int cell_1d_bfs(const float* e, float x) {
     asm("v_sub_f32_e32 %[t], %[m], %[x]\n\t"
         "v_ashrrev_i32_e32 %[t], 31, %[t]\n\t"
         "v_and_b32_e32 %[t], 4, %[t]\n\t"
-        "v_add_u32_e32 %[r], %[r], %[r]\n\t"
-        "v_add_u32_e32 %[r], %[r], %[t]\n\t"
-        "v_add_u32_e32 %[a], %[r], %[b]"
-        : [r] "+v"(r), [a] "=v"(addr), [t] "=&v"(tmp)
-        : [m] "v"(m), [x] "v"(x), [b] "v"(basev));
+        "v_add_u32_e32 %[t], %[t], %[nb]\n\t"
+        "v_lshl_add_u32 %[a], %[a], 1, %[t]"
+        : [a] "+v"(addr), [t] "=&v"(tmp)
+        : [m] "v"(m), [x] "v"(x), [nb] "v"(nbase));
   }
-  return (int)(r >> 2) - (1 << LOGP);
+  return (int)((addr - base) >> 2) - (1 << LOGP);
 }
 
 // X_k = mu + L z and X_{k+1} = b + A X_k + T eps, row by row, left-to-right
