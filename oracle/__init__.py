@@ -373,3 +373,72 @@ def lloyd_samples(d: int, L, seed: int, it: int, count: int, fresh: bool = True)
         Lib.oracle_lloyd_sample(d, _ptr(Lm), seed, int(bool(fresh)), it, m, _ptr(x))
         out[m] = x[:d]
     return out
+
+
+def _strat_setup():
+    Lib = lib()
+    if getattr(Lib, "_strat", False):
+        return Lib
+    P = ctypes.c_void_p
+    Lib.oracle_ln64.argtypes = [ctypes.c_double]
+    Lib.oracle_ln64.restype = ctypes.c_double
+    Lib.oracle_ppnd16.argtypes = [ctypes.c_double]
+    Lib.oracle_ppnd16.restype = ctypes.c_double
+    Lib.oracle_strat_edges.argtypes = [P, ctypes.c_int32, ctypes.c_float, ctypes.c_float, P]
+    Lib.oracle_strat_edges.restype = None
+    Lib.oracle_strat_pair.argtypes = [P, ctypes.c_int32, P, ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_uint64, ctypes.c_uint32, P, P]
+    Lib.oracle_strat_pair.restype = None
+    Lib.oracle_transitions_stratified.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_uint64,
+                                                  ctypes.c_uint32, P]
+    Lib.oracle_transitions_stratified.restype = ctypes.c_int
+    Lib._strat = True
+    return Lib
+
+
+def ln64(x: float) -> float:
+    return float(_strat_setup().oracle_ln64(float(x)))
+
+
+def ppnd16(p: float) -> float:
+    """Standard normal quantile (AS 241)."""
+    return float(_strat_setup().oracle_ppnd16(float(p)))
+
+
+def strat_edges(grid_k: np.ndarray, mu: float, L: float) -> np.ndarray:
+    """Marginal probabilities below the cell edges of a 1-D layer [N + 1]."""
+    g = np.ascontiguousarray(grid_k, np.float32).ravel()
+    e = np.zeros(g.size + 1, np.float64)
+    _strat_setup().oracle_strat_edges(_ptr(g), g.size, float(mu), float(L), _ptr(e))
+    return e
+
+
+def strat_pairs(model: Model, k: int, edges: np.ndarray, Ms: int, m0: int, count: int,
+                seed: int, contract: int = 0):
+    """(X_k, X_{k+1}) of stratified samples m0 .. m0+count-1 of layer k."""
+    Lib = _strat_setup()
+    e = np.ascontiguousarray(edges, np.float64)
+    xs = np.zeros(count, np.float32)
+    ys = np.zeros(count, np.float32)
+    x = ctypes.c_float()
+    y = ctypes.c_float()
+    for t in range(count):
+        Lib.oracle_strat_pair(model.cptr(), k, _ptr(e), m0 + t, Ms, seed, contract,
+                              ctypes.byref(x), ctypes.byref(y))
+        xs[t], ys[t] = x.value, y.value
+    return xs, ys
+
+
+def transitions_stratified(model: Model, grid: np.ndarray, N, Ms: int, seed: int,
+                           contract: int = 0) -> np.ndarray:
+    """Stratified counts (d = 1): Ms samples of X_k per cell of layer k, drawn
+    from the marginal conditioned on the cell; every row sums to Ms."""
+    N = np.ascontiguousarray(N, np.int32)
+    g = np.ascontiguousarray(grid, np.float32)
+    total = int(count_offsets(N)[-1])
+    counts = np.zeros(max(total, 1), np.int32)
+    rc = _strat_setup().oracle_transitions_stratified(model.cptr(), _ptr(g), _ptr(N), Ms, seed,
+                                                      contract, _ptr(counts))
+    if rc != 0:
+        raise ValueError(f"oracle_transitions_stratified rejected its arguments (code {rc})")
+    return counts[:total]

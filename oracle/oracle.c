@@ -750,3 +750,159 @@ int oracle_lloyd(int32_t d, int32_t N, const float *L, float *grid, uint64_t M, 
   free(cnt);
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Stratified time-layer estimate (not in the paper): the samples of     */
+/* X_k are drawn cell by cell from the marginal conditioned on the cell. */
+/* ------------------------------------------------------------------ */
+/* ln x in FP64 for finite x > 0: x = 2^e f with f in [1, 2) read from the
+   bits (subnormals scaled by 2^54 first), f folded into [sqrt(1/2),
+   sqrt(2)) by an exact halving; ln f = 2 atanh(s), s = (f - 1) / (f + 1),
+   as 2 s sum_{k=0..11} s^(2k) / (2k + 1) (Horner in s^2 with fma, the
+   coefficients 1 / (2k + 1) rounded to FP64); ln x = e ln2 + ln f. */
+double oracle_ln64(double x) {
+  uint64_t bits;
+  memcpy(&bits, &x, sizeof bits);
+  int e = 0;
+  if (((bits >> 52) & 0x7FF) == 0) {
+    x = x * 0x1p54;
+    memcpy(&bits, &x, sizeof bits);
+    e = -54;
+  }
+  e += (int)((bits >> 52) & 0x7FF) - 1023;
+  bits = (bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull;
+  double f;
+  memcpy(&f, &bits, sizeof f);
+  if (f > 1.4142135623730951) {
+    f = 0.5 * f;
+    e += 1;
+  }
+  const double s = (f - 1.0) / (f + 1.0);
+  const double s2 = s * s;
+  double P = 1.0 / 23.0;
+  for (int k = 10; k >= 0; --k) P = fma(P, s2, 1.0 / (double)(2 * k + 1));
+  const double lnf = (2.0 * s) * P;
+  return fma((double)e, 0.6931471805599453, lnf);
+}
+
+/* Standard normal quantile, Wichura's algorithm AS 241 (PPND16, Applied
+   Statistics 37, 1988): a rational function of (p - 1/2)^2 in the centre,
+   of sqrt(-ln min(p, 1 - p)) in the tails (ln from oracle_ln64); Horner
+   with separate multiply and add.  p <= 0 gives -inf, p >= 1 +inf. */
+static double horner8(const double *c, double r) {
+  double v = c[7];
+  for (int k = 6; k >= 0; --k) v = v * r + c[k];
+  return v;
+}
+
+double oracle_ppnd16(double p) {
+  static const double A[8] = {3.3871328727963666080e0, 1.3314166789178437745e+2,
+                              1.9715909503065514427e+3, 1.3731693765509461125e+4,
+                              4.5921953931549871457e+4, 6.7265770927008700853e+4,
+                              3.3430575583588128105e+4, 2.5090809287301226727e+3};
+  static const double B[8] = {1.0, 4.2313330701600911252e+1, 6.8718700749205790830e+2,
+                              5.3941960214247511077e+3, 2.1213794301586595867e+4,
+                              3.9307895800092710610e+4, 2.8729085735721942674e+4,
+                              5.2264952788528545610e+3};
+  static const double C[8] = {1.42343711074968357734e0, 4.63033784615654529590e0,
+                              5.76949722146069140550e0, 3.64784832476320460504e0,
+                              1.27045825245236838258e0, 2.41780725177450611770e-1,
+                              2.27238449892691845833e-2, 7.74545014278341407640e-4};
+  static const double D[8] = {1.0, 2.05319162663775882187e0, 1.67638483018380384940e0,
+                              6.89767334985100004550e-1, 1.48103976427480074590e-1,
+                              1.51986665636164571966e-2, 5.47593808499534494600e-4,
+                              1.05075007164441684324e-9};
+  static const double E[8] = {6.65790464350110377720e0, 5.46378491116411436990e0,
+                              1.78482653991729133580e0, 2.96560571828504891230e-1,
+                              2.65321895265761230930e-2, 1.24266094738807843860e-3,
+                              2.71155556874348757815e-5, 2.01033439929228813265e-7};
+  static const double F[8] = {1.0, 5.99832206555887937690e-1, 1.36929880922735805310e-1,
+                              1.48753612908506148525e-2, 7.86869131145613259100e-4,
+                              1.84631831751005468180e-5, 1.42151175831644588870e-7,
+                              2.04426310338993978564e-15};
+  if (!(p > 0.0)) return -INFINITY;
+  if (!(p < 1.0)) return INFINITY;
+  const double q = p - 0.5;
+  if (fabs(q) <= 0.425) {
+    const double r = 0.180625 - q * q;
+    return q * horner8(A, r) / horner8(B, r);
+  }
+  double r = q < 0.0 ? p : 1.0 - p;
+  r = sqrt(-oracle_ln64(r));
+  double x;
+  if (r <= 5.0) {
+    r = r - 1.6;
+    x = horner8(C, r) / horner8(D, r);
+  } else {
+    r = r - 5.0;
+    x = horner8(E, r) / horner8(F, r);
+  }
+  return q < 0.0 ? -x : x;
+}
+
+/* Marginal probabilities below the cell edges of a 1-D layer: e[0] = 0,
+   e[N] = 1, e[r + 1] = Phi(((double)m_r - mu) / L) for the FP32 midpoints
+   m_r = (x_r + x_{r+1}) / 2, with Phi(a) = erfc(-a / sqrt 2) / 2 (the
+   multiplier 1 / sqrt 2 rounded to FP64). */
+void oracle_strat_edges(const float *g, int32_t N, float mu, float L, double *e) {
+  e[0] = 0.0;
+  e[N] = 1.0;
+  for (int32_t r = 0; r + 1 < N; ++r) {
+    const float m = 0.5f * (g[r] + g[r + 1]);
+    const double a = ((double)m - (double)mu) / (double)L;
+    e[r + 1] = 0.5 * erfc(-a * 0.70710678118654752440);
+  }
+}
+
+/* Sample m of layer k, stratum (row) i = m / Ms: Philox counter
+   (m, k, contract, 4); u = (k52 + 1/2) 2^-52 with k52 = (r0 >> 12) 2^32 + r1;
+   p = e_i + u (e_{i+1} - e_i) (separate multiply and add); z = PPND16(p);
+   X_k = fma(L_k, (float)z, mu_k); eps = first Box-Muller normal of (r2, r3);
+   X_{k+1} = fma(T_k, eps, fma(A_k, X_k, b_k)). */
+void oracle_strat_pair(const oracle_model *mdl, int32_t k, const double *e, uint64_t m,
+                       uint64_t Ms, uint64_t seed, uint32_t contract, float *x, float *y) {
+  uint32_t key[2], r[4], ctr[4] = {(uint32_t)m, (uint32_t)k, contract, 4u};
+  seed_key(seed, key);
+  oracle_philox4x32_10(ctr, key, r);
+  const uint64_t i = m / Ms;
+  const double k52 = (double)(r[0] >> 12) * 4294967296.0 + (double)r[1];
+  const double u = (k52 + 0.5) * 0x1p-52;
+  const double t = u * (e[i + 1] - e[i]);
+  const double p = e[i] + t;
+  const double z = oracle_ppnd16(p);
+  float eps, unused;
+  oracle_box_muller(r[2], r[3], &eps, &unused);
+  const float xk = fmaf(mdl->L[(size_t)k], (float)z, mdl->mu[(size_t)k]);
+  *x = xk;
+  *y = fmaf(mdl->T[(size_t)k], eps, fmaf(mdl->A[(size_t)k], xk, mdl->b[(size_t)k]));
+}
+
+/* counts[k][i][j] = #{m in stratum i of layer k : cell_{k+1}(X_{k+1}) = j},
+   Ms samples per stratum, so every row sums to Ms.  d = 1 only. */
+int oracle_transitions_stratified(const oracle_model *mdl, const float *grid, const int32_t *N,
+                                  uint64_t Ms, uint64_t seed, uint32_t contract,
+                                  int32_t *counts) {
+  if (!mdl || mdl->d != 1 || N[0] != 1) return 1;
+  const int32_t n = mdl->n;
+  int64_t poff = 0, coff = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    const float *g0 = grid + poff, *g1 = grid + poff + N[k];
+    double *e = (double *)malloc(sizeof(double) * (size_t)(N[k] + 1));
+    oracle_strat_edges(g0, N[k], mdl->mu[k], mdl->L[k], e);
+    layer_grid lg;
+    layer_grid_init(&lg, g1, N[k + 1], 1);
+    int32_t *ck = counts + coff;
+    memset(ck, 0, sizeof(int32_t) * (size_t)N[k] * N[k + 1]);
+    for (uint64_t m = 0; m < Ms * (uint64_t)N[k]; ++m) {
+      float x, y;
+      oracle_strat_pair(mdl, k, e, m, Ms, seed, contract, &x, &y);
+      const int32_t j = layer_cell(&lg, &y);
+      ck[(m / Ms) * (uint64_t)N[k + 1] + j] += 1;
+    }
+    free(lg.aux);
+    free(e);
+    poff += N[k];
+    coff += (int64_t)N[k] * N[k + 1];
+  }
+  return 0;
+}
