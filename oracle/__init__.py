@@ -386,11 +386,13 @@ def _strat_setup():
     Lib.oracle_ppnd16.restype = ctypes.c_double
     Lib.oracle_strat_edges.argtypes = [P, ctypes.c_int32, ctypes.c_float, ctypes.c_float, P]
     Lib.oracle_strat_edges.restype = None
-    Lib.oracle_strat_pair.argtypes = [P, ctypes.c_int32, P, ctypes.c_uint64, ctypes.c_uint64,
+    Lib.oracle_strat_row.argtypes = [P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32]
+    Lib.oracle_strat_row.restype = ctypes.c_int64
+    Lib.oracle_strat_pair.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_uint64,
                                       ctypes.c_uint64, ctypes.c_uint32, P, P]
     Lib.oracle_strat_pair.restype = None
-    Lib.oracle_transitions_stratified.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_uint64,
-                                                  ctypes.c_uint32, P]
+    Lib.oracle_transitions_stratified.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_int32,
+                                                  ctypes.c_uint64, ctypes.c_uint32, P]
     Lib.oracle_transitions_stratified.restype = ctypes.c_int
     Lib._strat = True
     return Lib
@@ -413,9 +415,17 @@ def strat_edges(grid_k: np.ndarray, mu: float, L: float) -> np.ndarray:
     return e
 
 
-def strat_pairs(model: Model, k: int, edges: np.ndarray, Ms: int, m0: int, count: int,
+def strat_rows(edges: np.ndarray, M: int, alloc: int) -> np.ndarray:
+    """Samples of every row of a layer (alloc 0 equal, 1 proportional)."""
+    Lib = _strat_setup()
+    e = np.ascontiguousarray(edges, np.float64)
+    return np.array([Lib.oracle_strat_row(_ptr(e), i, M, alloc) for i in range(e.size - 1)],
+                    np.int64)
+
+
+def strat_pairs(model: Model, k: int, edges: np.ndarray, i: int, t0: int, count: int,
                 seed: int, contract: int = 0):
-    """(X_k, X_{k+1}) of stratified samples m0 .. m0+count-1 of layer k."""
+    """(X_k, X_{k+1}) of samples t0 .. t0+count-1 of row i of layer k."""
     Lib = _strat_setup()
     e = np.ascontiguousarray(edges, np.float64)
     xs = np.zeros(count, np.float32)
@@ -423,22 +433,23 @@ def strat_pairs(model: Model, k: int, edges: np.ndarray, Ms: int, m0: int, count
     x = ctypes.c_float()
     y = ctypes.c_float()
     for t in range(count):
-        Lib.oracle_strat_pair(model.cptr(), k, _ptr(e), m0 + t, Ms, seed, contract,
+        Lib.oracle_strat_pair(model.cptr(), k, _ptr(e), i, t0 + t, seed, contract,
                               ctypes.byref(x), ctypes.byref(y))
         xs[t], ys[t] = x.value, y.value
     return xs, ys
 
 
-def transitions_stratified(model: Model, grid: np.ndarray, N, Ms: int, seed: int,
-                           contract: int = 0) -> np.ndarray:
-    """Stratified counts (d = 1): Ms samples of X_k per cell of layer k, drawn
-    from the marginal conditioned on the cell; every row sums to Ms."""
+def transitions_stratified(model: Model, grid: np.ndarray, N, M: int, seed: int,
+                           contract: int = 0, alloc: int = 1) -> np.ndarray:
+    """Stratified counts (d = 1): the samples of X_k are drawn cell by cell
+    from the marginal conditioned on the cell, M per cell (alloc 0) or
+    max(1, rint(M p_i)) (alloc 1); row i sums to its sample count."""
     N = np.ascontiguousarray(N, np.int32)
     g = np.ascontiguousarray(grid, np.float32)
     total = int(count_offsets(N)[-1])
     counts = np.zeros(max(total, 1), np.int32)
-    rc = _strat_setup().oracle_transitions_stratified(model.cptr(), _ptr(g), _ptr(N), Ms, seed,
-                                                      contract, _ptr(counts))
+    rc = _strat_setup().oracle_transitions_stratified(model.cptr(), _ptr(g), _ptr(N), M, alloc,
+                                                      seed, contract, _ptr(counts))
     if rc != 0:
         raise ValueError(f"oracle_transitions_stratified rejected its arguments (code {rc})")
     return counts[:total]

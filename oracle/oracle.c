@@ -854,21 +854,34 @@ void oracle_strat_edges(const float *g, int32_t N, float mu, float L, double *e)
   }
 }
 
-/* Sample m of layer k, stratum (row) i = m / Ms: Philox counter
-   (m, k, contract, 4); u = (k52 + 1/2) 2^-52 with k52 = (r0 >> 12) 2^32 + r1;
-   p = e_i + u (e_{i+1} - e_i) (separate multiply and add); z = PPND16(p);
+/* Samples of row (stratum) i: alloc 0: M (equal allocation); alloc 1:
+   max(1, rint(M (e_{i+1} - e_i))) in FP64 (proportional allocation). */
+int64_t oracle_strat_row(const double *e, int32_t i, uint64_t M, int32_t alloc) {
+  if (alloc == 0) return (int64_t)M;
+  const int64_t r = (int64_t)rint((double)M * (e[i + 1] - e[i]));
+  return r > 1 ? r : 1;
+}
+
+/* Sample t of row i of layer k: Philox counter (t, k, contract, 4 + 256 i);
+   u = (k52 + 1/2) 2^-52 with k52 = (r0 >> 12) 2^32 + r1;
+   p = e_i + u (e_{i+1} - e_i) (separate multiply and add), kept inside
+   [2^-1074, 1 - 2^-53]; z = PPND16(p);
    X_k = fma(L_k, (float)z, mu_k); eps = first Box-Muller normal of (r2, r3);
    X_{k+1} = fma(T_k, eps, fma(A_k, X_k, b_k)). */
-void oracle_strat_pair(const oracle_model *mdl, int32_t k, const double *e, uint64_t m,
-                       uint64_t Ms, uint64_t seed, uint32_t contract, float *x, float *y) {
-  uint32_t key[2], r[4], ctr[4] = {(uint32_t)m, (uint32_t)k, contract, 4u};
+void oracle_strat_pair(const oracle_model *mdl, int32_t k, const double *e, int32_t i,
+                       uint64_t t, uint64_t seed, uint32_t contract, float *x, float *y) {
+  uint32_t key[2], r[4],
+      ctr[4] = {(uint32_t)t, (uint32_t)k, contract, 4u + 256u * (uint32_t)i};
   seed_key(seed, key);
   oracle_philox4x32_10(ctr, key, r);
-  const uint64_t i = m / Ms;
   const double k52 = (double)(r[0] >> 12) * 4294967296.0 + (double)r[1];
   const double u = (k52 + 0.5) * 0x1p-52;
-  const double t = u * (e[i + 1] - e[i]);
-  const double p = e[i] + t;
+  const double tt = u * (e[i + 1] - e[i]);
+  double p = e[i] + tt;
+  /* p rounds to 0 or 1 only in cells beyond ~8 standard deviations; the
+     nearest representable probabilities keep every sample finite */
+  if (!(p < 1.0)) p = 0x1.fffffffffffffp-1;
+  if (!(p > 0.0)) p = 0x1p-1074;
   const double z = oracle_ppnd16(p);
   float eps, unused;
   oracle_box_muller(r[2], r[3], &eps, &unused);
@@ -877,10 +890,10 @@ void oracle_strat_pair(const oracle_model *mdl, int32_t k, const double *e, uint
   *y = fmaf(mdl->T[(size_t)k], eps, fmaf(mdl->A[(size_t)k], xk, mdl->b[(size_t)k]));
 }
 
-/* counts[k][i][j] = #{m in stratum i of layer k : cell_{k+1}(X_{k+1}) = j},
-   Ms samples per stratum, so every row sums to Ms.  d = 1 only. */
+/* counts[k][i][j] = #{samples of row i of layer k in cell j of layer k+1};
+   row i has oracle_strat_row(e_k, i, M, alloc) samples.  d = 1 only. */
 int oracle_transitions_stratified(const oracle_model *mdl, const float *grid, const int32_t *N,
-                                  uint64_t Ms, uint64_t seed, uint32_t contract,
+                                  uint64_t M, int32_t alloc, uint64_t seed, uint32_t contract,
                                   int32_t *counts) {
   if (!mdl || mdl->d != 1 || N[0] != 1) return 1;
   const int32_t n = mdl->n;
@@ -893,11 +906,13 @@ int oracle_transitions_stratified(const oracle_model *mdl, const float *grid, co
     layer_grid_init(&lg, g1, N[k + 1], 1);
     int32_t *ck = counts + coff;
     memset(ck, 0, sizeof(int32_t) * (size_t)N[k] * N[k + 1]);
-    for (uint64_t m = 0; m < Ms * (uint64_t)N[k]; ++m) {
-      float x, y;
-      oracle_strat_pair(mdl, k, e, m, Ms, seed, contract, &x, &y);
-      const int32_t j = layer_cell(&lg, &y);
-      ck[(m / Ms) * (uint64_t)N[k + 1] + j] += 1;
+    for (int32_t i = 0; i < N[k]; ++i) {
+      const int64_t Mi = oracle_strat_row(e, i, M, alloc);
+      for (int64_t t = 0; t < Mi; ++t) {
+        float x, y;
+        oracle_strat_pair(mdl, k, e, i, (uint64_t)t, seed, contract, &x, &y);
+        ck[(int64_t)i * N[k + 1] + layer_cell(&lg, &y)] += 1;
+      }
     }
     free(lg.aux);
     free(e);

@@ -124,15 +124,17 @@ int oracle_lloyd(int32_t d, int32_t N, const float *L, float *grid, uint64_t M, 
                  uint64_t seed, int32_t fresh, double *distortion);
 
 /* Stratified time-layer estimate (d = 1, not in the paper): ln in FP64, the
-   normal quantile (AS 241), the cell-edge probabilities of a layer, one
-   stratified pair, and the counts (every row sums to Ms). */
+   normal quantile (AS 241), the cell-edge probabilities of a layer, the
+   samples of a row (equal or proportional allocation), one stratified pair,
+   and the counts (row i sums to its sample count). */
 double oracle_ln64(double x);
 double oracle_ppnd16(double p);
 void oracle_strat_edges(const float *g, int32_t N, float mu, float L, double *e);
-void oracle_strat_pair(const oracle_model *mdl, int32_t k, const double *e, uint64_t m,
-                       uint64_t Ms, uint64_t seed, uint32_t contract, float *x, float *y);
+int64_t oracle_strat_row(const double *e, int32_t i, uint64_t M, int32_t alloc);
+void oracle_strat_pair(const oracle_model *mdl, int32_t k, const double *e, int32_t i,
+                       uint64_t t, uint64_t seed, uint32_t contract, float *x, float *y);
 int oracle_transitions_stratified(const oracle_model *mdl, const float *grid, const int32_t *N,
-                                  uint64_t Ms, uint64_t seed, uint32_t contract,
+                                  uint64_t M, int32_t alloc, uint64_t seed, uint32_t contract,
                                   int32_t *counts);
 
 #ifdef __cplusplus

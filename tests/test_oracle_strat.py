@@ -1,12 +1,15 @@
 """Pins for the oracle's stratified time-layer estimate (d = 1; not in the
 paper: the samples of X_k are drawn cell by cell from the marginal
-conditioned on the cell, Ms per cell, so every row of counts sums to Ms).
+conditioned on the cell, M per cell or max(1, rint(M p_i)), so row i of the
+counts sums to its sample count).
 
 Pins: the normal quantile (AS 241) against scipy's; the FP64 logarithm
 against numpy's; the cell-edge probabilities against scipy's normal CDF;
 every stratified sample lies in its own cell; the stratum means equal the
 truncated-normal means; the counts estimate the exact transition
-probabilities obtained by numerical integration; the plain estimator agrees.
+probabilities obtained by numerical integration; the plain estimator agrees;
+proportional allocation lowers the spread of the estimated next-layer
+marginal below the plain estimator's at the same budget.
 """
 import numpy as np
 import pytest
@@ -62,7 +65,8 @@ def test_every_sample_lies_in_its_cell_and_strata_have_the_truncated_means(oracl
     off = int(N[:k].sum())
     gk = grid[off:off + N[k], 0]
     e = oracle_lib.strat_edges(gk, spec["mu"][k, 0], spec["L"][k, 0, 0])
-    x, _ = oracle_lib.strat_pairs(mdl, k, e, Ms, 0, N[k] * Ms, seed=17)
+    x = np.concatenate([oracle_lib.strat_pairs(mdl, k, e, i, 0, Ms, seed=17)[0]
+                        for i in range(N[k])])
     mids = 0.5 * (gk[1:] + gk[:-1])
     cells = np.searchsorted(mids, x, side="left")          # midpoints strictly below
     rows = np.arange(N[k] * Ms) // Ms
@@ -82,7 +86,7 @@ def test_counts_estimate_the_exact_transition_probabilities(oracle_lib):
     spec, mdl = _model(oracle_lib, n=2)
     grid, N = synth.layer_grids(spec, [1, 6, 7])
     Ms = 200_000
-    c = oracle_lib.transitions_stratified(mdl, grid, N, Ms, seed=5)
+    c = oracle_lib.transitions_stratified(mdl, grid, N, Ms, seed=5, alloc=0)
     k = 1
     off0, off1 = 1, 1 + 6
     gk, gk1 = grid[off0:off0 + 6, 0], grid[off1:off1 + 7, 0]
@@ -107,7 +111,8 @@ def test_plain_and_stratified_estimators_agree(oracle_lib):
     spec, mdl = _model(oracle_lib, n=3)
     grid, N = synth.layer_grids(spec, [1, 8, 8, 8])
     plain = oracle_lib.transitions(mdl, grid, N, 400_000, seed=3).astype(np.float64)
-    strat = oracle_lib.transitions_stratified(mdl, grid, N, 50_000, seed=3).astype(np.float64)
+    strat = oracle_lib.transitions_stratified(mdl, grid, N, 400_000, seed=3,
+                                              alloc=1).astype(np.float64)
     off = 8
     for k in (1, 2):
         P = plain[off:off + 64].reshape(8, 8)
@@ -117,3 +122,27 @@ def test_plain_and_stratified_estimators_agree(oracle_lib):
         rows = P.sum(axis=1) > 2000
         assert np.abs(pr[rows] - sr[rows]).max() < 0.02
         off += 64
+
+
+def test_proportional_rows_and_lower_spread(oracle_lib):
+    spec, mdl = _model(oracle_lib, n=2)
+    grid, N = synth.layer_grids(spec, [1, 12, 12])
+    k, M = 1, 6000
+    gk = grid[1:13, 0]
+    e = oracle_lib.strat_edges(gk, spec["mu"][k, 0], spec["L"][k, 0, 0])
+    rows = oracle_lib.strat_rows(e, M, 1)
+    assert np.all(rows >= 1) and abs(rows.sum() - M) <= N[k]
+    assert np.array_equal(rows, np.maximum(1, np.rint(M * np.diff(e)).astype(np.int64)))
+    assert np.all(oracle_lib.strat_rows(e, M, 0) == M)
+    # estimated probability of the central cells of layer 2: sum_i p_i c_ij / rows_i
+    p = np.diff(e)
+    est_s, est_p = [], []
+    for r in range(12):
+        cs = oracle_lib.transitions_stratified(mdl, grid, N, M, seed=100 + r, alloc=1)
+        cp = oracle_lib.transitions(mdl, grid, N, M, seed=100 + r)
+        S = cs[12:].reshape(12, 12).astype(np.float64)
+        P = cp[12:].reshape(12, 12).astype(np.float64)
+        assert np.array_equal(S.sum(axis=1), rows)
+        est_s.append((p[:, None] * S / S.sum(axis=1, keepdims=True))[:, 5:7].sum())
+        est_p.append(P[:, 5:7].sum() / M)
+    assert np.std(est_s) < 0.8 * np.std(est_p)
