@@ -128,7 +128,7 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
     ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1", "swing",
-                                           "rng", "nn", "lloyd"),
+                                           "rng", "nn", "lloyd", "strat"),
                     default="c2",
                     help="c2 (default): the 1-D time-layer workload of the headline metric; "
                          "c3: 2-D max-call, n=30, N=2000, M=1e7; batch: 256 uneven "
@@ -141,7 +141,8 @@ def main():
                          "constraints (100, 250); rng: the quarter-disc experiment, 500 x "
                          "1e9 Philox points; nn: 36.5M brute-force 2-D searches, N=100/250/500; "
                          "lloyd: randomized Lloyd grid optimization, d=2, N=500, 1e6 samples "
-                         "x 20 steps")
+                         "x 20 steps; strat: stratified 1-D counts, the c2 shape with 2e4 "
+                         "samples per cell")
     ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
     ap.add_argument("--groups", type=int, default=0,
                     help="c2/c3: layer groups of the two-pass forward (0: library default)")
@@ -184,6 +185,8 @@ def main():
         return run_nn(args)
     if args.workload == "lloyd":
         return run_lloyd(args)
+    if args.workload == "strat":
+        return run_strat(args)
 
     import torch
     import paper_1101_3228_amd as qt
@@ -854,6 +857,81 @@ def run_lloyd(args):
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": Mc / dt, "unit": "samples/s", "cores": 1,
                                "kind": "oracle", "sample": f"one step of {Mc} samples ({dt:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
+# Algorithmic lane-slots of one stratified pair: one Philox call 60, one
+# Box-Muller 71, the normal quantile's central branch (two degree-7 Horner
+# polynomials, q^2, r, product and quotient) 45, u and p 6, AR(1) 3, one
+# 9-step search 27, the count 1.
+ALG_SLOTS_STRAT = 60 + 71 + 45 + 6 + 3 + 27 + 1
+
+
+def run_strat(args):
+    """Stratified time-layer counts on the 1-D workload's shape (n = 50,
+    N = 500 Lloyd points per layer), proportional allocation of 1e7 samples
+    per layer (every row exact to its sample count); the plain time-layer
+    forward on the same plan and budget is timed beside it, and both price
+    the at-the-money put; the spread of that price over 8 seeds is compared
+    at a budget of 2e5 samples per layer (plain, proportional, equal)."""
+    import torch
+    import paper_1101_3228_amd as qt
+    torch.cuda.set_device(0)
+    spec, grid, N = _inputs()
+    plan = qt.Plan(spec, grid, N, device="cuda:0")
+    Mk = M_PAIRS
+    pairs = sum(plan.strat_row(k, i, Mk, 1) for k in range(N_LAYERS) for i in range(N[k]))
+    c_s = plan.new_counts()
+    c_p = plan.new_counts()
+    plan.transitions_stratified(Mk, 0x5EED0000, counts=c_s)
+    plan.transitions(M_PAIRS, 0x5EED0000, counts=c_p)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.transitions_stratified(Mk, 0x5EED0000, counts=c_s)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    e0.record()
+    for _ in range(args.steps):
+        plan.transitions(M_PAIRS, 0x5EED0000, counts=c_p)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / args.steps
+    phi = plan.payoff(qt.PUT, S0, S0, RATE, MATURITY, 0.2)
+    # spread of the at-the-money put over seeds at 2e5 samples per layer
+    # (not timed)
+    spread = {"plain": [], "proportional": [], "equal": []}
+    for r in range(8):
+        seed = 0x5EED0100 + r
+        plan.transitions(200_000, seed, counts=c_p)
+        spread["plain"].append(float(plan.bdp(c_p, phi)[0][0]))
+        plan.transitions_stratified(200_000, seed, alloc=1, counts=c_s)
+        spread["proportional"].append(float(plan.bdp(c_s, phi)[0][0]))
+        plan.transitions_stratified(200_000 // N_POINTS, seed, alloc=0, counts=c_s)
+        spread["equal"].append(float(plan.bdp(c_s, phi)[0][0]))
+    plan.transitions_stratified(Mk, 0x5EED0000, counts=c_s)
+    plan.transitions(M_PAIRS, 0x5EED0000, counts=c_p)
+    V_s, _ = plan.bdp(c_s, phi)
+    V_p, _ = plan.bdp(c_p, phi)
+    value = pairs / (ms * 1e-3)
+    out = {
+        "metric": "MC transition samples/s (stratified, 1-D)", "value": value,
+        "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, f64 quantile, int32 counts", "data": "synthetic",
+        "config": {"workload": "stratified 1-D time-layer counts, n=50, N=500 Lloyd points, "
+                               "proportional allocation of 1e7 samples per layer"},
+        "plain_forward_ms_same_pairs": ms_plain,
+        "V0_atm_put_sigma0.2": {"stratified": float(V_s[0]), "plain": float(V_p[0])},
+        "V0_std_over_8_seeds_at_2e5_per_layer": {k: float(np.std(v, ddof=1))
+                                                  for k, v in spread.items()},
+        "roofline": {"bound": "alu", "achieved": ALG_SLOTS_STRAT * value / 1e12,
+                     "peak": PEAK_SLOTS / 1e12, "unit": "Tlane-slot/s",
+                     "frac": ALG_SLOTS_STRAT * value / PEAK_SLOTS, "traffic": None,
+                     "kernel": f"strat_kernel<9> ({ALG_SLOTS_STRAT} lane-slots per pair)"},
+    }
     print(json.dumps(out), flush=True)
 
 

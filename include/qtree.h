@@ -305,6 +305,43 @@ qtree_status qtree_cells(const qtree_plan *plan, int32_t k, const float *x, int6
 qtree_status qtree_pi_quarter_disc(uint64_t seed, uint32_t rep0, int32_t reps, uint64_t npts,
                                    uint64_t *inside, void *stream);
 
+/* Stratified time-layer counts (d = 1; a variance reduction of Algorithm
+ * III's estimate, not in the paper).  For every layer k < n and every cell i
+ * of Gamma_k, M_i samples of X_k are drawn from its marginal N(mu_k, L_k^2)
+ * conditioned on the cell: M_i = M (alloc 0, equal allocation) or
+ * max(1, rint(M (e_{i+1} - e_i))) in FP64 (alloc 1, proportional allocation;
+ * qtree_strat_row returns M_i, -1 for a bad request).  Sample t of row i
+ * takes Philox counter (t, k, contract_id, 4 + 256 i), u = (k52 + 1/2) 2^-52
+ * with k52 = (r0 >> 12) 2^32 + r1, p = e_i + u (e_{i+1} - e_i) (kept inside
+ * [2^-1074, 1 - 2^-53]) for the marginal probabilities e below the cell
+ * edges (e_0 = 0, e_{r+1} = erfc(-a / sqrt 2) / 2 at a = (m_r - mu_k) / L_k
+ * for the FP32 midpoints m_r, e_N = 1, computed at plan creation), z =
+ * Phi^-1(p) by Wichura's algorithm AS 241 in FP64, X_k = fma(L_k, (float)z,
+ * mu_k); eps = the first Box-Muller normal of words (2, 3); X_{k+1} =
+ * fma(T_k, eps, fma(A_k, X_k, b_k)) and its cell j in Gamma_{k+1} by the
+ * tree's rule.  counts[k][i][j] = the number of row-i samples in cell j:
+ * row i sums to M_i, so pi^k_ij = counts / M_i and qtree_bdp applies
+ * unchanged.  counts: device int32[entries], overwritten entirely.
+ * workspace: device, at least qtree_strat_workspace_size(plan, M, alloc)
+ * bytes (the work list: tiles of 4 rows cut into segments of at most 65536
+ * samples; 0 for a bad request), caller-owned, in use until the call's work
+ * on `stream` ends.
+ * Errors (before any device work): EUNSUPPORTED (d != 1, N above 8192),
+ * EOVERFLOW (M outside 1 .. 2^31 - 1), EINVAL (NULL, alloc not 0 or 1,
+ * L_k <= 0 on a layer with N_k > 1), ENOMEM (workspace too small).
+ * Asynchronous on `stream`.
+ * qtree_strat_samples: (X_k, X_{k+1}) of samples t0 .. t0+count-1 of row i
+ * of layer k (t0 + count <= M_i), device float[count] each (a diagnostic). */
+size_t qtree_strat_workspace_size(const qtree_plan *plan, uint64_t M, int32_t alloc);
+qtree_status qtree_transitions_stratified(const qtree_plan *plan, uint64_t M, int32_t alloc,
+                                          uint64_t seed, uint32_t contract_id, int32_t *counts,
+                                          void *workspace, size_t workspace_bytes,
+                                          void *stream);
+int64_t qtree_strat_row(const qtree_plan *plan, int32_t k, int32_t i, uint64_t M, int32_t alloc);
+qtree_status qtree_strat_samples(const qtree_plan *plan, int32_t k, int32_t i, uint64_t M,
+                                 int32_t alloc, uint64_t t0, int64_t count, uint64_t seed,
+                                 uint32_t contract_id, float *x, float *y, void *stream);
+
 /* Grid optimization (Sec. 2, eq. Qerr): `steps` randomized Lloyd steps that
  * lower the quadratic quantization error E min_i |X - x_i|^2 of X = L z,
  * z ~ N(0, I_d).  A step draws M samples (sample m of step t: Philox counter

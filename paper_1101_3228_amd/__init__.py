@@ -89,6 +89,14 @@ def lib() -> ctypes.CDLL:
     L.qtree_lloyd_workspace_size.restype = ctypes.c_size_t
     L.qtree_lloyd.argtypes = [i32, i32, P, P, P, u64, i32, u64, i32, P, P, ctypes.c_size_t, P]
     L.qtree_lloyd.restype = ctypes.c_int
+    L.qtree_strat_workspace_size.argtypes = [P, u64, i32]
+    L.qtree_strat_workspace_size.restype = ctypes.c_size_t
+    L.qtree_transitions_stratified.argtypes = [P, u64, i32, u64, u32, P, P, ctypes.c_size_t, P]
+    L.qtree_transitions_stratified.restype = ctypes.c_int
+    L.qtree_strat_row.argtypes = [P, i32, i32, u64, i32]
+    L.qtree_strat_row.restype = ctypes.c_int64
+    L.qtree_strat_samples.argtypes = [P, i32, i32, u64, i32, u64, i64, u64, u32, P, P, P]
+    L.qtree_strat_samples.restype = ctypes.c_int
     L.qtree_layer_samples.argtypes = [P, i32, u64, i64, u64, u32, P, P, P]
     L.qtree_cells.argtypes = [P, i32, P, i64, P, P]
     for f in ("qtree_workspace_size", "qtree_plan_create", "qtree_transitions", "qtree_bdp",
@@ -202,6 +210,29 @@ class Plan:
         _check(lib().qtree_transitions(self._h, int(m0), int(M), int(seed), int(contract),
                                        int(mode), counts.data_ptr(), _stream_handle(stream)))
         return counts[:self.entries]
+
+    def transitions_stratified(self, M: int, seed: int, contract: int = 0, alloc: int = 1,
+                               counts=None, stream=None):
+        """Stratified counts (d = 1): the samples of X_k are drawn cell by cell
+        from the marginal conditioned on the cell, M per cell (alloc 0) or
+        max(1, rint(M p_i)) (alloc 1); row i sums to its sample count."""
+        import torch
+        if counts is None:
+            counts = self.new_counts()
+        need = lib().qtree_strat_workspace_size(self._h, int(M), int(alloc))
+        ws = getattr(self, "_strat_ws", None)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 16), dtype=torch.uint8, device=self.workspace.device)
+            self._strat_ws = ws
+        _check(lib().qtree_transitions_stratified(self._h, int(M), int(alloc), int(seed),
+                                                  int(contract), counts.data_ptr(),
+                                                  ws.data_ptr(), ws.numel(),
+                                                  _stream_handle(stream)))
+        return counts[:self.entries]
+
+    def strat_row(self, k: int, i: int, M: int, alloc: int = 1) -> int:
+        """Samples of row i of layer k in the stratified counts."""
+        return int(lib().qtree_strat_row(self._h, int(k), int(i), int(M), int(alloc)))
 
     def transitions_add(self, counts, M: int, seed: int, contract: int = 0,
                         mode: int = LAYERWISE, m0: int = 0, stream=None):
@@ -352,6 +383,20 @@ def layer_samples(plan: Plan, k: int, m0: int, count: int, seed: int, contract: 
     _check(lib().qtree_layer_samples(plan.handle, int(k), int(m0), int(count), int(seed),
                                      int(contract), x.data_ptr(), y.data_ptr(),
                                      _stream_handle(stream)))
+    return x[:count], y[:count]
+
+
+def strat_samples(plan: Plan, k: int, i: int, M: int, alloc: int, t0: int, count: int,
+                  seed: int, contract: int = 0, stream=None):
+    """Diagnostic: (X_k, X_{k+1}) of samples t0..t0+count-1 of row i of
+    layer k in the stratified counts."""
+    import torch
+    dev = plan.workspace.device
+    x = torch.empty(max(count, 1), dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    _check(lib().qtree_strat_samples(plan.handle, int(k), int(i), int(M), int(alloc), int(t0),
+                                     int(count), int(seed), int(contract), x.data_ptr(),
+                                     y.data_ptr(), _stream_handle(stream)))
     return x[:count], y[:count]
 
 

@@ -14,7 +14,8 @@ RATES_SRC = os.path.join(CSRC, "valu_rates.hip")
 RATES_BIN = os.path.join(PKG, "valu_rates")
 
 SOURCES = ["api.cpp", "batch.cpp", "quantizer.cpp", "mlp_api.cpp", "fwd.hip", "count.hip",
-           "bdp.hip", "diag.hip", "mlp.hip", "swing.hip", "lloyd.hip", "lloyd_api.cpp"]
+           "bdp.hip", "diag.hip", "mlp.hip", "swing.hip", "lloyd.hip", "lloyd_api.cpp",
+           "strat.hip"]
 
 # -ffp-contract=off: the sample arithmetic is a fixed sequence of IEEE
 # operations (explicit fmaf only); packed FP32 instructions are disabled.

@@ -100,6 +100,8 @@ WsLayout ws_layout(int d, int n, const int32_t* N, int64_t batch_chunks) {
   off = align_up(off + (size_t)pts * (d == 1 ? sizeof(float) : sizeof(float4)), 256);
   l.aux = off;
   if (d == 1) off = align_up(off + (size_t)mids * sizeof(float), 256);
+  l.edges = off;
+  if (d == 1) off = align_up(off + (size_t)(pts + n + 1) * sizeof(double), 256);
   // scratch of the two-pass counting (only when every count block has at
   // most kMaxTiles tiles)
   const int mt = max_tiles_of(n, N);
@@ -259,6 +261,7 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     const int64_t entries_k = k < n ? (int64_t)N[k] * N[k + 1] : 0;
     L.tiles = (int32_t)((entries_k + qtree::kTile - 1) / qtree::kTile);
     L.tile_off = p.total_tiles;
+    L.edge_off = (int32_t)(p.pt_off[k] + k);
     p.tile_off.push_back(p.total_tiles);
     p.total_tiles += (int32_t)((entries_k + qtree::kSuper - 1) / qtree::kSuper);
     if (k < n) {
@@ -286,6 +289,23 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
         m[r] = v;
       }
     }
+    p.marg_L.assign(model->L, model->L + n + 1);
+    // stratified sampling: probabilities of the marginal N(mu_k, L_k^2) below
+    // the cell edges, e_0 = 0, e_{r+1} = Phi(((double)m_r - mu_k) / L_k),
+    // e_N = 1, with Phi(a) = erfc(-a / sqrt 2) / 2
+    double* edges = reinterpret_cast<double*>(img.data() + p.lay.edges);
+    for (int k = 0; k <= n; ++k) {
+      const float* g = grid + p.pt_off[k];
+      double* e = edges + p.pt_off[k] + k;
+      e[0] = 0.0;
+      e[N[k]] = 1.0;
+      for (int r = 0; r + 1 < N[k]; ++r) {
+        const float m = 0.5f * (g[r] + g[r + 1]);
+        const double a = ((double)m - (double)model->mu[k]) / (double)model->L[k];
+        e[r + 1] = 0.5 * std::erfc(-a * 0.70710678118654752440);
+      }
+    }
+    p.edges.assign(edges, edges + p.points + n + 1);
   } else {
     float4* pts = reinterpret_cast<float4*>(img.data() + p.lay.points);
     for (int64_t t = 0; t < p.points; ++t) {
@@ -523,6 +543,124 @@ qtree_status qtree_transitions_add(const qtree_plan* plan, uint64_t m0, uint64_t
                                    uint32_t contract_id, qtree_mode mode, int32_t* counts,
                                    void* stream) {
   return transitions_impl(plan, m0, M, seed, contract_id, mode, counts, stream, false);
+}
+
+// Samples of row i of layer k (the rule of the device kernel).
+static uint64_t strat_row(const qtree_plan* plan, int k, int i, uint64_t M, int alloc) {
+  if (alloc == 0) return M;
+  const double* e = plan->edges.data() + plan->pt_off[k] + k;
+  const long long r = (long long)std::rint((double)M * (e[i + 1] - e[i]));
+  return r > 1 ? (uint64_t)r : 1ull;
+}
+
+static qtree_status strat_args(const qtree_plan* plan, uint64_t M, int32_t alloc, uint64_t seed,
+                               uint32_t contract_id, qtree::StratArgs& a) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (plan->d != 1) return fail(QTREE_EUNSUPPORTED, "stratified sampling is for d = 1");
+  if (alloc != 0 && alloc != 1) return fail(QTREE_EINVAL, "alloc must be 0 or 1");
+  if (M < 1 || M >= (1ull << 31)) return fail(QTREE_EOVERFLOW, "M must be in 1 .. 2^31 - 1");
+  for (int k = 0; k < plan->n; ++k) {
+    const float L = plan->marg_L[k];
+    if (plan->N[k] > 1 && !(L > 0.0f && std::isfinite(L)))
+      return fail(QTREE_EINVAL, "stratified sampling needs L_k > 0 on layers with N_k > 1");
+  }
+  if (plan->maxP > 8192) return fail(QTREE_EUNSUPPORTED, "N above 8192");
+  if (qtree::strat_lds_bytes(plan->maxP, plan->maxN) > 160 * 1024)
+    return fail(QTREE_EUNSUPPORTED, "count rows do not fit in LDS");
+  a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
+  a.mids = reinterpret_cast<const float*>(plan->ws + plan->lay.aux);
+  a.edges = reinterpret_cast<const double*>(plan->ws + plan->lay.edges);
+  a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  a.key1 = (uint32_t)(seed >> 32);
+  a.contract = contract_id;
+  a.M = M;
+  a.alloc = alloc;
+  a.n = plan->n;
+  a.maxP = plan->maxP;
+  a.maxN = plan->maxN;
+  return QTREE_OK;
+}
+
+// Work list of the stratified counts: every tile of kStratRows rows of every
+// layer, cut into segments of at most kStratSegment samples.
+static std::vector<qtree::StratUnit> strat_units(const qtree_plan* plan, uint64_t M, int alloc,
+                                                 bool* any_split) {
+  std::vector<qtree::StratUnit> u;
+  *any_split = false;
+  for (int k = 0; k < plan->n; ++k) {
+    for (int i0 = 0; i0 < plan->N[k]; i0 += qtree::kStratRows) {
+      uint64_t total = 0;
+      for (int i = i0; i < std::min(i0 + qtree::kStratRows, (int)plan->N[k]); ++i)
+        total += strat_row(plan, k, i, M, alloc);
+      const uint64_t segs = (total + qtree::kStratSegment - 1) / qtree::kStratSegment;
+      if (segs > 1) *any_split = true;
+      for (uint64_t g = 0; g < segs; ++g) {
+        qtree::StratUnit x{};
+        x.k = k;
+        x.i0 = i0;
+        x.split = segs > 1 ? 1 : 0;
+        x.s0 = g * qtree::kStratSegment;
+        x.s1 = std::min(total, (g + 1) * qtree::kStratSegment);
+        u.push_back(x);
+      }
+    }
+  }
+  return u;
+}
+
+size_t qtree_strat_workspace_size(const qtree_plan* plan, uint64_t M, int32_t alloc) {
+  qtree::StratArgs a{};
+  if (strat_args(plan, M, alloc, 0, 0, a) != QTREE_OK) return 0;
+  bool split = false;
+  return sizeof(qtree::StratUnit) * std::max<size_t>(1, strat_units(plan, M, alloc, &split).size());
+}
+
+qtree_status qtree_transitions_stratified(const qtree_plan* plan, uint64_t M, int32_t alloc,
+                                          uint64_t seed, uint32_t contract_id, int32_t* counts,
+                                          void* workspace, size_t workspace_bytes,
+                                          void* stream) {
+  qtree::StratArgs a{};
+  qtree_status st = strat_args(plan, M, alloc, seed, contract_id, a);
+  if (st != QTREE_OK) return st;
+  if (!counts || !workspace) return fail(QTREE_EINVAL, "counts or workspace is NULL");
+  bool split = false;
+  const std::vector<qtree::StratUnit> units = strat_units(plan, M, alloc, &split);
+  if (units.size() >= (1u << 31)) return fail(QTREE_EOVERFLOW, "too many work units");
+  if (workspace_bytes < sizeof(qtree::StratUnit) * units.size())
+    return fail(QTREE_ENOMEM, "workspace smaller than qtree_strat_workspace_size");
+  a.counts = counts;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* dev_units = static_cast<qtree::StratUnit*>(workspace);
+  // the copy from pageable memory is staged before the call returns
+  hipError_t e = hipMemcpyAsync(dev_units, units.data(), sizeof(qtree::StratUnit) * units.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && split) e = qtree::launch_zero_i32(counts, plan->entries, s);
+  if (e == hipSuccess) e = qtree::launch_strat(a, dev_units, (int)units.size(), s);
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "stratified launch");
+}
+
+int64_t qtree_strat_row(const qtree_plan* plan, int32_t k, int32_t i, uint64_t M, int32_t alloc) {
+  if (!plan || plan->d != 1 || k < 0 || k >= plan->n || i < 0 || i >= plan->N[k]) return -1;
+  if ((alloc != 0 && alloc != 1) || M < 1 || M >= (1ull << 31)) return -1;
+  return (int64_t)strat_row(plan, k, i, M, alloc);
+}
+
+qtree_status qtree_strat_samples(const qtree_plan* plan, int32_t k, int32_t i, uint64_t M,
+                                 int32_t alloc, uint64_t t0, int64_t count, uint64_t seed,
+                                 uint32_t contract_id, float* x, float* y, void* stream) {
+  qtree::StratArgs a{};
+  qtree_status st = strat_args(plan, M, alloc, seed, contract_id, a);
+  if (st != QTREE_OK) return st;
+  if (k < 0 || k >= plan->n) return fail(QTREE_EINVAL, "layer index out of range");
+  if (i < 0 || i >= plan->N[k]) return fail(QTREE_EINVAL, "row index out of range");
+  if (count < 0) return fail(QTREE_EINVAL, "count must be >= 0");
+  if (t0 + (uint64_t)count > strat_row(plan, k, i, M, alloc))
+    return fail(QTREE_EINVAL, "samples beyond the row's sample count");
+  if (count == 0) return QTREE_OK;
+  if (!x || !y) return fail(QTREE_EINVAL, "NULL array");
+  const hipError_t e =
+      qtree::launch_strat_samples(a, k, i, t0, count, x, y, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "stratified samples launch");
 }
 
 qtree_status qtree_bdp(const qtree_plan* plan, const int32_t* counts, const double* phi,

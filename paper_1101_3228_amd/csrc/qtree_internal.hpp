@@ -36,6 +36,7 @@ struct alignas(16) LayerDev {
   int32_t logP;     // log2(P)
   int32_t tiles;    // ceil(N_k N_{k+1} / kTile) (0 on the last layer)
   int32_t tile_off; // super tiles of the layers before k
+  int32_t edge_off; // 1-D: first of the N_k + 1 cell-edge probabilities of layer k
   float A[9], b[3], T[9], mu[3], L[9];
   float x0[3];      // start point of the pathwise mode (layer 0 record)
 };
@@ -45,6 +46,7 @@ struct WsLayout {
   size_t layers;   // LayerDev[n+1]
   size_t points;   // d == 1: float[sum N]; d >= 2: float4[sum N] = (g0, g1, g2, h)
   size_t aux;      // d == 1: float[sum P] midpoints padded with +inf
+  size_t edges;    // d == 1: double[sum (N_k + 1)] marginal probabilities below the cell edges
   size_t keys;     // uint16[n][batch chunks][kChunk] pass-A keys
   size_t segs;     // uint32[n][batch chunks][max tiles + 1] segment starts
   size_t total;
@@ -147,6 +149,31 @@ struct PayoffArgs {
   Contract c[kPayoffGroup];
 };
 hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s);
+
+// Stratified time-layer counts (d = 1): Ms samples per cell of layer k.
+struct StratArgs {
+  const LayerDev* layers;
+  const float* mids;      // sorted midpoints, padded per layer
+  const double* edges;    // cell-edge probabilities per layer
+  uint32_t key0, key1, contract;
+  uint64_t M;             // samples per row (alloc 0) or per layer (alloc 1)
+  int alloc;              // 0 equal, 1 proportional allocation
+  int32_t* counts;        // the plan's count blocks
+  int n, maxP, maxN;      // layers; largest padded midpoint count; largest N_k
+};
+constexpr int kStratRows = 4;            // rows (strata) per tile
+constexpr uint64_t kStratSegment = 65536;  // samples per workgroup at most
+// A workgroup's share: samples [s0, s1) of the tile of rows [i0, i0 + 4) of
+// layer k (in the tile's own order: row by row); split: the tile is shared
+// by several workgroups (its counts are added with atomics onto zeros).
+struct alignas(16) StratUnit {
+  int32_t k, i0, split, pad;
+  uint64_t s0, s1;
+};
+size_t strat_lds_bytes(int maxP, int maxN);
+hipError_t launch_strat(const StratArgs& a, const StratUnit* units, int n_units, hipStream_t s);
+hipError_t launch_strat_samples(const StratArgs& a, int k, int i, uint64_t t0, int64_t count,
+                                float* x, float* y, hipStream_t s);
 
 // Randomized Lloyd iteration (Sec. 2, eq. Qerr) on a device grid.
 struct LloydArgs {

@@ -23,6 +23,8 @@ struct qtree_plan {
   int32_t tune_groups = 0;  // layer groups of the two-pass forward (0: automatic)
   int32_t max_tiles = 0, total_tiles = 0;
   std::vector<int32_t> tile_off;  // first super tile of every layer (host copy)
+  std::vector<float> marg_L;      // d = 1: the marginal factor L_k of every layer
+  std::vector<double> edges;      // d = 1: host copy of the cell-edge probabilities
   int64_t batch_chunks = 0;      // scratch chunks per layer per pass
   bool two_pass_ok = false;
   hipEvent_t trace_keys = nullptr;

@@ -205,3 +205,11 @@ def test_lloyd_validation_before_device_work(L):
     assert need > 0 and L.qtree_lloyd_workspace_size(2, 0) == 0
     assert call(2, 4, eye2, g2, ws_bytes=need - 1) == 2       # workspace
     assert L.qtree_lloyd(2, 4, None, None, None, 10, 1, 0, 1, None, None, 0, None) == 1
+
+
+def test_stratified_validation_before_device_work(L):
+    qt.lib()
+    assert L.qtree_transitions_stratified(None, 100, 1, 1, 0, None, None, 0, None) == 1
+    assert L.qtree_strat_workspace_size(None, 100, 1) == 0
+    assert L.qtree_strat_samples(None, 0, 0, 100, 1, 0, 10, 1, 0, None, None, None) == 1
+    assert L.qtree_strat_row(None, 0, 0, 100, 1) == -1
