@@ -5,12 +5,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
+#include "qtree_batch.hpp"
 #include "qtree_internal.hpp"
 #include "qtree_plan.hpp"
 
@@ -102,6 +104,8 @@ WsLayout ws_layout(int d, int n, const int32_t* N, int64_t batch_chunks) {
   if (d == 1) off = align_up(off + (size_t)mids * sizeof(float), 256);
   l.edges = off;
   if (d == 1) off = align_up(off + (size_t)(pts + n + 1) * sizeof(double), 256);
+  l.guide = off;
+  if (d == 1) off = align_up(off + (size_t)(n + 1) * kGuideMax * sizeof(uint16_t), 256);
   // scratch of the two-pass counting (only when every count block has at
   // most kMaxTiles tiles)
   const int mt = max_tiles_of(n, N);
@@ -145,6 +149,87 @@ const char* qtree_status_string(qtree_status s) {
 const char* qtree_last_error(void) { return g_last_error.c_str(); }
 
 const char* qtree_version(void) { return "qtree 0.1 gfx950"; }
+
+// Guide table of a sorted 1-D midpoint array m[0 .. nm) (the cell search of
+// the forward kernels).  The device maps x to bucket
+//   b = (int)fminf(fmaxf(fmaf(x, scale, shift), 0), B - 1),
+// a non-decreasing function of x, so every bucket is an interval of floats;
+// the table stores c(first float of the bucket), c(x) = #{r : m_r < x}, and
+// K bounds c(last float) - c(first float) over the buckets.  The table size is
+// the smallest power of two in 256 .. kGuideMax with K <= 2, else with
+// K <= kGuideKMax; K = 0 when none qualifies (the kernels then use the
+// binary search).
+namespace {
+int64_t float_order(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, sizeof u);
+  return (u & 0x80000000u) ? -(int64_t)(u & 0x7FFFFFFFu) : (int64_t)u;
+}
+float order_float(int64_t v) {
+  const uint32_t u = v >= 0 ? (uint32_t)v : (0x80000000u | (uint32_t)(-v));
+  float x;
+  std::memcpy(&x, &u, sizeof x);
+  return x;
+}
+int guide_bucket(float x, float scale, float shift, int B) {
+  float t = std::fmaf(x, scale, shift);
+  t = std::fmax(t, 0.0f);
+  t = std::fmin(t, (float)(B - 1));
+  return (int)t;
+}
+struct Guide {
+  int B = 1, K = 0;
+  float scale = 0.f, shift = 0.f;
+  std::vector<uint16_t> tab;
+};
+Guide build_guide(const float* m, int nm) {
+  Guide best;
+  best.tab.assign(1, 0);
+  if (nm <= 0) return best;  // one cell: bucket 0, nothing to add
+  auto count_below = [&](float x) {
+    return (int)(std::lower_bound(m, m + nm, x) - m);  // #{m_r < x}
+  };
+  const int64_t lo_o = float_order(-FLT_MAX), hi_o = float_order(FLT_MAX);
+  for (int cap : {2, qtree::kGuideKMax}) {
+    for (int B = 256; B <= qtree::kGuideMax; B *= 2) {
+      Guide g;
+      g.B = B;
+      const float span = m[nm - 1] - m[0];
+      g.scale = span > 0.0f ? (float)B / span : 0.0f;
+      g.shift = -m[0] * g.scale;
+      if (!std::isfinite(g.scale) || !std::isfinite(g.shift)) continue;
+      // first float of every bucket (or past the end when a bucket is empty)
+      std::vector<int64_t> first(B + 1, hi_o + 1);
+      first[0] = lo_o;
+      for (int b = 1; b < B; ++b) {
+        int64_t lo = first[b - 1], hi = hi_o + 1;  // smallest v with bucket >= b
+        while (lo < hi) {
+          const int64_t mid = lo + (hi - lo) / 2;
+          if (guide_bucket(order_float(mid), g.scale, g.shift, B) >= b) hi = mid;
+          else lo = mid + 1;
+        }
+        first[b] = lo;
+      }
+      g.tab.assign(B, 0);
+      g.K = 0;
+      for (int b = 0; b < B; ++b) {
+        const int64_t f = first[b], l = first[b + 1] - 1;  // floats of bucket b
+        if (f > hi_o) {  // empty bucket: no float maps here
+          g.tab[b] = (uint16_t)nm;
+          continue;
+        }
+        const int c0 = count_below(order_float(f));
+        const int c1 = count_below(order_float(std::min(l, hi_o)));
+        g.tab[b] = (uint16_t)c0;
+        g.K = std::max(g.K, c1 - c0);
+      }
+      if (g.K <= cap) return g;
+    }
+  }
+  best.K = -1;  // no table: binary search
+  return best;
+}
+}  // namespace
 
 static qtree_status check_shape(int32_t d, int32_t n, const int32_t* N) {
   if (d < 1 || d > 3) return fail(QTREE_EINVAL, "d must be 1, 2 or 3");
@@ -290,6 +375,24 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
       }
     }
     p.marg_L.assign(model->L, model->L + n + 1);
+    // guide tables of the cell search, from the stored midpoints
+    uint16_t* guide = reinterpret_cast<uint16_t*>(img.data() + p.lay.guide);
+    p.gt_Kmax = 0;
+    p.gt_Bmax = 1;
+    for (int k = 0; k <= n; ++k) {
+      const Guide g = build_guide(mids + p.aux_off[k], N[k] - 1);
+      qtree::LayerDev& L = layers[k];
+      L.gt_off = k * qtree::kGuideMax;
+      L.gt_B = g.B;
+      L.gt_K = g.K;
+      L.gt_scale = g.scale;
+      L.gt_shift = g.shift;
+      std::memcpy(guide + (size_t)k * qtree::kGuideMax, g.tab.data(),
+                  sizeof(uint16_t) * g.tab.size());
+      if (g.K < 0) p.gt_Kmax = -1;
+      if (p.gt_Kmax >= 0) p.gt_Kmax = std::max(p.gt_Kmax, g.K);
+      p.gt_Bmax = std::max(p.gt_Bmax, g.B);
+    }
     // stratified sampling: probabilities of the marginal N(mu_k, L_k^2) below
     // the cell edges, e_0 = 0, e_{r+1} = Phi(((double)m_r - mu_k) / L_k),
     // e_N = 1, with Phi(a) = erfc(-a / sqrt 2) / 2
@@ -336,6 +439,11 @@ static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uin
   qtree::FwdArgs a{};
   a.layers = reinterpret_cast<const qtree::LayerDev*>(p->ws + p->lay.layers);
   a.mids = reinterpret_cast<const float*>(p->ws + p->lay.aux);
+  a.guide = reinterpret_cast<const uint16_t*>(p->ws + p->lay.guide);
+  a.gt_Kmax = p->d == 1 ? p->gt_Kmax : -1;
+  a.gt_Bmax = p->gt_Bmax;
+  if (a.gt_Kmax >= 0 && qtree::keys_lds_1d_guide(p->maxP, p->gt_Bmax, p->max_tiles) > 160 * 1024)
+    a.gt_Kmax = -1;  // the tables do not fit beside the midpoints: binary search
   a.pts = reinterpret_cast<const float4*>(p->ws + p->lay.points);
   a.pts1 = reinterpret_cast<const float*>(p->ws + p->lay.points);
   a.counts = counts;

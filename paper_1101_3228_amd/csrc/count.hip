@@ -44,6 +44,7 @@ struct KeysJob {
   const LayerDev* L0;
   const LayerDev* L1;
   const float* mids;
+  const uint16_t* guide;
   const float4* pts;
   uint32_t key0, key1, contract;
   int k, c;
@@ -214,6 +215,83 @@ __device__ __forceinline__ void keys_chunk_1d(const KeysJob& j, float* lds) {
   sort_and_write<KB>(j, key, T, stage, tcount, cursor);
 }
 
+// Pass A, d = 1, with the guide tables of both layers (every layer's K <= GK):
+// the LDS holds the sorted midpoints of both layers (padded with +inf to
+// maxP + kGuideKMax entries) and their tables (maxB 16-bit entries each).
+
+struct GuideLds {
+  float *mk, *mk1;
+  uint16_t *tk, *tk1, *stage;
+  uint32_t *tcount, *cursor;
+};
+
+__device__ __forceinline__ GuideLds guide_lds(float* lds, int maxP, int maxB, int T) {
+  GuideLds g;
+  const int PM = maxP + kGuideKMax;
+  g.mk = lds;
+  g.mk1 = lds + PM;
+  g.tk = reinterpret_cast<uint16_t*>(lds + 2 * PM);
+  g.tk1 = g.tk + maxB;
+  // 16-byte aligned staging (it is copied out with 16-byte accesses)
+  g.stage = reinterpret_cast<uint16_t*>(lds + ((2 * PM + maxB + 3) & ~3));
+  g.tcount = reinterpret_cast<uint32_t*>(g.stage + kChunk);
+  g.cursor = g.tcount + (T + 1);
+  return g;
+}
+
+template <int KB>
+__device__ __forceinline__ void guide_stage(const KeysJob& j, const GuideLds& g, int maxP) {
+  const LayerDev& L0 = *j.L0;
+  const LayerDev& L1 = *j.L1;
+  const int PM = maxP + kGuideKMax;
+  const float inf = __builtin_huge_valf();
+  for (int i = threadIdx.x; i < PM; i += KB) {
+    g.mk[i] = i < L0.P ? j.mids[L0.aux_off + i] : inf;
+    g.mk1[i] = i < L1.P ? j.mids[L1.aux_off + i] : inf;
+  }
+  for (int i = threadIdx.x; i < L0.gt_B; i += KB) g.tk[i] = j.guide[L0.gt_off + i];
+  for (int i = threadIdx.x; i < L1.gt_B; i += KB) g.tk1[i] = j.guide[L1.gt_off + i];
+}
+
+template <int KB, int GK>
+__device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g) {
+  constexpr int kKeys = kChunk / KB;
+  const LayerDev& L0 = *j.L0;
+  const LayerDev& L1 = *j.L1;
+  const int T = L0.tiles;
+  for (int t = threadIdx.x; t <= T; t += KB) g.tcount[t] = 0;
+  __syncthreads();
+
+  const float mu = vgpr_copy(L0.mu[0]), Lz = vgpr_copy(L0.L[0]), A = vgpr_copy(L0.A[0]);
+  const float b = vgpr_copy(L0.b[0]), Tk = vgpr_copy(L0.T[0]);
+  const float s0 = vgpr_copy(L0.gt_scale), h0 = vgpr_copy(L0.gt_shift);
+  const float s1 = vgpr_copy(L1.gt_scale), h1 = vgpr_copy(L1.gt_shift);
+  const float bm0 = (float)(L0.gt_B - 1), bm1 = (float)(L1.gt_B - 1);
+  const uint32_t N1 = (uint32_t)L0.N1;
+  const uint64_t pb = (j.lo >> 1) + (uint64_t)j.c * (kChunk / 2);
+  uint32_t key[kKeys];
+#pragma unroll
+  for (int e = 0; e < kKeys / 2; ++e) {
+    const uint64_t blk = pb + (uint64_t)e * KB + threadIdx.x;
+    const U4 r = philox4x32_10_vk(U4{(uint32_t)blk, (uint32_t)j.k, j.contract, 0u}, j.key0,
+                                  j.key1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint64_t m = 2 * blk + h;
+      const bool live = m >= j.lo && m < j.hi;
+      float z, eps;
+      box_muller(h ? r.z : r.x, h ? r.w : r.y, z, eps);
+      const float x = fmaf(Lz, z, mu);
+      const float y = fmaf(Tk, eps, fmaf(A, x, b));
+      const int c0 = cell_1d_guide<GK>(g.mk, g.tk, s0, h0, bm0, x);
+      const int c1 = cell_1d_guide<GK>(g.mk1, g.tk1, s1, h1, bm1, y);
+      const uint32_t kk = (uint32_t)c0 * N1 + (uint32_t)c1;
+      key[2 * e + h] = live ? kk : 0xFFFFFFFFu;
+    }
+  }
+  sort_and_write<KB>(j, key, T, g.stage, g.tcount, g.cursor);
+}
+
 // Pass A, d = 2, 3: S samples per lane share each LDS grid read, in
 // kChunk / (KB S) rounds whose keys stay in registers.  The grid
 // scans take tiles of kNdTile records (a smaller tile than the padding unit
@@ -366,6 +444,7 @@ __device__ __forceinline__ KeysJob plan_job(const FwdArgs& a, int k, int c) {
   j.L0 = &a.layers[k];
   j.L1 = &a.layers[k + 1];
   j.mids = a.mids;
+  j.guide = a.guide;
   j.pts = a.pts;
   j.key0 = a.key0;
   j.key1 = a.key1;
@@ -389,6 +468,17 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   int k, c;
   if (!unit_of_block_keys(a, k, c)) return;
   keys_chunk_1d<kBlock, LOGP>(plan_job(a, k, c), lds);
+}
+
+template <int GK>
+__global__ __launch_bounds__(kBlock) void fwd_keys_1d_guide(FwdArgs a) {
+  extern __shared__ float lds[];
+  int k, c;
+  if (!unit_of_block_keys(a, k, c)) return;
+  const KeysJob j = plan_job(a, k, c);
+  const GuideLds g = guide_lds(lds, a.maxP, a.gt_Bmax, a.layers[k].tiles);
+  guide_stage<kBlock>(j, g, a.maxP);
+  guide_chunk<kBlock, GK>(j, g);
 }
 
 template <int D, int S>
@@ -513,6 +603,12 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles) {
+  const size_t words = (2 * (size_t)(maxP + kGuideKMax) + (size_t)maxB + 3) & ~(size_t)3;
+  return sizeof(float) * words + sizeof(uint16_t) * kChunk +
+         sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
+}
+
 size_t keys_lds_1d(int maxP, int max_tiles) {
   return sizeof(float) * (2 * (size_t)maxP + 4) + sizeof(uint16_t) * kChunk +
          sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
@@ -525,7 +621,23 @@ size_t keys_lds_nd(int maxN, int max_tiles) {
 
 hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
   hipError_t e;
-  if (a.d == 1) {
+  if (a.d == 1 && a.gt_Kmax >= 0) {
+    // guide tables: one instance per bound K on the midpoints a bucket adds
+    const size_t lds = keys_lds_1d_guide(a.maxP, a.gt_Bmax, a.max_tiles);
+    const FwdArgs& g = a;
+    switch (a.gt_Kmax) {
+#define QTREE_KEYS_1D_GUIDE(K, GK)                                                        \
+  case K:                                                                                 \
+    if ((e = allow_lds(fwd_keys_1d_guide<GK>, lds)) != hipSuccess) return e;              \
+    hipLaunchKernelGGL(fwd_keys_1d_guide<GK>, keys_grid(g), dim3(kBlock), lds, s, g);     \
+    break;
+      QTREE_KEYS_1D_GUIDE(0, 1) QTREE_KEYS_1D_GUIDE(1, 1) QTREE_KEYS_1D_GUIDE(2, 2)
+      QTREE_KEYS_1D_GUIDE(3, 3) QTREE_KEYS_1D_GUIDE(4, 4)
+#undef QTREE_KEYS_1D_GUIDE
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else if (a.d == 1) {
     // one instance per search depth: the plan's largest padded midpoint count
     const size_t lds = keys_lds_1d(a.maxP, a.max_tiles);
     switch (a.maxP) {

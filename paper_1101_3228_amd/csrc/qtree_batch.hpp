@@ -53,6 +53,7 @@ hipError_t launch_batch_count(const BatchArgs& a, hipStream_t s);
 // `lds` bytes of dynamic LDS each.
 int batch_keys_occupancy(int dmax, int lg1, size_t lds);
 size_t keys_lds_1d(int maxP, int max_tiles);
+size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles);
 size_t keys_lds_nd(int maxN, int max_tiles);
 
 // BDP of one contract for payoffs [q0, q0 + nq) (nq <= 16).

@@ -22,6 +22,8 @@ constexpr int kChunk = 4096;          // samples per pass-A workgroup
 constexpr int kMaxTiles = 4096;       // larger count blocks use direct atomics
 constexpr int kDefaultBatch = 1 << 22;  // samples per layer per pass by default
 constexpr int kScanTile = 8;            // records per tile of the d >= 2 argmin scan
+constexpr int kGuideMax = 8192;         // largest guide table of a 1-D layer (entries)
+constexpr int kGuideKMax = 4;           // most midpoints one guide bucket may add
 
 // One record per layer k = 0..n, stored in the plan's device workspace.
 // Model coefficients are the FP32 inputs of the AR(1) proposition (Sec. 3);
@@ -37,6 +39,13 @@ struct alignas(16) LayerDev {
   int32_t tiles;    // ceil(N_k N_{k+1} / kTile) (0 on the last layer)
   int32_t tile_off; // super tiles of the layers before k
   int32_t edge_off; // 1-D: first of the N_k + 1 cell-edge probabilities of layer k
+  // 1-D guide table of the cell search: bucket b = (int)clamp(fma(x, gt_scale,
+  // gt_shift), 0, gt_B - 1); the cell is tab[b] + #{r < K : m[tab[b] + r] < x}
+  // for K >= gt_K (the table holds the count of midpoints below the bucket's
+  // first float; gt_K bounds the midpoints a bucket can add).
+  int32_t gt_off;   // first entry of the layer's table (16-bit entries)
+  int32_t gt_B, gt_K;
+  float gt_scale, gt_shift;
   float A[9], b[3], T[9], mu[3], L[9];
   float x0[3];      // start point of the pathwise mode (layer 0 record)
 };
@@ -47,6 +56,7 @@ struct WsLayout {
   size_t points;   // d == 1: float[sum N]; d >= 2: float4[sum N] = (g0, g1, g2, h)
   size_t aux;      // d == 1: float[sum P] midpoints padded with +inf
   size_t edges;    // d == 1: double[sum (N_k + 1)] marginal probabilities below the cell edges
+  size_t guide;    // d == 1: uint16[(n + 1) kGuideMax] guide tables of the cell search
   size_t keys;     // uint16[n][batch chunks][kChunk] pass-A keys
   size_t segs;     // uint32[n][batch chunks][max tiles + 1] segment starts
   size_t total;
@@ -59,6 +69,9 @@ bool two_pass_fits(int d, int n, const int32_t* N);
 struct FwdArgs {
   const LayerDev* layers;
   const float* mids;     // 1-D midpoints (padded per layer)
+  const uint16_t* guide; // 1-D guide tables (kGuideMax entries per layer)
+  int gt_Kmax;           // 1-D: largest guide K over the layers, -1 without tables
+  int gt_Bmax;           // 1-D: largest guide table
   const float4* pts;     // d >= 2 points with half norm
   const float* pts1;     // 1-D points
   int32_t* counts;

@@ -25,6 +25,8 @@ struct qtree_plan {
   std::vector<int32_t> tile_off;  // first super tile of every layer (host copy)
   std::vector<float> marg_L;      // d = 1: the marginal factor L_k of every layer
   std::vector<double> edges;      // d = 1: host copy of the cell-edge probabilities
+  int32_t gt_Kmax = -1;           // d = 1: largest guide K over the layers (-1: no tables)
+  int32_t gt_Bmax = 1;            // d = 1: largest guide table
   int64_t batch_chunks = 0;      // scratch chunks per layer per pass
   bool two_pass_ok = false;
   hipEvent_t trace_keys = nullptr;

@@ -61,6 +61,37 @@ __device__ __forceinline__ int cell_1d_bfs(const float* e, float x) {
   return (int)((addr - base) >> 2) - (1 << LOGP);
 }
 
+// cell_1d by a guide table: bucket b = (int)clamp(fma(x, scale, shift), 0,
+// B - 1) (bmax = B - 1), then c = tab[b] + #{r < K : m[tab[b] + r] < x}.
+// Exact when tab[b] counts the midpoints below the first float of bucket b
+// and K bounds the midpoints inside any bucket (the host builds both from
+// the same float formula), with m padded by K entries of +inf.  The
+// comparisons are the sign bit of m - x (see cell_1d_bfs); the K loads are
+// independent of each other.
+template <int K>
+__device__ __forceinline__ int cell_1d_guide(const float* m, const uint16_t* tab, float scale,
+                                             float shift, float bmax, float x) {
+  float t = fmaf(x, scale, shift);
+  t = fmaxf(t, 0.0f);
+  t = fminf(t, bmax);
+  const int c0 = tab[(int)t];
+  int c = c0;
+  // each comparison is consumed where its midpoint arrives: a volatile block
+  // keeps the compiler from sinking the comparisons to the end of the chunk,
+  // which would hold every loaded midpoint in a register until then
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    uint32_t tmp;
+    asm volatile(
+        "v_sub_f32_e32 %[t], %[m], %[x]\n\t"
+        "v_lshrrev_b32_e32 %[t], 31, %[t]\n\t"
+        "v_add_u32_e32 %[c], %[c], %[t]"
+        : [c] "+v"(c), [t] "=&v"(tmp)
+        : [m] "v"(m[c0 + r]), [x] "v"(x));
+  }
+  return c;
+}
+
 // X_k = mu + L z and X_{k+1} = b + A X_k + T eps, row by row, left-to-right
 // chains of fused multiply-adds (the AR(1) proposition of Sec. 3).
 template <int D>
