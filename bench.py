@@ -78,7 +78,7 @@ PEAK_SLOTS = 256 * 128 * 2.4e9         # lane-slots per second
 MLP_SLOTS_PER_QUERY = 768 * 11 + 512 + 256 + 256
 
 
-def _measured_traffic(kernel: str = "fwd_keys_1d"):
+def _measured_traffic(kernel: str = "fwd_keys_1d_guide"):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     runs (profiles/<kernel>_traffic.json), or None when the kernel's sources
     changed since the counters were taken."""
@@ -283,7 +283,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS,
                      "traffic": _measured_traffic(),
-                     "kernel": "fwd_keys_1d",
+                     "kernel": "fwd_keys_1d_guide<2>",
                      "alg_slots_per_pair": ALG_SLOTS_PER_PAIR},
     }
     if not args.no_cpu_baseline:
