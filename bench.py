@@ -13,7 +13,7 @@ buffered), as a stream of pricing requests would.  The value is pairs per
 second over whole steps, every step's BDP included.
 
 Prints one JSON line.  Roofline of the dominant kernel (the sampling pass,
-fwd_keys_1d): algorithmic VALU lane-slots per pair (the fixed arithmetic of
+fwd_keys_1d_guide): algorithmic VALU lane-slots per pair (the fixed arithmetic of
 one pair, see ALG_SLOTS_PER_PAIR) times the pairs of one step, divided by the
 time of the step's sampling launches measured with HIP events on their
 stream (from the start of the step to a trace event the library records
