@@ -70,11 +70,12 @@ struct TileJob {
 // per tile; the exclusive scan gives each tile's segment start; phase 2
 // places every key at its tile's cursor; the staged chunk is then copied to
 // its scratch slot with wide stores, and the segment starts with it.
-template <int KB>
+// ALL: every key of the chunk is valid (no 0xFFFFFFFF slots).
+template <int KB, bool ALL = false>
 __device__ __forceinline__ void count_keys(const uint32_t* key, uint32_t* tcount) {
 #pragma unroll
   for (int e = 0; e < kChunk / KB; ++e)
-    if (key[e] != 0xFFFFFFFFu) atomicAdd(&tcount[key[e] >> kTileBits], 1u);
+    if (ALL || key[e] != 0xFFFFFFFFu) atomicAdd(&tcount[key[e] >> kTileBits], 1u);
 }
 
 // Exclusive scan of tcount[0..T) in place (tcount[T] = total), copied to
@@ -104,27 +105,27 @@ __device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, i
   if (lane == 63) tcount[T] = incl;
 }
 
-template <int KB>
+template <int KB, bool ALL = false>
 __device__ __forceinline__ void place_keys(const uint32_t* key, uint32_t* cursor,
                                            uint16_t* stage) {
 #pragma unroll
   for (int e = 0; e < kChunk / KB; ++e) {
-    if (key[e] != 0xFFFFFFFFu) {
+    if (ALL || key[e] != 0xFFFFFFFFu) {
       const uint32_t pos = atomicAdd(&cursor[key[e] >> kTileBits], 1u);
       stage[pos] = (uint16_t)(key[e] & (kSuper - 1));
     }
   }
 }
 
-template <int KB>
+template <int KB, bool ALL = false>
 __device__ __forceinline__ void sort_and_write(const KeysJob& j, const uint32_t* key, int T,
                                                uint16_t* stage, uint32_t* tcount,
                                                uint32_t* cursor) {
-  count_keys<KB>(key, tcount);
+  count_keys<KB, ALL>(key, tcount);
   __syncthreads();
   scan_tiles(tcount, cursor, T);
   __syncthreads();
-  place_keys<KB>(key, cursor, stage);
+  place_keys<KB, ALL>(key, cursor, stage);
   __syncthreads();
   for (int t = threadIdx.x; t <= T; t += KB) j.seg[t] = tcount[t];
   const uint32_t total = tcount[T];
@@ -253,43 +254,71 @@ __device__ __forceinline__ void guide_stage(const KeysJob& j, const GuideLds& g,
   for (int i = threadIdx.x; i < L1.gt_B; i += KB) g.tk1[i] = j.guide[L1.gt_off + i];
 }
 
+// The keys of one chunk, whose samples are m0 + [0, kChunk) with
+// m0 = 2 pb: sample 2 (pb + e KB + lane) + h is key slot 2 e + h of the lane.
+// Every slot gets its key; the chunks at the ends of [lo, hi) then mark
+// their dead slots (guide_chunk).  The Philox key and the coefficients are
+// copied to vector registers once per chunk.
 template <int KB, int GK>
-__device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g) {
+__device__ __forceinline__ void guide_keys(const KeysJob& j, const GuideLds& g,
+                                           uint32_t (&key)[kChunk / KB]) {
   constexpr int kKeys = kChunk / KB;
   const LayerDev& L0 = *j.L0;
   const LayerDev& L1 = *j.L1;
-  const int T = L0.tiles;
-  for (int t = threadIdx.x; t <= T; t += KB) g.tcount[t] = 0;
-  __syncthreads();
-
   const float mu = vgpr_copy(L0.mu[0]), Lz = vgpr_copy(L0.L[0]), A = vgpr_copy(L0.A[0]);
   const float b = vgpr_copy(L0.b[0]), Tk = vgpr_copy(L0.T[0]);
   const float s0 = vgpr_copy(L0.gt_scale), h0 = vgpr_copy(L0.gt_shift);
   const float s1 = vgpr_copy(L1.gt_scale), h1 = vgpr_copy(L1.gt_shift);
+  const uint32_t k0 = vgpr_copy(j.key0), k1 = vgpr_copy(j.key1);
   const float bm0 = (float)(L0.gt_B - 1), bm1 = (float)(L1.gt_B - 1);
   const uint32_t N1 = (uint32_t)L0.N1;
-  const uint64_t pb = (j.lo >> 1) + (uint64_t)j.c * (kChunk / 2);
-  uint32_t key[kKeys];
+  // the low word of the chunk's first Philox block (the counter's word 0)
+  const uint32_t pb = (uint32_t)((j.lo >> 1) + (uint64_t)j.c * (kChunk / 2));
+  const uint32_t lane = threadIdx.x;
 #pragma unroll
   for (int e = 0; e < kKeys / 2; ++e) {
-    const uint64_t blk = pb + (uint64_t)e * KB + threadIdx.x;
-    const U4 r = philox4x32_10_vk(U4{(uint32_t)blk, (uint32_t)j.k, j.contract, 0u}, j.key0,
-                                  j.key1);
+    const U4 r = philox4x32_10(U4{pb + (uint32_t)(e * KB) + lane, (uint32_t)j.k, j.contract, 0u},
+                               k0, k1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const uint64_t m = 2 * blk + h;
-      const bool live = m >= j.lo && m < j.hi;
       float z, eps;
       box_muller(h ? r.z : r.x, h ? r.w : r.y, z, eps);
       const float x = fmaf(Lz, z, mu);
       const float y = fmaf(Tk, eps, fmaf(A, x, b));
       const int c0 = cell_1d_guide<GK>(g.mk, g.tk, s0, h0, bm0, x);
       const int c1 = cell_1d_guide<GK>(g.mk1, g.tk1, s1, h1, bm1, y);
-      const uint32_t kk = (uint32_t)c0 * N1 + (uint32_t)c1;
-      key[2 * e + h] = live ? kk : 0xFFFFFFFFu;
+      key[2 * e + h] = (uint32_t)c0 * N1 + (uint32_t)c1;
     }
   }
-  sort_and_write<KB>(j, key, T, g.stage, g.tcount, g.cursor);
+}
+
+template <int KB, int GK>
+__device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g) {
+  const int T = j.L0->tiles;
+  for (int t = threadIdx.x; t <= T; t += KB) g.tcount[t] = 0;
+  __syncthreads();
+  const uint64_t m0 = 2 * ((j.lo >> 1) + (uint64_t)j.c * (kChunk / 2));
+  uint32_t key[kChunk / KB];
+  guide_keys<KB, GK>(j, g, key);
+  if (m0 >= j.lo && m0 + kChunk <= j.hi) {
+    sort_and_write<KB, true>(j, key, T, g.stage, g.tcount, g.cursor);
+  } else {
+    // slot 2 e + h holds sample m0 + rel, rel = 2 (e KB + lane) + h; it is
+    // live when rel - rlo < rhi - rlo (unsigned), [rlo, rhi) = [lo, hi) - m0
+    // clamped to [0, kChunk]
+    const uint64_t lo = j.lo > m0 ? j.lo - m0 : 0;
+    const uint64_t hi = j.hi > m0 ? j.hi - m0 : 0;
+    const uint32_t rlo = (uint32_t)(lo < kChunk ? lo : kChunk);
+    const uint32_t rhi = (uint32_t)(hi < kChunk ? hi : kChunk);
+#pragma unroll
+    for (int e = 0; e < kChunk / KB / 2; ++e)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t rel = 2u * ((uint32_t)(e * KB) + threadIdx.x) + (uint32_t)h;
+        if (rel - rlo >= rhi - rlo) key[2 * e + h] = 0xFFFFFFFFu;
+      }
+    sort_and_write<KB>(j, key, T, g.stage, g.tcount, g.cursor);
+  }
 }
 
 // Pass A, d = 2, 3: S samples per lane share each LDS grid read, in

@@ -122,11 +122,32 @@ __device__ __forceinline__ void sincos_2pi_u24(uint32_t J, float& sn, float& cs)
   cs = __uint_as_float(__float_as_uint(b) ^ sgn_c);
 }
 
+// Correctly rounded square root of a in {+0, -0} u [2^-24, 64] (the
+// Box-Muller radius argument; -0 when u_a = 1).  r = the hardware estimate (within one ulp), rd its
+// predecessor (r (1 - 2^-24) rounds to it for every normal r), ru = the
+// successor of rd's successor; the residuals rd r - a and ru r - a, each
+// one rounded fma, decide between the three candidates (the neighbour test
+// of the IEEE square root): rd when rd r >= a, ru when ru r < a, else r.
+// An exact zero residual is +0, so each decision is the residual's sign bit
+// and the result is bits(rd) + [rd r < a] + [ru r < a].  On this domain no
+// residual underflows, so no input scaling is needed; a = +-0 gives
+// r = rd = +-0 (the hardware square root keeps the sign of zero), both
+// residuals +0 and the result +-0.
+__device__ __forceinline__ float sqrt_rn_radius(float a) {
+  const float r = __builtin_amdgcn_sqrtf(a);
+  const float rd = r * 0x1.fffffep-1f;
+  const uint32_t rb = __float_as_uint(rd);
+  const float ru = __uint_as_float(rb + 2u);
+  const uint32_t ed = __float_as_uint(fmaf(rd, r, -a));
+  const uint32_t eu = __float_as_uint(fmaf(ru, r, -a));
+  return __uint_as_float(rb + (ed >> 31) + (eu >> 31));
+}
+
 // Box-Muller: rho = sqrt(-2 ln u_a), u_a = ((ra >> 8) + 1) 2^-24 in (0, 1];
 // angle 2 pi u_b, u_b = (rb >> 8) 2^-24.  z0 = rho cos, z1 = rho sin.
 __device__ __forceinline__ void box_muller(uint32_t ra, uint32_t rb, float& z0, float& z1) {
   const float l = ln_u24((ra >> 8) + 1u);
-  const float rho = sqrtf(-2.0f * l);  // lowered to a correctly rounded sequence
+  const float rho = sqrt_rn_radius(-2.0f * l);
   float s, c;
   sincos_2pi_u24(rb >> 8, s, c);
   z0 = rho * c;

@@ -71,10 +71,14 @@ __device__ __forceinline__ int cell_1d_bfs(const float* e, float x) {
 template <int K>
 __device__ __forceinline__ int cell_1d_guide(const float* m, const uint16_t* tab, float scale,
                                              float shift, float bmax, float x) {
-  float t = fmaf(x, scale, shift);
-  t = fmaxf(t, 0.0f);
-  t = fminf(t, bmax);
+  // clamp by one median-of-three (x is finite, so it equals max then min)
+  const float t = __builtin_amdgcn_fmed3f(fmaf(x, scale, shift), 0.0f, bmax);
   const int c0 = tab[(int)t];
+  // the K candidates are loaded together (adjacent words: paired LDS reads),
+  // then compared
+  float mv[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) mv[r] = m[c0 + r];
   int c = c0;
   // each comparison is consumed where its midpoint arrives: a volatile block
   // keeps the compiler from sinking the comparisons to the end of the chunk,
@@ -87,7 +91,7 @@ __device__ __forceinline__ int cell_1d_guide(const float* m, const uint16_t* tab
         "v_lshrrev_b32_e32 %[t], 31, %[t]\n\t"
         "v_add_u32_e32 %[c], %[c], %[t]"
         : [c] "+v"(c), [t] "=&v"(tmp)
-        : [m] "v"(m[c0 + r]), [x] "v"(x));
+        : [m] "v"(mv[r]), [x] "v"(x));
   }
   return c;
 }
