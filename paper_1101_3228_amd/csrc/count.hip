@@ -38,6 +38,8 @@ namespace {
 constexpr int kBlock = 256;      // pass-A workgroup, d = 1
 constexpr int kBlockNd = 512;    // pass-A workgroup, d >= 2 (two waves per SIMD under one grid pair)
 constexpr int kCountBlock = 1024;
+constexpr int kGuideSub = 4;         // sub-counters per tile in the guide kernel's sort
+constexpr int kGuideSubTiles = 256;  // ... when a layer has at most this many tiles
 
 // One pass-A job: chunk c of the samples [lo, hi) of layer k.
 struct KeysJob {
@@ -65,17 +67,26 @@ struct TileJob {
   int first;
 };
 
-// Counting sort of a chunk's keys by tile, in LDS.  `tcount` holds T + 1
-// counters, `cursor` T, `stage` kChunk 16-bit slots.  Phase 1 counts keys
-// per tile; the exclusive scan gives each tile's segment start; phase 2
-// places every key at its tile's cursor; the staged chunk is then copied to
-// its scratch slot with wide stores, and the segment starts with it.
-// ALL: every key of the chunk is valid (no 0xFFFFFFFF slots).
-template <int KB, bool ALL = false>
+// Counting sort of a chunk's keys by tile, in LDS.  `tcount` holds T S + 1
+// counters, `cursor` T S, `stage` kChunk 16-bit slots.  Each tile has S
+// sub-counters, taken by lane & (S - 1): the lanes of a wave whose keys share
+// a tile then mostly update different words (same-word LDS atomics of one
+// wave are serialized), and tile t's segment is the concatenation of its S
+// sub-segments.  Phase 1 counts keys per (tile, sub-counter); the exclusive
+// scan gives each its start; phase 2 places every key at its cursor; the
+// staged chunk is then copied to its scratch slot with wide stores, and the
+// tile segment starts with it.  ALL: every key of the chunk is valid (no
+// 0xFFFFFFFF slots).
+template <int S>
+__device__ __forceinline__ uint32_t sub_counter(uint32_t key) {
+  return (key >> kTileBits) * S + (threadIdx.x & (S - 1));
+}
+
+template <int KB, bool ALL = false, int S = 1>
 __device__ __forceinline__ void count_keys(const uint32_t* key, uint32_t* tcount) {
 #pragma unroll
   for (int e = 0; e < kChunk / KB; ++e)
-    if (ALL || key[e] != 0xFFFFFFFFu) atomicAdd(&tcount[key[e] >> kTileBits], 1u);
+    if (ALL || key[e] != 0xFFFFFFFFu) atomicAdd(&tcount[sub_counter<S>(key[e])], 1u);
 }
 
 // Exclusive scan of tcount[0..T) in place (tcount[T] = total), copied to
@@ -105,30 +116,30 @@ __device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, i
   if (lane == 63) tcount[T] = incl;
 }
 
-template <int KB, bool ALL = false>
+template <int KB, bool ALL = false, int S = 1>
 __device__ __forceinline__ void place_keys(const uint32_t* key, uint32_t* cursor,
                                            uint16_t* stage) {
 #pragma unroll
   for (int e = 0; e < kChunk / KB; ++e) {
     if (ALL || key[e] != 0xFFFFFFFFu) {
-      const uint32_t pos = atomicAdd(&cursor[key[e] >> kTileBits], 1u);
+      const uint32_t pos = atomicAdd(&cursor[sub_counter<S>(key[e])], 1u);
       stage[pos] = (uint16_t)(key[e] & (kSuper - 1));
     }
   }
 }
 
-template <int KB, bool ALL = false>
+template <int KB, bool ALL = false, int S = 1>
 __device__ __forceinline__ void sort_and_write(const KeysJob& j, const uint32_t* key, int T,
                                                uint16_t* stage, uint32_t* tcount,
                                                uint32_t* cursor) {
-  count_keys<KB, ALL>(key, tcount);
+  count_keys<KB, ALL, S>(key, tcount);
   __syncthreads();
-  scan_tiles(tcount, cursor, T);
+  scan_tiles(tcount, cursor, T * S);
   __syncthreads();
-  place_keys<KB, ALL>(key, cursor, stage);
+  place_keys<KB, ALL, S>(key, cursor, stage);
   __syncthreads();
-  for (int t = threadIdx.x; t <= T; t += KB) j.seg[t] = tcount[t];
-  const uint32_t total = tcount[T];
+  for (int t = threadIdx.x; t <= T; t += KB) j.seg[t] = tcount[t * S];
+  const uint32_t total = tcount[T * S];
   uint4* out = reinterpret_cast<uint4*>(j.keys);
   const uint4* src = reinterpret_cast<const uint4*>(stage);
   const uint32_t vecs = (total + 7) / 8;  // 8 keys per 16-byte store
@@ -226,7 +237,7 @@ struct GuideLds {
   uint32_t *tcount, *cursor;
 };
 
-__device__ __forceinline__ GuideLds guide_lds(float* lds, int maxP, int maxB, int T) {
+__device__ __forceinline__ GuideLds guide_lds(float* lds, int maxP, int maxB, int TS) {
   GuideLds g;
   const int PM = maxP + kGuideKMax;
   g.mk = lds;
@@ -236,7 +247,7 @@ __device__ __forceinline__ GuideLds guide_lds(float* lds, int maxP, int maxB, in
   // 16-byte aligned staging (it is copied out with 16-byte accesses)
   g.stage = reinterpret_cast<uint16_t*>(lds + ((2 * PM + maxB + 3) & ~3));
   g.tcount = reinterpret_cast<uint32_t*>(g.stage + kChunk);
-  g.cursor = g.tcount + (T + 1);
+  g.cursor = g.tcount + (TS + 1);
   return g;
 }
 
@@ -292,16 +303,16 @@ __device__ __forceinline__ void guide_keys(const KeysJob& j, const GuideLds& g,
   }
 }
 
-template <int KB, int GK>
+template <int KB, int GK, int S>
 __device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g) {
   const int T = j.L0->tiles;
-  for (int t = threadIdx.x; t <= T; t += KB) g.tcount[t] = 0;
+  for (int t = threadIdx.x; t <= T * S; t += KB) g.tcount[t] = 0;
   __syncthreads();
   const uint64_t m0 = 2 * ((j.lo >> 1) + (uint64_t)j.c * (kChunk / 2));
   uint32_t key[kChunk / KB];
   guide_keys<KB, GK>(j, g, key);
   if (m0 >= j.lo && m0 + kChunk <= j.hi) {
-    sort_and_write<KB, true>(j, key, T, g.stage, g.tcount, g.cursor);
+    sort_and_write<KB, true, S>(j, key, T, g.stage, g.tcount, g.cursor);
   } else {
     // slot 2 e + h holds sample m0 + rel, rel = 2 (e KB + lane) + h; it is
     // live when rel - rlo < rhi - rlo (unsigned), [rlo, rhi) = [lo, hi) - m0
@@ -317,7 +328,7 @@ __device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g)
         const uint32_t rel = 2u * ((uint32_t)(e * KB) + threadIdx.x) + (uint32_t)h;
         if (rel - rlo >= rhi - rlo) key[2 * e + h] = 0xFFFFFFFFu;
       }
-    sort_and_write<KB>(j, key, T, g.stage, g.tcount, g.cursor);
+    sort_and_write<KB, false, S>(j, key, T, g.stage, g.tcount, g.cursor);
   }
 }
 
@@ -499,15 +510,15 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d(FwdArgs a) {
   keys_chunk_1d<kBlock, LOGP>(plan_job(a, k, c), lds);
 }
 
-template <int GK>
+template <int GK, int S>
 __global__ __launch_bounds__(kBlock) void fwd_keys_1d_guide(FwdArgs a) {
   extern __shared__ float lds[];
   int k, c;
   if (!unit_of_block_keys(a, k, c)) return;
   const KeysJob j = plan_job(a, k, c);
-  const GuideLds g = guide_lds(lds, a.maxP, a.gt_Bmax, a.layers[k].tiles);
+  const GuideLds g = guide_lds(lds, a.maxP, a.gt_Bmax, a.layers[k].tiles * S);
   guide_stage<kBlock>(j, g, a.maxP);
-  guide_chunk<kBlock, GK>(j, g);
+  guide_chunk<kBlock, GK, S>(j, g);
 }
 
 template <int D, int S>
@@ -632,10 +643,12 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+int guide_sub_counters(int max_tiles) { return max_tiles <= kGuideSubTiles ? kGuideSub : 1; }
+
 size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles) {
   const size_t words = (2 * (size_t)(maxP + kGuideKMax) + (size_t)maxB + 3) & ~(size_t)3;
-  return sizeof(float) * words + sizeof(uint16_t) * kChunk +
-         sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
+  const size_t ts = (size_t)max_tiles * guide_sub_counters(max_tiles);
+  return sizeof(float) * words + sizeof(uint16_t) * kChunk + sizeof(uint32_t) * (2 * ts + 1);
 }
 
 size_t keys_lds_1d(int maxP, int max_tiles) {
@@ -657,8 +670,15 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
     switch (a.gt_Kmax) {
 #define QTREE_KEYS_1D_GUIDE(K, GK)                                                        \
   case K:                                                                                 \
-    if ((e = allow_lds(fwd_keys_1d_guide<GK>, lds)) != hipSuccess) return e;              \
-    hipLaunchKernelGGL(fwd_keys_1d_guide<GK>, keys_grid(g), dim3(kBlock), lds, s, g);     \
+    if (guide_sub_counters(a.max_tiles) == kGuideSub) {                                   \
+      if ((e = allow_lds(fwd_keys_1d_guide<GK, kGuideSub>, lds)) != hipSuccess) return e; \
+      hipLaunchKernelGGL((fwd_keys_1d_guide<GK, kGuideSub>), keys_grid(g), dim3(kBlock),  \
+                         lds, s, g);                                                      \
+    } else {                                                                              \
+      if ((e = allow_lds(fwd_keys_1d_guide<GK, 1>, lds)) != hipSuccess) return e;         \
+      hipLaunchKernelGGL((fwd_keys_1d_guide<GK, 1>), keys_grid(g), dim3(kBlock), lds, s,  \
+                         g);                                                              \
+    }                                                                                     \
     break;
       QTREE_KEYS_1D_GUIDE(0, 1) QTREE_KEYS_1D_GUIDE(1, 1) QTREE_KEYS_1D_GUIDE(2, 2)
       QTREE_KEYS_1D_GUIDE(3, 3) QTREE_KEYS_1D_GUIDE(4, 4)

@@ -65,34 +65,21 @@ __device__ __forceinline__ int cell_1d_bfs(const float* e, float x) {
 // B - 1) (bmax = B - 1), then c = tab[b] + #{r < K : m[tab[b] + r] < x}.
 // Exact when tab[b] counts the midpoints below the first float of bucket b
 // and K bounds the midpoints inside any bucket (the host builds both from
-// the same float formula), with m padded by K entries of +inf.  The
-// comparisons are the sign bit of m - x (see cell_1d_bfs); the K loads are
-// independent of each other.
+// the same float formula), with m padded by K entries of +inf.  The clamp is
+// one median-of-three (x is finite, so it equals max then min); each
+// comparison is the sign bit of m - x (subtract, shift: full-rate
+// operations, where a compare and select issue at half rate).  Written as
+// plain arithmetic, the searches of neighbouring samples are free to be
+// scheduled together: the compiler issues the table reads of several samples,
+// then their paired candidate reads, before the first wait.
 template <int K>
 __device__ __forceinline__ int cell_1d_guide(const float* m, const uint16_t* tab, float scale,
                                              float shift, float bmax, float x) {
-  // clamp by one median-of-three (x is finite, so it equals max then min)
   const float t = __builtin_amdgcn_fmed3f(fmaf(x, scale, shift), 0.0f, bmax);
   const int c0 = tab[(int)t];
-  // the K candidates are loaded together (adjacent words: paired LDS reads),
-  // then compared
-  float mv[K];
-#pragma unroll
-  for (int r = 0; r < K; ++r) mv[r] = m[c0 + r];
   int c = c0;
-  // each comparison is consumed where its midpoint arrives: a volatile block
-  // keeps the compiler from sinking the comparisons to the end of the chunk,
-  // which would hold every loaded midpoint in a register until then
 #pragma unroll
-  for (int r = 0; r < K; ++r) {
-    uint32_t tmp;
-    asm volatile(
-        "v_sub_f32_e32 %[t], %[m], %[x]\n\t"
-        "v_lshrrev_b32_e32 %[t], 31, %[t]\n\t"
-        "v_add_u32_e32 %[c], %[c], %[t]"
-        : [c] "+v"(c), [t] "=&v"(tmp)
-        : [m] "v"(mv[r]), [x] "v"(x));
-  }
+  for (int r = 0; r < K; ++r) c += (int)(__float_as_uint(m[c0 + r] - x) >> 31);
   return c;
 }
 
