@@ -283,7 +283,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS,
                      "traffic": _measured_traffic(),
-                     "kernel": "fwd_keys_1d_guide<2>",
+                     "kernel": "fwd_keys_1d_guide<2, 4>",
                      "alg_slots_per_pair": ALG_SLOTS_PER_PAIR},
     }
     if not args.no_cpu_baseline:
