@@ -334,6 +334,14 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
   // host image of the workspace
   std::vector<char> img(p.lay.total, 0);
   auto* layers = reinterpret_cast<qtree::LayerDev*>(img.data() + p.lay.layers);
+  // histogram parts: a layer with fewer super tiles than the largest layer
+  // splits each into up to that ratio (at most 16) parts over the chunks, so
+  // that no workgroup of the histogram pass takes many times the keys of
+  // another (a one-point first layer has a single super tile)
+  int64_t st_max = 1;
+  for (int k = 0; k < n; ++k)
+    st_max = std::max<int64_t>(st_max, ((int64_t)N[k] * N[k + 1] + qtree::kSuper - 1) / qtree::kSuper);
+  int32_t total_units = 0;
   for (int k = 0; k <= n; ++k) {
     qtree::LayerDev L{};
     L.cnt_off = k < n ? p.cnt_off[k] : 0;
@@ -348,7 +356,13 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     L.tile_off = p.total_tiles;
     L.edge_off = (int32_t)(p.pt_off[k] + k);
     p.tile_off.push_back(p.total_tiles);
-    p.total_tiles += (int32_t)((entries_k + qtree::kSuper - 1) / qtree::kSuper);
+    const int64_t st_k = (entries_k + qtree::kSuper - 1) / qtree::kSuper;
+    p.total_tiles += (int32_t)st_k;
+    L.split = st_k > 0 ? (int32_t)std::min<int64_t>(16, std::max<int64_t>(1, st_max / st_k)) : 1;
+    L.unit_off = total_units;
+    p.split.push_back(L.split);
+    p.unit_off.push_back(total_units);
+    total_units += (int32_t)(st_k * L.split);
     if (k < n) {
       std::memcpy(L.A, model->A + dd * k, sizeof(float) * dd);
       std::memcpy(L.b, model->b + (size_t)d * k, sizeof(float) * d);
@@ -461,7 +475,7 @@ static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uin
   a.segs = reinterpret_cast<uint32_t*>(p->ws + p->lay.segs);
   a.max_tiles = p->max_tiles;
   a.seg_stride = p->max_tiles + 1;
-  a.total_tiles = p->total_tiles;
+  a.total_tiles = p->unit_off[p->n];
   return a;
 }
 
@@ -519,9 +533,14 @@ static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hip
       c.layer0 = k0;
       c.units = (k1 - k0) * b.chunks;
       c.units_per_xcd = (c.units + 7) / 8;
-      c.tile0 = p->tile_off[k0];
-      c.total_tiles = p->tile_off[k1] - p->tile_off[k0];
-      e = qtree::launch_fwd_keys(c, s);
+      c.tile0 = p->unit_off[k0];
+      c.total_tiles = p->unit_off[k1] - p->unit_off[k0];
+      // a split layer's histogram parts add into its count block: clear it
+      // first (ordered before the histogram pass by the stream and the fork)
+      bool any_split = false;
+      for (int k = k0; k < k1; ++k) any_split = any_split || p->split[k] > 1;
+      if (b.first_batch && any_split) e = qtree::launch_zero_split(c, k1 - k0, s);
+      if (e == hipSuccess) e = qtree::launch_fwd_keys(c, s);
       if (e != hipSuccess) break;
       if (g == groups - 1 && p->trace_keys) e = hipEventRecord(p->trace_keys, s);
       if (e != hipSuccess) break;

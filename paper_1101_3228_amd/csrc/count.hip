@@ -62,9 +62,11 @@ struct TileJob {
   const uint32_t* seg;
   int seg_stride;
   int chunks;
+  int c_lo, c_hi;     // the chunks [c_lo, c_hi) of this job
   int t;
   int32_t* counts_k;  // count block of the layer
   int first;
+  int atomic;         // one part of a split super tile: add nonzero bins atomically
 };
 
 // Counting sort of a chunk's keys by tile, in LDS.  `tcount` holds T S + 1
@@ -405,15 +407,15 @@ __device__ __forceinline__ void count_tile(const TileJob& j, uint32_t* hist, uin
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   constexpr int kWaves = kCountBlock / 64;
   constexpr int kInFlight = 4;
-  for (int c0 = 0; c0 < j.chunks; c0 += kCountBlock) {
+  for (int c0 = j.c_lo; c0 < j.c_hi; c0 += kCountBlock) {
     __syncthreads();
     const int c = c0 + (int)threadIdx.x;
-    if (c < j.chunks) {
+    if (c < j.c_hi) {
       sb[threadIdx.x] = j.seg[(size_t)c * j.seg_stride + f0];
       se[threadIdx.x] = j.seg[(size_t)c * j.seg_stride + f1];
     }
     __syncthreads();
-    const int cn = (j.chunks - c0) < kCountBlock ? (j.chunks - c0) : kCountBlock;
+    const int cn = (j.c_hi - c0) < kCountBlock ? (j.c_hi - c0) : kCountBlock;
     for (int g = wave * kInFlight; g < cn; g += kWaves * kInFlight) {
       uint32_t s0[kInFlight], s1[kInFlight], v[kInFlight];
       const uint4* kv[kInFlight];
@@ -455,7 +457,10 @@ __device__ __forceinline__ void count_tile(const TileJob& j, uint32_t* hist, uin
   const int64_t base = (int64_t)j.t * kSuper;
   const int bins = (int)((total - base) < kSuper ? (total - base) : kSuper);
   int32_t* dst = j.counts_k + base;
-  if (j.first) {
+  if (j.atomic) {
+    for (int i = threadIdx.x; i < bins; i += kCountBlock)
+      if (hist[i] != 0u) atomicAdd(&dst[i], (int32_t)hist[i]);
+  } else if (j.first) {
     for (int i = threadIdx.x; i < bins; i += kCountBlock) dst[i] = (int32_t)hist[i];
   } else {
     for (int i = threadIdx.x; i < bins; i += kCountBlock) dst[i] += (int32_t)hist[i];
@@ -533,10 +538,10 @@ __global__ __launch_bounds__(kBlockNd) void fwd_keys_nd(FwdArgs a) {
 __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
   extern __shared__ uint32_t hist[];
   const int b = a.tile0 + (int)blockIdx.x;
-  int lo = 0, hi = a.n - 1;  // largest k with tile_off_k <= b
+  int lo = 0, hi = a.n - 1;  // largest k with unit_off_k <= b
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (a.layers[mid].tile_off <= b) lo = mid; else hi = mid - 1;
+    if (a.layers[mid].unit_off <= b) lo = mid; else hi = mid - 1;
   }
   const int k = lo;
   TileJob j;
@@ -545,9 +550,16 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
   j.seg = a.segs + (size_t)k * a.chunks * a.seg_stride;
   j.seg_stride = a.seg_stride;
   j.chunks = a.chunks;
-  j.t = b - a.layers[k].tile_off;
+  // unit = super tile * split + part; part p takes chunks [p C / split, (p+1) C / split)
+  const int split = a.layers[k].split > 1 ? a.layers[k].split : 1;
+  const int r = b - a.layers[k].unit_off;
+  j.t = r / split;
+  const int part = r - j.t * split;
+  j.c_lo = (int)((int64_t)a.chunks * part / split);
+  j.c_hi = (int)((int64_t)a.chunks * (part + 1) / split);
   j.counts_k = a.counts + a.layers[k].cnt_off;
   j.first = a.first_batch;
+  j.atomic = split > 1;
   count_tile(j, hist, hist + kSuper, hist + kSuper + kCountBlock);
 }
 
@@ -622,6 +634,9 @@ __global__ __launch_bounds__(kCountBlock) void batch_count(BatchArgs a) {
   j.seg = a.segs + (size_t)C.seg_base + (size_t)T.k * C.chunks * (size_t)C.seg_stride;
   j.seg_stride = C.seg_stride;
   j.chunks = C.chunks;
+  j.c_lo = 0;
+  j.c_hi = C.chunks;
+  j.atomic = 0;
   j.t = T.t;
   j.counts_k = C.counts + C.layers[T.k].cnt_off;
   j.first = 1;
@@ -712,6 +727,22 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
     if ((e = allow_lds(fwd_keys_nd<3, 4>, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL((fwd_keys_nd<3, 4>), keys_grid(a), dim3(kBlockNd), lds, s, a);
   }
+  return hipGetLastError();
+}
+
+// One workgroup per layer of [layer0, layer0 + gridDim.x): a split layer's
+// count block is cleared before its histogram parts add into it.
+__global__ __launch_bounds__(256) void zero_split_kernel(FwdArgs a) {
+  const LayerDev& L = a.layers[a.layer0 + (int)blockIdx.x];
+  if (L.split <= 1) return;
+  const int64_t n = (int64_t)L.N * L.N1;
+  int32_t* dst = a.counts + L.cnt_off;
+  for (int64_t i = threadIdx.x; i < n; i += 256) dst[i] = 0;
+}
+
+hipError_t launch_zero_split(const FwdArgs& a, int nl, hipStream_t s) {
+  if (nl <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_split_kernel, dim3((unsigned)nl), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -38,6 +38,12 @@ struct alignas(16) LayerDev {
   int32_t logP;     // log2(P)
   int32_t tiles;    // ceil(N_k N_{k+1} / kTile) (0 on the last layer)
   int32_t tile_off; // super tiles of the layers before k
+  // Histogram pass: each super tile of layer k is split into `split` parts
+  // over the chunks (layers with few super tiles, such as a one-point first
+  // layer, would otherwise give all their keys to a few workgroups); the
+  // parts of a split layer add into its count block atomically, zeroed first.
+  int32_t split;    // parts per super tile (1: one workgroup stores the tile)
+  int32_t unit_off; // histogram-pass units (super tiles x parts) of the layers before k
   int32_t edge_off; // 1-D: first of the N_k + 1 cell-edge probabilities of layer k
   // 1-D guide table of the cell search: bucket b = (int)clamp(fma(x, gt_scale,
   // gt_shift), 0, gt_B - 1); the cell is tab[b] + #{r < K : m[tab[b] + r] < x}
@@ -92,10 +98,10 @@ struct FwdArgs {
   uint32_t* segs;
   int32_t seg_stride;     // max tiles + 1
   int32_t max_tiles;
-  int32_t total_tiles;    // super tiles of this launch (pass-B grid)
+  int32_t total_tiles;    // histogram units of this launch (pass-B grid)
   int32_t first_batch;    // pass B overwrites instead of adding
   int32_t layer0;         // first layer of this launch (units and tiles)
-  int32_t tile0;          // first super tile of this launch
+  int32_t tile0;          // first histogram unit of this launch
 };
 
 // Forward obstacle on the sum of the factors (see qtree_payoff_forward).
@@ -130,6 +136,8 @@ hipError_t launch_fwd_layer_nd(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd_path(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s);
 hipError_t launch_count_tiles(const FwdArgs& a, hipStream_t s);
+// Zero the count blocks of the split layers in [layer0, layer0 + nl).
+hipError_t launch_zero_split(const FwdArgs& a, int nl, hipStream_t s);
 
 struct BdpArgs {
   const LayerDev* layers;

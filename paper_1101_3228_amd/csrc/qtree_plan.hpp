@@ -23,6 +23,8 @@ struct qtree_plan {
   int32_t tune_groups = 0;  // layer groups of the two-pass forward (0: automatic)
   int32_t max_tiles = 0, total_tiles = 0;
   std::vector<int32_t> tile_off;  // first super tile of every layer (host copy)
+  std::vector<int32_t> unit_off;  // first histogram unit of every layer (host copy)
+  std::vector<int32_t> split;     // histogram parts per super tile of every layer
   std::vector<float> marg_L;      // d = 1: the marginal factor L_k of every layer
   std::vector<double> edges;      // d = 1: host copy of the cell-edge probabilities
   int32_t gt_Kmax = -1;           // d = 1: largest guide K over the layers (-1: no tables)
