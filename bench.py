@@ -384,7 +384,7 @@ def run_c3(args):
 def run_batch(args):
     """256 contracts with uneven n in [10, 100] and N_k in [50, 2000], d
     alternating 1 / 2, M = 1e6 pairs per layer each, two payoffs per contract;
-    one batched run (persistent sampling launch, histogram launch, BDP launch,
+    one batched run (sampling launches, histogram launch, BDP launch,
     replayed as a hipGraph) per step."""
     import torch
     import paper_1101_3228_amd as qt

@@ -230,9 +230,9 @@ qtree_status qtree_swing(const qtree_plan *plan, const int32_t *counts, const do
  * its count buffer, its obstacles phi [n_pay][points] and its value buffer V
  * [n_pay][points] (all device).  qtree_batch_plan builds a device work list
  * of (contract, layer, chunk range) units sorted longest first; a run then
- * issues, per scratch group, two persistent sampling launches (the d >= 2
- * units, then the 1-D units) that claim units from their list until it is
- * empty and one histogram launch, and then
+ * issues, per scratch group, two sampling launches (the d >= 2 units, then
+ * the 1-D units) with one workgroup per chunk of the list, in list order (the
+ * costly units are dispatched first), and one histogram launch, and then
  * one BDP launch in which each workgroup walks all layers of one contract for
  * up to 16 of its payoffs.  Counts and values are bit-for-bit / 1e-9 the
  * ones of qtree_transitions + qtree_bdp per contract (same Philox counters).
@@ -241,9 +241,9 @@ qtree_status qtree_swing(const qtree_plan *plan, const int32_t *counts, const do
  * fits) -- the only call besides the tuner that allocates device memory.
  * flags bit 0: capture the run sequence into a hipGraph after the first run
  * and replay it from then on (needs a non-NULL stream).
- * A tuner (optional) times the candidate persistent grids on the first run
- * and keeps the fastest per batch shape in a text cache (path given, else
- * $QTREE_TUNE_CACHE, else memory only).
+ * A tuner (optional) keeps per batch shape the workgroups per CU that fit of
+ * each sampling launch (its occupancy limit, found on the first run) in a
+ * text cache (path given, else $QTREE_TUNE_CACHE, else memory only).
  * ---------------------------------------------------------------------- */
 typedef struct {
   const qtree_plan *plan;
@@ -261,8 +261,8 @@ typedef struct qtree_batch qtree_batch;
 
 qtree_status qtree_tuner_create(const char *cache_path, qtree_tuner **out);
 void qtree_tuner_destroy(qtree_tuner *tuner);
-/* Cached choice for a batch signature, 0 if none: workgroups per CU of the
- * 1-D sampling launch in bits 0-7, of the d >= 2 launch in bits 8-15. */
+/* Cached entry for a batch signature, 0 if none: workgroups per CU that fit
+ * of the 1-D sampling launch in bits 0-7, of the d >= 2 launch in bits 8-15. */
 int32_t qtree_tuner_lookup(const qtree_tuner *tuner, const char *signature);
 
 qtree_status qtree_batch_plan(const qtree_contract *contracts, int32_t n, qtree_tuner *tuner,
@@ -270,8 +270,8 @@ qtree_status qtree_batch_plan(const qtree_contract *contracts, int32_t n, qtree_
 /* Run the batch on `stream`; if V0_host (double[sum n_pay], contracts in
  * order) is not NULL, copy every V_0 there and synchronise. */
 qtree_status qtree_batch_run(qtree_batch *batch, double *V0_host, void *stream);
-/* Work units, histogram tiles, scratch groups, and the persistent workgroups
- * per CU of the 1-D and of the d >= 2 sampling launch (any pointer may be
+/* Work units, histogram tiles, scratch groups, and the workgroups per CU
+ * that fit of the 1-D and of the d >= 2 sampling launch (any pointer may be
  * NULL). */
 qtree_status qtree_batch_info(const qtree_batch *batch, int64_t *units, int64_t *tiles,
                               int32_t *groups, int32_t *per_cu_1d, int32_t *per_cu_nd);

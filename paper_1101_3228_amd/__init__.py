@@ -461,7 +461,7 @@ class Tuner:
 
 
 class Batch:
-    """Many contracts priced together (persistent sampling launch, histogram
+    """Many contracts priced together (sampling launches, histogram
     launch, one BDP launch; optional hipGraph replay).  items: list of dicts
     with plan, M, seed, contract_id, counts, phi [n_pay, points], V."""
 

@@ -1,9 +1,9 @@
 // Batched forward step + BDP for many contracts with uneven n and N_k:
-// per scratch group, two persistent pass-A launches (device work queues of
-// (contract, layer, chunk range) units, longest first: one for the d >= 2
-// contracts, one for the 1-D ones) and one pass-B launch; then one BDP
-// launch for all (contract, payoff group) pairs, captured once into a
-// hipGraph; plus the autotuner that picks each persistent grid.
+// per scratch group, two pass-A launches over device work lists of
+// (contract, layer, chunk range) units, longest first, one workgroup per
+// chunk (one launch for the d >= 2 contracts, one for the 1-D ones), and one
+// pass-B launch; then one BDP launch for all (contract, payoff group) pairs,
+// captured once into a hipGraph; plus the tuner cache of the launch shapes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,9 +32,11 @@ struct qtree_tuner {
 namespace {
 
 // Units [off[x], off[x] + cnt[x]) of a group: x = 0 the 1-D list, x = 1 the
-// d >= 2 list.
+// d >= 2 list; the chunk prefix of list x starts at chunk_base[x] of the
+// batch's prefix table and its launch has n_chunks[x] workgroups.
 struct Group {
   int unit_off[2] = {0, 0}, n_units[2] = {0, 0}, tile_off = 0, n_tiles = 0;
+  int chunk_base[2] = {0, 0}, n_chunks[2] = {0, 0};
 };
 
 qtree_status hip_error(hipError_t e, const char* what) {
@@ -70,6 +72,7 @@ struct qtree_batch {
   std::vector<qtree_contract> c;
   std::vector<qtree::BatchContract> hc;
   std::vector<qtree::BatchUnit> units;
+  std::vector<int32_t> chunk_off;  // per group and list: first chunk of every unit, then the total
   std::vector<qtree::BatchTile> tiles;
   std::vector<qtree::BdpJob> jobs;
   std::vector<qtree::BdpTask> bdp_tasks;  // all backward steps, step by step
@@ -79,10 +82,10 @@ struct qtree_batch {
   std::vector<double> unit_cost;
   qtree::BatchContract* d_contracts = nullptr;
   qtree::BatchUnit* d_units = nullptr;
+  int32_t* d_chunk_off = nullptr;
   qtree::BatchTile* d_tiles = nullptr;
   qtree::BdpJob* d_jobs = nullptr;
   qtree::BdpTask* d_bdp_tasks = nullptr;
-  int* d_head = nullptr;
   uint16_t* d_keys = nullptr;
   uint32_t* d_segs = nullptr;
   int64_t n_v0 = 0;
@@ -90,7 +93,7 @@ struct qtree_batch {
   int dmax = 1;               // largest d among the d >= 2 contracts (1: none)
   int lg1 = 0;                // search depth of the 1-D launch class (log2 of its largest P)
   int cus = 256;
-  int per_cu[2] = {1, 1};     // persistent workgroups per CU of each launch
+  int per_cu[2] = {1, 1};     // workgroups per CU that fit, of each sampling launch
   int max_per_cu[2] = {1, 1};
   qtree_tuner* tuner = nullptr;
   std::string signature;
@@ -100,9 +103,10 @@ struct qtree_batch {
 
   ~qtree_batch() {
     if (exec) hipGraphExecDestroy(exec);
-    for (void* p : {(void*)d_contracts, (void*)d_units, (void*)d_tiles, (void*)d_jobs,
+    for (void* p : {(void*)d_contracts, (void*)d_units, (void*)d_chunk_off, (void*)d_tiles,
+                    (void*)d_jobs,
                     (void*)d_bdp_tasks,
-                    (void*)d_head, (void*)d_keys, (void*)d_segs})
+                    (void*)d_keys, (void*)d_segs})
       if (p) hipFree(p);
   }
 };
@@ -115,23 +119,13 @@ qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x) {
   qtree::BatchArgs a{};
   a.contracts = b->d_contracts;
   a.units = b->d_units + g.unit_off[x];
+  a.chunk_off = b->d_chunk_off + g.chunk_base[x];
   a.tiles = b->d_tiles + g.tile_off;
   a.n_units = g.n_units[x];
   a.n_tiles = g.n_tiles;
-  a.head = b->d_head + 32 * x;
   a.keys = b->d_keys;
   a.segs = b->d_segs;
   return a;
-}
-
-// Pass A of launch class x with `per_cu` workgroups per CU, for every group.
-hipError_t enqueue_keys(const qtree_batch* b, int x, int per_cu, hipStream_t s) {
-  for (const Group& g : b->groups) {
-    hipError_t e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax, b->lg1,
-                                            per_cu * b->cus, b->lds[x], s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
@@ -139,7 +133,7 @@ hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
     hipError_t e = hipSuccess;
     for (int x = 1; x >= 0 && e == hipSuccess; --x)  // the heavier d >= 2 list first
       e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax, b->lg1,
-                                   b->per_cu[x] * b->cus, b->lds[x], s);
+                                   g.n_chunks[x], b->lds[x], s);
     if (e == hipSuccess) e = qtree::launch_batch_count(group_args(b, g, 0), s);
     if (e != hipSuccess) return e;
   }
@@ -147,50 +141,17 @@ hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
                                  b->step_off.data(), (int)b->step_off.size() - 1, s);
 }
 
-bool has_units(const qtree_batch* b, int x) {
-  for (const Group& g : b->groups)
-    if (g.n_units[x] > 0) return true;
-  return false;
-}
-
-// Time each pass-A launch class with every candidate persistent grid (powers
-// of two up to the occupancy limit) and keep the fastest.
-qtree_status tune(qtree_batch* b, hipStream_t s) {
+// The workgroups per CU that fit of each sampling launch (its occupancy
+// limit: the launches give one workgroup to every chunk, so there is no grid
+// to choose), kept per batch shape in the tuner's cache.
+qtree_status tune(qtree_batch* b, hipStream_t) {
   auto it = b->tuner->best.find(b->signature);
   if (it != b->tuner->best.end()) {
     for (int x = 0; x < 2; ++x)
       b->per_cu[x] = std::max(1, std::min((it->second >> (8 * x)) & 0xFF, b->max_per_cu[x]));
     return QTREE_OK;
   }
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return set_error(QTREE_EDEVICE, "tuner events");
-  for (int x = 0; x < 2; ++x) {
-    if (!has_units(b, x)) continue;
-    float best_ms = 1e30f;
-    int best = b->per_cu[x];
-    for (int cand = 1; cand <= b->max_per_cu[x]; cand *= 2) {
-      hipError_t e = enqueue_keys(b, x, cand, s);  // warm-up
-      if (e == hipSuccess) e = hipEventRecord(e0, s);
-      if (e == hipSuccess) e = enqueue_keys(b, x, cand, s);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e != hipSuccess) {
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
-        return hip_error(e, "tuner run");
-      }
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = cand;
-      }
-    }
-    b->per_cu[x] = best;
-  }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  for (int x = 0; x < 2; ++x) b->per_cu[x] = b->max_per_cu[x];
   b->tuner->best[b->signature] = b->per_cu[0] | (b->per_cu[1] << 8);
   save_cache(b->tuner);
   return QTREE_OK;
@@ -316,7 +277,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     if (x == 1 && b->dmax == 1) continue;
     b->max_per_cu[x] =
         std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lg1, b->lds[x]));
-    b->per_cu[x] = std::min(2, b->max_per_cu[x]);
+    b->per_cu[x] = b->max_per_cu[x];
   }
   int dev = 0;
   hipDeviceProp_t prop;
@@ -406,10 +367,16 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
                        [&](size_t a2, size_t b2) { return gc[a2] > gc[b2]; });
       grp.unit_off[cls] = (int)b->units.size();
       grp.n_units[cls] = (int)gu.size();
+      grp.chunk_base[cls] = (int)b->chunk_off.size();
+      int32_t run = 0;
       for (size_t u : order) {
         b->units.push_back(gu[u]);
         b->unit_cost.push_back(gc[u]);
+        b->chunk_off.push_back(run);
+        run += gu[u].nchunks;
       }
+      b->chunk_off.push_back(run);
+      grp.n_chunks[cls] = run;
     }
     grp.tile_off = (int)b->tiles.size();
     for (int i = 0; i < n; ++i) {
@@ -446,7 +413,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
   if (e == hipSuccess) e = upload(&b->d_tiles, b->tiles);
   if (e == hipSuccess) e = upload(&b->d_jobs, b->jobs);
   if (e == hipSuccess) e = upload(&b->d_bdp_tasks, b->bdp_tasks);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_head), 256);
+  if (e == hipSuccess) e = upload(&b->d_chunk_off, b->chunk_off);
   if (e == hipSuccess)
     e = hipMalloc(reinterpret_cast<void**>(&b->d_keys), scratch_keys * per_chunk_key + 16);
   if (e == hipSuccess)

@@ -23,9 +23,9 @@
 //    the order of keys irrelevant.
 //
 // The same device routines serve one plan (fwd_keys_*, count_tiles) and a
-// batch of contracts (batch_keys, batch_count): the batch kernel is
-// persistent and pulls (contract, layer, chunks) units, longest first, from a
-// device work queue until it is empty.
+// batch of contracts (batch_keys, batch_count): the batch kernel takes one
+// chunk of a device work list of (contract, layer, chunks) units, longest
+// first, per workgroup.
 #include "qtree_batch.hpp"
 #include "qtree_internal.hpp"
 #include "qtree_rng.hpp"
@@ -565,23 +565,27 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
 
 // ------------------------------------------------------------- a batch
 
-// Persistent pass A over a work list of (contract, layer, chunk range)
-// units sorted by decreasing cost; each workgroup claims the next unit until
-// the list is exhausted (the claim counter is reset by batch_reset first).
-// One launch takes the 1-D units (256 lanes, a few registers, several
-// workgroups per CU), another the d >= 2 units (512 lanes under one grid pair).
+// Pass A over a work list of (contract, layer, chunk range) units sorted by
+// decreasing cost: workgroup b takes chunk b of the list (the chunks of unit
+// u are [chunk_off[u], chunk_off[u + 1])), so the costly units are dispatched
+// first.  One workgroup per chunk, as in the single-plan kernels, keeps the
+// register allocation of the chunk routine alone (a persistent claim loop
+// around it held ~40 more).  One launch takes the 1-D units (256 lanes),
+// another the d >= 2 units (512 lanes under one grid pair).
 template <int KB, typename Body>
 __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
-  __shared__ int unit_sh;
-  for (;;) {
-    if (threadIdx.x == 0) unit_sh = atomicAdd(a.head, 1);
-    __syncthreads();
-    const int u = unit_sh;
-    __syncthreads();
-    if (u >= a.n_units) return;
-    const BatchUnit U = a.units[u];
-    const BatchContract& C = a.contracts[U.c];
-    for (int c = U.chunk0; c < U.chunk0 + U.nchunks; ++c) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = a.n_units - 1;  // largest u with chunk_off[u] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.chunk_off[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int u = lo;
+  const BatchUnit U = a.units[u];
+  const BatchContract& C = a.contracts[U.c];
+  {
+    const int c = U.chunk0 + (b - a.chunk_off[u]);
+    {
       KeysJob j;
       j.L0 = &C.layers[U.k];
       j.L1 = &C.layers[U.k + 1];
@@ -597,7 +601,6 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
       j.keys = a.keys + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
       j.seg = a.segs + (size_t)C.seg_base + ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
       body(C, j);
-      __syncthreads();
     }
   }
 }
@@ -643,7 +646,6 @@ __global__ __launch_bounds__(kCountBlock) void batch_count(BatchArgs a) {
   count_tile(j, hist, hist + kSuper, hist + kSuper + kCountBlock);
 }
 
-__global__ void batch_reset(int* head) { *head = 0; }
 
 // ------------------------------------------------------------- launchers
 
@@ -776,8 +778,7 @@ hipError_t launch_count_tiles(const FwdArgs& a, hipStream_t s) {
 hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, size_t lds,
                              hipStream_t s) {
   hipError_t e = hipSuccess;
-  if (a.n_units == 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, a.head);
+  if (a.n_units == 0 || grid <= 0) return hipSuccess;
   if (dmax <= 1) {
 #define QTREE_LAUNCH_1D(LG)                                                                 \
   if ((e = allow_lds(batch_keys_1d<LG>, lds)) == hipSuccess)                                \

@@ -36,15 +36,16 @@ struct BatchTile {
 struct BatchArgs {
   const BatchContract* contracts;
   const BatchUnit* units;  // this group's units (longest first)
+  const int32_t* chunk_off;  // first chunk of every unit in this launch (n_units + 1 entries)
   const BatchTile* tiles;  // this group's tiles
   int32_t n_units, n_tiles;
-  int* head;               // claim counter of the persistent pass A
   uint16_t* keys;
   uint32_t* segs;
 };
 
-// Persistent pass A over a.units: dmax 1 runs the 1-D kernel (every unit
-// must be 1-D), 2 or 3 the d >= 2 kernel.  Resets a.head first.
+// Pass A over a.units, one workgroup per chunk (`grid` = a.chunk_off[n_units]
+// chunks): dmax 1 runs the 1-D kernel (every unit must be 1-D), 2 or 3 the
+// d >= 2 kernel.
 hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, size_t lds,
                              hipStream_t s);
 // Pass B over a.tiles.
