@@ -930,7 +930,7 @@ def run_strat(args):
         "roofline": {"bound": "alu", "achieved": ALG_SLOTS_STRAT * value / 1e12,
                      "peak": PEAK_SLOTS / 1e12, "unit": "Tlane-slot/s",
                      "frac": ALG_SLOTS_STRAT * value / PEAK_SLOTS, "traffic": None,
-                     "kernel": f"strat_kernel<9> ({ALG_SLOTS_STRAT} lane-slots per pair)"},
+                     "kernel": f"strat_kernel_guide<2, 4> ({ALG_SLOTS_STRAT} lane-slots per pair)"},
     }
     print(json.dumps(out), flush=True)
 

@@ -696,6 +696,9 @@ static qtree_status strat_args(const qtree_plan* plan, uint64_t M, int32_t alloc
     return fail(QTREE_EUNSUPPORTED, "count rows do not fit in LDS");
   a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
   a.mids = reinterpret_cast<const float*>(plan->ws + plan->lay.aux);
+  a.guide = reinterpret_cast<const uint16_t*>(plan->ws + plan->lay.guide);
+  a.gt_Kmax = plan->gt_Kmax;
+  a.gt_Bmax = plan->gt_Bmax;
   a.edges = reinterpret_cast<const double*>(plan->ws + plan->lay.edges);
   a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
   a.key1 = (uint32_t)(seed >> 32);

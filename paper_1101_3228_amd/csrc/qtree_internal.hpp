@@ -175,6 +175,8 @@ hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s);
 struct StratArgs {
   const LayerDev* layers;
   const float* mids;      // sorted midpoints, padded per layer
+  const uint16_t* guide;  // guide tables of the cell search (kGuideMax entries per layer)
+  int gt_Kmax, gt_Bmax;   // largest guide K (-1: no tables) and table over the layers
   const double* edges;    // cell-edge probabilities per layer
   uint32_t key0, key1, contract;
   uint64_t M;             // samples per row (alloc 0) or per layer (alloc 1)

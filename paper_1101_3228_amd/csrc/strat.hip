@@ -9,10 +9,14 @@
 //
 // Rows are taken kStratRows at a time (a tile); a tile with more than
 // kStratSegment samples is shared by several workgroups (host-built work
-// list).  A workgroup keeps its tile's counts in LDS (rows x N_{k+1} words)
-// while its lanes walk the samples, then writes the rows with plain stores,
-// zeros included, or, for a shared tile, adds its nonzero counts onto the
-// zeroed rows with atomics.  No sort and no histogram pass.
+// list).  A workgroup keeps its tile's counts in LDS (rows x N_{k+1} words,
+// times S sub-counters taken by lane mod S: the samples of a wave share a row
+// and mostly fall in a few cells, and same-word LDS atomics of one wave
+// serialize) while its lanes walk the samples, then writes the rows with
+// plain stores, zeros included, or, for a shared tile, adds its nonzero
+// counts onto the zeroed rows with atomics.  No sort and no histogram pass.
+// X_{k+1}'s cell comes from the layer's guide table (cell_1d_guide) when the
+// plan has tables, else from the breadth-first search.
 //
 // Sample t of row i of layer k, as in the arithmetic specification:
 // Philox counter (t, k, contract, 4 + 256 i); u = (k52 + 1/2) 2^-52 with
@@ -190,6 +194,60 @@ __global__ __launch_bounds__(kBlock) void strat_kernel(StratArgs a, const StratU
   }
 }
 
+// The same with layer k+1's guide table: its sorted midpoints (+inf beyond
+// its P, to maxP + kGuideKMax entries), its table, then the counts
+// [kStratRows][N1][S].
+template <int GK, int S>
+__global__ __launch_bounds__(kBlock) void strat_kernel_guide(StratArgs a,
+                                                             const StratUnit* units) {
+  extern __shared__ float lds[];
+  const StratUnit U = units[blockIdx.x];
+  const int k = U.k;
+  const LayerDev& L0 = a.layers[k];
+  const LayerDev& L1 = a.layers[k + 1];
+  const int i0 = U.i0;
+  const int N1 = L0.N1;
+  const int PM = a.maxP + kGuideKMax;
+  float* mk1 = lds;
+  uint16_t* tk1 = reinterpret_cast<uint16_t*>(lds + PM);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + PM + (a.gt_Bmax + 1) / 2);
+  const float inf = __builtin_huge_valf();
+  for (int i = threadIdx.x; i < PM; i += kBlock) mk1[i] = i < L1.P ? a.mids[L1.aux_off + i] : inf;
+  for (int i = threadIdx.x; i < L1.gt_B; i += kBlock) tk1[i] = a.guide[L1.gt_off + i];
+  for (int i = threadIdx.x; i < kStratRows * N1 * S; i += kBlock) cnt[i] = 0u;
+  __syncthreads();
+  const float s1 = L1.gt_scale, h1 = L1.gt_shift, bm1 = (float)(L1.gt_B - 1);
+  const double* e = a.edges + L0.edge_off;
+  uint64_t pre[kStratRows + 1];
+  pre[0] = 0;
+#pragma unroll
+  for (int r = 0; r < kStratRows; ++r)
+    pre[r + 1] = pre[r] + (i0 + r < L0.N ? strat_row(a, e, i0 + r) : 0ull);
+  const uint32_t sub = threadIdx.x & (S - 1);
+  for (uint64_t s = U.s0 + threadIdx.x; s < U.s1; s += kBlock) {
+    int row = 0;
+#pragma unroll
+    for (int r = 1; r < kStratRows; ++r) row += s >= pre[r] ? 1 : 0;
+    float x, y;
+    strat_pair(a, L0, k, i0 + row, s - pre[row], x, y);
+    const int j = cell_1d_guide<GK>(mk1, tk1, s1, h1, bm1, y);
+    atomicAdd(&cnt[(uint32_t)(row * N1 + j) * S + sub], 1u);
+  }
+  __syncthreads();
+  const int rows = L0.N - i0 < kStratRows ? L0.N - i0 : kStratRows;
+  int32_t* out = a.counts + L0.cnt_off + (int64_t)i0 * N1;
+  for (int i = threadIdx.x; i < rows * N1; i += kBlock) {
+    uint32_t v = 0u;
+#pragma unroll
+    for (int q = 0; q < S; ++q) v += cnt[i * S + q];
+    if (U.split) {
+      if (v) atomicAdd(&out[i], (int32_t)v);
+    } else {
+      out[i] = (int32_t)v;
+    }
+  }
+}
+
 __global__ void strat_samples_kernel(StratArgs a, int k, int i, uint64_t t0, int64_t count,
                                      float* x, float* y) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -204,8 +262,47 @@ size_t strat_lds_bytes(int maxP, int maxN) {
   return sizeof(float) * (size_t)maxP + sizeof(uint32_t) * (size_t)kStratRows * (size_t)maxN;
 }
 
+namespace {
+size_t strat_lds_guide(const StratArgs& a, int S) {
+  return sizeof(float) * ((size_t)a.maxP + kGuideKMax + ((size_t)a.gt_Bmax + 1) / 2) +
+         sizeof(uint32_t) * (size_t)kStratRows * (size_t)a.maxN * (size_t)S;
+}
+
+template <int GK, int S>
+hipError_t launch_strat_guide(const StratArgs& a, const StratUnit* units, int n_units,
+                              size_t lds, hipStream_t s) {
+  hipError_t e = lds <= 65536 ? hipSuccess
+                              : hipFuncSetAttribute(
+                                    reinterpret_cast<const void*>(strat_kernel_guide<GK, S>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((strat_kernel_guide<GK, S>), dim3((unsigned)n_units), dim3(kBlock), lds, s,
+                     a, units);
+  return hipGetLastError();
+}
+
+template <int GK>
+hipError_t launch_strat_guide_k(const StratArgs& a, const StratUnit* units, int n_units,
+                                hipStream_t s) {
+  // four sub-counters while the counts stay within 64 KiB (more would cost
+  // occupancy), else one
+  const size_t lds4 = strat_lds_guide(a, 4);
+  if (lds4 <= 65536) return launch_strat_guide<GK, 4>(a, units, n_units, lds4, s);
+  return launch_strat_guide<GK, 1>(a, units, n_units, strat_lds_guide(a, 1), s);
+}
+}  // namespace
+
 hipError_t launch_strat(const StratArgs& a, const StratUnit* units, int n_units, hipStream_t s) {
   const dim3 grid((unsigned)n_units);
+  if (a.gt_Kmax >= 0 && a.gt_Kmax <= kGuideKMax && strat_lds_guide(a, 1) <= 160 * 1024) {
+    switch (a.gt_Kmax) {
+      case 0:
+      case 1: return launch_strat_guide_k<1>(a, units, n_units, s);
+      case 2: return launch_strat_guide_k<2>(a, units, n_units, s);
+      case 3: return launch_strat_guide_k<3>(a, units, n_units, s);
+      default: return launch_strat_guide_k<4>(a, units, n_units, s);
+    }
+  }
   const size_t lds = strat_lds_bytes(a.maxP, a.maxN);
   hipError_t e = hipErrorInvalidValue;
   switch (a.maxP) {
