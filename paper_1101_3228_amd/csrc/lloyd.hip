@@ -12,9 +12,13 @@
 //     as fused multiply-add chains from 0), assigns them with the tree's own
 //     cell search, and adds to LDS accumulators: the count, each coordinate
 //     as the integer rint(x 2^24) and the squared distance to the cell's
-//     point as rint(|x - g|^2 2^16) (FP64).  The workgroup's totals are added
-//     to global accumulators with 64-bit atomics.  Integer sums make the
-//     result independent of the order of the samples.
+//     point as rint(|x - g|^2 2^16) (FP64).  The workgroup stores its totals,
+//     zeros included, as row b of a partial table with plain stores.
+//   reduce: each workgroup sums 8 columns of the table over its rows (the
+//     step's cell sums, counts and distortion).  Integer sums make the result
+//     independent of the order of the samples and of the workgroups (the
+//     table replaces device atomics from every workgroup onto the same ~N d
+//     words, which serialized at the L2).
 //   update: one thread per cell: new point = (sum 2^-24) / count in FP64,
 //     rounded once to FP32 (an empty cell keeps its point), then its record
 //     or the midpoint to its right; the distortion of the step.
@@ -75,12 +79,6 @@ __global__ void lloyd_prepare_kernel(LloydArgs a) {
   }
 }
 
-__global__ void lloyd_zero_kernel(LloydArgs a) {
-  const int i = (int)(blockIdx.x * kBlock + threadIdx.x);
-  if (i < a.N) a.cnt[i] = 0u;
-  if (i < a.N * a.d) a.sum[i] = 0ull;
-  if (i == 0) *a.dist = 0ull;
-}
 
 // LDS: d = 1: midpoints [P], points [N]; d >= 2: records [Npad]; then the
 // counts [N] and the sums [N][d] (8-byte aligned).
@@ -154,17 +152,47 @@ __global__ __launch_bounds__(kBlock) void lloyd_accum_kernel(LloydArgs a) {
   for (int off = 32; off > 0; off >>= 1) dist += __shfl_xor(dist, off, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = dist;
   __syncthreads();
+  unsigned long long* row = a.part + (size_t)blockIdx.x * a.E;
+  const int nd = a.N * D;
   if (threadIdx.x == 0) {
     unsigned long long t = 0ull;
     for (int w = 0; w < kBlock / 64; ++w) t += part[w];
-    atomicAdd(a.dist, t);
+    row[nd + a.N] = t;
   }
-  for (int i = threadIdx.x; i < a.N; i += kBlock) {
-    const unsigned int c = cnt[i];
-    if (c == 0u) continue;
-    atomicAdd(&a.cnt[i], c);
+  for (int i = threadIdx.x; i < nd; i += kBlock) row[i] = sum[i];
+  for (int i = threadIdx.x; i < a.N; i += kBlock) row[nd + i] = cnt[i];
+}
+
+// Column sums of the partial table over its `rows` rows: workgroup b takes
+// columns [8 b, 8 b + 8); lane l adds rows l, l + 256, ...; the 256 lane
+// sums of each column are then added in LDS.
+constexpr int kReduceCols = 8;
+__global__ __launch_bounds__(kBlock) void lloyd_reduce_kernel(LloydArgs a, int rows) {
+  __shared__ unsigned long long red[kReduceCols][kBlock];
+  const int c0 = (int)blockIdx.x * kReduceCols;
+  unsigned long long acc[kReduceCols] = {};
+  for (int r = threadIdx.x; r < rows; r += kBlock) {
+    const unsigned long long* src = a.part + (size_t)r * a.E + c0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) atomicAdd(&a.sum[(size_t)i * D + k], sum[(size_t)i * D + k]);
+    for (int q = 0; q < kReduceCols; ++q)
+      if (c0 + q < a.E) acc[q] += src[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kReduceCols; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < kReduceCols; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < kReduceCols) {
+    const int c = c0 + (int)threadIdx.x;
+    const int nd = a.N * a.d;
+    const unsigned long long v = red[threadIdx.x][0];
+    if (c < nd) a.sum[c] = v;
+    else if (c < nd + a.N) a.cnt[c - nd] = (unsigned int)v;
+    else if (c == nd + a.N) *a.dist = v;
   }
 }
 
@@ -213,8 +241,7 @@ hipError_t launch_lloyd_prepare(const LloydArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_lloyd_step(const LloydArgs& a, int blocks, hipStream_t s) {
-  const int nz = a.N * a.d > 1 ? a.N * a.d : 1;
-  hipLaunchKernelGGL(lloyd_zero_kernel, dim3((nz + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+  if (blocks < 1 || blocks > kLloydMaxBlocks) return hipErrorInvalidValue;
   const size_t lds = lloyd_lds_bytes(a.d, a.N, a.Npad, a.P);
   hipError_t e = hipSuccess;
   if (a.d == 1) {
@@ -237,6 +264,8 @@ hipError_t launch_lloyd_step(const LloydArgs& a, int blocks, hipStream_t s) {
       hipLaunchKernelGGL(lloyd_accum_kernel<3>, dim3(blocks), dim3(kBlock), lds, s, a);
   }
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lloyd_reduce_kernel, dim3((a.E + kReduceCols - 1) / kReduceCols),
+                     dim3(kBlock), 0, s, a, blocks);
   hipLaunchKernelGGL(lloyd_update_kernel, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                      a);
   return hipGetLastError();

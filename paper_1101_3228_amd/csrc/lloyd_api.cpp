@@ -28,7 +28,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct LloydLayout {
   int Npad, P, logP;
-  size_t recs, mids, cnt, sum, dist, total;
+  size_t recs, mids, cnt, sum, dist, part, total;
 };
 
 LloydLayout layout(int d, int N) {
@@ -51,6 +51,10 @@ LloydLayout layout(int d, int N) {
   off = align_up(off + sizeof(unsigned long long) * (size_t)N * d, 256);
   l.dist = off;
   off = align_up(off + sizeof(unsigned long long), 256);
+  l.part = off;
+  off = align_up(off + sizeof(unsigned long long) * qtree::kLloydMaxBlocks *
+                           ((size_t)N * d + (size_t)N + 1),
+                 256);
   l.total = off;
   return l;
 }
@@ -129,14 +133,18 @@ qtree_status qtree_lloyd(int32_t d, int32_t N, const float* L, const float* grid
   a.sum = reinterpret_cast<unsigned long long*>(ws + l.sum);
   a.dist = reinterpret_cast<unsigned long long*>(ws + l.dist);
   a.distortion = distortion;
+  a.part = reinterpret_cast<unsigned long long*>(ws + l.part);
+  a.E = N * d + N + 1;
   e = hipMemcpyAsync(grid, grid0, sizeof(float) * (size_t)N * d, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return set_error(QTREE_EDEVICE, std::string("start grid copy: ") +
                                                            hipGetErrorString(e));
   e = qtree::launch_lloyd_prepare(a, s);
-  // two workgroups per CU, fewer when the samples of a step are few
+  // two workgroups per CU (at most kLloydMaxBlocks), fewer when the samples
+  // of a step are few
   const uint64_t per_block = 256ull * (d == 1 ? 1 : 4);
   const uint64_t want = (M + per_block - 1) / per_block;
-  const int blocks = (int)(want < (uint64_t)(2 * cus) ? want : (uint64_t)(2 * cus));
+  const uint64_t cap = std::min<uint64_t>(2ull * cus, qtree::kLloydMaxBlocks);
+  const int blocks = (int)(want < cap ? want : cap);
   for (int32_t it = 0; it < steps && e == hipSuccess; ++it) {
     a.it = it;
     a.it_ctr = fresh ? (uint32_t)it : 0u;

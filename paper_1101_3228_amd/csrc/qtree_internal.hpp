@@ -215,7 +215,12 @@ struct LloydArgs {
   unsigned long long* sum;   // [N][d] two's complement sums of rint(x 2^24)
   unsigned long long* dist;  // sum of rint(|x - g|^2 2^16)
   double* distortion;        // [steps] or null
+  // per-workgroup partials of the accumulation: row b holds workgroup b's
+  // sums [N d], counts [N] and distortion [1] (E = N d + N + 1 words)
+  unsigned long long* part;
+  int E;
 };
+constexpr int kLloydMaxBlocks = 512;  // accumulation workgroups per step at most
 size_t lloyd_lds_bytes(int d, int N, int Npad, int P);
 hipError_t launch_lloyd_prepare(const LloydArgs& a, hipStream_t s);
 hipError_t launch_lloyd_step(const LloydArgs& a, int blocks, hipStream_t s);
