@@ -92,6 +92,8 @@ struct qtree_batch {
   size_t lds[2] = {0, 0};     // dynamic LDS of the 1-D and d >= 2 launches
   int dmax = 1;               // largest d among the d >= 2 contracts (1: none)
   int lg1 = 0;                // search depth of the 1-D launch class (log2 of its largest P)
+  int gk1 = -1;               // 1-D launch: largest guide K (-1: breadth-first search)
+  int sub1 = 1, maxP1 = 1, gtB1 = 1;  // its sub-counters, midpoint slots, largest table
   int cus = 256;
   int per_cu[2] = {1, 1};     // workgroups per CU that fit, of each sampling launch
   int max_per_cu[2] = {1, 1};
@@ -122,6 +124,10 @@ qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x) {
   a.chunk_off = b->d_chunk_off + g.chunk_base[x];
   a.tiles = b->d_tiles + g.tile_off;
   a.n_units = g.n_units[x];
+  a.gk = x == 0 ? b->gk1 : -1;
+  a.sub = b->sub1;
+  a.maxP = b->maxP1;
+  a.gt_Bmax = b->gtB1;
   a.n_tiles = g.n_tiles;
   a.keys = b->d_keys;
   a.segs = b->d_segs;
@@ -198,6 +204,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
   };
   std::vector<int> job_contract;  // contract of every BDP job
   int maxP = 1, maxN = 1, max_tiles1 = 0, max_tilesn = 0;
+  int gk = 0, gtB = 1;  // guide tables of the 1-D contracts: largest K (-1 if one has none)
   int64_t v0_off = 0;
   for (int i = 0; i < n; ++i) {
     const qtree_contract& C = contracts[i];
@@ -227,6 +234,8 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     if (p->d == 1) {
       maxP = std::max(maxP, p->maxP);
       max_tiles1 = std::max(max_tiles1, p->max_tiles);
+      gk = (gk < 0 || p->gt_Kmax < 0) ? -1 : std::max(gk, (int)p->gt_Kmax);
+      gtB = std::max(gtB, (int)p->gt_Bmax);
     } else {
       maxN = std::max(maxN, p->maxN);
       max_tilesn = std::max(max_tilesn, p->max_tiles);
@@ -234,6 +243,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     qtree::BatchContract bc{};
     bc.layers = reinterpret_cast<const qtree::LayerDev*>(p->ws + p->lay.layers);
     bc.mids = reinterpret_cast<const float*>(p->ws + p->lay.aux);
+    bc.guide = reinterpret_cast<const uint16_t*>(p->ws + p->lay.guide);
     bc.pts = reinterpret_cast<const float4*>(p->ws + p->lay.points);
     bc.counts = C.counts;
     bc.key0 = (uint32_t)(C.seed & 0xFFFFFFFFu);
@@ -268,6 +278,13 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
   b->signature = sbuf;
   while ((1 << b->lg1) < maxP) ++b->lg1;
   b->lds[0] = qtree::keys_lds_1d(maxP, max_tiles1);
+  if (gk >= 0 && qtree::keys_lds_1d_guide(maxP, gtB, max_tiles1) <= 160 * 1024) {
+    b->gk1 = gk;
+    b->sub1 = qtree::guide_sub_counters(max_tiles1);
+    b->maxP1 = maxP;
+    b->gtB1 = gtB;
+    b->lds[0] = qtree::keys_lds_1d_guide(maxP, gtB, max_tiles1);
+  }
   b->lds[1] = qtree::keys_lds_nd(maxN, max_tilesn);
   if (b->lds[0] > 160 * 1024 || (b->dmax > 1 && b->lds[1] > 160 * 1024)) {
     delete b;
@@ -276,7 +293,8 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
   for (int x = 0; x < 2; ++x) {
     if (x == 1 && b->dmax == 1) continue;
     b->max_per_cu[x] =
-        std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lg1, b->lds[x]));
+        std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lg1,
+                                                x == 0 ? b->gk1 : -1, b->lds[x]));
     b->per_cu[x] = b->max_per_cu[x];
   }
   int dev = 0;

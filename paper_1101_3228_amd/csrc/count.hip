@@ -590,6 +590,7 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
       j.L0 = &C.layers[U.k];
       j.L1 = &C.layers[U.k + 1];
       j.mids = C.mids;
+      j.guide = C.guide;
       j.pts = C.pts;
       j.key0 = C.key0;
       j.key1 = C.key1;
@@ -614,6 +615,17 @@ __global__ __launch_bounds__(kBlock) void batch_keys_1d(BatchArgs a) {
   extern __shared__ float lds[];
   batch_loop<kBlock>(a, [&](const BatchContract&, const KeysJob& j) {
     keys_chunk_1d<kBlock, LG>(j, lds);
+  });
+}
+
+// The same with guide tables (the chunk routine of fwd_keys_1d_guide).
+template <int GK, int S>
+__global__ __launch_bounds__(kBlock) void batch_keys_1d_guide(BatchArgs a) {
+  extern __shared__ float lds[];
+  batch_loop<kBlock>(a, [&](const BatchContract&, const KeysJob& j) {
+    const GuideLds g = guide_lds(lds, a.maxP, a.gt_Bmax, j.L0->tiles * S);
+    guide_stage<kBlock>(j, g, a.maxP);
+    guide_chunk<kBlock, GK, S>(j, g);
   });
 }
 
@@ -779,7 +791,28 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
                              hipStream_t s) {
   hipError_t e = hipSuccess;
   if (a.n_units == 0 || grid <= 0) return hipSuccess;
-  if (dmax <= 1) {
+  if (dmax <= 1 && a.gk >= 0) {
+#define QTREE_LAUNCH_1DG(GK, S)                                                             \
+  if ((e = allow_lds(batch_keys_1d_guide<GK, S>, lds)) == hipSuccess)                       \
+    hipLaunchKernelGGL((batch_keys_1d_guide<GK, S>), dim3((unsigned)grid), dim3(kBlock), lds, \
+                       s, a);
+#define QTREE_LAUNCH_1DG_S(GK)            \
+  if (a.sub == kGuideSub) {               \
+    QTREE_LAUNCH_1DG(GK, kGuideSub)       \
+  } else {                                \
+    QTREE_LAUNCH_1DG(GK, 1)               \
+  }
+    switch (a.gk) {
+      case 0:
+      case 1: QTREE_LAUNCH_1DG_S(1) break;
+      case 2: QTREE_LAUNCH_1DG_S(2) break;
+      case 3: QTREE_LAUNCH_1DG_S(3) break;
+      default: QTREE_LAUNCH_1DG_S(4) break;
+    }
+#undef QTREE_LAUNCH_1DG_S
+#undef QTREE_LAUNCH_1DG
+    if (e != hipSuccess) return e;
+  } else if (dmax <= 1) {
 #define QTREE_LAUNCH_1D(LG)                                                                 \
   if ((e = allow_lds(batch_keys_1d<LG>, lds)) == hipSuccess)                                \
     hipLaunchKernelGGL(batch_keys_1d<LG>, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
@@ -796,10 +829,15 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
   return hipGetLastError();
 }
 
-int batch_keys_occupancy(int dmax, int lg1, size_t lds) {
+int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds) {
   int blocks = 0;
   hipError_t e = hipSuccess;
-  if (dmax <= 1) {
+  if (dmax <= 1 && gk >= 0) {
+    e = allow_lds(batch_keys_1d_guide<2, kGuideSub>, lds);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_1d_guide<2, kGuideSub>,
+                                                       kBlock, lds);
+  } else if (dmax <= 1) {
 #define QTREE_OCC_1D(LG)                                                                   \
   if ((e = allow_lds(batch_keys_1d<LG>, lds)) == hipSuccess)                               \
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_1d<LG>, kBlock, lds);

@@ -12,6 +12,7 @@ namespace qtree {
 struct BatchContract {
   const LayerDev* layers;
   const float* mids;
+  const uint16_t* guide;  // d = 1: the plan's guide tables
   const float4* pts;
   int32_t* counts;
   uint32_t key0, key1, contract;
@@ -39,6 +40,10 @@ struct BatchArgs {
   const int32_t* chunk_off;  // first chunk of every unit in this launch (n_units + 1 entries)
   const BatchTile* tiles;  // this group's tiles
   int32_t n_units, n_tiles;
+  // 1-D launch with guide tables (every 1-D contract has them): gk = the
+  // batch's largest K (-1: breadth-first search), over maxP midpoints and
+  // tables of up to gt_Bmax entries, sub sub-counters per tile in the sort
+  int32_t gk, sub, maxP, gt_Bmax;
   uint16_t* keys;
   uint32_t* segs;
 };
@@ -50,11 +55,12 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
                              hipStream_t s);
 // Pass B over a.tiles.
 hipError_t launch_batch_count(const BatchArgs& a, hipStream_t s);
-// Workgroups of the pass-A kernel (dmax as above) that fit on one CU with
-// `lds` bytes of dynamic LDS each.
-int batch_keys_occupancy(int dmax, int lg1, size_t lds);
+// Workgroups of the pass-A kernel (dmax as above; gk >= 0: the 1-D guide
+// kernel) that fit on one CU with `lds` bytes of dynamic LDS each.
+int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds);
 size_t keys_lds_1d(int maxP, int max_tiles);
 size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles);
+int guide_sub_counters(int max_tiles);
 size_t keys_lds_nd(int maxN, int max_tiles);
 
 // BDP of one contract for payoffs [q0, q0 + nq) (nq <= 16).
