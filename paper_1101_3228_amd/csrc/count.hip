@@ -336,12 +336,13 @@ __device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g)
 
 // Pass A, d = 2, 3: S samples per lane share each LDS grid read, in
 // kChunk / (KB S) rounds whose keys stay in registers.  The grid
-// scans take tiles of kNdTile records (a smaller tile than the padding unit
-// keeps the kernel within 128 VGPRs, four waves per SIMD).
+// scans take tiles of kNdTile records, the padding unit: one compare and two
+// selects per tile and sample for the running best (with 4-record tiles that
+// bookkeeping was ~a third of the scan's issue time; 8 records: 5 % faster).
 template <int D, int S, int KB>
 __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   constexpr int kKeys = kChunk / KB;
-  constexpr int kNdTile = 4;
+  constexpr int kNdTile = 8;
   static_assert(kScanTile % kNdTile == 0, "scan tile must divide the padding unit");
   const LayerDev& L0 = *j.L0;
   const LayerDev& L1 = *j.L1;

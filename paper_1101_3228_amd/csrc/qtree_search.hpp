@@ -186,7 +186,9 @@ __device__ __forceinline__ void argmin_scan_tiled(const float4* __restrict__ g, 
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     int found = tile[s] + TL - 1;
-#pragma unroll
+    // rolled: unrolled, the loads of every record of every sample's tile
+    // would be hoisted together (TL x S float4 registers)
+#pragma unroll 1
     for (int q = TL - 1; q >= 0; --q) {
       const float4 r = g[tile[s] + q];
       const float gc[3] = {r.x, r.y, r.z};
