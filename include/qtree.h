@@ -103,6 +103,16 @@ void qtree_plan_destroy(qtree_plan *plan);
 qtree_status qtree_plan_trace(qtree_plan *plan, void *event_after_keys);
 /* LAYERWISE samples per layer one counting pass holds (0: one-pass atomics only). */
 int64_t qtree_plan_batch_samples(const qtree_plan *plan);
+/* The 1-D cell search of the LAYERWISE forward and the stratified counts
+ * (host query, no device work): *guide_k = the largest number of midpoints
+ * that one bucket of a layer's guide table adds (the search is the bucket's
+ * first cell plus that many comparisons), or -1 when some layer has no such
+ * table within the bound of 4 or the tables do not fit in LDS (then every
+ * layer is searched by the breadth-first binary search); *guide_buckets =
+ * the largest table (0 with -1).  d >= 2 plans report -1.  Either pointer
+ * may be NULL.  EINVAL if plan is NULL. */
+qtree_status qtree_plan_cell_search(const qtree_plan *plan, int32_t *guide_k,
+                                    int32_t *guide_buckets);
 /* Shape queries (host). */
 int32_t qtree_plan_dim(const qtree_plan *plan);
 int32_t qtree_plan_layers(const qtree_plan *plan);

@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
     L.qtree_plan_tune.restype = ctypes.c_int
     L.qtree_plan_trace.argtypes = [P, P]
     L.qtree_plan_trace.restype = ctypes.c_int
+    L.qtree_plan_cell_search.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.qtree_plan_cell_search.restype = ctypes.c_int
     L.qtree_plan_batch_samples.argtypes = [P]
     L.qtree_plan_batch_samples.restype = i64
     L.qtree_payoff_batch.argtypes = [P, i32, P, P, P, P, P, P, P, P, P]
@@ -240,6 +242,13 @@ class Plan:
         _check(lib().qtree_transitions_add(self._h, int(m0), int(M), int(seed), int(contract),
                                            int(mode), counts.data_ptr(), _stream_handle(stream)))
         return counts
+
+    def cell_search(self):
+        """(guide K, guide buckets) of the 1-D cell search; (-1, 0): the
+        breadth-first binary search (and every d >= 2 plan)."""
+        k, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().qtree_plan_cell_search(self._h, ctypes.byref(k), ctypes.byref(b)))
+        return int(k.value), int(b.value)
 
     def trace(self, event=None):
         """Record `event` (torch.cuda.Event) after each sampling pass."""

@@ -594,6 +594,18 @@ qtree_status qtree_plan_trace(qtree_plan* plan, void* event_after_keys) {
   return QTREE_OK;
 }
 
+qtree_status qtree_plan_cell_search(const qtree_plan* plan, int32_t* guide_k,
+                                    int32_t* guide_buckets) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  // the choice of fwd_args: d = 1 tables that fit beside the midpoints
+  int32_t k = plan->d == 1 ? plan->gt_Kmax : -1;
+  if (k >= 0 && qtree::keys_lds_1d_guide(plan->maxP, plan->gt_Bmax, plan->max_tiles) > 160 * 1024)
+    k = -1;
+  if (guide_k) *guide_k = k;
+  if (guide_buckets) *guide_buckets = k >= 0 ? plan->gt_Bmax : 0;
+  return QTREE_OK;
+}
+
 int64_t qtree_plan_batch_samples(const qtree_plan* p) {
   if (!p || !p->two_pass_ok) return 0;
   return p->d == 1 ? p->batch_chunks * qtree::kChunk - 2 : p->batch_chunks * qtree::kChunk;

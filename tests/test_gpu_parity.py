@@ -245,6 +245,8 @@ def test_c2_layerwise_full_size():
     spec = synth.bm_model(1, n, T=1.0)
     grid, N = synth.layer_grids(spec, [1] + [Nn] * n, base=_lloyd)
     plan = _plan(spec, grid, N)
+    # the search the benchmark times: guide tables of 1024 buckets, K = 2
+    assert plan.cell_search() == (2, 1024)
     counts = plan.transitions(M, synth.SEED_BASE)
     got = counts.cpu().numpy()
     off = plan.count_offsets()
