@@ -311,7 +311,10 @@ void qtree_batch_destroy(qtree_batch *batch);
  * qtree_layer_samples: X_k and X_{k+1} of LAYERWISE samples m0..m0+count-1
  *   of layer k (0 <= k < n), device float[count][d] each.
  * qtree_cells: Voronoi cell in layer k (0 <= k <= n) of `count` device points
- *   x (float[count][d]); cell: device int32[count].
+ *   x (float[count][d]); cell: device int32[count].  d >= 2: the forward's
+ *   tiled scan over the layer's records staged in LDS, four points per lane
+ *   (the brute-force search of Sec. 4); d = 1: the binary search over the
+ *   layer's sorted midpoints.
  * All asynchronous on `stream`. */
 qtree_status qtree_box_muller(const uint32_t *ra, const uint32_t *rb, int64_t count, float *z0,
                               float *z1, void *stream);

@@ -37,20 +37,44 @@ __global__ void layer_samples_kernel(FwdArgs a, int k, int64_t count, float* x, 
   }
 }
 
-template <int D>
-__global__ void cells_kernel(FwdArgs a, int k, const float* x, int64_t count, int32_t* cell) {
+// d = 1: the binary search over the layer's sorted midpoints (the cell the
+// forward's guide or breadth-first search returns).
+__global__ void cells_1d_kernel(FwdArgs a, int k, const float* x, int64_t count, int32_t* cell) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= count) return;
   const LayerDev& L = a.layers[k];
-  if (D == 1) {
-    cell[i] = cell_1d(a.mids + L.aux_off, L.logP, x[i]);
-  } else {
-    float q[1][D];
+  cell[i] = cell_1d(a.mids + L.aux_off, L.logP, x[i]);
+}
+
+// d >= 2: the forward's scan.  The layer's records staged in LDS, padded to
+// whole kScanTile-record tiles with records whose key is +inf; kCellsS points
+// per lane share every record read (argmin_scan_tiled, tiles of kScanTile).
+constexpr int kCellsS = 4;
+template <int D>
+__global__ __launch_bounds__(kBlock) void cells_kernel(FwdArgs a, int k, const float* x,
+                                                       int64_t count, int32_t* cell) {
+  extern __shared__ float4 recs[];
+  const LayerDev& L = a.layers[k];
+  const int N = L.N;
+  const int Npad = (N + kScanTile - 1) / kScanTile * kScanTile;
+  const float4 pad = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
+  for (int r = threadIdx.x; r < Npad; r += kBlock) recs[r] = r < N ? a.pts[L.pt_off + r] : pad;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kBlock * kCellsS + threadIdx.x;
+  float q[kCellsS][D];
+  int idx[kCellsS];
 #pragma unroll
-    for (int c = 0; c < D; ++c) q[0][c] = x[i * D + c];
-    int j;
-    argmin_scan<D, 1>(a.pts + L.pt_off, L.N, q, &j);
-    cell[i] = j;
+  for (int s = 0; s < kCellsS; ++s) {
+    const int64_t i = base + (int64_t)s * kBlock;
+    const int64_t ii = i < count ? i : count - 1;  // the tail repeats the last point
+#pragma unroll
+    for (int c = 0; c < D; ++c) q[s][c] = x[ii * D + c];
+  }
+  argmin_scan_tiled<D, kCellsS, kScanTile>(recs, Npad, q, idx);
+#pragma unroll
+  for (int s = 0; s < kCellsS; ++s) {
+    const int64_t i = base + (int64_t)s * kBlock;
+    if (i < count) cell[i] = idx[s];
   }
 }
 
@@ -113,13 +137,23 @@ hipError_t launch_layer_samples(const FwdArgs& a, int k, int64_t count, float* x
 
 hipError_t launch_cells(const FwdArgs& a, int k, const float* x, int64_t count, int32_t* cell,
                         hipStream_t s) {
-  const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);
-  if (a.d == 1)
-    hipLaunchKernelGGL((cells_kernel<1>), dim3(blocks), dim3(kBlock), 0, s, a, k, x, count, cell);
-  else if (a.d == 2)
-    hipLaunchKernelGGL((cells_kernel<2>), dim3(blocks), dim3(kBlock), 0, s, a, k, x, count, cell);
+  if (a.d == 1) {
+    const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(cells_1d_kernel, dim3(blocks), dim3(kBlock), 0, s, a, k, x, count, cell);
+    return hipGetLastError();
+  }
+  const unsigned blocks = (unsigned)((count + kBlock * kCellsS - 1) / (kBlock * kCellsS));
+  const size_t lds = sizeof(float4) * (size_t)((a.maxN + kScanTile - 1) / kScanTile * kScanTile);
+  const void* fn = a.d == 2 ? reinterpret_cast<const void*>(cells_kernel<2>)
+                            : reinterpret_cast<const void*>(cells_kernel<3>);
+  hipError_t e = lds <= 65536 ? hipSuccess
+                              : hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)lds);
+  if (e != hipSuccess) return e;
+  if (a.d == 2)
+    hipLaunchKernelGGL((cells_kernel<2>), dim3(blocks), dim3(kBlock), lds, s, a, k, x, count, cell);
   else
-    hipLaunchKernelGGL((cells_kernel<3>), dim3(blocks), dim3(kBlock), 0, s, a, k, x, count, cell);
+    hipLaunchKernelGGL((cells_kernel<3>), dim3(blocks), dim3(kBlock), lds, s, a, k, x, count, cell);
   return hipGetLastError();
 }
 
