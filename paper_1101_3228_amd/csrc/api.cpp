@@ -132,24 +132,6 @@ int64_t chunks_for(int d, uint64_t samples) {
 
 }  // namespace qtree
 
-extern "C" {
-
-const char* qtree_status_string(qtree_status s) {
-  switch (s) {
-    case QTREE_OK: return "ok";
-    case QTREE_EINVAL: return "invalid argument";
-    case QTREE_ENOMEM: return "workspace too small";
-    case QTREE_EOVERFLOW: return "count overflow (M >= 2^31 or m0 + M > 2^32)";
-    case QTREE_EDEVICE: return "HIP runtime error";
-    case QTREE_EUNSUPPORTED: return "unsupported by this build";
-  }
-  return "unknown status";
-}
-
-const char* qtree_last_error(void) { return g_last_error.c_str(); }
-
-const char* qtree_version(void) { return "qtree 0.1 gfx950"; }
-
 // Guide table of a sorted 1-D midpoint array m[0 .. nm) (the cell search of
 // the forward kernels).  The device maps x to bucket
 //   b = (int)fminf(fmaxf(fmaf(x, scale, shift), 0), B - 1),
@@ -157,8 +139,8 @@ const char* qtree_version(void) { return "qtree 0.1 gfx950"; }
 // the table stores c(first float of the bucket), c(x) = #{r : m_r < x}, and
 // K bounds c(last float) - c(first float) over the buckets.  The table size is
 // the smallest power of two in 256 .. kGuideMax with K <= 2, else with
-// K <= kGuideKMax; K = 0 when none qualifies (the kernels then use the
-// binary search).
+// K <= kGuideKMax; K = -1 when none qualifies (the kernels then use the
+// breadth-first binary search).
 namespace {
 int64_t float_order(float x) {
   uint32_t u;
@@ -230,6 +212,25 @@ Guide build_guide(const float* m, int nm) {
   return best;
 }
 }  // namespace
+
+extern "C" {
+
+const char* qtree_status_string(qtree_status s) {
+  switch (s) {
+    case QTREE_OK: return "ok";
+    case QTREE_EINVAL: return "invalid argument";
+    case QTREE_ENOMEM: return "workspace too small";
+    case QTREE_EOVERFLOW: return "count overflow (M >= 2^31 or m0 + M > 2^32)";
+    case QTREE_EDEVICE: return "HIP runtime error";
+    case QTREE_EUNSUPPORTED: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+const char* qtree_last_error(void) { return g_last_error.c_str(); }
+
+const char* qtree_version(void) { return "qtree 0.1 gfx950"; }
+
 
 static qtree_status check_shape(int32_t d, int32_t n, const int32_t* N) {
   if (d < 1 || d > 3) return fail(QTREE_EINVAL, "d must be 1, 2 or 3");

@@ -104,12 +104,12 @@ struct qtree_batch {
   hipGraphExec_t exec = nullptr;
 
   ~qtree_batch() {
-    if (exec) hipGraphExecDestroy(exec);
+    if (exec) (void)hipGraphExecDestroy(exec);
     for (void* p : {(void*)d_contracts, (void*)d_units, (void*)d_chunk_off, (void*)d_tiles,
                     (void*)d_jobs,
                     (void*)d_bdp_tasks,
                     (void*)d_keys, (void*)d_segs})
-      if (p) hipFree(p);
+      if (p) (void)hipFree(p);
   }
 };
 
@@ -306,7 +306,6 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
   int64_t group_keys = 0, group_segs = 0;
   const size_t per_chunk_key = sizeof(uint16_t) * qtree::kChunk;
   std::vector<int> group_of(n);
-  Group g;
   int gi = 0;
   for (int i = 0; i < n; ++i) {
     qtree::BatchContract& bc = b->hc[i];
@@ -469,7 +468,7 @@ qtree_status qtree_batch_run(qtree_batch* b, double* V0_host, void* stream) {
         if (e2 != hipSuccess) e = e2;
       }
       if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return hip_error(e, "graph capture");
     }
   }

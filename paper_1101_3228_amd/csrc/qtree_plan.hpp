@@ -45,13 +45,13 @@ struct qtree_plan {
   mutable int hist_groups = 0;
 
   ~qtree_plan() {
-    if (aux) hipStreamSynchronize(aux);  // histogram passes of asynchronous calls
+    if (aux) (void)hipStreamSynchronize(aux);  // histogram passes of asynchronous calls
     for (hipEvent_t& e : fork)
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
     for (hipEvent_t& e : hist_done)
-      if (e) hipEventDestroy(e);
-    if (join) hipEventDestroy(join);
-    if (aux) hipStreamDestroy(aux);
+      if (e) (void)hipEventDestroy(e);
+    if (join) (void)hipEventDestroy(join);
+    if (aux) (void)hipStreamDestroy(aux);
   }
 };
 
