@@ -386,7 +386,7 @@ def run_c3(args):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS,
                      "traffic": _measured_traffic("fwd_keys_nd"),
-                     "kernel": "fwd_keys_nd<2,4>"},
+                     "kernel": "fwd_keys_nd<2, 8>"},
     }
     print(json.dumps(out), flush=True)
 
