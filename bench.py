@@ -824,7 +824,6 @@ def run_lloyd(args):
     of the 2-D max-call workload), N = 500 points from a 20 x 25 product of
     N(0, 1) quantile grids, 1e6 fresh samples per step, 20 steps."""
     import torch
-    import oracle as O
     import paper_1101_3228_amd as qt
     import synth
     torch.cuda.set_device(0)
@@ -861,6 +860,7 @@ def run_lloyd(args):
                                "point + 206 per sample)"},
     }
     if not args.no_cpu_baseline:
+        import oracle as O
         t0 = time.perf_counter()
         Mc = 200_000
         O.lloyd(d, g0, L, Mc, 1, 0x5EED0000)

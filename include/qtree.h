@@ -312,7 +312,7 @@ void qtree_batch_destroy(qtree_batch *batch);
  *   of layer k (0 <= k < n), device float[count][d] each.
  * qtree_cells: Voronoi cell in layer k (0 <= k <= n) of `count` device points
  *   x (float[count][d]); cell: device int32[count].  d >= 2: the forward's
- *   tiled scan over the layer's records staged in LDS, four points per lane
+ *   tiled scan over the layer's records staged in LDS, eight points per lane
  *   (the brute-force search of Sec. 4); d = 1: the binary search over the
  *   layer's sorted midpoints.
  * All asynchronous on `stream`. */

@@ -49,7 +49,7 @@ __global__ void cells_1d_kernel(FwdArgs a, int k, const float* x, int64_t count,
 // d >= 2: the forward's scan.  The layer's records staged in LDS, padded to
 // whole kScanTile-record tiles with records whose key is +inf; kCellsS points
 // per lane share every record read (argmin_scan_tiled, tiles of kScanTile).
-constexpr int kCellsS = 4;
+constexpr int kCellsS = 8;
 template <int D>
 __global__ __launch_bounds__(kBlock) void cells_kernel(FwdArgs a, int k, const float* x,
                                                        int64_t count, int32_t* cell) {

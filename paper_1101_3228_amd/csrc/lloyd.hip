@@ -31,7 +31,7 @@ namespace qtree {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSamplesNd = 4;  // samples per lane per round, d >= 2 (share each record read)
+constexpr int kSamplesNd = 8;  // samples per lane per round, d >= 2 (share each record read)
 
 __device__ __forceinline__ long long fixed_of(double v, double scale) {
   return (long long)__builtin_rint(v * scale);

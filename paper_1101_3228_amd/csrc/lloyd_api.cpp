@@ -141,7 +141,7 @@ qtree_status qtree_lloyd(int32_t d, int32_t N, const float* L, const float* grid
   e = qtree::launch_lloyd_prepare(a, s);
   // two workgroups per CU (at most kLloydMaxBlocks), fewer when the samples
   // of a step are few
-  const uint64_t per_block = 256ull * (d == 1 ? 1 : 4);
+  const uint64_t per_block = 256ull * (d == 1 ? 1 : 8);  // samples per workgroup round
   const uint64_t want = (M + per_block - 1) / per_block;
   const uint64_t cap = std::min<uint64_t>(2ull * cus, qtree::kLloydMaxBlocks);
   const int blocks = (int)(want < cap ? want : cap);
