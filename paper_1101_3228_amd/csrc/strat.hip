@@ -197,8 +197,11 @@ __global__ __launch_bounds__(kBlock) void strat_kernel(StratArgs a, const StratU
 // The same with layer k+1's guide table: its sorted midpoints (+inf beyond
 // its P, to maxP + kGuideKMax entries), its table, then the counts
 // [kStratRows][N1][S].
+// Launch bounds of four workgroups per CU hold the kernel to 128 VGPRs, four
+// waves per SIMD, without spills (145 VGPRs, three waves, unbounded: 6 %
+// slower).
 template <int GK, int S>
-__global__ __launch_bounds__(kBlock) void strat_kernel_guide(StratArgs a,
+__global__ __launch_bounds__(kBlock, 4) void strat_kernel_guide(StratArgs a,
                                                              const StratUnit* units) {
   extern __shared__ float lds[];
   const StratUnit U = units[blockIdx.x];
