@@ -317,6 +317,8 @@ def layer_counts_one(model: Model, grid: np.ndarray, N, k: int, M: int, seed: in
         L._one = True
     N = np.ascontiguousarray(N, np.int32)
     g = np.ascontiguousarray(grid, np.float32)
+    if not 0 <= k < N.size - 1:
+        raise ValueError(f"layer {k} outside 0..{N.size - 2}")
     out = np.zeros((int(N[k]), int(N[k + 1])), np.int32)
     rc = L.oracle_layer_counts(model.cptr(), _ptr(g), _ptr(N), k, m0, M, seed, contract,
                                _ptr(out), nthreads)
