@@ -125,8 +125,6 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--async-forward", action="store_true",
-                    help="C2: qtree_transitions_async (histogram passes overlap the next step)")
     ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
     ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1", "swing",
@@ -218,22 +216,14 @@ def main():
     for e in bdp_done:
         e.record(s_bdp)
 
-    # --async-forward: qtree_transitions_async, whose counts are complete at
-    # `done` (the BDP stream waits for it) while the forward stream moves on
-    # to the next step's sampling during the last layer group's histogram
-    # pass; it measured the same step time as the joined call (the overlap
-    # slows the next sampling pass by what it saves), so the default joins.
     def step(i, ev=None):
         b = i % 2
         s_fwd.wait_event(bdp_done[b])              # counts[b] free again
         if ev is not None:
             ev[0].record(s_fwd)
         done = fwd_done[b] if ev is None else ev[1]
-        if args.async_forward:
-            plan.transitions(M_PAIRS, 0x5EED0000 + i, counts=counts[b], stream=s_fwd, done=done)
-        else:
-            plan.transitions(M_PAIRS, 0x5EED0000 + i, counts=counts[b], stream=s_fwd)
-            done.record(s_fwd)
+        plan.transitions(M_PAIRS, 0x5EED0000 + i, counts=counts[b], stream=s_fwd)
+        done.record(s_fwd)
         s_bdp.wait_event(done)
         plan.payoff_batch(kinds, c_S0, c_K, c_r, c_T, c_sig, out=phi[b], stream=s_bdp)
         plan.bdp(counts[b], phi[b], V=V[b], want_v0=False, stream=s_bdp)
@@ -283,8 +273,7 @@ def main():
                                "N=500 Lloyd points/layer, M=1e7 pairs/layer, "
                                "12-contract sigma x K BDP sweep",
                    "layers": N_LAYERS, "points_per_layer": N_POINTS, "pairs_per_layer": M_PAIRS,
-                   "contracts": len(contracts), "mode": "layerwise",
-                   "forward_call": "async" if args.async_forward else "sync"},
+                   "contracts": len(contracts), "mode": "layerwise"},
         "forward_ms": fwd_ms,
         "sampling_pass_ms": keys_ms,
         "histogram_pass_ms": fwd_ms - keys_ms,

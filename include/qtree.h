@@ -164,22 +164,6 @@ qtree_status qtree_transitions(const qtree_plan *plan, uint64_t m0, uint64_t M, 
                                uint32_t contract_id, qtree_mode mode, int32_t *counts,
                                void *stream);
 
-/* As qtree_transitions, but the call does not make `stream` wait for the
- * histogram passes of the LAYERWISE two-pass forward (the last layer group's
- * runs on the plan's own stream): `done_event` (a hipEvent_t, required) is
- * recorded when `counts` is complete, on the plan's stream, or on `stream`
- * when the call has no pass there (PATHWISE, one-pass counting, one layer
- * group, M = 0).  Every consumer of `counts` must wait for `done_event`
- * (hipStreamWaitEvent), and `counts` and the plan's workspace must stay
- * allocated until it has completed.  The sampling pass of a later call on the
- * same plan waits by itself for the histogram passes of this one that read
- * the same key scratch, so back-to-back calls overlap the histogram of one
- * with the sampling of the next.  Counts are those of qtree_transitions.
- * Errors: as qtree_transitions; EINVAL if done_event is NULL. */
-qtree_status qtree_transitions_async(const qtree_plan *plan, uint64_t m0, uint64_t M,
-                                     uint64_t seed, uint32_t contract_id, qtree_mode mode,
-                                     int32_t *counts, void *done_event, void *stream);
-
 /* As qtree_transitions but adds to `counts` instead of overwriting them:
  * counts over [m0, m0+M) accumulate onto earlier calls, so a run can be split
  * into sample chunks (and resumed) with totals identical to one call. */

@@ -66,8 +66,6 @@ def lib() -> ctypes.CDLL:
         getattr(L, f).restype = i64
     L.qtree_transitions.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
     L.qtree_transitions_add.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
-    L.qtree_transitions_async.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P, P]
-    L.qtree_transitions_async.restype = ctypes.c_int
     L.qtree_transitions_add.restype = ctypes.c_int
     L.qtree_bdp.argtypes = [P, P, P, i32, P, P, P]
     L.qtree_payoff.argtypes = [P, i32, f64, f64, f64, f64, P, P, P, P]
@@ -207,22 +205,12 @@ class Plan:
         return torch.empty(max(self.entries, 4), dtype=torch.int32, device=self.workspace.device)
 
     def transitions(self, M: int, seed: int, contract: int = 0, mode: int = LAYERWISE,
-                    m0: int = 0, counts=None, stream=None, done=None):
-        """Transition counts (device int32 [entries]); asynchronous.  done: a
-        torch.cuda.Event recorded when the counts are complete, in which case
-        `stream` does not wait for the last histogram pass (consumers wait on
-        `done`; see qtree_transitions_async)."""
+                    m0: int = 0, counts=None, stream=None):
+        """Transition counts (device int32 [entries]); asynchronous on `stream`."""
         if counts is None:
             counts = self.new_counts()
-        if done is None:
-            _check(lib().qtree_transitions(self._h, int(m0), int(M), int(seed), int(contract),
-                                           int(mode), counts.data_ptr(), _stream_handle(stream)))
-        else:
-            if done.cuda_event == 0:
-                done.record()  # create the underlying hipEvent_t
-            _check(lib().qtree_transitions_async(self._h, int(m0), int(M), int(seed),
-                                                 int(contract), int(mode), counts.data_ptr(),
-                                                 done.cuda_event, _stream_handle(stream)))
+        _check(lib().qtree_transitions(self._h, int(m0), int(M), int(seed), int(contract),
+                                       int(mode), counts.data_ptr(), _stream_handle(stream)))
         return counts[:self.entries]
 
     def transitions_stratified(self, M: int, seed: int, contract: int = 0, alloc: int = 1,

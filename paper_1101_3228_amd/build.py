@@ -9,9 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqtree.so")
-# calibration program of the ALU rooflines (VALU issue rate per opcode)
-RATES_SRC = os.path.join(CSRC, "valu_rates.hip")
-RATES_BIN = os.path.join(PKG, "valu_rates")
+BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["api.cpp", "batch.cpp", "quantizer.cpp", "mlp_api.cpp", "fwd.hip", "count.hip",
            "bdp.hip", "diag.hip", "mlp.hip", "swing.hip", "lloyd.hip", "lloyd_api.cpp",
@@ -32,33 +30,33 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+def _run(cmd, verbose: bool, what: str) -> None:
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"hipcc failed building {what}")
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source to an object in _build/ (in parallel), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(BUILD, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    cflags = [f for f in FLAGS if f != "-shared"]
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 16)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_run, [hipcc(), *cflags, *inc, "-c", "-o", o,
+                                 os.path.join(CSRC, s)], verbose, s)
+                for s, o in zip(SOURCES, objs)]
+        for f in futs:
+            f.result()
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libqtree.so")
+    _run([hipcc(), *FLAGS, "-o", tmp, *objs], verbose, "libqtree.so")
     os.replace(tmp, LIB)
-    build_rates(verbose)
     return LIB
-
-
-def build_rates(verbose: bool = False) -> str:
-    flags = [f for f in FLAGS if f not in ("-shared", "-fPIC")]
-    tmp = RATES_BIN + ".tmp"
-    cmd = [hipcc(), *flags, "-o", tmp, RATES_SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building valu_rates")
-    os.replace(tmp, RATES_BIN)
-    return RATES_BIN
 
 
 if __name__ == "__main__":

@@ -488,8 +488,6 @@ static hipError_t ensure_aux(const qtree_plan* p, int groups) {
   if (!p->aux) e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking);
   for (int g = 0; g < groups && e == hipSuccess; ++g) {
     if (!p->fork[g]) e = hipEventCreateWithFlags(&p->fork[g], hipEventDisableTiming);
-    if (e == hipSuccess && !p->hist_done[g])
-      e = hipEventCreateWithFlags(&p->hist_done[g], hipEventDisableTiming);
   }
   if (e == hipSuccess && !p->join) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
   return e;
@@ -499,13 +497,9 @@ static hipError_t ensure_aux(const qtree_plan* p, int groups) {
 // split into `groups`; with more than one, the histogram pass of group g runs
 // on the plan's stream while the sampling pass of group g + 1 runs on `s`
 // (the passes of different layers touch disjoint scratch), and `s` waits for
-// the histograms before the scratch is reused and before returning.  With
-// `done`, `s` does not wait at the end: `done` is recorded on the plan's
-// stream after the last histogram pass, and the sampling of a layer group in
-// a later call waits for the latest histogram pass of every group of an
-// earlier call whose layers overlap it (they read the same scratch).
-static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hipStream_t s,
-                           hipEvent_t done) {
+// the histograms before the scratch is reused and before returning, so the
+// call is complete on `s` like a single-stream one.
+static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hipStream_t s) {
   const uint64_t end = a.m0 + a.M;
   const uint64_t bs = p->d == 1 ? (uint64_t)p->batch_chunks * qtree::kChunk - 2
                                 : (uint64_t)p->batch_chunks * qtree::kChunk;
@@ -548,12 +542,7 @@ static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hip
       // first (ordered before the histogram pass by the stream and the fork)
       bool any_split = false;
       for (int k = k0; k < k1; ++k) any_split = any_split || p->split[k] > 1;
-      if (lo == a.m0)  // histograms of an earlier call still reading these layers' keys
-        for (int h = 0; h < p->hist_groups && e == hipSuccess; ++h)
-          if (p->hist_k0[h] < k1 && k0 < p->hist_k1[h])
-            e = hipStreamWaitEvent(s, p->hist_done[h], 0);
-      if (e == hipSuccess && b.first_batch && any_split)
-        e = qtree::launch_zero_split(c, k1 - k0, s);
+      if (b.first_batch && any_split) e = qtree::launch_zero_split(c, k1 - k0, s);
       if (e == hipSuccess) e = qtree::launch_fwd_keys(c, s);
       if (e != hipSuccess) break;
       if (g == groups - 1 && p->trace_keys) e = hipEventRecord(p->trace_keys, s);
@@ -564,23 +553,13 @@ static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hip
         e = hipEventRecord(p->fork[g], s);
         if (e == hipSuccess) e = hipStreamWaitEvent(p->aux, p->fork[g], 0);
         if (e == hipSuccess) e = qtree::launch_count_tiles(c, p->aux);
-        if (e == hipSuccess) e = hipEventRecord(p->hist_done[g], p->aux);
       }
-    }
-    if (groups > 1 && lo == a.m0) {
-      // from now on the waits of a later call refer to this call's groups
-      for (int g = 0; g < groups; ++g) {
-        p->hist_k0[g] = (int)((int64_t)p->n * g / groups);
-        p->hist_k1[g] = (int)((int64_t)p->n * (g + 1) / groups);
-      }
-      p->hist_groups = groups;
     }
     if (e == hipSuccess && groups > 1) e = hipEventRecord(p->join, p->aux);
     if (e != hipSuccess) return e;
     first = false;
   }
-  if (groups > 1) return done ? hipEventRecord(done, p->aux) : hipStreamWaitEvent(s, p->join, 0);
-  return done ? hipEventRecord(done, s) : hipSuccess;
+  return groups > 1 ? hipStreamWaitEvent(s, p->join, 0) : hipSuccess;
 }
 
 // Split each layer's M samples into chunks; one workgroup per (layer, chunk).
@@ -664,8 +643,7 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
 
 static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64_t M,
                                      uint64_t seed, uint32_t contract_id, qtree_mode mode,
-                                     int32_t* counts, void* stream, bool zero,
-                                     hipEvent_t done = nullptr) {
+                                     int32_t* counts, void* stream, bool zero) {
   if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
   if (!counts) return fail(QTREE_EINVAL, "counts is NULL");
   if (reinterpret_cast<uintptr_t>(counts) % 16)
@@ -682,20 +660,16 @@ static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64
     e = qtree::launch_zero_i32(counts, plan->entries, s);
     if (e != hipSuccess) return hip_fail(e, "zero fill");
   }
-  if (M == 0) {
-    e = done ? hipEventRecord(done, s) : hipSuccess;
-    return e == hipSuccess ? QTREE_OK : hip_fail(e, "event record");
-  }
+  if (M == 0) return QTREE_OK;
   qtree::FwdArgs a = fwd_args(plan, m0, M, seed, contract_id, counts);
   if (mode == QTREE_PATHWISE) {
     e = qtree::launch_fwd_path(a, s);
   } else if (two) {
-    e = two_pass(plan, a, zero, s, done);
+    e = two_pass(plan, a, zero, s);
   } else {
     plan_units(a, plan);
     e = plan->d == 1 ? qtree::launch_fwd_layer_1d(a, s) : qtree::launch_fwd_layer_nd(a, s);
   }
-  if (e == hipSuccess && done && !two) e = hipEventRecord(done, s);
   if (e != hipSuccess) return hip_fail(e, "forward kernel launch");
   return QTREE_OK;
 }
@@ -704,14 +678,6 @@ qtree_status qtree_transitions(const qtree_plan* plan, uint64_t m0, uint64_t M, 
                                uint32_t contract_id, qtree_mode mode, int32_t* counts,
                                void* stream) {
   return transitions_impl(plan, m0, M, seed, contract_id, mode, counts, stream, true);
-}
-
-qtree_status qtree_transitions_async(const qtree_plan* plan, uint64_t m0, uint64_t M,
-                                     uint64_t seed, uint32_t contract_id, qtree_mode mode,
-                                     int32_t* counts, void* done_event, void* stream) {
-  if (!done_event) return fail(QTREE_EINVAL, "done_event is NULL");
-  return transitions_impl(plan, m0, M, seed, contract_id, mode, counts, stream, true,
-                          static_cast<hipEvent_t>(done_event));
 }
 
 qtree_status qtree_transitions_add(const qtree_plan* plan, uint64_t m0, uint64_t M, uint64_t seed,

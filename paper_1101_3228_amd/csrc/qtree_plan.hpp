@@ -37,18 +37,10 @@ struct qtree_plan {
   mutable hipStream_t aux = nullptr;
   mutable hipEvent_t fork[kMaxGroups] = {};
   mutable hipEvent_t join = nullptr;
-  // after the last histogram pass of each layer group of the latest call, and
-  // that group's layers [k0, k1): a later call's sampling of overlapping
-  // layers (whose keys share the scratch) waits for it
-  mutable hipEvent_t hist_done[kMaxGroups] = {};
-  mutable int hist_k0[kMaxGroups] = {}, hist_k1[kMaxGroups] = {};
-  mutable int hist_groups = 0;
 
   ~qtree_plan() {
-    if (aux) (void)hipStreamSynchronize(aux);  // histogram passes of asynchronous calls
+    if (aux) (void)hipStreamSynchronize(aux);
     for (hipEvent_t& e : fork)
-      if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t& e : hist_done)
       if (e) (void)hipEventDestroy(e);
     if (join) (void)hipEventDestroy(join);
     if (aux) (void)hipStreamDestroy(aux);

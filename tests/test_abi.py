@@ -96,11 +96,6 @@ def test_plan_create_rejects_bad_inputs_before_device_work(L):
     assert L.qtree_transitions(None, 0, 10, 1, 0, 0, ctypes.c_void_p(4096), None) == 1
     assert L.qtree_bdp(None, None, None, 1, None, None, None) == 1
     assert L.qtree_plan_cell_search(None, None, None) == 1
-    assert L.qtree_transitions_async(None, 0, 10, 1, 0, 0, ctypes.c_void_p(4096),
-                                     ctypes.c_void_p(8), None) == 1
-    assert L.qtree_transitions_async(None, 0, 10, 1, 0, 0, ctypes.c_void_p(4096), None,
-                                     None) == 1
-    assert b"done_event" in L.qtree_last_error()
 
 
 def test_library_quantizer_matches_oracle_quantizer(L):

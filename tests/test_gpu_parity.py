@@ -414,38 +414,3 @@ def test_zero_midpoint_and_signed_zero_samples():
     assert np.array_equal(counts, ref)
     # every sample sits at a zero, below no midpoint: all mass in cell 0 -> 0
     assert counts[0] == 40_001 and counts[1:3].sum() == 0
-
-
-@pytest.mark.parametrize("name", ["bm1", "bm2"])
-def test_async_transitions_back_to_back(name):
-    """qtree_transitions_async: back-to-back calls on one plan, each consumed
-    on another stream that waits only for its `done` event (the layer split
-    changes between calls, so a call's sampling must wait for the earlier
-    histogram passes of overlapping layers), give the synchronous counts; the
-    first also equals the oracle."""
-    _print_case(f"async transitions {name}")
-    spec = MODELS[name]()
-    grid, N = synth.layer_grids(spec, SHAPES[name])
-    plan = _plan(spec, grid, N)
-    M, seeds = 120_001, [0x5EED0051 + i for i in range(5)]
-    groups = [4, 4, 3, 8, 2]
-    ref = []
-    for sd, g in zip(seeds, groups):
-        plan.tune(groups=g)
-        ref.append(plan.transitions(M, sd, contract=2).cpu().numpy())
-    assert np.array_equal(ref[0], O.transitions(_omodel(spec), grid, N, M, seed=seeds[0],
-                                                contract=2, nthreads=THREADS))
-    fwd, use = torch.cuda.Stream(), torch.cuda.Stream()
-    outs = [plan.new_counts() for _ in seeds]
-    dones = [torch.cuda.Event() for _ in seeds]
-    got = [None] * len(seeds)
-    for i, (sd, g) in enumerate(zip(seeds, groups)):
-        plan.tune(groups=g)
-        plan.transitions(M, sd, contract=2, counts=outs[i], stream=fwd, done=dones[i])
-        use.wait_event(dones[i])
-        with torch.cuda.stream(use):
-            got[i] = outs[i][:plan.entries].clone()
-    torch.cuda.synchronize()
-    plan.tune(groups=0)
-    for i in range(len(seeds)):
-        assert np.array_equal(got[i].cpu().numpy(), ref[i]), i
