@@ -458,6 +458,20 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def tree_band_fmas(plan, pi) -> int:
+    """Multiply-adds of one contract's backward recursion on a tree: the sum
+    over the rows of every layer of the width of the row's nonzero band (the
+    band table that qtree_pi writes after the layer offsets)."""
+    import torch
+    n = plan.n
+    base, _ = pi._qtree_pi
+    off = base - pi.data_ptr()
+    band_at = off + ((8 * n + 255) // 256) * 256
+    rows = int(plan.point_offsets()[n])
+    b = pi[band_at:band_at + 8 * rows].view(torch.int32).view(rows, 2).cpu().numpy()
+    return int(np.sum(b[:, 1] - b[:, 0]))
+
+
 def run_c5(args):
     """The put surrogate (6-256-256-256-1, BF16 weights, two activation
     terms): labels from the tree (N = 100 optimal points per layer, counts
@@ -508,19 +522,37 @@ def run_c5(args):
     alg_flop = 2.0 * (6 * 256 + 2 * 256 * 256 + 256)      # per query
     achieved = alg_flop * Q / (ms * 1e-3) / 1e12
 
-    # the tree on a sample of the same queries (counts cached; payoff + BDP)
+    # the tree on the same 1e6 queries: counts and transition weights cached
+    # per n, contract records resident on the device; one qtree_bdp_many
+    # launch per n (obstacles computed in the kernel), timed with HIP events
     inside = mask.cpu().numpy().astype(bool)
-    sample = xq[:100_000]
-    pricer.price(sample[:2000])
+    groups = pricer.specs(xq)
+    vals = pricer.price_specs(groups, stream=stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pricer.price(sample)
+    t_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t_ev[0].record(stream)
+    reps = max(1, args.steps // 5)
+    for _ in range(reps):
+        pricer.price_specs(groups, out=vals, stream=stream)
+    t_ev[1].record(stream)
     torch.cuda.synchronize()
-    tree_rate = sample.shape[0] / (time.perf_counter() - t0)
-    t0 = time.perf_counter()
-    pricer.price(xq[~inside])
+    tree_ms = t_ev[0].elapsed_time(t_ev[1]) / reps
+    tree_rate = Q / (tree_ms * 1e-3)
+    # FP64 work of the tree side: one multiply-add per weight inside every
+    # row's nonzero band, per contract (the band table of qtree_pi)
+    band_fma = 0
+    for n, (rows, _) in groups.items():
+        plan, _, pi = pricer.tree(n)
+        band_fma += rows.size * tree_band_fmas(plan, pi)
+    tree_tflops = 2.0 * band_fma / (tree_ms * 1e-3) / 1e12
+    out_groups = pricer.specs(xq[~inside])
     torch.cuda.synchronize()
-    fallback_s = time.perf_counter() - t0
+    f_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    f_ev[0].record(stream)
+    pricer.price_specs(out_groups, stream=stream)
+    f_ev[1].record(stream)
+    torch.cuda.synchronize()
+    fallback_s = f_ev[0].elapsed_time(f_ev[1]) * 1e-3
     blended = Q / (ms * 1e-3 + fallback_s)
 
     cpu = None
@@ -550,6 +582,12 @@ def run_c5(args):
                    "queries": Q, "act_terms": args.act_terms, "train_rows": int(xtr.shape[0]),
                    "epochs": args.epochs},
         "tree_options_per_s": tree_rate,
+        "tree_ms": tree_ms,
+        "tree_roofline": {"bound": "fp64", "achieved": tree_tflops, "peak": 78.6,
+                          "unit": "TFLOP/s", "frac": tree_tflops / 78.6,
+                          "kernel": "bdp_many_kernel (all layers, 64 contracts per "
+                                    "workgroup; FLOP = 2 x the multiply-adds inside the "
+                                    "rows' nonzero bands, obstacles not counted)"},
         "with_fallback_options_per_s": blended,
         "speedup_vs_tree": value / tree_rate,
         "accuracy_r19": {"mean": float(err.mean()), "median": float(np.median(err)),

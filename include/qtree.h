@@ -137,12 +137,16 @@ int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
  *                        the sampling pass of the next group.  The call still
  *                        completes in order on `stream` (which waits for it).
  *                        A plan used with groups > 1 must not be used from
- *                        two host threads at once. */
+ *                        two host threads at once.
+ *   QTREE_TUNE_ND_SAMPLES : d >= 2 two-pass sampling: samples per lane that
+ *                        share each grid record read from LDS, 8 (default) or 4.
+ */
 typedef enum {
   QTREE_TUNE_CHUNK = 0,
   QTREE_TUNE_XCD_MAP = 1,
   QTREE_TUNE_COUNT = 2,
-  QTREE_TUNE_GROUPS = 3
+  QTREE_TUNE_GROUPS = 3,
+  QTREE_TUNE_ND_SAMPLES = 4
 } qtree_tune_key;
 qtree_status qtree_plan_tune(qtree_plan *plan, int32_t key, int64_t value);
 
@@ -183,6 +187,44 @@ qtree_status qtree_transitions_add(const qtree_plan *plan, uint64_t m0, uint64_t
  * before returning; otherwise it is asynchronous. */
 qtree_status qtree_bdp(const qtree_plan *plan, const int32_t *counts, const double *phi,
                        int32_t n_pay, double *V, double *V0_host, void *stream);
+
+/* The estimated transition weights pi^k_ij = c_ij / p_i (eq. defPi read
+ * from layer k to k+1; Sec. 3: the counters p^k_ij normalised by their row
+ * totals), FP64, with the range of the nonzero columns of every row, in a
+ * caller-owned device buffer `pi` of qtree_pi_workspace_size bytes
+ * (256-byte aligned).  A row that no sample reached gets zero weights (its
+ * continuation value is 0, as in qtree_bdp).  Computed once per count set;
+ * qtree_bdp_many reads it.  counts: device int32 as written by
+ * qtree_transitions.  Asynchronous. */
+qtree_status qtree_pi_workspace_size(const qtree_plan *plan, size_t *bytes);
+qtree_status qtree_pi(const qtree_plan *plan, const int32_t *counts, void *pi, size_t pi_bytes,
+                      void *stream);
+
+/* One contract's obstacle, the parameters of qtree_payoff in one record:
+ * kind bit 0 put on S^1 (0) or call on max_a S^a (1), bit 1 European; sigma
+ * [d] used; mix: row-major d x d in the first d*d entries, used when
+ * has_mix != 0 (else y = x). */
+typedef struct {
+  double S0, K, r, Tm;
+  double sigma[3];
+  double mix[9];
+  int32_t kind;
+  int32_t has_mix;
+} qtree_payoff_spec;
+
+/* Quantized BDP (Sec. 2) of n_q contracts on one tree, FP64:
+ *   V_n = phi_n,  V_k(i) = max(phi_k(i), sum_j pi^k_ij V_{k+1}(j)),
+ * with phi_k the obstacle of qtree_payoff computed from the contract's
+ * record where it is needed (never stored), and pi from qtree_pi; one
+ * launch prices every contract (64 per workgroup, their value vectors
+ * resident on chip through all layers).  specs: device
+ * qtree_payoff_spec[n_q] (not validated: non-finite parameters give
+ * non-finite prices); V0: device double[n_q] output, V_0 of each contract.
+ * Layers of at most 256 points (EUNSUPPORTED beyond).  The prices equal
+ * those of qtree_payoff + qtree_bdp up to the rounding of the weights
+ * (relative ~1e-15).  Asynchronous. */
+qtree_status qtree_bdp_many(const qtree_plan *plan, const void *pi, size_t pi_bytes, int64_t n_q,
+                            const qtree_payoff_spec *specs, double *V0, void *stream);
 
 /* Discounted obstacle on the plan's grid points, FP64, device output
  * phi: double[sum N_k]:  phi_k(x) = exp(-r t_k) payoff(S_{t_k}(x)),
@@ -251,9 +293,21 @@ qtree_status qtree_swing(const qtree_plan *plan, const int32_t *counts, const do
  * fits) -- the only call besides the tuner that allocates device memory.
  * flags bit 0: capture the run sequence into a hipGraph after the first run
  * and replay it from then on (needs a non-NULL stream).
- * A tuner (optional) keeps per batch shape the workgroups per CU that fit of
- * each sampling launch (its occupancy limit, found on the first run) in a
- * text cache (path given, else $QTREE_TUNE_CACHE, else memory only).
+ *
+ * Autotuner.  A run's launch configuration (never its results) is a code:
+ * bit 0 set = 4 instead of 8 samples per lane share each grid read in the
+ * d >= 2 sampling launch; bit 1 = the 1-D sampling launch runs on a second
+ * stream beside the d >= 2 one instead of after it; bits 8-15 = at most that
+ * many workgroups per CU for the d >= 2 launch (0: its occupancy limit).
+ * With a tuner, the first run of a batch whose shape signature the tuner
+ * does not know times the forward launches of every candidate configuration
+ * (both sample counts, serial and overlapped launches when the batch has
+ * both kinds, the occupancy limit and one workgroup per CU below it) with
+ * HIP events on the run's stream, after one warm-up, and keeps the fastest;
+ * that run blocks the host until the timings are in.  The tuner caches
+ * (signature, code, milliseconds) in a text file (path given, else
+ * $QTREE_TUNE_CACHE, else memory only), so later batches of the same shape
+ * skip the timing.  Without a tuner the default code 0 is used.
  * ---------------------------------------------------------------------- */
 typedef struct {
   const qtree_plan *plan;
@@ -271,8 +325,7 @@ typedef struct qtree_batch qtree_batch;
 
 qtree_status qtree_tuner_create(const char *cache_path, qtree_tuner **out);
 void qtree_tuner_destroy(qtree_tuner *tuner);
-/* Cached entry for a batch signature, 0 if none: workgroups per CU that fit
- * of the 1-D sampling launch in bits 0-7, of the d >= 2 launch in bits 8-15. */
+/* Cached configuration code for a batch signature, -1 if none. */
 int32_t qtree_tuner_lookup(const qtree_tuner *tuner, const char *signature);
 
 qtree_status qtree_batch_plan(const qtree_contract *contracts, int32_t n, qtree_tuner *tuner,
@@ -280,11 +333,20 @@ qtree_status qtree_batch_plan(const qtree_contract *contracts, int32_t n, qtree_
 /* Run the batch on `stream`; if V0_host (double[sum n_pay], contracts in
  * order) is not NULL, copy every V_0 there and synchronise. */
 qtree_status qtree_batch_run(qtree_batch *batch, double *V0_host, void *stream);
-/* Work units, histogram tiles, scratch groups, and the workgroups per CU
- * that fit of the 1-D and of the d >= 2 sampling launch (any pointer may be
- * NULL). */
+/* Work units, histogram tiles, scratch groups, and the workgroups per CU of
+ * the 1-D and of the d >= 2 sampling launch under the current configuration
+ * (any pointer may be NULL). */
 qtree_status qtree_batch_info(const qtree_batch *batch, int64_t *units, int64_t *tiles,
                               int32_t *groups, int32_t *per_cu_1d, int32_t *per_cu_nd);
+/* The configuration code in use, the forward time the tuner measured for it
+ * (ms; 0 if not measured) and how many candidates this batch timed (0 when
+ * the code came from the cache or from qtree_batch_set_config). */
+qtree_status qtree_batch_tuning(const qtree_batch *batch, int32_t *config, double *ms,
+                                int32_t *timed);
+/* Use configuration `config` from now on (the tuner is skipped; a captured
+ * graph is dropped and captured again on the next run).  EINVAL for an
+ * unknown code. */
+qtree_status qtree_batch_set_config(qtree_batch *batch, int32_t config);
 const char *qtree_batch_signature(const qtree_batch *batch);
 void qtree_batch_destroy(qtree_batch *batch);
 

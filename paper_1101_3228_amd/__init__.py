@@ -66,6 +66,13 @@ def lib() -> ctypes.CDLL:
         getattr(L, f).restype = i64
     L.qtree_transitions.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
     L.qtree_transitions_add.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
+    L.qtree_transitions_noalloc.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
+    L.qtree_pi_workspace_size.argtypes = [P, P]
+    L.qtree_pi.argtypes = [P, P, P, ctypes.c_size_t, P]
+    L.qtree_bdp_many.argtypes = [P, P, ctypes.c_size_t, i64, P, P, P]
+    for f in ("qtree_pi_workspace_size", "qtree_pi", "qtree_bdp_many"):
+        getattr(L, f).restype = ctypes.c_int
+    L.qtree_transitions_noalloc.restype = ctypes.c_int
     L.qtree_transitions_add.restype = ctypes.c_int
     L.qtree_bdp.argtypes = [P, P, P, i32, P, P, P]
     L.qtree_payoff.argtypes = [P, i32, f64, f64, f64, f64, P, P, P, P]
@@ -325,6 +332,35 @@ class Plan:
                                  _stream_handle(stream)))
         return (float(p0[0]) if want_p0 else None), P
 
+    def pi(self, counts, out=None, stream=None):
+        """Transition weights pi = c / p of the counts (device workspace of
+        qtree_pi, uint8), for bdp_many."""
+        import torch
+        b = ctypes.c_size_t(0)
+        _check(lib().qtree_pi_workspace_size(self._h, ctypes.byref(b)))
+        if out is None:
+            out = torch.empty(b.value + 256, dtype=torch.uint8, device=counts.device)
+        base = (out.data_ptr() + 255) // 256 * 256
+        _check(lib().qtree_pi(self._h, counts.data_ptr(), base, b.value,
+                              _stream_handle(stream)))
+        out._qtree_pi = (base, b.value)
+        return out
+
+    def bdp_many(self, pi, specs, V0=None, stream=None):
+        """V_0 of many contracts on one tree (qtree_bdp_many).  pi: from
+        Plan.pi; specs: device uint8 tensor of qtree_payoff_spec records (or a
+        host PAYOFF_SPEC array, copied over); returns device float64 [n]."""
+        import torch
+        if isinstance(specs, np.ndarray):
+            specs = torch.from_numpy(specs.view(np.uint8).reshape(-1)).to(pi.device)
+        nq = specs.numel() // PAYOFF_SPEC.itemsize
+        if V0 is None:
+            V0 = torch.empty(nq, dtype=torch.float64, device=pi.device)
+        base, size = pi._qtree_pi
+        _check(lib().qtree_bdp_many(self._h, base, size, nq, specs.data_ptr(), V0.data_ptr(),
+                                    _stream_handle(stream)))
+        return V0
+
     def bdp(self, counts, phi, V=None, want_v0: bool = True, stream=None):
         """Backward dynamic programming (FP64).  phi: device float64
         [n_pay, points] (or [points]).  Returns (V0 numpy [n_pay] or None, V)."""
@@ -337,6 +373,29 @@ class Plan:
         _check(lib().qtree_bdp(self._h, counts.data_ptr(), phi2.data_ptr(), n_pay, V.data_ptr(),
                                _np_ptr(V0) if want_v0 else None, _stream_handle(stream)))
         return V0, V
+
+
+#: Host image of qtree_payoff_spec (one contract's obstacle parameters).
+PAYOFF_SPEC = np.dtype([("S0", "<f8"), ("K", "<f8"), ("r", "<f8"), ("Tm", "<f8"),
+                        ("sigma", "<f8", (3,)), ("mix", "<f8", (9,)), ("kind", "<i4"),
+                        ("has_mix", "<i4")])
+
+
+def payoff_specs(d: int, kinds, S0, K, r, T, sigma, mix=None) -> np.ndarray:
+    """Pack contract parameters into qtree_payoff_spec records (host):
+    sigma [n, d] (broadcastable), mix [n, d, d] or None (identity)."""
+    kinds = np.atleast_1d(np.asarray(kinds, np.int32))
+    n = kinds.size
+    out = np.zeros(n, PAYOFF_SPEC)
+    out["kind"] = kinds
+    for f, v in (("S0", S0), ("K", K), ("r", r), ("Tm", T)):
+        out[f] = np.broadcast_to(np.asarray(v, np.float64), (n,))
+    out["sigma"][:, :d] = np.broadcast_to(np.asarray(sigma, np.float64).reshape(-1, d), (n, d))
+    if mix is not None:
+        m = np.broadcast_to(np.asarray(mix, np.float64).reshape(-1, d * d), (n, d * d))
+        out["mix"][:, :d * d] = m
+        out["has_mix"] = 1
+    return out
 
 
 def box_muller(ra, rb, stream=None):
@@ -443,6 +502,10 @@ def _batch_setup():
     L.qtree_batch_run.restype = ctypes.c_int
     L.qtree_batch_info.argtypes = [P, P, P, P, P, P]
     L.qtree_batch_info.restype = ctypes.c_int
+    L.qtree_batch_tuning.argtypes = [P, P, P, P]
+    L.qtree_batch_tuning.restype = ctypes.c_int
+    L.qtree_batch_set_config.argtypes = [P, ctypes.c_int32]
+    L.qtree_batch_set_config.restype = ctypes.c_int
     L.qtree_batch_signature.argtypes = [P]
     L.qtree_batch_signature.restype = ctypes.c_char_p
     L.qtree_batch_destroy.argtypes = [P]
@@ -507,6 +570,17 @@ class Batch:
                                                ctypes.byref(pn)))
         return {"units": u.value, "tiles": t.value, "groups": g.value,
                 "per_cu_1d": p1.value, "per_cu_nd": pn.value}
+
+    def tuning(self):
+        """(configuration code, measured forward ms, candidates timed)."""
+        c, t = ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        _check(_batch_setup().qtree_batch_tuning(self._h, ctypes.byref(c), ctypes.byref(ms),
+                                                 ctypes.byref(t)))
+        return {"config": c.value, "ms": ms.value, "timed": t.value}
+
+    def set_config(self, code: int):
+        _check(_batch_setup().qtree_batch_set_config(self._h, int(code)))
 
     @property
     def signature(self) -> str:

@@ -79,7 +79,7 @@ size_t keys_lds_bytes(int d, int n, const int32_t* N) {
     maxP = next_pow2(N[k]) > maxP ? next_pow2(N[k]) : maxP;
   }
   const size_t grids =
-      d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)(maxN + kScanTile);
+      d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)(maxN + kScanGroup);
   return grids + sizeof(uint16_t) * kChunk +
          sizeof(uint32_t) * (2 * (size_t)max_tiles_of(n, N) + 1 + 256);
 }
@@ -330,6 +330,7 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     p.batch_chunks = c;
   }
   p.two_pass_ok = p.batch_chunks > 0;
+  p.two_pass_shape = qtree::two_pass_fits(d, n, N);
   p.lay = qtree::ws_layout(d, n, N, p.batch_chunks);
 
   // host image of the workspace
@@ -477,6 +478,7 @@ static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uin
   a.max_tiles = p->max_tiles;
   a.seg_stride = p->max_tiles + 1;
   a.total_tiles = p->unit_off[p->n];
+  a.nd_samples = p->tune_nd_samples;
   return a;
 }
 
@@ -499,14 +501,17 @@ static hipError_t ensure_aux(const qtree_plan* p, int groups) {
 // (the passes of different layers touch disjoint scratch), and `s` waits for
 // the histograms before the scratch is reused and before returning, so the
 // call is complete on `s` like a single-stream one.
-static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hipStream_t s) {
+static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hipStream_t s,
+                           const qtree::CountScratch& sc) {
   const uint64_t end = a.m0 + a.M;
-  const uint64_t bs = p->d == 1 ? (uint64_t)p->batch_chunks * qtree::kChunk - 2
-                                : (uint64_t)p->batch_chunks * qtree::kChunk;
+  const uint64_t bs = p->d == 1 ? (uint64_t)sc.chunks * qtree::kChunk - 2
+                                : (uint64_t)sc.chunks * qtree::kChunk;
+  a.keys = sc.keys;
+  a.segs = sc.segs;
   // automatic: four groups hide most of the 1-D histogram pass; for d >= 2
   // that pass is ~1 % of the forward and more launches only add tails
   const int want = p->tune_groups > 0 ? p->tune_groups : (p->d == 1 ? 4 : 1);
-  const int groups = std::max(1, std::min(want, p->n));
+  const int groups = std::max(1, std::min(std::min(want, sc.max_groups), p->n));
   if (groups > 1) {
     hipError_t e = ensure_aux(p, groups);
     if (e != hipSuccess) return e;
@@ -622,7 +627,7 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
   }
   if (key == QTREE_TUNE_COUNT) {
     if (value < 0 || value > 2) return fail(QTREE_EINVAL, "count mode must be 0, 1 or 2");
-    if (value == 2 && !plan->two_pass_ok)
+    if (value == 2 && !plan->two_pass_shape)
       return fail(QTREE_EUNSUPPORTED, "count blocks too large for two-pass counting");
     plan->tune_count = (int32_t)value;
     return QTREE_OK;
@@ -631,6 +636,11 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
     if (value < 0 || value > qtree_plan::kMaxGroups)
       return fail(QTREE_EINVAL, "groups must be in 0..8");
     plan->tune_groups = (int32_t)value;
+    return QTREE_OK;
+  }
+  if (key == QTREE_TUNE_ND_SAMPLES) {
+    if (value != 4 && value != 8) return fail(QTREE_EINVAL, "samples per lane must be 4 or 8");
+    plan->tune_nd_samples = (int32_t)value;
     return QTREE_OK;
   }
   if (key == QTREE_TUNE_XCD_MAP) {
@@ -643,7 +653,8 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
 
 static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64_t M,
                                      uint64_t seed, uint32_t contract_id, qtree_mode mode,
-                                     int32_t* counts, void* stream, bool zero) {
+                                     int32_t* counts, void* stream, bool zero,
+                                     const qtree::CountScratch* scratch = nullptr) {
   if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
   if (!counts) return fail(QTREE_EINVAL, "counts is NULL");
   if (reinterpret_cast<uintptr_t>(counts) % 16)
@@ -652,10 +663,23 @@ static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64
     return fail(QTREE_EINVAL, "unknown mode");
   if (M >= (1ull << 31)) return fail(QTREE_EOVERFLOW, "M must be < 2^31");
   if (m0 + M > (1ull << 32)) return fail(QTREE_EOVERFLOW, "m0 + M must be <= 2^32");
+  // the two-pass scratch: the plan's workspace, or the caller's
+  qtree::CountScratch sc;
+  if (scratch) {
+    sc = *scratch;
+  } else {
+    sc.keys = reinterpret_cast<uint16_t*>(plan->ws + plan->lay.keys);
+    sc.segs = reinterpret_cast<uint32_t*>(plan->ws + plan->lay.segs);
+    sc.chunks = plan->two_pass_ok ? plan->batch_chunks : 0;
+    sc.max_groups = qtree_plan::kMaxGroups;
+  }
+  const bool two_ok = plan->two_pass_shape && sc.chunks > 0;
+  const bool two = mode == QTREE_LAYERWISE && M > 0 &&
+                   (plan->tune_count == 2 || (plan->tune_count == 0 && two_ok));
+  if (two && !two_ok)
+    return fail(QTREE_EUNSUPPORTED, "two-pass counting needs scratch this call does not have");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
-  const bool two = mode == QTREE_LAYERWISE && M > 0 &&
-                   (plan->tune_count == 2 || (plan->tune_count == 0 && plan->two_pass_ok));
   if (zero && !two) {
     e = qtree::launch_zero_i32(counts, plan->entries, s);
     if (e != hipSuccess) return hip_fail(e, "zero fill");
@@ -665,7 +689,7 @@ static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64
   if (mode == QTREE_PATHWISE) {
     e = qtree::launch_fwd_path(a, s);
   } else if (two) {
-    e = two_pass(plan, a, zero, s);
+    e = two_pass(plan, a, zero, s, sc);
   } else {
     plan_units(a, plan);
     e = plan->d == 1 ? qtree::launch_fwd_layer_1d(a, s) : qtree::launch_fwd_layer_nd(a, s);
@@ -673,6 +697,44 @@ static qtree_status transitions_impl(const qtree_plan* plan, uint64_t m0, uint64
   if (e != hipSuccess) return hip_fail(e, "forward kernel launch");
   return QTREE_OK;
 }
+
+}  // extern "C"
+
+namespace qtree {
+// Forward step whose two-pass counting uses `bytes` of caller scratch at
+// `base` (keys [n][chunks][kChunk], then segment starts [n][chunks][max
+// tiles + 1]) and one layer group (no stream or event of the plan).
+qtree_status transitions_on_scratch(const qtree_plan* plan, uint64_t m0, uint64_t M,
+                                    uint64_t seed, uint32_t contract_id, qtree_mode mode,
+                                    int32_t* counts, void* stream, void* base, size_t bytes) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  CountScratch sc;
+  sc.max_groups = 1;
+  sc.chunks = 0;
+  const bool layerwise_two = mode == QTREE_LAYERWISE && M > 0 && plan->tune_count != 1 &&
+                             plan->two_pass_shape;
+  if (layerwise_two) {
+    const size_t key_chunk = sizeof(uint16_t) * kChunk;
+    const size_t seg_chunk = sizeof(uint32_t) * (size_t)(plan->max_tiles + 1);
+    const size_t per = (size_t)plan->n * (key_chunk + seg_chunk);
+    int64_t c = (int64_t)(bytes / per);
+    while (c > 0 && align_up((size_t)plan->n * (size_t)c * key_chunk, 256) +
+                            (size_t)plan->n * (size_t)c * seg_chunk > bytes)
+      --c;
+    if (c < 1)
+      return fail(QTREE_EUNSUPPORTED,
+                  "one chunk per layer needs " + std::to_string(per) + " bytes of scratch, " +
+                      std::to_string(bytes) + " available");
+    sc.chunks = c;
+    sc.keys = static_cast<uint16_t*>(base);
+    sc.segs = reinterpret_cast<uint32_t*>(
+        static_cast<char*>(base) + align_up((size_t)plan->n * (size_t)c * key_chunk, 256));
+  }
+  return transitions_impl(plan, m0, M, seed, contract_id, mode, counts, stream, true, &sc);
+}
+}  // namespace qtree
+
+extern "C" {
 
 qtree_status qtree_transitions(const qtree_plan* plan, uint64_t m0, uint64_t M, uint64_t seed,
                                uint32_t contract_id, qtree_mode mode, int32_t* counts,
@@ -889,6 +951,85 @@ qtree_status qtree_payoff_batch(const qtree_plan* plan, int32_t n_pay, const int
     if (e != hipSuccess) return hip_fail(e, "payoff launch");
   }
   return QTREE_OK;
+}
+
+// Layout of the transition-weight workspace: layer offsets, row bands, weights.
+struct PiLayout {
+  size_t off, band, pi, total;
+  int64_t rows, weights;
+};
+static PiLayout pi_layout(const qtree_plan* p) {
+  PiLayout l{};
+  l.rows = p->pt_off[p->n];
+  l.weights = 0;
+  for (int k = 0; k < p->n; ++k) l.weights += (int64_t)p->N[k] * ((p->N[k + 1] + 3) & ~3);
+  l.off = 0;
+  l.band = align_up(sizeof(int64_t) * (size_t)p->n, 256);
+  l.pi = align_up(l.band + sizeof(int2) * (size_t)l.rows, 256);
+  l.total = l.pi + sizeof(double) * (size_t)l.weights;
+  return l;
+}
+
+qtree_status qtree_pi_workspace_size(const qtree_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(QTREE_EINVAL, "plan and bytes must be non-NULL");
+  *bytes = pi_layout(plan).total;
+  return QTREE_OK;
+}
+
+qtree_status qtree_pi(const qtree_plan* plan, const int32_t* counts, void* pi, size_t pi_bytes,
+                      void* stream) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (!counts || !pi) return fail(QTREE_EINVAL, "counts and pi must be non-NULL");
+  if (reinterpret_cast<uintptr_t>(pi) % 256) return fail(QTREE_EINVAL, "pi must be 256-byte aligned");
+  const PiLayout l = pi_layout(plan);
+  if (pi_bytes < l.total)
+    return fail(QTREE_ENOMEM, "pi needs " + std::to_string(l.total) + " bytes");
+  char* base = static_cast<char*>(pi);
+  qtree::PiArgs a{};
+  a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
+  a.counts = counts;
+  a.pi_off = reinterpret_cast<const int64_t*>(base + l.off);
+  a.band = reinterpret_cast<int2*>(base + l.band);
+  a.pi = reinterpret_cast<double*>(base + l.pi);
+  a.rows = l.rows;
+  a.n = plan->n;
+  hipError_t e = qtree::launch_pi(a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "pi launch");
+}
+
+qtree_status qtree_bdp_many(const qtree_plan* plan, const void* pi, size_t pi_bytes, int64_t n_q,
+                            const qtree_payoff_spec* specs, double* V0, void* stream) {
+  static_assert(sizeof(qtree_payoff_spec) == sizeof(qtree::Contract),
+                "qtree_payoff_spec must match the device contract record");
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (!pi) return fail(QTREE_EINVAL, "pi is NULL");
+  if (n_q < 0) return fail(QTREE_EINVAL, "n_q must be >= 0");
+  if (n_q == 0) return QTREE_OK;
+  if (!specs || !V0) return fail(QTREE_EINVAL, "specs and V0 must be non-NULL");
+  if (reinterpret_cast<uintptr_t>(specs) % 8 || reinterpret_cast<uintptr_t>(V0) % 8)
+    return fail(QTREE_EINVAL, "specs and V0 must be 8-byte aligned");
+  const PiLayout l = pi_layout(plan);
+  if (pi_bytes < l.total)
+    return fail(QTREE_ENOMEM, "pi needs " + std::to_string(l.total) + " bytes");
+  if (qtree::bdp_many_maxr(plan->maxN) < 0)
+    return fail(QTREE_EUNSUPPORTED, "qtree_bdp_many takes layers of at most 256 points");
+  const char* base = static_cast<const char*>(pi);
+  qtree::ManyArgs a{};
+  a.layers = reinterpret_cast<const qtree::LayerDev*>(plan->ws + plan->lay.layers);
+  a.pts1 = reinterpret_cast<const float*>(plan->ws + plan->lay.points);
+  a.pts = reinterpret_cast<const float4*>(plan->ws + plan->lay.points);
+  a.pi_off = reinterpret_cast<const int64_t*>(base + l.off);
+  a.band = reinterpret_cast<const int2*>(base + l.band);
+  a.pi = reinterpret_cast<const double*>(base + l.pi);
+  a.specs = reinterpret_cast<const qtree::Contract*>(specs);
+  a.V0 = V0;
+  a.nq = n_q;
+  a.n = plan->n;
+  a.d = plan->d;
+  a.max_n = plan->maxN;
+  a.np_max = (plan->maxN + 3) & ~3;
+  hipError_t e = qtree::launch_bdp_many(a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "bdp_many launch");
 }
 
 qtree_status qtree_payoff(const qtree_plan* plan, int32_t kind, double S0, double K, double r,

@@ -24,9 +24,8 @@ using qtree::set_error;
 
 struct qtree_tuner {
   std::string path;
-  // batch signature -> workgroups per CU: 1-D launch in the low byte, d >= 2
-  // launch in the next
-  std::map<std::string, int> best;
+  // batch signature -> (configuration code, its measured forward time in ms)
+  std::map<std::string, std::pair<int, double>> best;
 };
 
 namespace {
@@ -52,19 +51,45 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
   return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
 }
 
+// Cache file: one line per batch signature, "qtree-batch <signature> <code> <ms>".
 void load_cache(qtree_tuner* t) {
   if (t->path.empty()) return;
   std::ifstream in(t->path);
-  std::string key;
-  int v;
-  while (in >> key >> v) t->best[key] = v;
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string tag, key;
+    int code = 0;
+    double ms = 0.0;
+    if (ls >> tag >> key >> code >> ms && tag == "qtree-batch") t->best[key] = {code, ms};
+  }
 }
 
 void save_cache(const qtree_tuner* t) {
   if (t->path.empty()) return;
   std::ofstream out(t->path, std::ios::trunc);
-  for (const auto& kv : t->best) out << kv.first << " " << kv.second << "\n";
+  for (const auto& kv : t->best)
+    out << "qtree-batch " << kv.first << " " << kv.second.first << " " << kv.second.second
+        << "\n";
 }
+
+// Launch configuration of a batch run; counts and values never depend on it.
+//   nd_samples: samples per lane sharing each grid read in the d >= 2 launch;
+//   overlap:    the 1-D sampling launch runs on a second stream beside the
+//               d >= 2 one (both then share the chip), instead of after it;
+//   nd_cap:     workgroups per CU of the d >= 2 launch (0: as many as fit),
+//               enforced by the launch's dynamic LDS.
+struct BatchConfig {
+  int nd_samples = 8, overlap = 0, nd_cap = 0;
+  int code() const { return (nd_samples == 4 ? 1 : 0) | (overlap << 1) | (nd_cap << 8); }
+  static BatchConfig from(int c) {
+    BatchConfig k;
+    k.nd_samples = (c & 1) ? 4 : 8;
+    k.overlap = (c >> 1) & 1;
+    k.nd_cap = (c >> 8) & 0xFF;
+    return k;
+  }
+};
 
 }  // namespace
 
@@ -95,16 +120,25 @@ struct qtree_batch {
   int gk1 = -1;               // 1-D launch: largest guide K (-1: breadth-first search)
   int sub1 = 1, maxP1 = 1, gtB1 = 1;  // its sub-counters, midpoint slots, largest table
   int cus = 256;
-  int per_cu[2] = {1, 1};     // workgroups per CU that fit, of each sampling launch
-  int max_per_cu[2] = {1, 1};
+  int max_per_cu[2] = {1, 1};  // workgroups per CU that fit, of each sampling launch
+  BatchConfig cfg;
+  bool cfg_fixed = false;      // set by qtree_batch_set_config: the tuner keeps out
+  double tuned_ms = 0.0;       // measured forward time of cfg (0: not measured)
+  int candidates = 0;          // configurations timed by the tuner in this process
   qtree_tuner* tuner = nullptr;
   std::string signature;
   bool use_graph = false;
   bool tuned = false;
   hipGraphExec_t exec = nullptr;
+  hipStream_t side = nullptr;  // second stream of the overlapped configuration
+  hipEvent_t fork = nullptr, join = nullptr;
 
   ~qtree_batch() {
+    if (side) (void)hipStreamSynchronize(side);
     if (exec) (void)hipGraphExecDestroy(exec);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
     for (void* p : {(void*)d_contracts, (void*)d_units, (void*)d_chunk_off, (void*)d_tiles,
                     (void*)d_jobs,
                     (void*)d_bdp_tasks,
@@ -115,9 +149,8 @@ struct qtree_batch {
 
 namespace {
 
-// Arguments of launch x (0: 1-D pass A, 1: d >= 2 pass A) of group g; the two
-// launches claim from separate counters.
-qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x) {
+// Arguments of launch x (0: 1-D pass A, 1: d >= 2 pass A) of group g.
+qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x, const BatchConfig& c) {
   qtree::BatchArgs a{};
   a.contracts = b->d_contracts;
   a.units = b->d_units + g.unit_off[x];
@@ -129,36 +162,129 @@ qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x) {
   a.maxP = b->maxP1;
   a.gt_Bmax = b->gtB1;
   a.n_tiles = g.n_tiles;
+  a.nd_samples = c.nd_samples;
   a.keys = b->d_keys;
   a.segs = b->d_segs;
   return a;
 }
 
-hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
+// Dynamic LDS of the d >= 2 launch under a configuration: enough for the
+// kernel, and with a cap, enough that no more than nd_cap workgroups fit on
+// a CU (160 KiB of LDS each).
+size_t nd_lds(const qtree_batch* b, const BatchConfig& c) {
+  size_t lds = b->lds[1];
+  if (c.nd_cap > 0) lds = std::max(lds, (size_t)(160 * 1024) / (size_t)(c.nd_cap + 1) + 16);
+  return lds;
+}
+
+int nd_per_cu(const qtree_batch* b, const BatchConfig& c) {
+  return c.nd_cap > 0 ? std::min(c.nd_cap, b->max_per_cu[1]) : b->max_per_cu[1];
+}
+
+hipError_t ensure_side(qtree_batch* b) {
+  hipError_t e = hipSuccess;
+  if (!b->side) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+  if (e == hipSuccess && !b->fork) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e == hipSuccess && !b->join) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+  return e;
+}
+
+// The sampling and histogram launches of every scratch group.
+hipError_t enqueue_forward(const qtree_batch* b, const BatchConfig& c, hipStream_t s) {
   for (const Group& g : b->groups) {
     hipError_t e = hipSuccess;
-    for (int x = 1; x >= 0 && e == hipSuccess; --x)  // the heavier d >= 2 list first
-      e = qtree::launch_batch_keys(group_args(b, g, x), x == 0 ? 1 : b->dmax, b->lg1,
-                                   g.n_chunks[x], b->lds[x], s);
-    if (e == hipSuccess) e = qtree::launch_batch_count(group_args(b, g, 0), s);
+    const bool both = g.n_units[0] > 0 && g.n_units[1] > 0;
+    if (c.overlap && both) {
+      // the 1-D list on the side stream, the d >= 2 list on s, then join
+      e = hipEventRecord(b->fork, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->fork, 0);
+      if (e == hipSuccess)
+        e = qtree::launch_batch_keys(group_args(b, g, 0, c), 1, b->lg1, g.n_chunks[0], b->lds[0],
+                                     b->side);
+      if (e == hipSuccess) e = hipEventRecord(b->join, b->side);
+      if (e == hipSuccess)
+        e = qtree::launch_batch_keys(group_args(b, g, 1, c), b->dmax, b->lg1, g.n_chunks[1],
+                                     nd_lds(b, c), s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join, 0);
+    } else {
+      for (int x = 1; x >= 0 && e == hipSuccess; --x)  // the heavier d >= 2 list first
+        e = qtree::launch_batch_keys(group_args(b, g, x, c), x == 0 ? 1 : b->dmax, b->lg1,
+                                     g.n_chunks[x], x == 0 ? b->lds[0] : nd_lds(b, c), s);
+    }
+    if (e == hipSuccess) e = qtree::launch_batch_count(group_args(b, g, 0, c), s);
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t enqueue_all(const qtree_batch* b, hipStream_t s) {
+  hipError_t e = enqueue_forward(b, b->cfg, s);
+  if (e != hipSuccess) return e;
   return qtree::launch_bdp_steps(b->d_jobs, (int)b->jobs.size(), b->max_last, b->d_bdp_tasks,
                                  b->step_off.data(), (int)b->step_off.size() - 1, s);
 }
 
-// The workgroups per CU that fit of each sampling launch (its occupancy
-// limit: the launches give one workgroup to every chunk, so there is no grid
-// to choose), kept per batch shape in the tuner's cache.
-qtree_status tune(qtree_batch* b, hipStream_t) {
+// The candidate configurations of a batch: samples per lane 8 / 4, serial or
+// overlapped sampling launches (when the batch has both kinds), and the d >= 2
+// launch at its occupancy limit or one workgroup per CU below it.
+std::vector<BatchConfig> candidates(const qtree_batch* b) {
+  bool both = false, nd = false;
+  for (const Group& g : b->groups) {
+    both = both || (g.n_units[0] > 0 && g.n_units[1] > 0);
+    nd = nd || g.n_units[1] > 0;
+  }
+  std::vector<BatchConfig> out;
+  for (int ns : {8, 4})
+    for (int ov = 0; ov <= (both ? 1 : 0); ++ov)
+      for (int cap = 0; cap <= 1; ++cap) {
+        BatchConfig c;
+        c.nd_samples = ns;
+        c.overlap = ov;
+        c.nd_cap = cap && b->max_per_cu[1] > 1 ? b->max_per_cu[1] - 1 : 0;
+        if (cap && c.nd_cap == 0) continue;
+        if (!nd && (ns != 8 || cap)) continue;  // no d >= 2 launch: nothing to vary there
+        out.push_back(c);
+      }
+  return out;
+}
+
+// Tuner: a cached configuration for this batch's signature, else every
+// candidate's forward launches timed with HIP events on `s` (after one
+// warm-up of the first), the fastest kept and written to the cache.
+qtree_status tune(qtree_batch* b, hipStream_t s) {
   auto it = b->tuner->best.find(b->signature);
   if (it != b->tuner->best.end()) {
-    for (int x = 0; x < 2; ++x)
-      b->per_cu[x] = std::max(1, std::min((it->second >> (8 * x)) & 0xFF, b->max_per_cu[x]));
+    b->cfg = BatchConfig::from(it->second.first);
+    b->tuned_ms = it->second.second;
     return QTREE_OK;
   }
-  for (int x = 0; x < 2; ++x) b->per_cu[x] = b->max_per_cu[x];
-  b->tuner->best[b->signature] = b->per_cu[0] | (b->per_cu[1] << 8);
+  const std::vector<BatchConfig> cand = candidates(b);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess && cand.size() > 1) e = ensure_side(b);
+  if (e == hipSuccess) e = enqueue_forward(b, cand[0], s);  // warm-up
+  double best_ms = 0.0;
+  BatchConfig best = cand[0];
+  for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+    e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = enqueue_forward(b, cand[i], s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (i == 0 || ms < best_ms)) {
+      best_ms = ms;
+      best = cand[i];
+    }
+    ++b->candidates;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_error(e, "batch tuning");
+  b->cfg = best;
+  b->tuned_ms = best_ms;
+  b->tuner->best[b->signature] = {best.code(), best_ms};
   save_cache(b->tuner);
   return QTREE_OK;
 }
@@ -180,9 +306,9 @@ qtree_status qtree_tuner_create(const char* cache_path, qtree_tuner** out) {
 void qtree_tuner_destroy(qtree_tuner* t) { delete t; }
 
 int32_t qtree_tuner_lookup(const qtree_tuner* t, const char* signature) {
-  if (!t || !signature) return 0;
+  if (!t || !signature) return -1;
   auto it = t->best.find(signature);
-  return it == t->best.end() ? 0 : it->second;
+  return it == t->best.end() ? -1 : it->second.first;
 }
 
 qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_tuner* tuner,
@@ -294,8 +420,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     if (x == 1 && b->dmax == 1) continue;
     b->max_per_cu[x] =
         std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lg1,
-                                                x == 0 ? b->gk1 : -1, b->lds[x]));
-    b->per_cu[x] = b->max_per_cu[x];
+                                                x == 0 ? b->gk1 : -1, b->lds[x], 8));
   }
   int dev = 0;
   hipDeviceProp_t prop;
@@ -446,12 +571,16 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
 qtree_status qtree_batch_run(qtree_batch* b, double* V0_host, void* stream) {
   if (!b) return set_error(QTREE_EINVAL, "batch is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (b->tuner && !b->tuned) {
+  if (b->tuner && !b->tuned && !b->cfg_fixed) {
     qtree_status st = tune(b, s);
     if (st != QTREE_OK) return st;
     b->tuned = true;
   }
   hipError_t e;
+  if (b->cfg.overlap) {
+    e = ensure_side(b);
+    if (e != hipSuccess) return hip_error(e, "batch side stream");
+  }
   if (b->exec) {
     e = hipGraphLaunch(b->exec, s);
     if (e != hipSuccess) return hip_error(e, "graph launch");
@@ -493,8 +622,36 @@ qtree_status qtree_batch_info(const qtree_batch* b, int64_t* units, int64_t* til
   if (units) *units = (int64_t)b->units.size();
   if (tiles) *tiles = (int64_t)b->tiles.size();
   if (groups) *groups = (int32_t)b->groups.size();
-  if (per_cu_1d) *per_cu_1d = b->per_cu[0];
-  if (per_cu_nd) *per_cu_nd = b->per_cu[1];
+  if (per_cu_1d) *per_cu_1d = b->max_per_cu[0];
+  if (per_cu_nd) *per_cu_nd = nd_per_cu(b, b->cfg);
+  return QTREE_OK;
+}
+
+qtree_status qtree_batch_tuning(const qtree_batch* b, int32_t* config, double* ms,
+                                int32_t* timed) {
+  if (!b) return set_error(QTREE_EINVAL, "batch is NULL");
+  if (config) *config = b->cfg.code();
+  if (ms) *ms = b->tuned_ms;
+  if (timed) *timed = b->candidates;
+  return QTREE_OK;
+}
+
+qtree_status qtree_batch_set_config(qtree_batch* b, int32_t config) {
+  if (!b) return set_error(QTREE_EINVAL, "batch is NULL");
+  const BatchConfig c = BatchConfig::from(config);
+  if (config < 0 || c.code() != config)
+    return set_error(QTREE_EINVAL, "unknown configuration code");
+  if (c.nd_cap > 8) return set_error(QTREE_EINVAL, "workgroups per CU must be <= 8");
+  if (c.nd_cap > 0 && nd_lds(b, c) > 160 * 1024)
+    return set_error(QTREE_EINVAL, "workgroup cap below what the kernel's LDS allows");
+  if (b->exec) {  // the captured graph holds the old launches
+    hipError_t e = hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    if (e != hipSuccess) return hip_error(e, "graph destroy");
+  }
+  b->cfg = c;
+  b->cfg_fixed = true;
+  b->tuned_ms = 0.0;
   return QTREE_OK;
 }
 

@@ -209,4 +209,266 @@ hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------- many contracts, one tree
+//
+// The conditional expectation of the quantized BDP (Sec. 2) is a product of
+// the transition matrix pi^k (N_k x N_{k+1}) with the values V_{k+1} of every
+// contract priced on the tree; its cost is sum_k N_k N_{k+1} multiply-adds
+// per contract.  pi_kernel turns the counts into pi^k_ij = c_ij / p_i once
+// (FP64, rows padded with zeros to a multiple of 4 columns) and records the
+// range of the nonzero columns of every row; bdp_many_kernel then runs the
+// whole backward recursion of 64 contracts per workgroup with their V_{k+1}
+// resident in LDS ([j][64]: lane = contract, so every LDS read is one
+// conflict-free 512-byte row), the obstacle phi_k computed where it is
+// used, and pi read with scalar loads (a wave's rows are uniform).
+
+__global__ __launch_bounds__(256) void pi_kernel(PiArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // row over layers 0..n-1
+  if (r >= a.rows) return;
+  int lo = 0, hi = a.n - 1;  // the layer k with pt_off_k <= r < pt_off_k + N_k
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.layers[mid].pt_off <= r) lo = mid; else hi = mid - 1;
+  }
+  const LayerDev& L = a.layers[lo];
+  const int i = (int)(r - L.pt_off);
+  const int N1 = L.N1, N1p = (N1 + 3) & ~3;
+  const int32_t* row = a.counts + L.cnt_off + (int64_t)i * N1;
+  int64_t p = 0;
+  int jlo = N1p, jhi = 0;
+  for (int j = lane; j < N1; j += 64) {
+    const int32_t c = row[j];
+    p += c;
+    if (c != 0) {
+      jlo = j < jlo ? j : jlo;
+      jhi = j + 1;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    p += __shfl_xor(p, off, 64);
+    const int l2 = __shfl_xor(jlo, off, 64), h2 = __shfl_xor(jhi, off, 64);
+    jlo = l2 < jlo ? l2 : jlo;
+    jhi = h2 > jhi ? h2 : jhi;
+  }
+  double* out = a.pi + a.pi_off[lo] + (int64_t)i * N1p;
+  const double inv_p = p > 0 ? (double)p : 1.0;
+  for (int j = lane; j < N1p; j += 64) {
+    const int32_t c = j < N1 ? row[j] : 0;
+    out[j] = p > 0 ? (double)c / inv_p : 0.0;
+  }
+  if (lane == 0) {
+    // whole groups of 4 columns; an empty row scans nothing (continuation 0)
+    a.band[r] = p > 0 ? make_int2(jlo & ~3, (jhi + 3) & ~3) : make_int2(0, 0);
+  }
+}
+
+// pi_off[k] = sum_{l < k} N_l N1p_l (one thread; n is at most a few thousand).
+__global__ void pi_offsets_kernel(const LayerDev* layers, int n, int64_t* pi_off) {
+  int64_t o = 0;
+  for (int k = 0; k < n; ++k) {
+    pi_off[k] = o;
+    o += (int64_t)layers[k].N * (int64_t)((layers[k].N1 + 3) & ~3);
+  }
+}
+
+hipError_t launch_pi(const PiArgs& a, hipStream_t s) {
+  if (a.rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pi_offsets_kernel, dim3(1), dim3(1), 0, s, a.layers, a.n,
+                     const_cast<int64_t*>(a.pi_off));
+  hipLaunchKernelGGL(pi_kernel, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+namespace {
+
+// Obstacle of contract C on layer k (the arithmetic of payoff_kernel, so
+// both give the same phi bit for bit): the layer's discount and drifts once,
+// then one exponential per asset and grid point.
+struct LayerObstacle {
+  double disc;
+  double drift[3];  // (r - sigma_c^2 / 2) t_k
+  bool euro;        // European before maturity: phi = -inf
+};
+
+template <int D>
+__device__ __forceinline__ LayerObstacle layer_obstacle(const Contract& C, int n, int k) {
+  LayerObstacle o;
+  const double t = C.Tm * (double)k / (double)n;
+  o.disc = exp(-C.r * t);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    o.drift[c] = c < D ? (C.r - 0.5 * C.sigma[c] * C.sigma[c]) * t : 0.0;
+  o.euro = (C.kind & 2) && k < n;
+  return o;
+}
+
+template <int D>
+__device__ __forceinline__ double obstacle(const Contract& C, const LayerObstacle& o,
+                                           const float* xs) {
+  double y[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    double v = 0.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) v += C.mix[c * D + e] * (double)xs[e];
+    y[c] = C.has_mix ? v : (double)xs[c];
+  }
+  double v;
+  if (C.kind & 1) {
+    double smax = -__builtin_huge_val();
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double sc = C.S0 * exp(o.drift[c] + C.sigma[c] * y[c]);
+      smax = sc > smax ? sc : smax;
+    }
+    v = o.disc * fmax(smax - C.K, 0.0);
+  } else {
+    const double sc = C.S0 * exp(o.drift[0] + C.sigma[0] * y[0]);
+    v = o.disc * fmax(C.K - sc, 0.0);
+  }
+  return o.euro ? -__builtin_huge_val() : v;
+}
+
+template <int D>
+__device__ __forceinline__ void grid_point(const ManyArgs& a, const LayerDev& L, int i,
+                                           float* xs) {
+  const int64_t at = (int64_t)L.pt_off + i;
+  if (D == 1) {
+    xs[0] = a.pts1[at];
+  } else {
+    const float4 g = a.pts[at];
+    xs[0] = g.x;
+    xs[1] = g.y;
+    if (D == 3) xs[2] = g.z;
+  }
+}
+
+}  // namespace
+
+// Workgroup b prices contracts 64 b .. 64 b + 63 (lane = contract); wave w
+// owns the rows i = w + 4 t of every layer, R of them at a time, and keeps
+// their new values in registers until every wave has finished reading
+// V_{k+1}.  MAXR >= ceil(N_max / 4).
+template <int D, int MAXR, int R>
+__global__ __launch_bounds__(256) void bdp_many_kernel(ManyArgs a) {
+  extern __shared__ double Vs[];  // [Np_max][64]
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const Contract C = a.specs[q < a.nq ? q : a.nq - 1];
+  // zero the padding rows once (they meet only zero weights, but must be finite)
+  for (int j = wave; j < a.np_max; j += 4) Vs[j * 64 + lane] = 0.0;
+  __syncthreads();
+  {
+    const LayerDev& L = a.layers[a.n];
+    const LayerObstacle ob = layer_obstacle<D>(C, a.n, a.n);
+    for (int i = wave; i < L.N; i += 4) {
+      float xs[3];
+      grid_point<D>(a, L, i, xs);
+      Vs[i * 64 + lane] = obstacle<D>(C, ob, xs);
+    }
+  }
+  __syncthreads();
+  for (int k = a.n - 1; k >= 0; --k) {
+    const LayerDev& L = a.layers[k];
+    const int Nk = L.N, N1p = (L.N1 + 3) & ~3;
+    const double* P = a.pi + a.pi_off[k];
+    const int2* B = a.band + L.pt_off;
+    const LayerObstacle ob = layer_obstacle<D>(C, a.n, k);
+    double res[MAXR];
+#pragma unroll
+    for (int t0 = 0; t0 < MAXR; t0 += R) {
+      const int ib = wave + 4 * t0;
+      if (ib >= Nk) break;
+      int jlo = 1 << 30, jhi = 0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = ib + 4 * t;
+        if (i < Nk) {
+          const int2 b = B[i];
+          if (b.y > b.x) {
+            jlo = b.x < jlo ? b.x : jlo;
+            jhi = b.y > jhi ? b.y : jhi;
+          }
+        }
+      }
+      double acc[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) acc[t] = 0.0;
+      const double* prow[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = ib + 4 * t < Nk ? ib + 4 * t : ib;  // rows past the end repeat row ib
+        prow[t] = P + (int64_t)i * N1p;
+      }
+      for (int j = jlo; j < jhi; j += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = Vs[(j + u) * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[t] = fma(prow[t][j + u], v[u], acc[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = ib + 4 * t;
+        if (i < Nk) {
+          float xs[3];
+          grid_point<D>(a, L, i, xs);
+          const double f = obstacle<D>(C, ob, xs);
+          res[t0 + t] = f > acc[t] ? f : acc[t];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXR; ++t) {
+      const int i = wave + 4 * t;
+      if (i < Nk) Vs[i * 64 + lane] = res[t];
+    }
+    __syncthreads();
+  }
+  if (wave == 0 && q < a.nq) a.V0[q] = Vs[lane];
+}
+
+int bdp_many_maxr(int max_n) {
+  const int rows = (max_n + 3) / 4;
+  return rows <= 8 ? 8 : rows <= 16 ? 16 : rows <= 32 ? 32 : rows <= 64 ? 64 : -1;
+}
+
+size_t bdp_many_lds(int max_np) { return sizeof(double) * 64 * (size_t)max_np; }
+
+template <int D>
+static hipError_t launch_bdp_many_d(const ManyArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.nq + 63) / 64));
+  const size_t lds = bdp_many_lds(a.np_max);
+  hipError_t e = hipSuccess;
+  switch (bdp_many_maxr(a.max_n)) {
+#define QTREE_MANY(MR)                                                                   \
+  case MR:                                                                               \
+    if (lds > 65536)                                                                     \
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(bdp_many_kernel<D, MR, 4>),  \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
+    if (e != hipSuccess) return e;                                                       \
+    hipLaunchKernelGGL((bdp_many_kernel<D, MR, 4>), grid, dim3(256), lds, s, a);         \
+    break;
+    QTREE_MANY(8) QTREE_MANY(16) QTREE_MANY(32) QTREE_MANY(64)
+#undef QTREE_MANY
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bdp_many(const ManyArgs& a, hipStream_t s) {
+  if (a.nq <= 0) return hipSuccess;
+  if (a.d == 1) return launch_bdp_many_d<1>(a, s);
+  if (a.d == 2) return launch_bdp_many_d<2>(a, s);
+  return launch_bdp_many_d<3>(a, s);
+}
+
 }  // namespace qtree

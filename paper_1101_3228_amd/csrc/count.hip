@@ -339,21 +339,22 @@ __device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g)
 }
 
 // Pass A, d = 2, 3: S samples per lane share each LDS grid read, in
-// kChunk / (KB S) rounds whose keys stay in registers.  The grid
-// scans take tiles of kNdTile records, the padding unit: one compare and two
-// selects per tile and sample for the running best (with 4-record tiles that
-// bookkeeping was ~a third of the scan's issue time; 8 records: 5 % faster).
+// kChunk / (KB S) rounds whose keys stay in registers.  The grid scans load
+// tiles of kNdTile records one tile ahead and keep the running best once per
+// group of kScanGroup records (the padding unit): one compare and two selects
+// per group and sample, then a rescan of the winning group (the bookkeeping
+// once per 4-record tile was ~a third of the scan's issue time).
 template <int D, int S, int KB>
 __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   constexpr int kKeys = kChunk / KB;
   constexpr int kNdTile = 8;
-  static_assert(kScanTile % kNdTile == 0, "scan tile must divide the padding unit");
+  static_assert(kScanGroup % kNdTile == 0, "scan tile must divide the padding unit");
   const LayerDev& L0 = *j.L0;
   const LayerDev& L1 = *j.L1;
   const int N0 = L0.N, N1 = L0.N1, T = L0.tiles;
-  // both grids padded to whole scan tiles with records whose key is +inf
-  const int P0 = (N0 + kScanTile - 1) / kScanTile * kScanTile;
-  const int P1 = (N1 + kScanTile - 1) / kScanTile * kScanTile;
+  // both grids padded to whole bookkeeping groups with records whose key is +inf
+  const int P0 = (N0 + kScanGroup - 1) / kScanGroup * kScanGroup;
+  const int P1 = (N1 + kScanGroup - 1) / kScanGroup * kScanGroup;
   float4* gk = lds4;
   float4* gk1 = lds4 + P0;
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + P0 + P1);
@@ -382,8 +383,8 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
       layer_pair<D>(L0, z, e, xs[s], ys[s]);
     }
     int ii[S], jj[S];
-    argmin_scan_tiled<D, S, kNdTile>(gk, P0, xs, ii);
-    argmin_scan_tiled<D, S, kNdTile>(gk1, P1, ys, jj);
+    argmin_scan_grouped<D, S, kNdTile, kScanGroup / kNdTile>(gk, P0, xs, ii);
+    argmin_scan_grouped<D, S, kNdTile, kScanGroup / kNdTile>(gk1, P1, ys, jj);
     // the round is not unrolled, so its keys go to fixed registers by a
     // uniform select (a dynamic index would put the array in scratch)
 #pragma unroll
@@ -539,10 +540,22 @@ __global__ __launch_bounds__(kBlockNd) void fwd_keys_nd(FwdArgs a) {
   keys_chunk_nd<D, S, kBlockNd>(plan_job(a, k, c), lds4);
 }
 
-// Workgroup b owns super tile t of layer k (tile0 + b = tile_off_k + t).
+// Workgroup b owns histogram unit tile0 + u (super tile t of layer k, or
+// one part of it).  With the XCD map, workgroup b runs on XCD b mod 8 and
+// takes unit u = (b mod 8) per + b / 8: consecutive units -- the super tiles
+// of one layer, whose key segments share cache lines in every chunk -- run on
+// one XCD and meet those lines in its L2.
 __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
   extern __shared__ uint32_t hist[];
-  const int b = a.tile0 + (int)blockIdx.x;
+  int u = (int)blockIdx.x;
+  if (a.xcd_map) {
+    const int per = (a.total_tiles + 7) / 8;
+    const int slot = (int)blockIdx.x >> 3;
+    if (slot >= per) return;
+    u = ((int)blockIdx.x & 7) * per + slot;
+    if (u >= a.total_tiles) return;
+  }
+  const int b = a.tile0 + u;
   int lo = 0, hi = a.n - 1;  // largest k with unit_off_k <= b
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -634,11 +647,11 @@ __global__ __launch_bounds__(kBlock) void batch_keys_1d_guide(BatchArgs a) {
   });
 }
 
-template <int DMAX>
+template <int DMAX, int S2>
 __global__ __launch_bounds__(kBlockNd) void batch_keys_nd(BatchArgs a) {
   extern __shared__ float4 lds4[];
   batch_loop<kBlockNd>(a, [&](const BatchContract& C, const KeysJob& j) {
-    if (DMAX < 3 || C.d == 2) keys_chunk_nd<2, kSamplesNd2, kBlockNd>(j, lds4);
+    if (DMAX < 3 || C.d == 2) keys_chunk_nd<2, S2, kBlockNd>(j, lds4);
     else keys_chunk_nd<3, 4, kBlockNd>(j, lds4);
   });
 }
@@ -691,7 +704,7 @@ size_t keys_lds_1d(int maxP, int max_tiles) {
 }
 
 size_t keys_lds_nd(int maxN, int max_tiles) {
-  return sizeof(float4) * 2 * (size_t)(maxN + kScanTile) + sizeof(uint16_t) * kChunk +
+  return sizeof(float4) * 2 * (size_t)(maxN + kScanGroup) + sizeof(uint16_t) * kChunk +
          sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
 }
 
@@ -737,6 +750,10 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
         if ((e = allow_lds(fwd_keys_1d<0>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(fwd_keys_1d<0>, keys_grid(a), dim3(kBlock), lds, s, a);
     }
+  } else if (a.d == 2 && a.nd_samples == 4) {
+    const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
+    if ((e = allow_lds(fwd_keys_nd<2, 4>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_keys_nd<2, 4>), keys_grid(a), dim3(kBlockNd), lds, s, a);
   } else if (a.d == 2) {
     const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
     if ((e = allow_lds(fwd_keys_nd<2, kSamplesNd2>, lds)) != hipSuccess) return e;
@@ -769,7 +786,10 @@ hipError_t launch_count_tiles(const FwdArgs& a, hipStream_t s) {
   const size_t lds = sizeof(uint32_t) * (kSuper + 2 * kCountBlock);
   hipError_t e = allow_lds(count_tiles, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(count_tiles, dim3((unsigned)a.total_tiles), dim3(kCountBlock), lds, s, a);
+  if (a.total_tiles <= 0) return hipSuccess;
+  const unsigned grid =
+      a.xcd_map ? 8u * (unsigned)((a.total_tiles + 7) / 8) : (unsigned)a.total_tiles;
+  hipLaunchKernelGGL(count_tiles, dim3(grid), dim3(kCountBlock), lds, s, a);
   return hipGetLastError();
 }
 
@@ -824,17 +844,25 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
     QTREE_BATCH_1D_SWITCH(lg1, QTREE_LAUNCH_1D)
 #undef QTREE_LAUNCH_1D
     if (e != hipSuccess) return e;
-  } else if (dmax == 2) {
-    if ((e = allow_lds(batch_keys_nd<2>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys_nd<2>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
   } else {
-    if ((e = allow_lds(batch_keys_nd<3>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_keys_nd<3>, dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
+#define QTREE_LAUNCH_ND(DM, S2)                                                            \
+  if ((e = allow_lds(batch_keys_nd<DM, S2>, lds)) != hipSuccess) return e;                 \
+  hipLaunchKernelGGL((batch_keys_nd<DM, S2>), dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
+    if (dmax == 2 && a.nd_samples == 4) {
+      QTREE_LAUNCH_ND(2, 4)
+    } else if (dmax == 2) {
+      QTREE_LAUNCH_ND(2, kSamplesNd2)
+    } else if (a.nd_samples == 4) {
+      QTREE_LAUNCH_ND(3, 4)
+    } else {
+      QTREE_LAUNCH_ND(3, kSamplesNd2)
+    }
+#undef QTREE_LAUNCH_ND
   }
   return hipGetLastError();
 }
 
-int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds) {
+int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples) {
   int blocks = 0;
   hipError_t e = hipSuccess;
   if (dmax <= 1 && gk >= 0) {
@@ -848,14 +876,22 @@ int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_1d<LG>, kBlock, lds);
     QTREE_BATCH_1D_SWITCH(lg1, QTREE_OCC_1D)
 #undef QTREE_OCC_1D
-  } else if (dmax == 2) {
-    e = allow_lds(batch_keys_nd<2>, lds);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_nd<2>, kBlockNd, lds);
   } else {
-    e = allow_lds(batch_keys_nd<3>, lds);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_nd<3>, kBlockNd, lds);
+#define QTREE_OCC_ND(DM, S2)                                                               \
+  e = allow_lds(batch_keys_nd<DM, S2>, lds);                                               \
+  if (e == hipSuccess)                                                                     \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_nd<DM, S2>, kBlockNd, \
+                                                     lds);
+    if (dmax == 2 && nd_samples == 4) {
+      QTREE_OCC_ND(2, 4)
+    } else if (dmax == 2) {
+      QTREE_OCC_ND(2, kSamplesNd2)
+    } else if (nd_samples == 4) {
+      QTREE_OCC_ND(3, 4)
+    } else {
+      QTREE_OCC_ND(3, kSamplesNd2)
+    }
+#undef QTREE_OCC_ND
   }
   return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }

@@ -44,6 +44,7 @@ struct BatchArgs {
   // batch's largest K (-1: breadth-first search), over maxP midpoints and
   // tables of up to gt_Bmax entries, sub sub-counters per tile in the sort
   int32_t gk, sub, maxP, gt_Bmax;
+  int32_t nd_samples;  // d >= 2 launch: samples per lane sharing each grid read (8 or 4)
   uint16_t* keys;
   uint32_t* segs;
 };
@@ -57,7 +58,7 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
 hipError_t launch_batch_count(const BatchArgs& a, hipStream_t s);
 // Workgroups of the pass-A kernel (dmax as above; gk >= 0: the 1-D guide
 // kernel) that fit on one CU with `lds` bytes of dynamic LDS each.
-int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds);
+int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples);
 size_t keys_lds_1d(int maxP, int max_tiles);
 size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles);
 int guide_sub_counters(int max_tiles);

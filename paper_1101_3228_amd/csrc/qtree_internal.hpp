@@ -22,6 +22,7 @@ constexpr int kChunk = 4096;          // samples per pass-A workgroup
 constexpr int kMaxTiles = 4096;       // larger count blocks use direct atomics
 constexpr int kDefaultBatch = 1 << 22;  // samples per layer per pass by default
 constexpr int kScanTile = 8;            // records per tile of the d >= 2 argmin scan
+constexpr int kScanGroup = 32;          // records per bookkeeping group (forward d >= 2 scan)
 constexpr int kGuideMax = 8192;         // largest guide table of a 1-D layer (entries)
 constexpr int kGuideKMax = 4;           // most midpoints one guide bucket may add
 
@@ -101,6 +102,7 @@ struct FwdArgs {
   int32_t total_tiles;    // histogram units of this launch (pass-B grid)
   int32_t first_batch;    // pass B overwrites instead of adding
   int32_t layer0;         // first layer of this launch (units and tiles)
+  int32_t nd_samples;     // d >= 2: samples per lane sharing each grid read (8 or 4)
   int32_t tile0;          // first histogram unit of this launch
 };
 
@@ -170,6 +172,36 @@ struct PayoffArgs {
   Contract c[kPayoffGroup];
 };
 hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s);
+
+// Transition weights pi^k = c / p (FP64, rows padded to N1p = multiple of 4)
+// and the nonzero column range of every row, for the many-contract BDP.
+struct PiArgs {
+  const LayerDev* layers;
+  const int32_t* counts;
+  const int64_t* pi_off;  // [n] first weight of layer k (device)
+  double* pi;
+  int2* band;             // [rows] columns [x, y) hold every nonzero weight of the row
+  int64_t rows;           // sum_{k<n} N_k
+  int32_t n;
+};
+hipError_t launch_pi(const PiArgs& a, hipStream_t s);
+
+// Backward recursion of many contracts on one tree (64 per workgroup).
+struct ManyArgs {
+  const LayerDev* layers;
+  const float* pts1;
+  const float4* pts;
+  const int64_t* pi_off;
+  const double* pi;
+  const int2* band;
+  const Contract* specs;  // [nq] (device)
+  double* V0;             // [nq] (device)
+  int64_t nq;
+  int32_t n, d, max_n, np_max;  // np_max: largest N_k rounded up to a multiple of 4
+};
+int bdp_many_maxr(int max_n);  // -1: beyond the supported 256 points per layer
+size_t bdp_many_lds(int max_np);
+hipError_t launch_bdp_many(const ManyArgs& a, hipStream_t s);
 
 // Stratified time-layer counts (d = 1): Ms samples per cell of layer k.
 struct StratArgs {

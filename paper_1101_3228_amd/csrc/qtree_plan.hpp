@@ -21,6 +21,7 @@ struct qtree_plan {
   int32_t tune_xcd_map = 1;
   int32_t tune_count = 0;  // 0 automatic, 1 direct atomics, 2 two-pass
   int32_t tune_groups = 0;  // layer groups of the two-pass forward (0: automatic)
+  int32_t tune_nd_samples = 8;  // d >= 2 pass A: samples per lane sharing each grid read
   int32_t max_tiles = 0, total_tiles = 0;
   std::vector<int32_t> tile_off;  // first super tile of every layer (host copy)
   std::vector<int32_t> unit_off;  // first histogram unit of every layer (host copy)
@@ -30,7 +31,8 @@ struct qtree_plan {
   int32_t gt_Kmax = -1;           // d = 1: largest guide K over the layers (-1: no tables)
   int32_t gt_Bmax = 1;            // d = 1: largest guide table
   int64_t batch_chunks = 0;      // scratch chunks per layer per pass
-  bool two_pass_ok = false;
+  bool two_pass_ok = false;       // the workspace holds two-pass scratch
+  bool two_pass_shape = false;    // the count blocks and LDS allow two-pass counting
   hipEvent_t trace_keys = nullptr;
   // stream and events of the overlapped histogram passes (made on first use)
   static constexpr int kMaxGroups = 8;
@@ -50,4 +52,16 @@ struct qtree_plan {
 namespace qtree {
 // Record a failure for qtree_last_error and return its status.
 qtree_status set_error(qtree_status s, const std::string& msg);
+
+// Scratch of the two-pass counting: keys and segment starts for `chunks`
+// chunks per layer per pass, and the most layer groups a call may use.
+struct CountScratch {
+  uint16_t* keys = nullptr;
+  uint32_t* segs = nullptr;
+  int64_t chunks = 0;
+  int max_groups = 1;
+};
+qtree_status transitions_on_scratch(const qtree_plan* plan, uint64_t m0, uint64_t M,
+                                    uint64_t seed, uint32_t contract_id, qtree_mode mode,
+                                    int32_t* counts, void* stream, void* base, size_t bytes);
 }  // namespace qtree

@@ -21,7 +21,8 @@ import math
 
 import numpy as np
 
-from . import EUROPEAN, PUT, Plan, _check, _np_ptr, _stream_handle, gauss_quantizer, lib
+from . import (EUROPEAN, PUT, Plan, _check, _np_ptr, _stream_handle, gauss_quantizer, lib,
+               payoff_specs)
 
 N_PARAMS = 133633
 N_INPUTS = 6
@@ -183,33 +184,51 @@ class PutTreePricer:
         self._trees = {}
 
     def tree(self, n: int):
+        """(plan, counts, pi) of the tree with n layers, built on first use."""
         n = int(n)
         if n not in self._trees:
             grid, N = unit_bm_grid(n, self.N)
             plan = Plan(unit_bm_model(n), grid, N, device=self.device, batch_samples=self.M)
             counts = plan.transitions(self.M, self.seed, contract=self.contract)
-            self._trees[n] = (plan, counts)
+            self._trees[n] = (plan, counts, plan.pi(counts))
         return self._trees[n]
+
+    def specs(self, x) -> dict:
+        """Contract records of the queries, grouped by n: {n: (rows, device
+        qtree_payoff_spec bytes)}; x: host [Q, 6] rows (S0/K, sigma, r, T, n, rho)."""
+        import torch
+        x = np.asarray(x, np.float64)
+        kind = PUT if self.american else PUT | EUROPEAN
+        ns = np.rint(x[:, 4]).astype(np.int64)
+        if np.any(ns < 1):
+            raise ValueError("n must be >= 1")
+        out = {}
+        for n in np.unique(ns):
+            rows = np.flatnonzero(ns == n)
+            q = x[rows]
+            rec = payoff_specs(1, np.full(rows.size, kind, np.int32), q[:, 0], 1.0, q[:, 2],
+                               q[:, 3], q[:, 1].reshape(-1, 1),
+                               np.sqrt(q[:, 3]).reshape(-1, 1, 1))
+            out[int(n)] = (rows, torch.from_numpy(rec.view(np.uint8).reshape(-1)).to(self.device))
+        return out
+
+    def price_specs(self, groups: dict, out=None, stream=None):
+        """V_0 / K of pre-built query groups (see specs) on the device:
+        one qtree_bdp_many launch per n.  Returns {n: device float64 [rows]}."""
+        res = {} if out is None else out
+        for n, (rows, sp) in groups.items():
+            plan, _, pi = self.tree(n)
+            res[n] = plan.bdp_many(pi, sp, V0=res.get(n), stream=stream)
+        return res
 
     def price(self, x, stream=None) -> np.ndarray:
         """x: host float [Q, 6] rows (S0/K, sigma, r, T, n, rho) -> V_0 / K (float64)."""
         x = np.asarray(x, np.float64)
         out = np.empty(x.shape[0], np.float64)
-        kind = PUT if self.american else PUT | EUROPEAN
-        ns = np.rint(x[:, 4]).astype(np.int64)
-        if np.any(ns < 1):
-            raise ValueError("n must be >= 1")
-        for n in np.unique(ns):
-            rows = np.flatnonzero(ns == n)
-            plan, counts = self.tree(int(n))
-            for c0 in range(0, rows.size, self.chunk):
-                r = rows[c0:c0 + self.chunk]
-                q = x[r]
-                phi = plan.payoff_batch(np.full(r.size, kind, np.int32), q[:, 0], 1.0, q[:, 2],
-                                        q[:, 3], q[:, 1].reshape(-1, 1),
-                                        mix=np.sqrt(q[:, 3]).reshape(-1, 1, 1), stream=stream)
-                V0, _ = plan.bdp(counts, phi, stream=stream)
-                out[r] = V0
+        groups = self.specs(x)
+        vals = self.price_specs(groups, stream=stream)
+        for n, (rows, _) in groups.items():
+            out[rows] = vals[n].cpu().numpy()
         return out
 
 

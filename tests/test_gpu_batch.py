@@ -92,7 +92,42 @@ def test_batch_scratch_groups_and_graph_replay(tmp_path):
         for it, rc in zip(items, ref_counts):
             assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), rc), rep
         assert np.allclose(V0, ref_v0, rtol=1e-12, atol=0), rep
-    assert tuner.lookup(batch.signature) >= 1
+    # the first run timed every candidate and kept the fastest
+    tu = batch.tuning()
+    assert tu["timed"] >= 2 and tu["ms"] > 0.0
+    assert tuner.lookup(batch.signature) == tu["config"]
     assert os.path.exists(tmp_path / "tune.txt")
     again = qt.Tuner(str(tmp_path / "tune.txt"))
-    assert again.lookup(batch.signature) == tuner.lookup(batch.signature)
+    assert again.lookup(batch.signature) == tu["config"]
+    # a batch of the same shape takes the cached choice without timing
+    same = qt.Batch(items, tuner=again, scratch_bytes=3 << 20)
+    same.run()
+    t2 = same.tuning()
+    assert t2["config"] == tu["config"] and t2["timed"] == 0
+    assert t2["ms"] == pytest.approx(tu["ms"], rel=1e-5)
+
+
+def test_batch_counts_identical_under_every_configuration():
+    """Every configuration the tuner may pick (samples per lane 8 / 4,
+    serial or overlapped sampling launches, a capped occupancy) gives the
+    same counts and values, eagerly and in a replayed graph."""
+    print("[gpu-case] batch configurations", flush=True)
+    items = _contracts(10, shrink=0.12, M=50_001, seed=13)
+    ref_counts, ref_v0 = _single(items)
+    batch = qt.Batch(items, graph=True)
+    cap = max(1, batch.info()["per_cu_nd"] - 1)
+    stream = torch.cuda.Stream()
+    for code in (0, 1, 2, 3, cap << 8, (cap << 8) | 3):
+        batch.set_config(code)
+        assert batch.tuning()["config"] == code
+        for rep in range(2):                  # the eager run, then a replay
+            for it in items:
+                it["counts"].fill_(-1)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                V0 = batch.run(stream=stream)
+            for it, rc in zip(items, ref_counts):
+                assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), rc), code
+            assert np.allclose(V0, ref_v0, rtol=1e-12, atol=0), code
+    with pytest.raises(qt.QtreeError):
+        batch.set_config(1 << 20)

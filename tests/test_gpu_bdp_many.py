@@ -1,0 +1,107 @@
+"""qtree_pi + qtree_bdp_many (the quantized BDP of Sec. 2 for many contracts
+on one tree, obstacles computed in the kernel) against the oracle's payoff
+and backward step on the same counts: within 1e-9 relative for puts and
+max-calls, American and European, with and without a factor map, d = 1, 2,
+3, several workgroups of 64 contracts with a ragged last one, layer sizes
+up to the 256-point limit, and rows no sample reached."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1101_3228_amd as qt
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    print(f"[gpu-case] {name}", flush=True)
+
+
+def _contracts(rng, nq, d):
+    kinds = rng.integers(0, 2, nq) * 2 + (1 if d > 1 else 0)   # American / European
+    S0 = rng.uniform(80.0, 125.0, nq)
+    K = np.full(nq, 100.0)
+    r = rng.uniform(0.0, 0.1, nq)
+    T = rng.uniform(0.25, 2.0, nq)
+    sigma = rng.uniform(0.1, 0.4, (nq, d))
+    mix = None
+    if d == 1:
+        mix = np.sqrt(T).reshape(nq, 1, 1)
+    else:
+        rho = rng.uniform(-0.3, 0.9, nq)
+        mix = np.zeros((nq, d, d))
+        for q in range(nq):
+            R = synth.corr_matrix(d, rho[q])
+            mix[q] = np.sqrt(T[q]) * np.linalg.cholesky(R)
+    return kinds.astype(np.int32), S0, K, r, T, sigma, mix
+
+
+def _check(plan, spec, grid, N, counts, nq, seed, identity_mix=False):
+    d = spec["d"]
+    rng = np.random.default_rng(seed)
+    kinds, S0, K, r, T, sigma, mix = _contracts(rng, nq, d)
+    if identity_mix:
+        mix = None
+    pi = plan.pi(counts)
+    specs = qt.payoff_specs(d, kinds, S0, K, r, T, sigma, mix)
+    got = plan.bdp_many(pi, specs).cpu().numpy()
+    c = counts.cpu().numpy()
+    want = np.empty(nq)
+    for q in range(nq):
+        phi = O.payoff(int(kinds[q]), d, N, grid, S0[q], K[q], r[q], T[q], sigma[q],
+                       None if mix is None else mix[q])
+        want[q] = O.bdp(c, N, phi)[0][0]
+    err = np.abs(got - want)
+    assert np.all(err <= 1e-9 * np.abs(want) + 1e-13), (np.max(err), int(np.argmax(err)))
+    # the same prices as qtree_payoff + qtree_bdp, one contract at a time
+    for q in (0, nq - 1):
+        phi = plan.payoff(int(kinds[q]), S0[q], K[q], r[q], T[q], sigma[q],
+                          None if mix is None else mix[q])
+        V0, _ = plan.bdp(counts, phi)
+        assert abs(V0[0] - got[q]) <= 1e-12 * abs(V0[0]) + 1e-14
+    return got
+
+
+def test_bdp_many_1d_with_empty_rows():
+    _case("bdp_many 1-D n=12 N<=100, far grid points")
+    spec = synth.bm_model(1, 12, T=1.0)
+    sizes = [1] + [int(s) for s in np.linspace(20, 100, 12).round()]
+    grid, N = synth.layer_grids(spec, sizes, base=qt.gauss_quantizer)
+    # move the last point of two layers far out: rows no sample reaches
+    off = O.point_offsets(N)
+    for k in (5, 9):
+        grid[off[k + 1] - 1, 0] = 40.0
+    plan = qt.Plan(spec, grid, N)
+    counts = plan.transitions(400_001, synth.SEED_BASE + 3)
+    c = counts.cpu().numpy()
+    blk = O.layer_counts(c, N, 5)
+    assert blk[-1].sum() == 0   # an empty source row is exercised
+    _check(plan, spec, grid, N, counts, 150, 1)
+
+
+@pytest.mark.parametrize("d,shape", [(2, (16, 16)), (3, (6, 6, 7))])
+def test_bdp_many_nd_max_call(d, shape):
+    _case(f"bdp_many d={d} {shape}")
+    spec = synth.bm_model(d, 6, T=1.0, rho=0.2)
+    sizes = [1] + [shape] * 6
+    grid, N = synth.layer_grids(spec, sizes)
+    plan = qt.Plan(spec, grid, N)
+    counts = plan.transitions(200_003, synth.SEED_BASE + 4)
+    _check(plan, spec, grid, N, counts, 70, 2)
+    _check(plan, spec, grid, N, counts, 64, 3, identity_mix=True)
+
+
+def test_bdp_many_rejects_large_layers():
+    _case("bdp_many N=300 rejected")
+    spec = synth.bm_model(1, 2, T=1.0)
+    grid, N = synth.layer_grids(spec, [1, 300, 300])
+    plan = qt.Plan(spec, grid, N)
+    counts = plan.transitions(10_000, 1)
+    pi = plan.pi(counts)
+    specs = qt.payoff_specs(1, [0], 100.0, 100.0, 0.05, 1.0, [[0.2]])
+    with pytest.raises(qt.QtreeError) as e:
+        plan.bdp_many(pi, specs)
+    assert e.value.status == 5
+    torch.cuda.synchronize()

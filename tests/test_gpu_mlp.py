@@ -160,7 +160,7 @@ def test_tree_labels_match_oracle():
     x = synth.box_queries(40, 23)
     for n in (10, 13):
         x[:, 4] = n
-        plan, counts = pricer.tree(n)
+        plan, counts, _ = pricer.tree(n)
         model = S.unit_bm_model(n)
         grid, N = S.unit_bm_grid(n, 60)
         mdl = O.Model(1, n, model["A"], model["b"], model["T"], model["mu"], model["L"],
