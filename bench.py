@@ -48,27 +48,59 @@ SIGMAS = (0.1, 0.2, 0.3, 0.4)
 K_RATIOS = (0.8, 1.0, 1.2)
 S0, RATE, MATURITY = 100.0, 0.05, 1.0
 
-# VALU peak: 128 lanes per clock per CU.  gfx950 issues all-VGPR FP32
-# fma/add/mul, integer add/sub, bitwise ops and right shifts at up to 128
-# lanes/clock/CU (measured 105-121); every other VALU op (compares, selects,
-# min/max, 32x32 multiplies, conversions, any op with an SGPR operand) at 64,
-# and those pair with the former (min + add: 118); FP32 transcendentals at
-# 32.  Algorithmic lane-slots therefore price every op 1 and a transcendental
-# 4 against the 128-lane peak (profiles/valu_op_rates.md).
-#
-# Algorithmic VALU lane-slots of one 1-D pair at N = 500:
-#   Philox4x32-10, half a call per pair: 10 rounds x (2 x 32x32->64 mad +
-#     4 xor) / 2                                                         = 30
-#   Box-Muller, one per pair: word->integer split 2, convert 1, exponent and
-#     mantissa split 3, fold 3, t 1, Mercator series 13 fma + 2, Cody-Waite
-#     3 + 2, scale 1, correctly rounded sqrt 12 (v_sqrt [4] + 2 fma + 2 cmp
-#     + 2 select + 2 add); angle split 6, convert 2, sin 5 + cos 5 + square 1,
-#     reflection 2, quadrant 4; two products 2                           = 71
-#   AR(1) sample: 3 fma                                                  =  3
-#   two binary searches over 512 padded midpoints: 2 x 9 steps x
-#     (address, compare, select)                                         = 54
-#   flat count index i N_{k+1} + j                                       =  1
-ALG_SLOTS_PER_PAIR = 30 + 71 + 3 + 54 + 1
+# ALU roofline.  Peak: 256 CUs x 128 lanes x 2.4 GHz = 78.6e12 lane-slots/s,
+# the published FP32 vector rate (157.3 TFLOP/s at 2 flops per FMA lane).
+# gfx950 issues all-VGPR FP32 fma/add/mul, integer add/sub, bitwise ops and
+# right shifts at up to 128 lanes per clock per CU (measured 104-117), every
+# other VALU op (compares, selects, min/max, left shifts, 3-input and 32x32
+# multiplies, conversions, FP64) at 64 (58-63), and FP32 transcendentals at
+# 32 (profiles/valu_op_rates.md).  An algorithmic operation is therefore
+# priced at its issue cost in slots of the 128-lane peak: F = 1 for the
+# full-rate class, H = 2 for the half-rate class, TR = 4 for a
+# transcendental (in mixes a half-rate op measured between 1.3 and 2.3 slots:
+# min + add 110 lanes/clock, mad_u64 + xor 78).  The operations counted are
+# those the method needs, each in its cheapest gfx950 form; sorting keys for
+# the count is not counted (the paper's count is one atomic increment).
+F, H, TR = 1, 2, 4
+# Philox4x32-10, one call: 10 rounds x (two 32x32->64 products, four xors)
+PHILOX_CALL = 10 * (2 * H + 4 * F)                                       # 80
+# ln(K 2^-24) by the fixed FP32 sequence: word split (shift, +1) 2F, convert
+# H, exponent (shift, bias) 2F, mantissa (and, or) 2F, fold (compare, two
+# selects) 3H, t F, Horner 12F, t^2 and r 2F, e - 24 and convert F + H,
+# Cody-Waite 2F
+LN_U24 = 2 * F + H + 2 * F + 2 * F + 3 * H + F + 12 * F + 2 * F + F + H + 2 * F  # 34
+# correctly rounded sqrt: v_sqrt TR, predecessor F, successor F, two
+# residual fmas 2F, two sign shifts 2F, two adds 2F
+SQRT_RN = TR + F + F + 2 * F + 2 * F + 2 * F                             # 12
+# sin and cos of 2 pi J 2^-24: word and quadrant splits 3F, reflection
+# (compare, subtract, select) 2H + F, convert and scale H + F, y^2 F, sine
+# 5F, cosine 5F, swap 2H, quadrant (and, compare, two selects) F + 3H, sign
+# words (and, shift; add, and, shift) 3F + 2H, sign xors 2F
+SINCOS = 3 * F + 2 * H + F + H + F + F + 5 * F + 5 * F + 2 * H + F + 3 * H + 3 * F + 2 * H + 2 * F  # 42
+BOX_MULLER = LN_U24 + F + SQRT_RN + SINCOS + 2 * F                       # 91
+KEY_INCR = H + F          # flat count index i N_{k+1} + j, one count increment
+# 1-D guide-table search with K candidate midpoints: bucket fma F, clamp
+# (med3) H, convert H, table and candidate addresses 2H, K x (subtract,
+# sign shift, add) 3F
+def guide_search(K: int) -> int:
+    return F + H + H + 2 * H + 3 * F * K
+# breadth-first binary search, per step: subtract, shift, and, add (4F) and
+# the shift-add of the child address (H)
+BFS_STEP = 4 * F + H
+# d >= 2 exact argmin, per grid point and sample: two fmas 2F and half of a
+# 3-input minimum H/2
+ND_POINT = 2 * F + H / 2                                                 # 3
+# One 1-D pair at N = 500 (the guide tables of these grids add K = 2
+# midpoints per bucket): half a Philox call, one Box-Muller, three AR(1)
+# fmas, two guide searches, index and increment
+ALG_SLOTS_PER_PAIR = PHILOX_CALL // 2 + BOX_MULLER + 3 * F + 2 * guide_search(2) + KEY_INCR  # 167
+# one d = 2 pair besides its searches: a Philox call, two Box-Muller, the
+# AR(1) rows (2 x 2 for X_k, 2 x 4 for X_{k+1}: 12F), index and increment
+ALG_SLOTS_2D_PAIR = PHILOX_CALL + 2 * BOX_MULLER + 12 * F + KEY_INCR     # 277
+ALG_SLOTS_2D_POINT = ND_POINT
+# The same pair with every operation priced 1 (transcendental 4): the
+# unweighted count reported beside the weighted one.
+ALG_SLOTS_PER_PAIR_UNWEIGHTED = 30 + 71 + 3 + 2 * 11 + 2
 PEAK_SLOTS = 256 * 128 * 2.4e9         # lane-slots per second
 
 # Algorithmic VALU lane-slots of one surrogate query (the matrix products run
@@ -125,6 +157,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="default run: skip the 2-D workload's nested line")
+    ap.add_argument("--c3-steps", type=int, default=3,
+                    help="default run: timed steps of the 2-D workload")
     ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
                     help="pairs per layer in the oracle sample")
     ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1", "swing",
@@ -144,6 +180,8 @@ def main():
                          "x 20 steps; strat: stratified 1-D counts, the c2 shape with 2e4 "
                          "samples per cell")
     ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
+    ap.add_argument("--tail", type=int, default=100,
+                    help="c2 with --groups: the last layer group's share in percent")
     ap.add_argument("--groups", type=int, default=0,
                     help="c2/c3: layer groups of the two-pass forward (0: library default)")
     ap.add_argument("--act-terms", type=int, default=1, choices=(1, 2),
@@ -197,7 +235,11 @@ def main():
     plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M_PAIRS)
     assert plan.batch_samples >= M_PAIRS, "counting scratch must hold one layer's samples"
     if args.groups:
-        plan.tune(groups=args.groups)
+        plan.tune(groups=args.groups, tail=args.tail)
+        tuning = {"fixed": plan.tuning()}
+    else:
+        # the library's autotuner picks the layer groups (untimed warm-up)
+        tuning = plan.autotune(M_PAIRS, seed=0x5EED00FF)
     contracts = [(s, kr) for s in SIGMAS for kr in K_RATIOS]
     nc = len(contracts)
     kinds = np.full(nc, qt.PUT, np.int32)
@@ -256,6 +298,7 @@ def main():
     V0 = V[:, 0].cpu().numpy()
     pairs = N_LAYERS * M_PAIRS
     achieved = ALG_SLOTS_PER_PAIR * pairs / (keys_ms * 1e-3)
+    hist = histogram_pass(plan, counts[0], s_fwd, pairs, max(3, args.steps // 4))
     out = {
         "metric": "MC transition samples/s (cell search+count)",
         "value": pairs / (ms_step * 1e-3),
@@ -283,100 +326,186 @@ def main():
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS,
                      "traffic": _measured_traffic(),
                      "kernel": "fwd_keys_1d_guide<2, 4>",
-                     "alg_slots_per_pair": ALG_SLOTS_PER_PAIR},
+                     "alg_slots_per_pair": ALG_SLOTS_PER_PAIR,
+                     "frac_unweighted": ALG_SLOTS_PER_PAIR_UNWEIGHTED * pairs
+                     / (keys_ms * 1e-3) / PEAK_SLOTS,
+                     "alg_slots_per_pair_unweighted": ALG_SLOTS_PER_PAIR_UNWEIGHTED},
+        "histogram_pass": hist,
+        "tuning": tuning,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, grid, N, args.cpu_pairs)
+    del plan, counts, phi, V
+    torch.cuda.empty_cache()
+    if not args.no_c3:
+        log("2-D workload")
+        out["c3"] = measure_c3(args.c3_steps, 1, not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)
 
 
-# Algorithmic VALU lane-slots of one d = 2 pair, excluding the searches:
-# one Philox call 60, two Box-Muller 142, AR(1) 12 FMA; each grid point of the two
-# searches costs 2 FMA + 1/2 of a 3-input min = 2.5 lane-slots.
-ALG_SLOTS_2D_PAIR = 60 + 142 + 12
-ALG_SLOTS_2D_POINT = 2.5
+# LDS atomic peak: one 32-bit atomic per LDS bank per clock, 32 banks per CU
+# (128 bytes per clock), 256 CUs at 2.4 GHz.
+LDS_ATOMIC_PEAK = 256 * 32 * 2.4e9
 
 
-def alg_slots_pair(d: int, Nk: int, Nk1: int) -> float:
+def histogram_pass(plan, counts, stream, pairs: int, reps: int) -> dict:
+    """The counting pass of the 1-D forward on its own: forwards with one
+    layer group, so the sampling launch and the histogram launch follow each
+    other on one stream, with the library's trace event between them.  The
+    histogram pass does one LDS atomic per pair, reads the 2-byte keys and the
+    segment tables and stores the count blocks once."""
+    import torch
+    plan.tune(groups=1)
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(reps + 1)]
+    for e in evs:
+        e[1].record(stream)
+    torch.cuda.synchronize()
+    for i, e in enumerate(evs):
+        e[0].record(stream)
+        plan.trace(e[1])
+        plan.transitions(M_PAIRS, 0x5EED0100 + i, counts=counts, stream=stream)
+        e[2].record(stream)
+    plan.trace(None)
+    plan.tune(groups=0)
+    torch.cuda.synchronize()
+    keys_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs[1:]]))
+    hist_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs[1:]]))
+    # algorithmic bytes: the 2-byte keys and every chunk's segment table
+    # (tiles + 1 words, tiles = ceil(N_k N_{k+1} / 4096)) are read, the
+    # count blocks written once
+    chunks = (M_PAIRS // 2 + 2048) // 2048
+    tiles = (N_POINTS * N_POINTS + 4095) // 4096
+    read = 2 * pairs + 4 * N_LAYERS * chunks * (tiles + 1)
+    written = 4 * plan.entries
+    rate = pairs / (hist_ms * 1e-3)
+    return {"ms": hist_ms, "sampling_ms_alone": keys_ms, "lds_atomics_per_s": rate,
+            "lds_atomic_peak": LDS_ATOMIC_PEAK, "lds_atomic_frac": rate / LDS_ATOMIC_PEAK,
+            "hbm_read_bytes": read, "hbm_written_bytes": written,
+            "hbm_GBps": (read + written) / (hist_ms * 1e-3) / 1e9,
+            "count_flush_GBps": written / (hist_ms * 1e-3) / 1e9,
+            "kernel": "count_tiles (one layer group, one stream)"}
+
+
+def alg_slots_pair(d: int, Nk: int, Nk1: int, guide_k: int = 2) -> float:
     """Algorithmic lane-slots of one pair from layer k (Nk points) to k+1:
-    1-D as ALG_SLOTS_PER_PAIR with the two search depths of these sizes,
-    d = 2 as ALG_SLOTS_2D_PAIR plus 2.5 per grid point of both layers."""
+    1-D with guide-table searches adding guide_k midpoints (guide_k < 0: the
+    breadth-first binary search of the layers' depths), d = 2 as
+    ALG_SLOTS_2D_PAIR plus ND_POINT per grid point of both layers."""
     if d == 1:
-        depth = sum(max(0, int(np.ceil(np.log2(max(Nv, 1))))) for Nv in (Nk, Nk1))
-        return 30 + 71 + 3 + 1 + 3 * depth
+        if guide_k >= 0:
+            search = 2 * guide_search(guide_k)
+        else:
+            search = BFS_STEP * sum(max(0, int(np.ceil(np.log2(max(Nv, 1)))))
+                                    for Nv in (Nk, Nk1))
+        return PHILOX_CALL // 2 + BOX_MULLER + 3 * F + search + KEY_INCR
     return ALG_SLOTS_2D_PAIR + ALG_SLOTS_2D_POINT * (Nk + Nk1)
 
 
-def run_c3(args):
+C3_LAYERS, C3_SHAPE, C3_M = 30, (40, 50), 10_000_000
+
+
+def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict:
     """2-D max-call state, n = 30, N = 2000 (40 x 50 product of Lloyd grids
     mapped by sqrt(t_k) chol(R)), rho = 0.3, M = 1e7 pairs per layer; BDP of
-    the American and European max-call (sigma 0.2 / 0.3)."""
+    the American and European max-call (sigma 0.2 / 0.3).  One step = the
+    forward (sampling and histogram passes), the obstacles and the BDP."""
     import torch
     import paper_1101_3228_amd as qt
     import synth
     torch.cuda.set_device(0)
-    n, M = 30, 10_000_000
+    n, M = C3_LAYERS, C3_M
     spec = synth.bm_model(2, n, T=MATURITY, rho=0.3)
-    grid, N = synth.layer_grids(spec, [1] + [(40, 50)] * n, base=qt.gauss_quantizer)
+    grid, N = synth.layer_grids(spec, [1] + [C3_SHAPE] * n, base=qt.gauss_quantizer)
     plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M)
-    if args.groups:
-        plan.tune(groups=args.groups)
     counts = plan.new_counts()
+    if groups:
+        plan.tune(groups=groups)
+        tuning = {"fixed": plan.tuning()}
+    else:
+        tuning = plan.autotune(M, seed=0x5EED00FF, counts=counts)
     s_fwd = torch.cuda.current_stream()
-    ev_keys = torch.cuda.Event(enable_timing=True)
-    ev_keys.record(s_fwd)
 
     def step(i, ev=None):
         if ev is not None:
             ev[0].record(s_fwd)
         plan.transitions(M, 0x5EED0000 + i, counts=counts, stream=s_fwd)
         if ev is not None:
-            ev[1].record(s_fwd)
+            ev[2].record(s_fwd)
         phi = plan.payoff_batch([qt.MAX_CALL, qt.MAX_CALL | qt.EUROPEAN], S0, S0, RATE,
                                 MATURITY, [[0.2, 0.3], [0.2, 0.3]], stream=s_fwd)
         return plan.bdp(counts, phi, want_v0=False, stream=s_fwd)[1]
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step(i)
     torch.cuda.synchronize()
-    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
     for e in evs:
         e[1].record(s_fwd)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(s_fwd)
-    for i in range(args.steps):
+    for i in range(steps):
         plan.trace(evs[i][1])
-        V = step(i, (evs[i][0], evs[i][2]))
+        V = step(i, evs[i])
     plan.trace(None)
     t1.record(s_fwd)
     torch.cuda.synchronize()
-    ms_step = t0.elapsed_time(t1) / args.steps
+    ms_step = t0.elapsed_time(t1) / steps
     keys_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     fwd_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in evs]))
     pairs = n * M
     points = sum(int(N[k]) + int(N[k + 1]) for k in range(n)) * M
     alg = ALG_SLOTS_2D_PAIR * pairs + ALG_SLOTS_2D_POINT * points
     achieved = alg / (keys_ms * 1e-3)
+    alg_unw = (60 + 142 + 12 + 2) * pairs + 2.5 * points   # every op 1
     V0 = V[:, 0].cpu().numpy()
     out = {
-        "metric": "MC transition samples/s (cell search+count)",
-        "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 samples, int32 counts, f64 BDP", "data": "synthetic",
-        "config": {"workload": "2-D max-call tree, time-layer parallel: n=30 layers, "
-                               "N=2000 (40x50 Lloyd product) points/layer, M=1e7 pairs/layer",
-                   "layers": n, "points_per_layer": 2000, "pairs_per_layer": M},
-        "forward_ms": fwd_ms, "sampling_pass_ms": keys_ms,
+        "workload": "2-D max-call tree, time-layer parallel: n=30 layers, N=2000 (40x50 "
+                    "Lloyd product) points/layer, M=1e7 pairs/layer",
+        "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "steps": steps,
+        "ms_per_step": ms_step, "forward_ms": fwd_ms, "sampling_pass_ms": keys_ms,
+        "histogram_pass_ms": fwd_ms - keys_ms,
         "paper_convention_gflops": 6.0 * points / (keys_ms * 1e-3) / 1e9,
         "V0_american_european": [float(V0[0]), float(V0[1])],
+        "tuning": tuning,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS,
                      "traffic": _measured_traffic("fwd_keys_nd"),
-                     "kernel": "fwd_keys_nd<2, 8>"},
+                     "kernel": "fwd_keys_nd<2, 8>",
+                     "alg_slots_per_pair_avg": alg / pairs,
+                     "frac_unweighted": alg_unw / (keys_ms * 1e-3) / PEAK_SLOTS},
     }
+    if with_cpu:
+        import oracle as O
+        Mc = 20_000
+        threads = min(os.cpu_count() or 1, n)
+        mdl = O.Model(spec["d"], spec["n"], spec["A"], spec["b"], spec["T"], spec["mu"],
+                      spec["L"], spec["x0"])
+        tc = time.perf_counter()
+        O.transitions(mdl, grid, N, Mc, seed=0x5EED0000, nthreads=threads)
+        dt = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": Mc * n / dt, "unit": "pairs/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"all {n} layers x {Mc} pairs ({Mc * n:.3g} pairs, "
+                                         f"{dt:.1f} s)"}
+    return out
+
+
+def run_c3(args):
+    """The 2-D workload as its own line (see measure_c3)."""
+    r = measure_c3(args.steps, args.warmup, not args.no_cpu_baseline, args.groups)
+    out = {
+        "metric": "MC transition samples/s (cell search+count)",
+        "value": r["value"], "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, int32 counts, f64 BDP", "data": "synthetic",
+        "config": {"workload": r["workload"], "layers": C3_LAYERS, "points_per_layer": 2000,
+                   "pairs_per_layer": C3_M},
+    }
+    out.update({k: v for k, v in r.items() if k not in ("workload", "value", "unit", "steps",
+                                                        "ms_per_step")})
     print(json.dumps(out), flush=True)
 
 
@@ -781,9 +910,10 @@ def run_rng(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     est = 4.0 * inside.cpu().numpy().astype(np.float64) / npts
-    # Philox call (10 rounds x (2 mad + 4 xor)) + two points x (2 shifts, 2
-    # 48-bit squares, 64-bit add, compare, count)
-    slots = 60 + 2 * 7
+    # one Philox call + two points x (two shifts 2F, two 48-bit squares as
+    # 32x32->64 products 2H, the 64-bit sum 2F, the 64-bit compare H, the
+    # count F)
+    slots = PHILOX_CALL + 2 * (5 * F + 3 * H)
     achieved = slots * (npts / 2) * reps / (ms * 1e-3)
     print(json.dumps({
         "metric": "Philox points/s (quarter-disc experiment)", "value": npts * reps / (ms * 1e-3),
@@ -796,7 +926,7 @@ def run_rng(args):
         "paper_context_gtx480_s_per_1e9": {"drand48": 0.2562, "MRG32k3a": 0.2573, "XORWOW": 0.2085},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
-                     "kernel": "pi_quarter_disc_kernel (74 lane-slots per Philox block)"},
+                     "kernel": f"pi_quarter_disc_kernel ({slots} lane-slots per Philox block)"},
     }), flush=True)
 
 
@@ -840,8 +970,9 @@ def run_nn(args):
         "runs": out, "paper_context_gtx480_s": {"N100": 0.09, "N250": 0.23, "N500": 0.41},
         "roofline": {"bound": "alu", "achieved": slots / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": slots / PEAK_SLOTS, "traffic": None,
-                     "kernel": "cells_kernel<2> at N = 500 (2.5 lane-slots per query and "
-                               "grid point: 2 FMA + half of a 3-input min)"},
+                     "kernel": "cells_kernel<2> at N = 500 (3 lane-slots per query and "
+                               "grid point: 2 FMA + half of a 3-input min at its issue "
+                               "cost)"},
     }), flush=True)
 
 
@@ -872,7 +1003,8 @@ def run_lloyd(args):
     ms = e0.elapsed_time(e1)
     dd = dist.cpu().numpy()
     value = M * steps / (ms * 1e-3)
-    alg = ALG_SLOTS_2D_POINT * N + 60 + 142 + 4      # search + Philox + two Box-Muller + L z
+    # search + Philox + two Box-Muller + L z (4 fma)
+    alg = ALG_SLOTS_2D_POINT * N + PHILOX_CALL + 2 * BOX_MULLER + 4 * F
     out = {
         "metric": "Lloyd samples/s (grid optimization, eq. Qerr)", "value": value,
         "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": ms / steps,
@@ -883,8 +1015,9 @@ def run_lloyd(args):
         "distortion_first_last": [float(dd[0]), float(dd[-1])],
         "roofline": {"bound": "alu", "achieved": alg * value / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": alg * value / PEAK_SLOTS, "traffic": None,
-                     "kernel": "lloyd_accum_kernel<2> (2.5 lane-slots per sample and grid "
-                               "point + 206 per sample)"},
+                     "kernel": f"lloyd_accum_kernel<2> ({ALG_SLOTS_2D_POINT} lane-slots per "
+                               f"sample and grid point + {alg - ALG_SLOTS_2D_POINT * N:.0f} per "
+                               "sample)"},
     }
     if not args.no_cpu_baseline:
         import oracle as O
@@ -897,11 +1030,12 @@ def run_lloyd(args):
     print(json.dumps(out), flush=True)
 
 
-# Algorithmic lane-slots of one stratified pair: one Philox call 60, one
-# Box-Muller 71, the normal quantile's central branch (two degree-7 Horner
-# polynomials, q^2, r, product and quotient) 45, u and p 6, AR(1) 3, one
-# 9-step search 27, the count 1.
-ALG_SLOTS_STRAT = 60 + 71 + 45 + 6 + 3 + 27 + 1
+# Algorithmic lane-slots of one stratified pair: one Philox call, one
+# Box-Muller, the normal quantile's central branch in FP64 (two degree-7
+# Horner polynomials, q^2, r, product and the quotient's reciprocal and two
+# Newton steps: 45 FP64 operations, each H), u and p (6 FP64 operations, H),
+# AR(1) 3F, one guide search (K = 2), index and increment.
+ALG_SLOTS_STRAT = PHILOX_CALL + BOX_MULLER + 45 * H + 6 * H + 3 * F + guide_search(2) + KEY_INCR
 
 
 def run_strat(args):

@@ -140,15 +140,33 @@ int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
  *                        two host threads at once.
  *   QTREE_TUNE_ND_SAMPLES : d >= 2 two-pass sampling: samples per lane that
  *                        share each grid record read from LDS, 8 (default) or 4.
+ *   QTREE_TUNE_TAIL    : with layer groups, the last group's share of the
+ *                        layers in percent of each other group's (10..100,
+ *                        default 100: equal groups); its histogram pass is
+ *                        the one no sampling pass overlaps.
  */
 typedef enum {
   QTREE_TUNE_CHUNK = 0,
   QTREE_TUNE_XCD_MAP = 1,
   QTREE_TUNE_COUNT = 2,
   QTREE_TUNE_GROUPS = 3,
-  QTREE_TUNE_ND_SAMPLES = 4
+  QTREE_TUNE_ND_SAMPLES = 4,
+  QTREE_TUNE_TAIL = 5
 } qtree_tune_key;
 qtree_status qtree_plan_tune(qtree_plan *plan, int32_t key, int64_t value);
+/* Current value of a tuning key (-1 for a NULL plan or an unknown key). */
+int64_t qtree_plan_get_tune(const qtree_plan *plan, int32_t key);
+/* Autotuner of a plan's LAYERWISE forward: times, with HIP events on
+ * `stream`, one forward of M samples per layer (seed `seed`, contract 0,
+ * written to `counts`, device int32 [entries]) under each candidate --
+ * d = 1: one layer group, or 2, 4, 6 groups with the last at 100, 50 or 33
+ * percent of the others; d >= 2: 8 or 4 samples per lane, 1 or 2 groups --
+ * three runs each (the fastest counts) after one warm-up, and sets the
+ * fastest (QTREE_TUNE_GROUPS, _TAIL,
+ * _ND_SAMPLES).  *best_ms (may be NULL) receives its time.  Blocks the
+ * host until the timings are in.  Counts never depend on the choice. */
+qtree_status qtree_plan_autotune(qtree_plan *plan, uint64_t M, uint64_t seed, int32_t *counts,
+                                 void *stream, double *best_ms);
 
 /* Monte Carlo transition counts p^k_ij (Sec. 3 Algorithm I/II, Sec. 4
  * Algorithm III) over samples m = m0 .. m0+M-1.

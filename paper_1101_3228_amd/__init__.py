@@ -188,8 +188,14 @@ class Plan:
         return self._h
 
     def tune(self, chunk: int | None = None, xcd_map: int | None = None,
-             count: int | None = None, groups: int | None = None):
-        """Launch tuning (QTREE_TUNE_CHUNK / _XCD_MAP / _COUNT / _GROUPS); results unchanged."""
+             count: int | None = None, groups: int | None = None,
+             nd_samples: int | None = None, tail: int | None = None):
+        """Launch tuning (QTREE_TUNE_CHUNK / _XCD_MAP / _COUNT / _GROUPS /
+        _ND_SAMPLES / _TAIL); results unchanged."""
+        if nd_samples is not None:
+            _check(lib().qtree_plan_tune(self._h, 4, int(nd_samples)))
+        if tail is not None:
+            _check(lib().qtree_plan_tune(self._h, 5, int(tail)))
         if chunk is not None:
             _check(lib().qtree_plan_tune(self._h, 0, int(chunk)))
         if xcd_map is not None:
@@ -199,6 +205,29 @@ class Plan:
         if groups is not None:
             _check(lib().qtree_plan_tune(self._h, 3, int(groups)))
         return self
+
+    def autotune(self, M: int, seed: int = 1, counts=None, stream=None) -> dict:
+        """qtree_plan_autotune: time the candidate forward configurations and
+        keep the fastest; returns it with its time."""
+        if counts is None:
+            counts = self.new_counts()
+        ms = ctypes.c_double(0.0)
+        L = lib()
+        L.qtree_plan_autotune.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.qtree_plan_autotune.restype = ctypes.c_int
+        _check(L.qtree_plan_autotune(self._h, int(M), int(seed), counts.data_ptr(),
+                                     _stream_handle(stream), ctypes.byref(ms)))
+        return {"ms": ms.value, **self.tuning()}
+
+    def tuning(self) -> dict:
+        """The plan's launch tuning (groups, tail share, samples per lane)."""
+        L = lib()
+        L.qtree_plan_get_tune.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.qtree_plan_get_tune.restype = ctypes.c_int64
+        return {"groups": int(L.qtree_plan_get_tune(self._h, 3)),
+                "tail": int(L.qtree_plan_get_tune(self._h, 5)),
+                "nd_samples": int(L.qtree_plan_get_tune(self._h, 4))}
 
     def count_offsets(self) -> np.ndarray:
         N = self.N.astype(np.int64)

@@ -495,6 +495,18 @@ static hipError_t ensure_aux(const qtree_plan* p, int groups) {
   return e;
 }
 
+// First layer of group g of `groups`: the first groups - 1 groups get equal
+// shares of the layers and the last a share tune_tail percent of theirs (its
+// histogram pass is the one no sampling pass overlaps).
+static int group_start(const qtree_plan* p, int groups, int g) {
+  if (g <= 0) return 0;
+  if (g >= groups) return p->n;
+  const int64_t w = 100 * (int64_t)(groups - 1) + p->tune_tail;  // total weight
+  int k = (int)((int64_t)p->n * 100 * g / w);
+  k = std::max(k, g);  // every group keeps at least one layer
+  return std::min(k, p->n - (groups - g));
+}
+
 // Two-pass forward over sample batches that fit the scratch.  The layers are
 // split into `groups`; with more than one, the histogram pass of group g runs
 // on the plan's stream while the sampling pass of group g + 1 runs on `s`
@@ -535,8 +547,8 @@ static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hip
     hipError_t e = hipSuccess;
     if (groups > 1 && lo > a.m0) e = hipStreamWaitEvent(s, p->join, 0);  // scratch reuse
     for (int g = 0; g < groups && e == hipSuccess; ++g) {
-      const int k0 = (int)((int64_t)p->n * g / groups);
-      const int k1 = (int)((int64_t)p->n * (g + 1) / groups);
+      const int k0 = group_start(p, groups, g);
+      const int k1 = group_start(p, groups, g + 1);
       qtree::FwdArgs c = b;
       c.layer0 = k0;
       c.units = (k1 - k0) * b.chunks;
@@ -636,6 +648,11 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
     if (value < 0 || value > qtree_plan::kMaxGroups)
       return fail(QTREE_EINVAL, "groups must be in 0..8");
     plan->tune_groups = (int32_t)value;
+    return QTREE_OK;
+  }
+  if (key == QTREE_TUNE_TAIL) {
+    if (value < 10 || value > 100) return fail(QTREE_EINVAL, "tail share must be 10..100");
+    plan->tune_tail = (int32_t)value;
     return QTREE_OK;
   }
   if (key == QTREE_TUNE_ND_SAMPLES) {
@@ -746,6 +763,81 @@ qtree_status qtree_transitions_add(const qtree_plan* plan, uint64_t m0, uint64_t
                                    uint32_t contract_id, qtree_mode mode, int32_t* counts,
                                    void* stream) {
   return transitions_impl(plan, m0, M, seed, contract_id, mode, counts, stream, false);
+}
+
+int64_t qtree_plan_get_tune(const qtree_plan* plan, int32_t key) {
+  if (!plan) return -1;
+  switch (key) {
+    case QTREE_TUNE_CHUNK: return plan->tune_chunk;
+    case QTREE_TUNE_XCD_MAP: return plan->tune_xcd_map;
+    case QTREE_TUNE_COUNT: return plan->tune_count;
+    case QTREE_TUNE_GROUPS: return plan->tune_groups;
+    case QTREE_TUNE_ND_SAMPLES: return plan->tune_nd_samples;
+    case QTREE_TUNE_TAIL: return plan->tune_tail;
+  }
+  return -1;
+}
+
+qtree_status qtree_plan_autotune(qtree_plan* plan, uint64_t M, uint64_t seed, int32_t* counts,
+                                 void* stream, double* best_ms) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (!counts) return fail(QTREE_EINVAL, "counts is NULL");
+  if (M < 1 || M >= (1ull << 31)) return fail(QTREE_EOVERFLOW, "M must be in 1 .. 2^31 - 1");
+  // candidates: (groups, tail share, samples per lane)
+  struct Cand {
+    int groups, tail, nds;
+  };
+  std::vector<Cand> cand;
+  if (plan->d == 1) {
+    cand.push_back({1, 100, 8});
+    for (int g : {2, 4, 6})
+      for (int t : {100, 50, 33}) cand.push_back({g, t, 8});
+  } else {
+    for (int nds : {8, 4})
+      for (int g : {1, 2}) cand.push_back({g, 100, nds});
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t keep_g = plan->tune_groups, keep_t = plan->tune_tail,
+                keep_s = plan->tune_nd_samples;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  double best = -1.0;
+  Cand win = cand[0];
+  qtree_status st = QTREE_OK;
+  // one warm-up run, then every candidate kReps times (its fastest run counts)
+  constexpr int kReps = 3;
+  for (size_t i = 0; i <= cand.size() * kReps && e == hipSuccess && st == QTREE_OK; ++i) {
+    const Cand c = cand[i == 0 ? 0 : (i - 1) / kReps];
+    plan->tune_groups = c.groups;
+    plan->tune_tail = c.tail;
+    plan->tune_nd_samples = c.nds;
+    e = hipEventRecord(e0, s);
+    if (e != hipSuccess) break;
+    st = transitions_impl(plan, 0, M, seed, 0, QTREE_LAYERWISE, counts, stream, true);
+    if (st != QTREE_OK) break;
+    e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && i > 0 && (best < 0.0 || ms < best)) {
+      best = ms;
+      win = c;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != QTREE_OK || e != hipSuccess) {
+    plan->tune_groups = keep_g;
+    plan->tune_tail = keep_t;
+    plan->tune_nd_samples = keep_s;
+    return st != QTREE_OK ? st : hip_fail(e, "autotune timing");
+  }
+  plan->tune_groups = win.groups;
+  plan->tune_tail = win.tail;
+  plan->tune_nd_samples = win.nds;
+  if (best_ms) *best_ms = best;
+  return QTREE_OK;
 }
 
 // Samples of row i of layer k (the rule of the device kernel).

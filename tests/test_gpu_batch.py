@@ -131,3 +131,57 @@ def test_batch_counts_identical_under_every_configuration():
             assert np.allclose(V0, ref_v0, rtol=1e-12, atol=0), code
     with pytest.raises(qt.QtreeError):
         batch.set_config(1 << 20)
+
+
+@pytest.mark.timeout(900)
+def test_c4_full_batch_equals_one_plan_at_a_time():
+    """The full batched workload: 256 contracts (d alternating 1 / 2, n in
+    [10, 100], N_k in [50, 2000], M = 1e6 pairs per layer each, two payoffs
+    each), one batched run.  Every contract's counts equal a single-plan
+    forward bit for bit (compared on the device), every V_0 agrees within
+    1e-12 relative, and the cheapest 1-D and 2-D contracts equal the oracle."""
+    print("[gpu-case] C4 full batch", flush=True)
+    specs = synth.batch_contracts(256, M=1_000_000)
+    qcache = {}
+
+    def q(Nv):
+        if Nv not in qcache:
+            qcache[Nv] = qt.gauss_quantizer(Nv)
+        return qcache[Nv]
+    items = []
+    for i, sp in enumerate(specs):
+        model = synth.bm_model(sp["d"], sp["n"], T=sp["T"], rho=sp["rho"])
+        grid, N = synth.layer_grids(model, sp["sizes"], base=q)
+        plan = qt.Plan(model, grid, N, batch_samples=1)
+        kinds = [qt.PUT, qt.PUT | qt.EUROPEAN] if sp["d"] == 1 else \
+            [qt.MAX_CALL, qt.MAX_CALL | qt.EUROPEAN]
+        phi = plan.payoff_batch(kinds, 100.0, 100.0 * sp["K_over_S0"], sp["r"], sp["T"],
+                                [[sp["sigma"], sp["sigma"] * 1.2]] * 2)
+        items.append(dict(plan=plan, M=sp["M"], seed=synth.SEED_BASE + i, contract_id=i,
+                          counts=plan.new_counts(), phi=phi, V=torch.empty_like(phi),
+                          model=model, grid=grid, N=N, d=sp["d"]))
+    batch = qt.Batch(items, scratch_bytes=40 << 30)
+    V0 = batch.run()
+    print(f"[gpu-case] C4 batch ran: {batch.info()}", flush=True)
+    tmp = torch.empty(max(it["plan"].entries for it in items) + 4, dtype=torch.int32,
+                      device="cuda")
+    at = 0
+    big2d = 0
+    for it in items:
+        plan, e = it["plan"], it["plan"].entries
+        c = plan.transitions(it["M"], it["seed"], contract=it["contract_id"], counts=tmp)
+        assert torch.equal(c[:e], it["counts"][:e]), it["contract_id"]
+        v, _ = plan.bdp(c, it["phi"])
+        assert np.allclose(V0[at:at + v.size], v, rtol=1e-12, atol=0), it["contract_id"]
+        at += v.size
+        big2d += it["d"] == 2 and int(np.max(it["N"])) >= 1000
+    assert big2d >= 10
+    cost = [(it["plan"].n * int(np.max(it["N"])) ** it["d"], j) for j, it in enumerate(items)]
+    for dim in (1, 2):
+        j = min(cj for cj in cost if items[cj[1]]["d"] == dim)[1]
+        it = items[j]
+        sp = it["model"]
+        mdl = O.Model(sp["d"], sp["n"], sp["A"], sp["b"], sp["T"], sp["mu"], sp["L"], sp["x0"])
+        ref = O.transitions(mdl, it["grid"], it["N"], it["M"], seed=it["seed"],
+                            contract=it["contract_id"], nthreads=16)
+        assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), ref), j

@@ -202,7 +202,7 @@ def test_surrogate_learns_tree_prices_and_falls_back():
     assert np.array_equal(yp[~inside], yte[~inside])           # the tree, exactly
     err = _r19(yp[inside], yte[inside])
     print(f"R19 error: mean {err.mean():.2e} p99 {np.quantile(err, 0.99):.2e}", flush=True)
-    assert np.median(err) < 1e-2
+    assert np.median(err) < 1e-2     # a short training run; the full-size gate is below
     # what the network gains: the same in-box queries, network against tree
     import time
     xin = torch.from_numpy(xte[inside]).cuda()
@@ -220,3 +220,29 @@ def test_surrogate_learns_tree_prices_and_falls_back():
     print(f"options/s: network {inside.sum() / t_net:.3e}, tree {inside.sum() / t_tree:.3e}",
           flush=True)
     assert t_tree > 10 * t_net
+
+
+@pytest.mark.timeout(900)
+def test_c5_surrogate_accuracy_at_full_size():
+    """The surrogate at the learned-part workload's size: labels from 1e5
+    tree solves (N = 100 points per layer, M = 2e6 pairs per layer, n in
+    [10, 100]), 6000 epochs of training (the benchmark's setting), then the
+    held-out in-box error against the tree, |y - t| / max(t, 1e-2) in units
+    of K: its mean must be at most 1e-3; the median, p99 and the share of
+    queries within 1e-3 are printed."""
+    _case("C5 surrogate accuracy, full size")
+    pricer = S.PutTreePricer(N=100, M=2_000_000)
+    xtr = synth.box_queries(100_000, 0x5EED0000)
+    ytr = pricer.price(xtr)
+    sur = S.Surrogate(pricer, LO, HI, synth.mlp_init(0x5EED0001), out_scale=0.05,
+                      act_terms=1, max_batch=4096, baseline=1)
+    sur.fit(xtr, ytr, epochs=6000, lr=2e-3, lr_final=1e-6)
+    xte = synth.box_queries(20_000, 0x5EED0002)
+    yte = pricer.price(xte)
+    yp, used = sur.price(xte)
+    assert not used.any()
+    err = _r19(yp, yte)
+    print(f"[gpu-case] C5 R19 error: mean {err.mean():.2e} median {np.median(err):.2e} "
+          f"p99 {np.quantile(err, 0.99):.2e} max {err.max():.2e} "
+          f"within 1e-3 {np.mean(err <= 1e-3):.3f}", flush=True)
+    assert err.mean() <= 1e-3

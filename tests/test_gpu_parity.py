@@ -263,11 +263,13 @@ def test_c2_layerwise_full_size():
     assert np.allclose(V0, rV0, rtol=1e-9, atol=0)
 
 
-def test_c3_2d_full_size_sampled():
+def test_c3_2d_full_size():
     """2-D max-call state, n = 30, N = 2000 (40 x 50 product of Lloyd grids
-    mapped by sqrt(t_k) chol(R)), M = 1e7 pairs per layer: every layer sums
-    to M; 4096 random samples of three layers checked one by one (sample and
-    both cells); the first layer recomputed in full by the oracle."""
+    mapped by sqrt(t_k) chol(R)), M = 1e7 pairs per layer, in the benchmark's
+    launch configuration: every layer sums to M; the first, a middle and the
+    last layer recomputed in full by the oracle and compared count by count
+    (4e6 counts each for the later two); 4096 random samples of three layers
+    checked one by one (sample and both cells)."""
     _print_case("C3 full")
     n, M = 30, 10_000_000
     spec = synth.bm_model(2, n, T=1.0, rho=0.3)
@@ -299,8 +301,9 @@ def test_c3_2d_full_size_sampled():
         # every sampled transition is present in the counts
         blk = got[off[k]:off[k + 1]].reshape(N[k], N[k + 1])
         assert np.all(blk[ci, cj] > 0)
-    ref0 = O.layer_counts_one(mdl, grid, N, 0, M, seed=synth.SEED_BASE, nthreads=THREADS)
-    assert np.array_equal(got[off[0]:off[1]].reshape(N[0], N[1]), ref0)
+    for k in (0, 15, n - 1):
+        ref = O.layer_counts_one(mdl, grid, N, k, M, seed=synth.SEED_BASE, nthreads=THREADS)
+        assert np.array_equal(got[off[k]:off[k + 1]].reshape(N[k], N[k + 1]), ref), k
 
 
 def test_chunked_accumulation_equals_one_call(small_case):
@@ -414,3 +417,25 @@ def test_zero_midpoint_and_signed_zero_samples():
     assert np.array_equal(counts, ref)
     # every sample sits at a zero, below no midpoint: all mass in cell 0 -> 0
     assert counts[0] == 40_001 and counts[1:3].sum() == 0
+
+
+@pytest.mark.parametrize("name", ["bm1", "bm2"])
+def test_autotune_choice_and_every_candidate_give_the_same_counts(name):
+    """qtree_plan_autotune times the candidate layer-group / tail /
+    samples-per-lane configurations and keeps one; the counts under the
+    chosen and under every candidate equal the oracle's."""
+    _print_case(f"plan autotune {name}")
+    spec = MODELS[name]()
+    grid, N = synth.layer_grids(spec, SHAPES[name])
+    plan = _plan(spec, grid, N)
+    M, seed = 90_001, 0x5EED0071
+    ref = O.transitions(_omodel(spec), grid, N, M, seed=seed, contract=3, nthreads=THREADS)
+    got = plan.autotune(M, seed=seed)
+    assert got["ms"] > 0.0
+    assert np.array_equal(plan.transitions(M, seed, contract=3).cpu().numpy(), ref)
+    cands = ([(1, 100, 8)] + [(g, t, 8) for g in (2, 4, 6) for t in (100, 50, 33)]
+             if spec["d"] == 1 else [(g, 100, s) for s in (8, 4) for g in (1, 2)])
+    assert (got["groups"], got["tail"], got["nd_samples"]) in cands
+    for g, t, s in cands:
+        plan.tune(groups=g, tail=t, nd_samples=s)
+        assert np.array_equal(plan.transitions(M, seed, contract=3).cpu().numpy(), ref), (g, t, s)
