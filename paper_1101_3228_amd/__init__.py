@@ -66,13 +66,11 @@ def lib() -> ctypes.CDLL:
         getattr(L, f).restype = i64
     L.qtree_transitions.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
     L.qtree_transitions_add.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
-    L.qtree_transitions_noalloc.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
     L.qtree_pi_workspace_size.argtypes = [P, P]
     L.qtree_pi.argtypes = [P, P, P, ctypes.c_size_t, P]
     L.qtree_bdp_many.argtypes = [P, P, ctypes.c_size_t, i64, P, P, P]
     for f in ("qtree_pi_workspace_size", "qtree_pi", "qtree_bdp_many"):
         getattr(L, f).restype = ctypes.c_int
-    L.qtree_transitions_noalloc.restype = ctypes.c_int
     L.qtree_transitions_add.restype = ctypes.c_int
     L.qtree_bdp.argtypes = [P, P, P, i32, P, P, P]
     L.qtree_payoff.argtypes = [P, i32, f64, f64, f64, f64, P, P, P, P]
