@@ -377,6 +377,59 @@ def lloyd_samples(d: int, L, seed: int, it: int, count: int, fresh: bool = True)
     return out
 
 
+def sample_moments(d: int, x: np.ndarray):
+    """Exact integer moment sums of the admissible samples (finite, within
+    [-64, 64]): returns (count, s1 int64[d], s2 int64[d][d])."""
+    Lib = lib()
+    P = ctypes.c_void_p
+    Lib.oracle_sample_moments.argtypes = [ctypes.c_int32, P, ctypes.c_int64, P, P]
+    Lib.oracle_sample_moments.restype = ctypes.c_int64
+    xv = np.ascontiguousarray(np.asarray(x, np.float32).reshape(-1, d))
+    s1 = np.zeros(d, np.int64)
+    s2 = np.zeros((d, d), np.int64)
+    cnt = Lib.oracle_sample_moments(d, _ptr(xv), xv.shape[0], _ptr(s1), _ptr(s2))
+    return int(cnt), s1, s2
+
+
+def moment_grid(d: int, x: np.ndarray, base: np.ndarray):
+    """Moment-matching grid (Sec. 2): base [N][d] mapped by the sample mean
+    and the Cholesky factor of the sample covariance of x [M][d].  Returns
+    (grid float32 [N][d], mean [d], cov [d][d], chol [d][d], count)."""
+    Lib = lib()
+    P = ctypes.c_void_p
+    Lib.oracle_moment_map.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, ctypes.c_int32,
+                                      P, P]
+    Lib.oracle_moment_map.restype = None
+    cnt, s1, s2 = sample_moments(d, x)
+    b = np.ascontiguousarray(np.asarray(base, np.float32).reshape(-1, d))
+    grid = np.zeros_like(b)
+    mom = np.zeros(d + 2 * d * d, np.float64)
+    Lib.oracle_moment_map(d, cnt, _ptr(s1), _ptr(s2), _ptr(b), b.shape[0], _ptr(grid),
+                          _ptr(mom))
+    return (grid, mom[:d], mom[d:d + d * d].reshape(d, d), mom[d + d * d:].reshape(d, d), cnt)
+
+
+def lloyd_empirical(d: int, grid: np.ndarray, x: np.ndarray, batch: int, steps: int,
+                    gamma: float = 1.0):
+    """Lloyd steps (gamma = 1) or relaxed steps (0 < gamma < 1) of eq. Qerr on
+    windows of `batch` samples of x [M][d].  Returns (grid float32 [N][d],
+    distortion float64 [steps], rejected samples)."""
+    Lib = lib()
+    P = ctypes.c_void_p
+    Lib.oracle_lloyd_empirical.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P, P]
+    Lib.oracle_lloyd_empirical.restype = ctypes.c_int
+    g = np.ascontiguousarray(np.asarray(grid, np.float32).reshape(-1, d)).copy()
+    xv = np.ascontiguousarray(np.asarray(x, np.float32).reshape(-1, d))
+    dist = np.zeros(max(steps, 1), np.float64)
+    rej = np.zeros(1, np.int64)
+    rc = Lib.oracle_lloyd_empirical(d, g.shape[0], _ptr(g), _ptr(xv), xv.shape[0], int(batch),
+                                    int(steps), float(gamma), _ptr(dist), _ptr(rej))
+    if rc != 0:
+        raise MemoryError("oracle_lloyd_empirical")
+    return g, dist[:steps], int(rej[0])
+
+
 def _strat_setup():
     Lib = lib()
     if getattr(Lib, "_strat", False):

@@ -752,6 +752,122 @@ int oracle_lloyd(int32_t d, int32_t N, const float *L, float *grid, uint64_t M, 
 }
 
 /* ------------------------------------------------------------------ */
+/* Grids from samples of a marginal of any law.  Sec. 2 uses optimal     */
+/* grids of Gaussian marginals and, otherwise, sub-optimal grids that    */
+/* match the first two moments of X_k.  The moment-matching grid here    */
+/* maps a standard grid `base` (for instance an N(0, I_d) quantizer) by  */
+/* the sample mean and the Cholesky factor of the sample covariance.     */
+/* The Lloyd map of eq. Qerr (every point to the mean of its Voronoi     */
+/* cell) is applied to windows of a caller's sample set; gamma < 1 moves */
+/* each point only that fraction of the way (the batch form of the       */
+/* competitive-learning step toward the cell's samples).                 */
+/* ------------------------------------------------------------------ */
+static int sample_admissible(const float *x, int d) {
+  for (int c = 0; c < d; ++c)
+    if (!(fabsf(x[c]) <= 64.0f)) return 0; /* also false for NaN */
+  return 1;
+}
+
+int64_t oracle_sample_moments(int32_t d, const float *x, int64_t M, int64_t *s1, int64_t *s2) {
+  int64_t cnt = 0;
+  for (int c = 0; c < d; ++c) s1[c] = 0;
+  for (int c = 0; c < d * d; ++c) s2[c] = 0;
+  for (int64_t m = 0; m < M; ++m) {
+    const float *xm = x + (size_t)m * d;
+    if (!sample_admissible(xm, d)) continue;
+    cnt += 1;
+    for (int r = 0; r < d; ++r) {
+      s1[r] += fixed_scaled((double)xm[r], 0x1p24);
+      for (int c = 0; c < d; ++c)
+        s2[r * d + c] += fixed_scaled((double)xm[r] * (double)xm[c], 0x1p16);
+    }
+  }
+  return cnt;
+}
+
+void oracle_moment_map(int32_t d, int64_t count, const int64_t *s1, const int64_t *s2,
+                       const float *base, int32_t N, float *grid, double *moments) {
+  double mean[3] = {0.0, 0.0, 0.0}, cov[9] = {0.0}, chol[9] = {0.0};
+  if (count > 0) {
+    for (int r = 0; r < d; ++r) mean[r] = ((double)s1[r] * 0x1p-24) / (double)count;
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c)
+        cov[r * d + c] = ((double)s2[r * d + c] * 0x1p-16) / (double)count - mean[r] * mean[c];
+  }
+  /* lower Cholesky factor, column by column; a non-positive pivot (a
+     degenerate direction) gives a zero column */
+  for (int r = 0; r < d; ++r) {
+    for (int c = 0; c <= r; ++c) {
+      double v = cov[r * d + c];
+      for (int q = 0; q < c; ++q) v = v - chol[r * d + q] * chol[c * d + q];
+      if (r == c) chol[r * d + c] = v > 0.0 ? sqrt(v) : 0.0;
+      else chol[r * d + c] = chol[c * d + c] > 0.0 ? v / chol[c * d + c] : 0.0;
+    }
+  }
+  for (int32_t i = 0; i < N; ++i) {
+    for (int r = 0; r < d; ++r) {
+      double v = mean[r];
+      for (int c = 0; c <= r; ++c) v = v + chol[r * d + c] * (double)base[(size_t)i * d + c];
+      grid[(size_t)i * d + r] = (float)v;
+    }
+  }
+  if (moments) {
+    for (int r = 0; r < d; ++r) moments[r] = mean[r];
+    for (int c = 0; c < d * d; ++c) {
+      moments[d + c] = cov[c];
+      moments[d + d * d + c] = chol[c];
+    }
+  }
+}
+
+int oracle_lloyd_empirical(int32_t d, int32_t N, float *grid, const float *x, int64_t M,
+                           int64_t batch, int32_t steps, double gamma, double *distortion,
+                           int64_t *rejected) {
+  int64_t *sum = (int64_t *)calloc((size_t)N * d, sizeof(int64_t));
+  int64_t *cnt = (int64_t *)calloc((size_t)N, sizeof(int64_t));
+  if (!sum || !cnt) { free(sum); free(cnt); return -1; }
+  int64_t bad = 0;
+  for (int32_t t = 0; t < steps; ++t) {
+    memset(sum, 0, sizeof(int64_t) * (size_t)N * d);
+    memset(cnt, 0, sizeof(int64_t) * (size_t)N);
+    int64_t dist = 0, used = 0;
+    layer_grid lg;
+    layer_grid_init(&lg, grid, N, d);
+    const int64_t start = (int64_t)(((uint64_t)t * (uint64_t)batch) % (uint64_t)M);
+    for (int64_t j = 0; j < batch; ++j) {
+      const int64_t m = (start + j) % M;
+      const float *xm = x + (size_t)m * d;
+      if (!sample_admissible(xm, d)) { bad += 1; continue; }
+      const int32_t i = layer_cell(&lg, xm);
+      const float *g = grid + (size_t)i * d;
+      double d2 = 0.0;
+      for (int c = 0; c < d; ++c) {
+        const double dx = (double)xm[c] - (double)g[c];
+        d2 = d2 + dx * dx;
+        sum[(size_t)i * d + c] += fixed_scaled((double)xm[c], 0x1p24);
+      }
+      cnt[i] += 1;
+      used += 1;
+      dist += fixed_scaled(d2, 0x1p16);
+    }
+    free(lg.aux);
+    if (distortion) distortion[t] = used > 0 ? ((double)dist * 0x1p-16) / (double)used : 0.0;
+    for (int32_t i = 0; i < N; ++i) {
+      if (cnt[i] == 0) continue;
+      for (int c = 0; c < d; ++c) {
+        const double mean = ((double)sum[(size_t)i * d + c] * 0x1p-24) / (double)cnt[i];
+        const double g = (double)grid[(size_t)i * d + c];
+        grid[(size_t)i * d + c] = gamma == 1.0 ? (float)mean : (float)(g + gamma * (mean - g));
+      }
+    }
+  }
+  if (rejected) *rejected = bad;
+  free(sum);
+  free(cnt);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Stratified time-layer estimate (not in the paper): the samples of     */
 /* X_k are drawn cell by cell from the marginal conditioned on the cell. */
 /* ------------------------------------------------------------------ */

@@ -123,6 +123,30 @@ void oracle_lloyd_sample(int32_t d, const float *L, uint64_t seed, int32_t fresh
 int oracle_lloyd(int32_t d, int32_t N, const float *L, float *grid, uint64_t M, int32_t iters,
                  uint64_t seed, int32_t fresh, double *distortion);
 
+/* Grids from samples of a marginal of any law (Sec. 2: grids matching the
+   first two moments of X_k when no optimal grid is available; the Lloyd
+   stationarity condition of eq. Qerr on an empirical measure).  A sample is
+   admissible when every coordinate is finite and within [-64, 64]; the
+   others are skipped and counted.
+   oracle_sample_moments: exact integer sums s1[c] = sum rint(x_c 2^24),
+     s2[r d + c] = sum rint(x_r x_c 2^16) over the admissible samples of
+     x[M][d]; returns their number.
+   oracle_moment_map: mean, covariance and lower Cholesky factor (FP64) from
+     those sums, and grid[i] = mean + chol base[i] (FP64, rounded once);
+     moments[d + 2 d d] = mean, covariance, factor.
+   oracle_lloyd_empirical: `steps` steps over windows of `batch` samples
+     (step t takes samples (t batch + j) mod M, j < batch): cells by the
+     tree's rule, exact cell sums, new point = mean (gamma == 1) or
+     g + gamma (mean - g) (0 < gamma < 1), a cell without samples keeps its
+     point; distortion[t] = mean squared distance of the window's admissible
+     samples before the move; rejected = inadmissible samples met. */
+int64_t oracle_sample_moments(int32_t d, const float *x, int64_t M, int64_t *s1, int64_t *s2);
+void oracle_moment_map(int32_t d, int64_t count, const int64_t *s1, const int64_t *s2,
+                       const float *base, int32_t N, float *grid, double *moments);
+int oracle_lloyd_empirical(int32_t d, int32_t N, float *grid, const float *x, int64_t M,
+                           int64_t batch, int32_t steps, double gamma, double *distortion,
+                           int64_t *rejected);
+
 /* Stratified time-layer estimate (d = 1, not in the paper): ln in FP64, the
    normal quantile (AS 241), the cell-edge probabilities of a layer, the
    samples of a row (equal or proportional allocation), one stratified pair,

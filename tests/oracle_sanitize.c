@@ -150,6 +150,29 @@ static void run_dim(int d) {
   CHECK(oracle_lloyd(d, N[n], Lm, gl, 2000, 3, 5, 1, dist) == 0);
   for (int t = 0; t < 3; ++t) CHECK(dist[t] >= 0.0);
 
+  /* grids from samples: moment matching, then Lloyd steps on windows (one
+     inadmissible sample among them) */
+  {
+    const int64_t Ms = 1000;
+    float *xs = calloc((size_t)Ms * d, sizeof(float));
+    for (int64_t m = 0; m < Ms; ++m)
+      for (int c = 0; c < d; ++c) xs[m * d + c] = (float)sin(0.37 * (double)(m * d + c + 1));
+    xs[17 * d] = NAN;
+    int64_t s1[3], s2[9], rej = -1;
+    CHECK(oracle_sample_moments(d, xs, Ms, s1, s2) == Ms - 1);
+    float *gm = calloc((size_t)N[n] * d, sizeof(float));
+    double mom[3 + 18];
+    oracle_moment_map(d, Ms - 1, s1, s2, gl, N[n], gm, mom);
+    for (int c = 0; c < d; ++c) CHECK(mom[d + c * d + c] > 0.0);
+    if (d == 1)
+      for (int32_t i = 0; i + 1 < N[n]; ++i) gm[i + 1] = fmaxf(gm[i + 1], nextafterf(gm[i], 1e9f));
+    double dist4[4];
+    CHECK(oracle_lloyd_empirical(d, N[n], gm, xs, Ms, 370, 4, 0.5, dist4, &rej) == 0);
+    CHECK(rej == 1 || rej == 2);
+    free(gm);
+    free(xs);
+  }
+
   if (d == 1) {
     int32_t *cs = calloc((size_t)entries, sizeof(int32_t));
     CHECK(oracle_transitions_stratified(&s.m, g, N, 50, 1, 9, 1, cs) == 0);
