@@ -193,6 +193,27 @@ qtree_status qtree_transitions_add(const qtree_plan *plan, uint64_t m0, uint64_t
                                    uint32_t contract_id, qtree_mode mode, int32_t *counts,
                                    void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the counts
+ * of qtree_transitions, bit for bit, with the LAYERWISE two-pass key scratch
+ * taken from a fixed device array of the library (QTREE_FIXED_SCRATCH_BYTES
+ * per device, held until the process ends) instead of the plan's workspace,
+ * so a plan created with batch_samples = 0 still counts in two passes.  The
+ * call allocates nothing (no hipMalloc, no stream or event creation: one
+ * layer group on `stream`); samples run in as many passes as the array
+ * holds.  The array keeps the last call's contents and is shared by every
+ * call on the device: calls that overlap in time on one device (different
+ * streams or host threads) race and must be serialised by the caller.  The
+ * current device must be the plan's.  EUNSUPPORTED (nothing launched) when
+ * one chunk of every layer does not fit the array (n (8192 + 4 (tiles + 1))
+ * bytes, tiles = the largest layer's ceil(N_k N_{k+1} / 4096)); other errors
+ * as qtree_transitions.  PATHWISE calls and plans tuned to one-pass counting
+ * use no scratch. */
+#define QTREE_FIXED_SCRATCH_BYTES (64u << 20)
+qtree_status qtree_transitions_fixed_scratch(const qtree_plan *plan, uint64_t m0, uint64_t M,
+                                             uint64_t seed, uint32_t contract_id,
+                                             qtree_mode mode, int32_t *counts, void *stream);
+
 /* Quantized backward dynamic programming (Sec. 2), FP64, for n_pay obstacle
  * vectors sharing one set of counts:
  *   V_n = phi_n;  V_k(i) = max(phi_k(i), sum_j c_ij V_{k+1}(j) / p_i),

@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
         getattr(L, f).restype = i64
     L.qtree_transitions.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
     L.qtree_transitions_add.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
+    L.qtree_transitions_fixed_scratch.argtypes = [P, u64, u64, u64, u32, ctypes.c_int, P, P]
+    L.qtree_transitions_fixed_scratch.restype = ctypes.c_int
     L.qtree_pi_workspace_size.argtypes = [P, P]
     L.qtree_pi.argtypes = [P, P, P, ctypes.c_size_t, P]
     L.qtree_bdp_many.argtypes = [P, P, ctypes.c_size_t, i64, P, P, P]
@@ -245,6 +247,18 @@ class Plan:
             counts = self.new_counts()
         _check(lib().qtree_transitions(self._h, int(m0), int(M), int(seed), int(contract),
                                        int(mode), counts.data_ptr(), _stream_handle(stream)))
+        return counts[:self.entries]
+
+    def transitions_fixed_scratch(self, M: int, seed: int, contract: int = 0,
+                                  mode: int = LAYERWISE, m0: int = 0, counts=None, stream=None):
+        """The counts of `transitions`, with the two-pass scratch taken from the
+        library's fixed device array (the call allocates nothing; `counts`
+        must then be passed in by a caller that cannot allocate)."""
+        if counts is None:
+            counts = self.new_counts()
+        _check(lib().qtree_transitions_fixed_scratch(self._h, int(m0), int(M), int(seed),
+                                                     int(contract), int(mode), counts.data_ptr(),
+                                                     _stream_handle(stream)))
         return counts[:self.entries]
 
     def transitions_stratified(self, M: int, seed: int, contract: int = 0, alloc: int = 1,
