@@ -79,7 +79,7 @@ size_t keys_lds_bytes(int d, int n, const int32_t* N) {
     maxP = next_pow2(N[k]) > maxP ? next_pow2(N[k]) : maxP;
   }
   const size_t grids =
-      d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)(maxN + kScanGroup);
+      d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)(maxN + kScanTile);
   return grids + sizeof(uint16_t) * kChunk +
          sizeof(uint32_t) * (2 * (size_t)max_tiles_of(n, N) + 1 + 256);
 }

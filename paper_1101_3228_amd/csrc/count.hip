@@ -339,22 +339,23 @@ __device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g)
 }
 
 // Pass A, d = 2, 3: S samples per lane share each LDS grid read, in
-// kChunk / (KB S) rounds whose keys stay in registers.  The grid scans load
-// tiles of kNdTile records one tile ahead and keep the running best once per
-// group of kScanGroup records (the padding unit): one compare and two selects
-// per group and sample, then a rescan of the winning group (the bookkeeping
-// once per 4-record tile was ~a third of the scan's issue time).
+// kChunk / (KB S) rounds whose keys stay in registers.  The grid scans take
+// tiles of kScanTile records, the padding unit, loaded one tile ahead: one
+// compare and two selects per tile and sample for the running best, then a
+// rescan of the winning tile (with 4-record tiles that bookkeeping was ~a
+// third of the scan's issue time; 8 records: 5 % faster; tiles of 16 and
+// groups of 2 or 4 tiles per running-best update: 2.5 %, 3.4 % and 20 %
+// slower at N = 2000).
 template <int D, int S, int KB>
 __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   constexpr int kKeys = kChunk / KB;
-  constexpr int kNdTile = 8;
-  static_assert(kScanGroup % kNdTile == 0, "scan tile must divide the padding unit");
+  constexpr int kNdTile = kScanTile;
   const LayerDev& L0 = *j.L0;
   const LayerDev& L1 = *j.L1;
   const int N0 = L0.N, N1 = L0.N1, T = L0.tiles;
-  // both grids padded to whole bookkeeping groups with records whose key is +inf
-  const int P0 = (N0 + kScanGroup - 1) / kScanGroup * kScanGroup;
-  const int P1 = (N1 + kScanGroup - 1) / kScanGroup * kScanGroup;
+  // both grids padded to whole scan tiles with records whose key is +inf
+  const int P0 = (N0 + kScanTile - 1) / kScanTile * kScanTile;
+  const int P1 = (N1 + kScanTile - 1) / kScanTile * kScanTile;
   float4* gk = lds4;
   float4* gk1 = lds4 + P0;
   uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + P0 + P1);
@@ -383,8 +384,8 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
       layer_pair<D>(L0, z, e, xs[s], ys[s]);
     }
     int ii[S], jj[S];
-    argmin_scan_grouped<D, S, kNdTile, kScanGroup / kNdTile>(gk, P0, xs, ii);
-    argmin_scan_grouped<D, S, kNdTile, kScanGroup / kNdTile>(gk1, P1, ys, jj);
+    argmin_scan_tiled<D, S, kNdTile>(gk, P0, xs, ii);
+    argmin_scan_tiled<D, S, kNdTile>(gk1, P1, ys, jj);
     // the round is not unrolled, so its keys go to fixed registers by a
     // uniform select (a dynamic index would put the array in scratch)
 #pragma unroll
@@ -704,7 +705,7 @@ size_t keys_lds_1d(int maxP, int max_tiles) {
 }
 
 size_t keys_lds_nd(int maxN, int max_tiles) {
-  return sizeof(float4) * 2 * (size_t)(maxN + kScanGroup) + sizeof(uint16_t) * kChunk +
+  return sizeof(float4) * 2 * (size_t)(maxN + kScanTile) + sizeof(uint16_t) * kChunk +
          sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
 }
 

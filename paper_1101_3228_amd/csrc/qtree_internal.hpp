@@ -22,7 +22,6 @@ constexpr int kChunk = 4096;          // samples per pass-A workgroup
 constexpr int kMaxTiles = 4096;       // larger count blocks use direct atomics
 constexpr int kDefaultBatch = 1 << 22;  // samples per layer per pass by default
 constexpr int kScanTile = 8;            // records per tile of the d >= 2 argmin scan
-constexpr int kScanGroup = 32;          // records per bookkeeping group (forward d >= 2 scan)
 constexpr int kGuideMax = 8192;         // largest guide table of a 1-D layer (entries)
 constexpr int kGuideKMax = 4;           // most midpoints one guide bucket may add
 
@@ -248,14 +247,32 @@ struct LloydArgs {
   unsigned long long* dist;  // sum of rint(|x - g|^2 2^16)
   double* distortion;        // [steps] or null
   // per-workgroup partials of the accumulation: row b holds workgroup b's
-  // sums [N d], counts [N] and distortion [1] (E = N d + N + 1 words)
+  // sums [N d], counts [N], distortion, admissible and inadmissible samples
+  // (E = N d + N + 3 words)
   unsigned long long* part;
   int E;
+  // samples of a caller's set instead of Philox draws: step window
+  // (start + m) mod Ms, m < M; samples with a coordinate outside [-64, 64]
+  // (or NaN) are skipped and counted
+  const float* xs;           // [Ms][d] device, or null (Philox samples)
+  uint64_t Ms;
+  uint64_t start;
+  double gamma;              // new point g + gamma (mean - g); 1: the mean
+  unsigned long long* used;  // admissible samples of the step
+  unsigned long long* rej;   // inadmissible samples of the step
+  unsigned long long* rej_total;  // running total over the steps
+  long long* rejected;       // caller's copy of the total, or null
 };
 constexpr int kLloydMaxBlocks = 512;  // accumulation workgroups per step at most
 size_t lloyd_lds_bytes(int d, int N, int Npad, int P);
 hipError_t launch_lloyd_prepare(const LloydArgs& a, hipStream_t s);
 hipError_t launch_lloyd_step(const LloydArgs& a, int blocks, hipStream_t s);
+// Moment-matching grids: exact integer moment sums of a device sample set,
+// sums = [count, s1 (d), s2 (d d)], and the grid mean + chol(cov) base.
+hipError_t launch_sample_moments(int d, const float* x, uint64_t M, long long* sums,
+                                 hipStream_t s);
+hipError_t launch_moment_grid(int d, const long long* sums, const float* base, int N,
+                              float* grid, double* moments, hipStream_t s);
 
 hipError_t launch_pi_quarter_disc(uint32_t key0, uint32_t key1, uint32_t rep0, int reps,
                                   uint64_t blocks, unsigned long long* inside, hipStream_t s);

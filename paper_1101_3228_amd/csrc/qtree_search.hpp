@@ -201,80 +201,6 @@ __device__ __forceinline__ void argmin_scan_tiled(const float4* __restrict__ g, 
   }
 }
 
-// The same argmin with the running-best bookkeeping once per group of G
-// tiles of TL records: the minimum of a whole group (v_min3 chains over its
-// G TL keys) is compared with the best so far, and only the first group
-// attaining the minimum is rescanned, from its last record down, for the
-// lowest index whose key equals it.  The compare and two selects of the
-// bookkeeping then fall on one record in G TL instead of one in TL, for a
-// rescan of G TL records per point.  Bit-identical to argmin_scan (same keys,
-// lowest index among the minimal ones).  Npad must be a multiple of G TL,
-// the padding records giving +inf for every x (g = 0, h = +inf).
-template <int D, int S, int TL, int G>
-__device__ __forceinline__ void argmin_scan_grouped(const float4* __restrict__ g, int Npad,
-                                                    const float (*xs)[D], int* idx) {
-  constexpr int GR = TL * G;
-  float best[S];
-  int grp[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    best[s] = __builtin_huge_valf();
-    grp[s] = 0;
-  }
-  // the records of the next tile are loaded while the current one is
-  // scanned (the very last load repeats the last tile, inside the array)
-  float4 cur[TL];
-#pragma unroll
-  for (int q = 0; q < TL; ++q) cur[q] = g[q];
-  for (int g0 = 0; g0 < Npad; g0 += GR) {
-    float m[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) m[s] = __builtin_huge_valf();
-#pragma unroll
-    for (int tt = 0; tt < G; ++tt) {
-      const int p0 = g0 + tt * TL;
-      const int pn = p0 + TL < Npad ? p0 + TL : p0;
-      float4 nxt[TL];
-#pragma unroll
-      for (int q = 0; q < TL; ++q) nxt[q] = g[pn + q];
-#pragma unroll
-      for (int q = 0; q < TL; ++q) {
-        const float4 r = cur[q];
-        const float gc[3] = {r.x, r.y, r.z};
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          float key = r.w;
-#pragma unroll
-          for (int c = 0; c < D; ++c) key = fmaf(-xs[s][c], gc[c], key);
-          m[s] = fminf(m[s], key);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < TL; ++q) cur[q] = nxt[q];
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const bool lt = m[s] < best[s];
-      best[s] = lt ? m[s] : best[s];
-      grp[s] = lt ? g0 : grp[s];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    int found = grp[s] + GR - 1;
-#pragma unroll 1
-    for (int q = GR - 1; q >= 0; --q) {
-      const float4 r = g[grp[s] + q];
-      const float gc[3] = {r.x, r.y, r.z};
-      float key = r.w;
-#pragma unroll
-      for (int c = 0; c < D; ++c) key = fmaf(-xs[s][c], gc[c], key);
-      found = key == best[s] ? grp[s] + q : found;
-    }
-    idx[s] = found;
-  }
-}
-
 // Standard normals z (for X_k) and eps (for the innovation) of LAYERWISE
 // sample m of layer k.  Philox counter (block, k, contract, tag): d = 1 uses
 // block m >> 1 and the Box-Muller pair m & 1; d = 2 block m; d = 3 blocks
