@@ -490,6 +490,45 @@ qtree_status qtree_lloyd(int32_t d, int32_t N, const float *L, const float *grid
                          double *distortion, void *workspace, size_t workspace_bytes,
                          void *stream);
 
+/* Grids for marginals of any law (Sec. 2: optimal grids where they are
+ * known, otherwise sub-optimal grids matching the first two moments of X_k;
+ * the Lloyd condition of eq. Qerr on an empirical measure).  A sample is
+ * admissible when every coordinate is finite and within [-64, 64]; the
+ * others are skipped (and counted by qtree_lloyd_samples).
+ *
+ * qtree_lloyd_samples: `steps` Lloyd steps as in qtree_lloyd, but step t
+ *   takes the window of `batch` samples (t batch + j) mod M, j < batch, of
+ *   the caller's set x (device float[M][d], row-major, M <= 2^40), and moves
+ *   each point to its cell's sample mean (gamma = 1) or the fraction gamma
+ *   of the way there, new = g + gamma (mean - g) in FP64 rounded once
+ *   (0 < gamma < 1: the batch form of the competitive-learning step).
+ *   grid0: host float[N][d] (limits as qtree_lloyd); grid: device output;
+ *   batch: 1 .. 2^31 - 1; distortion: device double[steps] or NULL, entry t
+ *   = mean of |x - g|^2 over the window's admissible samples before the move
+ *   (0 if none); rejected: device int64 or NULL, the inadmissible samples
+ *   met over all steps; workspace: qtree_lloyd_workspace_size(d, N) bytes.
+ *   Errors as qtree_lloyd, and EINVAL for gamma outside (0, 1] or M = 0.
+ *   Asynchronous on `stream`.
+ * qtree_sample_moments: exact integer moment sums of the admissible samples
+ *   of x (device float[M][d], M <= 2^31): sums (device int64[1 + d + d d])
+ *   = count, s1[r] = sum rint(x_r 2^24), s2[r][c] = sum rint(x_r x_c 2^16)
+ *   (the product exact in FP64); order independent.  Asynchronous.
+ * qtree_moment_grid: from such sums, mean = s1 2^-24 / count, covariance
+ *   = s2 2^-16 / count - mean mean', its lower Cholesky factor (column by
+ *   column; a non-positive pivot gives a zero column) in FP64, and
+ *   grid[i] = mean + chol base[i] (FP64, rounded once).  base, grid: device
+ *   float[N][d]; moments: device double[d + 2 d d] (mean, covariance,
+ *   factor) or NULL.  A zero count gives a zero mean and factor.
+ *   Asynchronous. */
+qtree_status qtree_lloyd_samples(int32_t d, int32_t N, const float *grid0, float *grid,
+                                 const float *x, uint64_t M, uint64_t batch, int32_t steps,
+                                 double gamma, double *distortion, int64_t *rejected,
+                                 void *workspace, size_t workspace_bytes, void *stream);
+qtree_status qtree_sample_moments(int32_t d, const float *x, uint64_t M, int64_t *sums,
+                                  void *stream);
+qtree_status qtree_moment_grid(int32_t d, const int64_t *sums, const float *base, int32_t N,
+                               float *grid, double *moments, void *stream);
+
 /* Host helpers for inputs (FP64, host memory, no device work). */
 /* 1-D quadratic-optimal quantizer of N(0,1) with N points (Sec. 2,
  * eq. Qerr): stationary grid of Lloyd's method, out: double[N], ascending. */

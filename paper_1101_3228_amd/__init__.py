@@ -98,6 +98,13 @@ def lib() -> ctypes.CDLL:
     L.qtree_lloyd_workspace_size.restype = ctypes.c_size_t
     L.qtree_lloyd.argtypes = [i32, i32, P, P, P, u64, i32, u64, i32, P, P, ctypes.c_size_t, P]
     L.qtree_lloyd.restype = ctypes.c_int
+    L.qtree_lloyd_samples.argtypes = [i32, i32, P, P, P, u64, u64, i32, f64, P, P, P,
+                                      ctypes.c_size_t, P]
+    L.qtree_lloyd_samples.restype = ctypes.c_int
+    L.qtree_sample_moments.argtypes = [i32, P, u64, P, P]
+    L.qtree_sample_moments.restype = ctypes.c_int
+    L.qtree_moment_grid.argtypes = [i32, P, P, i32, P, P, P]
+    L.qtree_moment_grid.restype = ctypes.c_int
     L.qtree_strat_workspace_size.argtypes = [P, u64, i32]
     L.qtree_strat_workspace_size.restype = ctypes.c_size_t
     L.qtree_transitions_stratified.argtypes = [P, u64, i32, u64, u32, P, P, ctypes.c_size_t, P]
@@ -480,6 +487,61 @@ def lloyd(d: int, grid0, L, M: int, steps: int, seed: int, fresh: bool = True, g
                              int(steps), int(seed), int(bool(fresh)), distortion.data_ptr(),
                              workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
     return grid, distortion
+
+
+def lloyd_samples(grid0, x, batch: int, steps: int, gamma: float = 1.0, grid=None,
+                  distortion=None, rejected=None, workspace=None, stream=None):
+    """Lloyd steps (gamma = 1) or relaxed steps (0 < gamma < 1) of eq. Qerr on
+    windows of `batch` samples of the device set x [M, d] (float32), from the
+    host start grid grid0 [N][d].  Returns (grid [N, d] float32, distortion
+    [steps] float64, rejected [1] int64), all on x's device."""
+    import torch
+    d = int(x.shape[1])
+    g0 = np.ascontiguousarray(np.asarray(grid0, np.float32).reshape(-1, d))
+    N = g0.shape[0]
+    dev = x.device
+    if grid is None:
+        grid = torch.empty((N, d), dtype=torch.float32, device=dev)
+    if distortion is None:
+        distortion = torch.zeros(max(steps, 1), dtype=torch.float64, device=dev)
+    if rejected is None:
+        rejected = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws_bytes = lib().qtree_lloyd_workspace_size(d, int(N))
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().qtree_lloyd_samples(d, int(N), _np_ptr(g0), grid.data_ptr(), x.data_ptr(),
+                                     int(x.shape[0]), int(batch), int(steps), float(gamma),
+                                     distortion.data_ptr(), rejected.data_ptr(),
+                                     workspace.data_ptr(), workspace.numel(),
+                                     _stream_handle(stream)))
+    return grid, distortion, rejected
+
+
+def sample_moments(x, sums=None, stream=None):
+    """Exact integer moment sums of the admissible samples of the device set
+    x [M, d]: device int64 [1 + d + d d] = (count, s1, s2)."""
+    import torch
+    d = int(x.shape[1])
+    if sums is None:
+        sums = torch.empty(1 + d + d * d, dtype=torch.int64, device=x.device)
+    _check(lib().qtree_sample_moments(d, x.data_ptr(), int(x.shape[0]), sums.data_ptr(),
+                                      _stream_handle(stream)))
+    return sums
+
+
+def moment_grid(x, base, stream=None):
+    """Moment-matching grid (Sec. 2): the device base grid [N, d] mapped by the
+    sample mean and the Cholesky factor of the sample covariance of the device
+    set x [M, d].  Returns (grid [N, d] float32, moments [d + 2 d d] float64:
+    mean, covariance, factor)."""
+    import torch
+    d = int(x.shape[1])
+    sums = sample_moments(x, stream=stream)
+    grid = torch.empty_like(base)
+    mom = torch.empty(d + 2 * d * d, dtype=torch.float64, device=x.device)
+    _check(lib().qtree_moment_grid(d, sums.data_ptr(), base.data_ptr(), int(base.shape[0]),
+                                   grid.data_ptr(), mom.data_ptr(), _stream_handle(stream)))
+    return grid, mom
 
 
 def layer_samples(plan: Plan, k: int, m0: int, count: int, seed: int, contract: int = 0,

@@ -219,3 +219,35 @@ def box_queries(count: int, seed: int, lo=PUT_BOX_LO, hi=PUT_BOX_HI, frac_out: f
         if c == 4:
             x[q, c] = np.ceil(x[q, c])
     return x.astype(np.float32)
+
+
+# ----------------------------------------------------- samples of other laws
+
+def marginal_samples(d: int, M: int, seed: int, bad: int = 0) -> np.ndarray:
+    """Samples of a non-Gaussian marginal, FP32 [M][d]: coordinate 0 a
+    log-normal shifted to mean ~0 (skewed, heavy right tail), coordinate 1 a
+    two-component Gaussian mixture, coordinate 2 uniform on [-2, 3], with a
+    linear mixing so the coordinates correlate; `bad` of them (at seeded
+    positions) replaced by inadmissible values (NaN, +-inf, +-100)."""
+    rng = np.random.default_rng(seed)
+    cols = [np.exp(0.6 * rng.standard_normal(M)) - np.exp(0.18),
+            np.where(rng.random(M) < 0.3, rng.normal(-1.5, 0.4, M), rng.normal(0.8, 0.7, M)),
+            rng.uniform(-2.0, 3.0, M)]
+    x = np.stack(cols[:d], axis=1)
+    if d > 1:
+        mix = np.tril(np.full((d, d), 0.4)) + 0.6 * np.eye(d)
+        x = x @ mix.T
+    x = x.astype(np.float32)
+    if bad:
+        pos = rng.choice(M, size=bad, replace=False)
+        vals = np.array([np.nan, np.inf, -np.inf, 100.0, -100.0], np.float32)
+        x[pos, rng.integers(0, d, bad)] = vals[rng.integers(0, vals.size, bad)]
+    return x
+
+
+def product_base(d: int, sizes, base) -> np.ndarray:
+    """Product of 1-D standard grids base(n) (one per axis), FP32 [prod][d],
+    the last axis fastest."""
+    axes = [np.asarray(base(int(n)), np.float64) for n in sizes]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    return np.stack([m.ravel() for m in mesh], axis=1)[:, :d].astype(np.float32)
