@@ -456,6 +456,36 @@ qtree_status qtree_strat_samples(const qtree_plan *plan, int32_t k, int32_t i, u
                                  int32_t alloc, uint64_t t0, int64_t count, uint64_t seed,
                                  uint32_t contract_id, float *x, float *y, void *stream);
 
+/* Banded stratified counts (d = 1; not in the paper): the counts of
+ * qtree_transitions_stratified keeping, of row i of layer k, only the band
+ * of columns its samples can reach, packed row after row, instead of the
+ * dense N_k x N_{k+1} blocks.  Rows r = sum_{l<k} N_l + i, r < R = sum_{k<n}
+ * N_k.  The band of a row comes from the plan: X_k lies in cell i (the end
+ * cells reach mu_k - 38.5 L_k and mu_k + 8.3 L_k, the quantiles of the
+ * clamped probabilities) and eps within +-5.769 (the largest Box-Muller
+ * normal), so X_{k+1} = A_k X_k + b_k + T_k eps lies in an interval whose
+ * cells of layer k+1, widened for FP32 rounding, form the band.
+ * qtree_strat_band (host query): *values = the packed length; row_off
+ *   (host int64[R + 1] or NULL): row r's columns row_lo[r] + w,
+ *   w < row_off[r + 1] - row_off[r], are stored at band[row_off[r] + w];
+ *   row_lo (host int32[R] or NULL).  EUNSUPPORTED for d != 1.
+ * qtree_transitions_stratified_banded: as qtree_transitions_stratified
+ *   with band: device int32[values], overwritten entirely; *overflow
+ *   (device uint32, zeroed by the call) receives the number of samples
+ *   that fell outside their row's band (0 unless the band is wrong; those
+ *   samples are not stored).  Same workspace and errors.  Asynchronous.
+ * qtree_bdp_banded: qtree_bdp on banded counts (the row total is the sum of
+ *   the band).  EUNSUPPORTED for d != 1. */
+qtree_status qtree_strat_band(const qtree_plan *plan, int64_t *values, int64_t *row_off,
+                              int32_t *row_lo);
+qtree_status qtree_transitions_stratified_banded(const qtree_plan *plan, uint64_t M,
+                                                 int32_t alloc, uint64_t seed,
+                                                 uint32_t contract_id, int32_t *band,
+                                                 uint32_t *overflow, void *workspace,
+                                                 size_t workspace_bytes, void *stream);
+qtree_status qtree_bdp_banded(const qtree_plan *plan, const int32_t *band, const double *phi,
+                              int32_t n_pay, double *V, double *V0_host, void *stream);
+
 /* Grid optimization (Sec. 2, eq. Qerr): `steps` randomized Lloyd steps that
  * lower the quadratic quantization error E min_i |X - x_i|^2 of X = L z,
  * z ~ N(0, I_d).  A step draws M samples (sample m of step t: Philox counter

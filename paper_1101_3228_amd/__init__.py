@@ -110,6 +110,13 @@ def lib() -> ctypes.CDLL:
     L.qtree_transitions_stratified.argtypes = [P, u64, i32, u64, u32, P, P, ctypes.c_size_t, P]
     L.qtree_transitions_stratified.restype = ctypes.c_int
     L.qtree_strat_row.argtypes = [P, i32, i32, u64, i32]
+    L.qtree_strat_band.argtypes = [P, P, P, P]
+    L.qtree_strat_band.restype = ctypes.c_int
+    L.qtree_transitions_stratified_banded.argtypes = [P, u64, i32, u64, u32, P, P, P,
+                                                      ctypes.c_size_t, P]
+    L.qtree_transitions_stratified_banded.restype = ctypes.c_int
+    L.qtree_bdp_banded.argtypes = [P, P, P, i32, P, P, P]
+    L.qtree_bdp_banded.restype = ctypes.c_int
     L.qtree_strat_row.restype = ctypes.c_int64
     L.qtree_strat_samples.argtypes = [P, i32, i32, u64, i32, u64, i64, u64, u32, P, P, P]
     L.qtree_strat_samples.restype = ctypes.c_int
@@ -286,6 +293,50 @@ class Plan:
                                                   ws.data_ptr(), ws.numel(),
                                                   _stream_handle(stream)))
         return counts[:self.entries]
+
+    def strat_band(self):
+        """Banded layout of the stratified counts (d = 1): (values, row_off
+        int64 [R + 1], row_lo int32 [R]) over the R = sum_{k<n} N_k rows."""
+        R = int(np.sum(self.N[:-1]))
+        values = ctypes.c_int64(0)
+        off = np.zeros(R + 1, np.int64)
+        lo = np.zeros(max(R, 1), np.int32)
+        _check(lib().qtree_strat_band(self._h, ctypes.byref(values), _np_ptr(off), _np_ptr(lo)))
+        return int(values.value), off, lo[:R]
+
+    def transitions_stratified_banded(self, M: int, seed: int, contract: int = 0,
+                                      alloc: int = 1, band=None, overflow=None, stream=None):
+        """Banded stratified counts: (band device int32 [values], overflow
+        device uint32 [1] as int32)."""
+        import torch
+        dev = self.workspace.device
+        values = self.strat_band()[0]
+        if band is None:
+            band = torch.empty(max(values, 1), dtype=torch.int32, device=dev)
+        if overflow is None:
+            overflow = torch.empty(1, dtype=torch.int32, device=dev)
+        need = lib().qtree_strat_workspace_size(self._h, int(M), int(alloc))
+        ws = getattr(self, "_strat_ws", None)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 16), dtype=torch.uint8, device=dev)
+            self._strat_ws = ws
+        _check(lib().qtree_transitions_stratified_banded(
+            self._h, int(M), int(alloc), int(seed), int(contract), band.data_ptr(),
+            overflow.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+        return band[:values], overflow
+
+    def bdp_banded(self, band, phi, V=None, want_v0: bool = True, stream=None):
+        """qtree_bdp on banded counts; as `bdp`."""
+        import torch
+        phi2 = phi.reshape(-1, self.points)
+        n_pay = phi2.shape[0]
+        if V is None:
+            V = torch.empty((n_pay, self.points), dtype=torch.float64, device=phi.device)
+        V0 = np.zeros(n_pay, np.float64) if want_v0 else None
+        _check(lib().qtree_bdp_banded(self._h, band.data_ptr(), phi2.data_ptr(), n_pay,
+                                      V.data_ptr(), _np_ptr(V0) if want_v0 else None,
+                                      _stream_handle(stream)))
+        return V0, V
 
     def strat_row(self, k: int, i: int, M: int, alloc: int = 1) -> int:
         """Samples of row i of layer k in the stratified counts."""

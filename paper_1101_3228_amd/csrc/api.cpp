@@ -106,6 +106,12 @@ WsLayout ws_layout(int d, int n, const int32_t* N, int64_t batch_chunks) {
   if (d == 1) off = align_up(off + (size_t)(pts + n + 1) * sizeof(double), 256);
   l.guide = off;
   if (d == 1) off = align_up(off + (size_t)(n + 1) * kGuideMax * sizeof(uint16_t), 256);
+  l.band = off;
+  if (d == 1) {
+    const int64_t rows = pts - N[n];
+    off = align_up(off + sizeof(int64_t) * (size_t)(rows + 1) + sizeof(int32_t) * (size_t)rows,
+                   256);
+  }
   // scratch of the two-pass counting (only when every count block has at
   // most kMaxTiles tiles)
   const int mt = max_tiles_of(n, N);
@@ -262,6 +268,57 @@ static bool all_finite(const float* p, size_t count) {
   for (size_t i = 0; i < count; ++i)
     if (!std::isfinite(p[i])) return false;
   return true;
+}
+
+// Banded layout of the stratified counts (d = 1): the columns of layer k+1
+// that the samples of row i of layer k can reach.  X_k lies in cell i
+// (between the FP32 midpoints m_{i-1} and m_i; the end cells reach
+// mu_k - 38.5 L_k and mu_k + 8.3 L_k, the normal quantiles of the clamped
+// probabilities 2^-1074 and 1 - 2^-53), and eps within +-5.769 (the largest
+// Box-Muller radius), so X_{k+1} = A_k X_k + b_k + T_k eps lies in an
+// interval, widened by a margin for the FP32 rounding of the samples, whose
+// cells (layer k+1's midpoints strictly below its ends) form the band.
+// Writes int64 offsets [R + 1] then int32 first columns [R] at `dst` and
+// keeps host copies in the plan.
+static void band_table(qtree_plan& p, const qtree_model* model, const float* mids, char* dst) {
+  const int n = p.n;
+  const int64_t R = p.pt_off[n];
+  p.band_off.assign((size_t)R + 1, 0);
+  p.band_lo.assign((size_t)R, 0);
+  int64_t o = 0;
+  for (int k = 0; k < n; ++k) {
+    const float* m0 = mids + p.aux_off[k];
+    const float* m1 = mids + p.aux_off[k + 1];
+    const int n1 = p.N[k + 1] - 1;  // midpoints of layer k+1
+    const double mu = model->mu[k], L = std::fabs((double)model->L[k]);
+    const double A = model->A[k], b = model->b[k], T = std::fabs((double)model->T[k]);
+    for (int i = 0; i < p.N[k]; ++i) {
+      double xl = i == 0 ? mu - 38.5 * L : (double)m0[i - 1];
+      double xh = i == p.N[k] - 1 ? mu + 8.3 * L : (double)m0[i];
+      const double mx = 1e-6 * (1.0 + std::fabs(mu) + 40.0 * L + std::fabs(xl) + std::fabs(xh));
+      xl -= mx;
+      xh += mx;
+      double yl = (A >= 0.0 ? A * xl : A * xh) + b - 5.769 * T;
+      double yh = (A >= 0.0 ? A * xh : A * xl) + b + 5.769 * T;
+      const double my = 1e-6 * (1.0 + std::fabs(yl) + std::fabs(yh));
+      yl -= my;
+      yh += my;
+      const int lo = (int)(std::lower_bound(m1, m1 + n1, yl,
+                                            [](float m, double y) { return (double)m < y; }) -
+                           m1);
+      const int hi = (int)(std::lower_bound(m1, m1 + n1, yh,
+                                            [](float m, double y) { return (double)m < y; }) -
+                           m1) + 1;
+      const int64_t r = p.pt_off[k] + i;
+      p.band_lo[(size_t)r] = lo;
+      p.band_off[(size_t)r] = o;
+      o += hi - lo;
+    }
+  }
+  p.band_off[(size_t)R] = o;
+  std::memcpy(dst, p.band_off.data(), sizeof(int64_t) * (size_t)(R + 1));
+  std::memcpy(dst + sizeof(int64_t) * (size_t)(R + 1), p.band_lo.data(),
+              sizeof(int32_t) * (size_t)R);
 }
 
 qtree_status qtree_plan_create(const qtree_model* model, const float* grid, const int32_t* N,
@@ -425,6 +482,7 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
       }
     }
     p.edges.assign(edges, edges + p.points + n + 1);
+    band_table(p, model, mids, img.data() + p.lay.band);
   } else {
     float4* pts = reinterpret_cast<float4*>(img.data() + p.lay.points);
     for (int64_t t = 0; t < p.points; ++t) {
@@ -937,6 +995,51 @@ qtree_status qtree_transitions_stratified(const qtree_plan* plan, uint64_t M, in
   return e == hipSuccess ? QTREE_OK : hip_fail(e, "stratified launch");
 }
 
+qtree_status qtree_strat_band(const qtree_plan* plan, int64_t* values, int64_t* row_off,
+                              int32_t* row_lo) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (plan->d != 1) return fail(QTREE_EUNSUPPORTED, "banded counts are for d = 1");
+  const int64_t R = plan->pt_off[plan->n];
+  if (values) *values = plan->band_off[(size_t)R];
+  if (row_off) std::memcpy(row_off, plan->band_off.data(), sizeof(int64_t) * (size_t)(R + 1));
+  if (row_lo) std::memcpy(row_lo, plan->band_lo.data(), sizeof(int32_t) * (size_t)R);
+  return QTREE_OK;
+}
+
+qtree_status qtree_transitions_stratified_banded(const qtree_plan* plan, uint64_t M,
+                                                 int32_t alloc, uint64_t seed,
+                                                 uint32_t contract_id, int32_t* band,
+                                                 uint32_t* overflow, void* workspace,
+                                                 size_t workspace_bytes, void* stream) {
+  qtree::StratArgs a{};
+  qtree_status st = strat_args(plan, M, alloc, seed, contract_id, a);
+  if (st != QTREE_OK) return st;
+  if (!band || !overflow || !workspace)
+    return fail(QTREE_EINVAL, "band, overflow or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(band) % 4 || reinterpret_cast<uintptr_t>(overflow) % 4)
+    return fail(QTREE_EINVAL, "band and overflow must be 4-byte aligned");
+  bool split = false;
+  const std::vector<qtree::StratUnit> units = strat_units(plan, M, alloc, &split);
+  if (units.size() >= (1u << 31)) return fail(QTREE_EOVERFLOW, "too many work units");
+  if (workspace_bytes < sizeof(qtree::StratUnit) * units.size())
+    return fail(QTREE_ENOMEM, "workspace smaller than qtree_strat_workspace_size");
+  const int64_t R = plan->pt_off[plan->n];
+  a.counts = band;
+  a.band_off = reinterpret_cast<const int64_t*>(plan->ws + plan->lay.band);
+  a.band_lo = reinterpret_cast<const int32_t*>(plan->ws + plan->lay.band +
+                                               sizeof(int64_t) * (size_t)(R + 1));
+  a.overflow = overflow;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* dev_units = static_cast<qtree::StratUnit*>(workspace);
+  hipError_t e = hipMemcpyAsync(dev_units, units.data(), sizeof(qtree::StratUnit) * units.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = qtree::launch_zero_i32(reinterpret_cast<int32_t*>(overflow), 1, s);
+  if (e == hipSuccess && split)
+    e = qtree::launch_zero_i32(band, plan->band_off[(size_t)R], s);
+  if (e == hipSuccess) e = qtree::launch_strat(a, dev_units, (int)units.size(), s);
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "stratified launch");
+}
+
 int64_t qtree_strat_row(const qtree_plan* plan, int32_t k, int32_t i, uint64_t M, int32_t alloc) {
   if (!plan || plan->d != 1 || k < 0 || k >= plan->n || i < 0 || i >= plan->N[k]) return -1;
   if ((alloc != 0 && alloc != 1) || M < 1 || M >= (1ull << 31)) return -1;
@@ -961,8 +1064,24 @@ qtree_status qtree_strat_samples(const qtree_plan* plan, int32_t k, int32_t i, u
   return e == hipSuccess ? QTREE_OK : hip_fail(e, "stratified samples launch");
 }
 
+static qtree_status bdp_impl(const qtree_plan* plan, const int32_t* counts, const double* phi,
+                             int32_t n_pay, double* V, double* V0_host, void* stream,
+                             bool banded);
+
 qtree_status qtree_bdp(const qtree_plan* plan, const int32_t* counts, const double* phi,
                        int32_t n_pay, double* V, double* V0_host, void* stream) {
+  return bdp_impl(plan, counts, phi, n_pay, V, V0_host, stream, false);
+}
+
+qtree_status qtree_bdp_banded(const qtree_plan* plan, const int32_t* band, const double* phi,
+                              int32_t n_pay, double* V, double* V0_host, void* stream) {
+  if (plan && plan->d != 1) return fail(QTREE_EUNSUPPORTED, "banded counts are for d = 1");
+  return bdp_impl(plan, band, phi, n_pay, V, V0_host, stream, true);
+}
+
+static qtree_status bdp_impl(const qtree_plan* plan, const int32_t* counts, const double* phi,
+                             int32_t n_pay, double* V, double* V0_host, void* stream,
+                             bool banded) {
   if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
   if (!counts || !phi || !V) return fail(QTREE_EINVAL, "counts, phi and V must be non-NULL");
   if (n_pay < 1) return fail(QTREE_EINVAL, "n_pay must be >= 1");
@@ -976,6 +1095,11 @@ qtree_status qtree_bdp(const qtree_plan* plan, const int32_t* counts, const doub
   a.P = plan->points;
   a.n_pay = n_pay;
   const int n = plan->n;
+  if (banded) {
+    a.band_off = reinterpret_cast<const int64_t*>(plan->ws + plan->lay.band);
+    a.band_lo = reinterpret_cast<const int32_t*>(plan->ws + plan->lay.band +
+                                                 sizeof(int64_t) * (size_t)(plan->pt_off[n] + 1));
+  }
   hipError_t e = qtree::launch_copy_last_layer(a, plan->pt_off[n], plan->N[n], s);
   if (e != hipSuccess) return hip_fail(e, "bdp launch");
   for (int k = n - 1; k >= 0; --k) {

@@ -27,19 +27,32 @@ __global__ __launch_bounds__(kBlock) void bdp_layer_kernel(BdpArgs a, int N_k, i
   if (i >= N_k) return;
   const int q0 = blockIdx.y * kPay;
   const int nq = (a.n_pay - q0) < kPay ? (a.n_pay - q0) : kPay;
-  const int32_t* row = a.counts + cnt_k + (int64_t)i * N_k1;
+  // the row's counts: dense, or the band of columns j0 .. j0 + len - 1
+  const int32_t* row;
+  int len;
+  int64_t col0 = pt_k1;
+  if (a.band_off) {
+    const int64_t r = pt_k + i;
+    const int64_t o = a.band_off[r];
+    row = a.counts + o;
+    len = (int)(a.band_off[r + 1] - o);
+    col0 += a.band_lo[r];
+  } else {
+    row = a.counts + cnt_k + (int64_t)i * N_k1;
+    len = N_k1;
+  }
   int64_t p = 0;
   double s[kPay];
 #pragma unroll
   for (int q = 0; q < kPay; ++q) s[q] = 0.0;
-  for (int j = lane; j < N_k1; j += 64) {
+  for (int j = lane; j < len; j += 64) {
     const int32_t c = row[j];
     p += c;
     if (c != 0) {
       const double cd = (double)c;
 #pragma unroll
       for (int q = 0; q < kPay; ++q)
-        if (q < nq) s[q] = fma(cd, a.V[(int64_t)(q0 + q) * a.P + pt_k1 + j], s[q]);
+        if (q < nq) s[q] = fma(cd, a.V[(int64_t)(q0 + q) * a.P + col0 + j], s[q]);
     }
   }
 #pragma unroll

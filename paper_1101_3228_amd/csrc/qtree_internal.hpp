@@ -63,6 +63,8 @@ struct WsLayout {
   size_t aux;      // d == 1: float[sum P] midpoints padded with +inf
   size_t edges;    // d == 1: double[sum (N_k + 1)] marginal probabilities below the cell edges
   size_t guide;    // d == 1: uint16[(n + 1) kGuideMax] guide tables of the cell search
+  size_t band;     // d == 1: int64[R + 1] band offsets, then int32[R] first band columns
+                   // of the R = sum_{k<n} N_k count rows (banded stratified counts)
   size_t keys;     // uint16[n][batch chunks][kChunk] pass-A keys
   size_t segs;     // uint32[n][batch chunks][max tiles + 1] segment starts
   size_t total;
@@ -147,6 +149,10 @@ struct BdpArgs {
   double* V;
   int64_t P;  // points per payoff vector (sum N_k)
   int32_t n_pay;
+  // banded counts (else null): row r = pt_off_k + i holds columns
+  // band_lo[r] + w, w < band_off[r + 1] - band_off[r], at counts[band_off[r] + w]
+  const int64_t* band_off;
+  const int32_t* band_lo;
 };
 hipError_t launch_bdp_layer(const BdpArgs& a, int k, int N_k, int N_k1, int64_t pt_k,
                             int64_t pt_k1, int64_t cnt_k, hipStream_t s);
@@ -212,8 +218,14 @@ struct StratArgs {
   uint32_t key0, key1, contract;
   uint64_t M;             // samples per row (alloc 0) or per layer (alloc 1)
   int alloc;              // 0 equal, 1 proportional allocation
-  int32_t* counts;        // the plan's count blocks
+  int32_t* counts;        // the plan's count blocks, or the band values
   int n, maxP, maxN;      // layers; largest padded midpoint count; largest N_k
+  // banded output (else null): row r = pt_off_k + i keeps columns
+  // band_lo[r] .. band_lo[r] + W_r - 1 at counts[band_off[r] ..], W_r =
+  // band_off[r + 1] - band_off[r]; counts outside the band go to *overflow
+  const int64_t* band_off;
+  const int32_t* band_lo;
+  uint32_t* overflow;
 };
 constexpr int kStratRows = 4;            // rows (strata) per tile
 constexpr uint64_t kStratSegment = 65536;  // samples per workgroup at most

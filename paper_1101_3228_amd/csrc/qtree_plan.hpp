@@ -29,6 +29,8 @@ struct qtree_plan {
   std::vector<int32_t> split;     // histogram parts per super tile of every layer
   std::vector<float> marg_L;      // d = 1: the marginal factor L_k of every layer
   std::vector<double> edges;      // d = 1: host copy of the cell-edge probabilities
+  std::vector<int64_t> band_off;  // d = 1: banded stratified counts, row offsets [R + 1]
+  std::vector<int32_t> band_lo;   // d = 1: first band column of every row [R]
   int32_t gt_Kmax = -1;           // d = 1: largest guide K over the layers (-1: no tables)
   int32_t gt_Bmax = 1;            // d = 1: largest guide table
   int64_t batch_chunks = 0;      // scratch chunks per layer per pass

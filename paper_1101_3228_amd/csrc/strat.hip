@@ -15,6 +15,9 @@
 // serialize) while its lanes walk the samples, then writes the rows with
 // plain stores, zeros included, or, for a shared tile, adds its nonzero
 // counts onto the zeroed rows with atomics.  No sort and no histogram pass.
+// A banded output keeps of each row only the columns its samples can reach
+// (a band the plan computes from the cell, the AR(1) step and the largest
+// Box-Muller normal), packed row after row.
 // X_{k+1}'s cell comes from the layer's guide table (cell_1d_guide) when the
 // plan has tables, else from the breadth-first search.
 //
@@ -144,6 +147,60 @@ __device__ __forceinline__ void strat_pair(const StratArgs& a, const LayerDev& L
   y = fmaf(L.T[0], eps, fmaf(L.A[0], x, L.b[0]));
 }
 
+// Stores a tile's rows (cnt: [rows][N1][S] sub-counters in LDS): the whole
+// rows with plain stores (zeros included), or, for a tile shared by several
+// workgroups, its nonzero counts added onto the zeroed rows; with a banded
+// output only the columns of each row's band, counting the rest in
+// *overflow (no sample reaches them when the band is right).
+template <int S>
+__device__ __forceinline__ void store_tile(const StratArgs& a, const StratUnit& U,
+                                           const LayerDev& L0, const uint32_t* cnt) {
+  const int i0 = U.i0, N1 = L0.N1;
+  const int rows = L0.N - i0 < kStratRows ? L0.N - i0 : kStratRows;
+  if (a.band_off) {
+    __shared__ int64_t boff[kStratRows];
+    __shared__ int32_t blo[kStratRows], bw[kStratRows];
+    if ((int)threadIdx.x < rows) {
+      const int64_t r = (int64_t)L0.pt_off + i0 + threadIdx.x;
+      boff[threadIdx.x] = a.band_off[r];
+      bw[threadIdx.x] = (int32_t)(a.band_off[r + 1] - a.band_off[r]);
+      blo[threadIdx.x] = a.band_lo[r];
+    }
+    __syncthreads();
+    uint32_t lost = 0u;
+    for (int i = threadIdx.x; i < rows * N1; i += kBlock) {
+      uint32_t v = 0u;
+#pragma unroll
+      for (int q = 0; q < S; ++q) v += cnt[i * S + q];
+      const int row = i / N1;
+      const uint32_t w = (uint32_t)(i - row * N1 - blo[row]);
+      if (w < (uint32_t)bw[row]) {
+        int32_t* dst = a.counts + boff[row] + w;
+        if (U.split) {
+          if (v) atomicAdd(dst, (int32_t)v);
+        } else {
+          *dst = (int32_t)v;
+        }
+      } else {
+        lost += v;
+      }
+    }
+    if (lost) atomicAdd(a.overflow, lost);
+    return;
+  }
+  int32_t* out = a.counts + L0.cnt_off + (int64_t)i0 * N1;
+  for (int i = threadIdx.x; i < rows * N1; i += kBlock) {
+    uint32_t v = 0u;
+#pragma unroll
+    for (int q = 0; q < S; ++q) v += cnt[i * S + q];
+    if (U.split) {
+      if (v) atomicAdd(&out[i], (int32_t)v);
+    } else {
+      out[i] = (int32_t)v;
+    }
+  }
+}
+
 }  // namespace
 
 // Workgroup b takes unit b of the work list.
@@ -184,14 +241,7 @@ __global__ __launch_bounds__(kBlock) void strat_kernel(StratArgs a, const StratU
     atomicAdd(&cnt[row * N1 + j], 1u);
   }
   __syncthreads();
-  const int rows = L0.N - i0 < kStratRows ? L0.N - i0 : kStratRows;
-  int32_t* out = a.counts + L0.cnt_off + (int64_t)i0 * N1;
-  if (U.split) {
-    for (int i = threadIdx.x; i < rows * N1; i += kBlock)
-      if (cnt[i]) atomicAdd(&out[i], (int32_t)cnt[i]);
-  } else {
-    for (int i = threadIdx.x; i < rows * N1; i += kBlock) out[i] = (int32_t)cnt[i];
-  }
+  store_tile<1>(a, U, L0, cnt);
 }
 
 // The same with layer k+1's guide table: its sorted midpoints (+inf beyond
@@ -237,18 +287,7 @@ __global__ __launch_bounds__(kBlock, 4) void strat_kernel_guide(StratArgs a,
     atomicAdd(&cnt[(uint32_t)(row * N1 + j) * S + sub], 1u);
   }
   __syncthreads();
-  const int rows = L0.N - i0 < kStratRows ? L0.N - i0 : kStratRows;
-  int32_t* out = a.counts + L0.cnt_off + (int64_t)i0 * N1;
-  for (int i = threadIdx.x; i < rows * N1; i += kBlock) {
-    uint32_t v = 0u;
-#pragma unroll
-    for (int q = 0; q < S; ++q) v += cnt[i * S + q];
-    if (U.split) {
-      if (v) atomicAdd(&out[i], (int32_t)v);
-    } else {
-      out[i] = (int32_t)v;
-    }
-  }
+  store_tile<S>(a, U, L0, cnt);
 }
 
 __global__ void strat_samples_kernel(StratArgs a, int k, int i, uint64_t t0, int64_t count,

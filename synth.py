@@ -69,6 +69,22 @@ def ou_model(n: int, alpha=(1.0, 5.0), sig=(1.0, 1.0), rho: float = 0.0, T: floa
                 x0=np.zeros(2, np.float32))
 
 
+def ou1_model(n: int, alpha: float = 2.0, sig: float = 0.8, theta: float = 0.5,
+              x0: float = -0.3, T: float = 1.0):
+    """One-factor Ornstein-Uhlenbeck state reverting to theta:
+    X_{k+1} = e^{-alpha dt} X_k + theta (1 - e^{-alpha dt}) + T_k eps, with the
+    exact Gaussian marginals of X_k from X_0 = x0.  FP32."""
+    dt = T / n
+    a = np.exp(-alpha * dt)
+    sd = lambda t: sig * np.sqrt((1.0 - np.exp(-2.0 * alpha * t)) / (2.0 * alpha))
+    t = np.arange(n + 1) * dt
+    mu = theta + (x0 - theta) * np.exp(-alpha * t)
+    return dict(d=1, n=n, A=np.full((n, 1, 1), a, np.float32),
+                b=np.full((n, 1), theta * (1.0 - a), np.float32),
+                T=np.full((n, 1, 1), sd(dt), np.float32), mu=mu.reshape(-1, 1).astype(np.float32),
+                L=sd(t).reshape(-1, 1, 1).astype(np.float32), x0=np.array([x0], np.float32))
+
+
 def quantile_grid_1d(N: int) -> np.ndarray:
     """Sorted N(0,1) test grid: quantiles of N(0, 3) (the point density
     f^{1/3} of asymptotically optimal quadratic quantizers), FP64."""
