@@ -265,6 +265,21 @@ typedef struct {
 qtree_status qtree_bdp_many(const qtree_plan *plan, const void *pi, size_t pi_bytes, int64_t n_q,
                             const qtree_payoff_spec *specs, double *V0, void *stream);
 
+/* The same for many trees in one launch (a tree per number of layers, for
+ * instance): tree t (plans[t], its weights pi[t] of pi_bytes[t] bytes from
+ * qtree_pi) prices contracts q_begin[t] .. q_begin[t+1] - 1 of specs / V0
+ * (q_begin: host int64[n_trees + 1], nondecreasing).  All trees share one
+ * dimension; layers of at most 256 points.  The call copies a table of the
+ * trees (80 bytes each) into `workspace` (device, >= 80 n_trees bytes,
+ * 16-byte aligned), in use until the launch ends.  Workgroups take the trees
+ * with the most layers first.  V0 equals qtree_bdp_many tree by tree, bit
+ * for bit.  Asynchronous. */
+qtree_status qtree_bdp_many_trees(int32_t n_trees, const qtree_plan *const *plans,
+                                  const void *const *pi, const size_t *pi_bytes,
+                                  const int64_t *q_begin, const qtree_payoff_spec *specs,
+                                  double *V0, void *workspace, size_t workspace_bytes,
+                                  void *stream);
+
 /* Discounted obstacle on the plan's grid points, FP64, device output
  * phi: double[sum N_k]:  phi_k(x) = exp(-r t_k) payoff(S_{t_k}(x)),
  * t_k = k Tm / n, S^a_t(x) = S0 exp((r - sigma_a^2/2) t + sigma_a y_a) with

@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
     L.qtree_pi_workspace_size.argtypes = [P, P]
     L.qtree_pi.argtypes = [P, P, P, ctypes.c_size_t, P]
     L.qtree_bdp_many.argtypes = [P, P, ctypes.c_size_t, i64, P, P, P]
+    L.qtree_bdp_many_trees.argtypes = [i32, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+    L.qtree_bdp_many_trees.restype = ctypes.c_int
     for f in ("qtree_pi_workspace_size", "qtree_pi", "qtree_bdp_many"):
         getattr(L, f).restype = ctypes.c_int
     L.qtree_transitions_add.restype = ctypes.c_int
@@ -538,6 +540,29 @@ def lloyd(d: int, grid0, L, M: int, steps: int, seed: int, fresh: bool = True, g
                              int(steps), int(seed), int(bool(fresh)), distortion.data_ptr(),
                              workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
     return grid, distortion
+
+
+def bdp_many_trees(trees, specs, q_begin, V0=None, workspace=None, stream=None):
+    """V_0 of many contracts on many trees in one launch (qtree_bdp_many_trees).
+    trees: [(plan, pi)] with pi from Plan.pi; specs: device uint8 tensor of
+    qtree_payoff_spec records, tree t pricing records q_begin[t] ..
+    q_begin[t+1] - 1; returns device float64 [q_begin[-1]]."""
+    import torch
+    T = len(trees)
+    qb = np.ascontiguousarray(q_begin, np.int64)
+    assert qb.size == T + 1
+    dev = specs.device
+    if V0 is None:
+        V0 = torch.empty(max(int(qb[-1]), 1), dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = torch.empty(max(80 * T, 16), dtype=torch.uint8, device=dev)
+    plans = (ctypes.c_void_p * max(T, 1))(*[p.handle.value for p, _ in trees])
+    pis = (ctypes.c_void_p * max(T, 1))(*[pi._qtree_pi[0] for _, pi in trees])
+    sizes = (ctypes.c_size_t * max(T, 1))(*[pi._qtree_pi[1] for _, pi in trees])
+    _check(lib().qtree_bdp_many_trees(T, plans, pis, sizes, _np_ptr(qb), specs.data_ptr(),
+                                      V0.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                      _stream_handle(stream)))
+    return V0
 
 
 def lloyd_samples(grid0, x, batch: int, steps: int, gamma: float = 1.0, grid=None,

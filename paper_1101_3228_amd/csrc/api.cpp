@@ -1248,6 +1248,84 @@ qtree_status qtree_bdp_many(const qtree_plan* plan, const void* pi, size_t pi_by
   return e == hipSuccess ? QTREE_OK : hip_fail(e, "bdp_many launch");
 }
 
+qtree_status qtree_bdp_many_trees(int32_t n_trees, const qtree_plan* const* plans,
+                                  const void* const* pi, const size_t* pi_bytes,
+                                  const int64_t* q_begin, const qtree_payoff_spec* specs,
+                                  double* V0, void* workspace, size_t workspace_bytes,
+                                  void* stream) {
+  static_assert(sizeof(qtree::ManyTree) == 80, "the header states 80 bytes per tree record");
+  if (n_trees < 0) return fail(QTREE_EINVAL, "n_trees must be >= 0");
+  if (n_trees == 0) return QTREE_OK;
+  if (!plans || !pi || !pi_bytes || !q_begin)
+    return fail(QTREE_EINVAL, "plans, pi, pi_bytes and q_begin must be non-NULL");
+  if (q_begin[0] < 0) return fail(QTREE_EINVAL, "q_begin[0] must be >= 0");
+  int d = 0, max_n = 0;
+  int64_t blocks = 0;
+  std::vector<int> order((size_t)n_trees);
+  for (int t = 0; t < n_trees; ++t) {
+    const qtree_plan* p = plans[t];
+    if (!p || !pi[t]) return fail(QTREE_EINVAL, "plan or pi " + std::to_string(t) + " is NULL");
+    if (t == 0) d = p->d;
+    if (p->d != d) return fail(QTREE_EINVAL, "every tree must have the same dimension");
+    if (reinterpret_cast<uintptr_t>(pi[t]) % 256) return fail(QTREE_EINVAL, "pi must be 256-byte aligned");
+    if (pi_bytes[t] < pi_layout(p).total)
+      return fail(QTREE_ENOMEM, "pi " + std::to_string(t) + " is smaller than qtree_pi_workspace_size");
+    if (q_begin[t + 1] < q_begin[t]) return fail(QTREE_EINVAL, "q_begin must be nondecreasing");
+    max_n = std::max(max_n, p->maxN);
+    blocks += (q_begin[t + 1] - q_begin[t] + 63) / 64;
+    order[(size_t)t] = t;
+  }
+  if (q_begin[n_trees] > q_begin[0] && (!specs || !V0))
+    return fail(QTREE_EINVAL, "specs and V0 must be non-NULL");
+  if (reinterpret_cast<uintptr_t>(specs) % 8 || reinterpret_cast<uintptr_t>(V0) % 8)
+    return fail(QTREE_EINVAL, "specs and V0 must be 8-byte aligned");
+  if (qtree::bdp_many_maxr(max_n) < 0)
+    return fail(QTREE_EUNSUPPORTED, "qtree_bdp_many takes layers of at most 256 points");
+  if (blocks >= (1ll << 31)) return fail(QTREE_EOVERFLOW, "too many contracts");
+  if (!workspace || workspace_bytes < sizeof(qtree::ManyTree) * (size_t)n_trees)
+    return fail(QTREE_ENOMEM, "workspace must hold " + std::to_string(n_trees) + " tree records");
+  if (reinterpret_cast<uintptr_t>(workspace) % 16) return fail(QTREE_EINVAL, "workspace must be 16-byte aligned");
+  if (blocks == 0) return QTREE_OK;
+  // trees with the most layers (the longest workgroups) first
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return plans[x]->n > plans[y]->n; });
+  std::vector<qtree::ManyTree> tab((size_t)n_trees);
+  int32_t blk = 0;
+  for (int r = 0; r < n_trees; ++r) {
+    const int t = order[(size_t)r];
+    const qtree_plan* p = plans[t];
+    const PiLayout l = pi_layout(p);
+    const char* base = static_cast<const char*>(pi[t]);
+    qtree::ManyTree& T = tab[(size_t)r];
+    T.layers = reinterpret_cast<const qtree::LayerDev*>(p->ws + p->lay.layers);
+    T.pts1 = reinterpret_cast<const float*>(p->ws + p->lay.points);
+    T.pts = reinterpret_cast<const float4*>(p->ws + p->lay.points);
+    T.pi_off = reinterpret_cast<const int64_t*>(base + l.off);
+    T.band = reinterpret_cast<const int2*>(base + l.band);
+    T.pi = reinterpret_cast<const double*>(base + l.pi);
+    T.q0 = q_begin[t];
+    T.nq = q_begin[t + 1] - q_begin[t];
+    T.blk0 = blk;
+    T.n = p->n;
+    blk += (int32_t)((T.nq + 63) / 64);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(workspace, tab.data(), sizeof(qtree::ManyTree) * tab.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "tree table copy");
+  qtree::ManyArgs a{};
+  a.specs = reinterpret_cast<const qtree::Contract*>(specs);
+  a.V0 = V0;
+  a.d = d;
+  a.max_n = max_n;
+  a.np_max = (max_n + 3) & ~3;
+  a.trees = static_cast<const qtree::ManyTree*>(workspace);
+  a.n_trees = n_trees;
+  a.blocks = (int32_t)blocks;
+  e = qtree::launch_bdp_many(a, s);
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "bdp_many launch");
+}
+
 qtree_status qtree_payoff(const qtree_plan* plan, int32_t kind, double S0, double K, double r,
                           double Tm, const double* sigma, const double* mix, double* phi,
                           void* stream) {

@@ -234,7 +234,10 @@ hipError_t launch_payoff(const PayoffArgs& a, hipStream_t s) {
 // whole backward recursion of 64 contracts per workgroup with their V_{k+1}
 // resident in LDS ([j][64]: lane = contract, so every LDS read is one
 // conflict-free 512-byte row), the obstacle phi_k computed where it is
-// used, and pi read with scalar loads (a wave's rows are uniform).
+// used, and pi read with scalar loads (a wave's rows are uniform).  One
+// launch may cover many trees (a table of trees, one per number of layers
+// for instance): workgroup b then prices 64 contracts of the tree whose
+// range of workgroups holds b, the trees with the most layers first.
 
 __global__ __launch_bounds__(256) void pi_kernel(PiArgs a) {
   const int lane = threadIdx.x & 63;
@@ -346,9 +349,9 @@ __device__ __forceinline__ double obstacle(const Contract& C, const LayerObstacl
 }
 
 template <int D>
-__device__ __forceinline__ void grid_point(const ManyArgs& a, const LayerDev& L, int i,
+__device__ __forceinline__ void grid_point(const ManyTree& a, int64_t pt_off, int i,
                                            float* xs) {
-  const int64_t at = (int64_t)L.pt_off + i;
+  const int64_t at = pt_off + i;
   if (D == 1) {
     xs[0] = a.pts1[at];
   } else {
@@ -361,77 +364,147 @@ __device__ __forceinline__ void grid_point(const ManyArgs& a, const LayerDev& L,
 
 }  // namespace
 
+// Read-only device memory in the global address space: uniform loads through
+// such pointers may become scalar loads (a generic pointer taken from the
+// tree table would be read with flat vector loads).
+typedef const double __attribute__((address_space(1)))* GlobalF64;
+typedef const int32_t __attribute__((address_space(1)))* GlobalI32;
+typedef const int64_t __attribute__((address_space(1)))* GlobalI64;
+typedef const uint64_t __attribute__((address_space(1)))* GlobalU64;
+
+
 // Workgroup b prices contracts 64 b .. 64 b + 63 (lane = contract); wave w
-// owns the rows i = w + 4 t of every layer, R of them at a time, and keeps
-// their new values in registers until every wave has finished reading
-// V_{k+1}.  MAXR >= ceil(N_max / 4).
-template <int D, int MAXR, int R>
-__global__ __launch_bounds__(256) void bdp_many_kernel(ManyArgs a) {
+// of W owns the rows i = w + W t of every layer, R of them at a time, and
+// keeps their new values in registers until every wave has finished reading
+// V_{k+1}.  MAXR >= ceil(N_max / W).  The weights of a row group reach the
+// FMAs as scalar operands: the loads of the next column group are issued
+// once the current group's V_{k+1} values are in (scalar and LDS loads share
+// one counter), so they travel while the current group's FMAs run.
+template <int D, int W, int MAXR, int R>
+__global__ __launch_bounds__(64 * W) void bdp_many_kernel(ManyArgs a) {
   extern __shared__ double Vs[];  // [Np_max][64]
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
-  const Contract C = a.specs[q < a.nq ? q : a.nq - 1];
+  // the workgroup's tree: the one tree, or the last table entry with
+  // blk0 <= blockIdx.x
+  ManyTree T;
+  int64_t qb = (int64_t)blockIdx.x * 64, qe = a.nq;
+  if (a.trees) {
+    // the table is read through a global pointer, so the record's values are
+    // known to be uniform (a generic load could be a per-lane one)
+    constexpr int kWords = (int)(sizeof(ManyTree) / 8);
+    const GlobalU64 tab = (GlobalU64)a.trees;
+    constexpr int kBlk0 = (int)(offsetof(ManyTree, blk0) / 4);
+    int lo = 0, hi = a.n_trees - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (((GlobalI32)tab)[mid * 2 * kWords + kBlk0] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    uint64_t raw[kWords];
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) raw[w] = tab[lo * kWords + w];
+    __builtin_memcpy(&T, raw, sizeof(ManyTree));
+    qb = T.q0 + ((int64_t)blockIdx.x - T.blk0) * 64;
+    qe = T.q0 + T.nq;
+  } else {
+    T.layers = a.layers;
+    T.pts1 = a.pts1;
+    T.pts = a.pts;
+    T.pi_off = a.pi_off;
+    T.pi = a.pi;
+    T.band = a.band;
+    T.n = a.n;
+  }
+  const int64_t q = qb + lane;
+  const Contract C = a.specs[q < qe ? q : qe - 1];
   // zero the padding rows once (they meet only zero weights, but must be finite)
-  for (int j = wave; j < a.np_max; j += 4) Vs[j * 64 + lane] = 0.0;
+  for (int j = wave; j < a.np_max; j += W) Vs[j * 64 + lane] = 0.0;
   __syncthreads();
+  // per-layer fields through global pointers (uniform values)
+  const GlobalI32 lay = (GlobalI32)T.layers;
+  constexpr int kLayWords = (int)(sizeof(LayerDev) / 4);
+  constexpr int kN = (int)(offsetof(LayerDev, N) / 4), kN1 = (int)(offsetof(LayerDev, N1) / 4),
+                kPt = (int)(offsetof(LayerDev, pt_off) / 4);
   {
-    const LayerDev& L = a.layers[a.n];
-    const LayerObstacle ob = layer_obstacle<D>(C, a.n, a.n);
-    for (int i = wave; i < L.N; i += 4) {
+    const int Nn = lay[T.n * kLayWords + kN];
+    const int64_t pt = lay[T.n * kLayWords + kPt];
+    const LayerObstacle ob = layer_obstacle<D>(C, T.n, T.n);
+    for (int i = wave; i < Nn; i += W) {
       float xs[3];
-      grid_point<D>(a, L, i, xs);
+      grid_point<D>(T, pt, i, xs);
       Vs[i * 64 + lane] = obstacle<D>(C, ob, xs);
     }
   }
   __syncthreads();
-  for (int k = a.n - 1; k >= 0; --k) {
-    const LayerDev& L = a.layers[k];
-    const int Nk = L.N, N1p = (L.N1 + 3) & ~3;
-    const double* P = a.pi + a.pi_off[k];
-    const int2* B = a.band + L.pt_off;
-    const LayerObstacle ob = layer_obstacle<D>(C, a.n, k);
+  for (int k = T.n - 1; k >= 0; --k) {
+    const int Nk = lay[k * kLayWords + kN], N1p = (lay[k * kLayWords + kN1] + 3) & ~3;
+    const int64_t pt = lay[k * kLayWords + kPt];
+    const GlobalF64 P = (GlobalF64)T.pi + ((GlobalI64)T.pi_off)[k];
+    const GlobalI32 B = (GlobalI32)(T.band + pt);  // (lo, hi) pairs
+    const LayerObstacle ob = layer_obstacle<D>(C, T.n, k);
     double res[MAXR];
 #pragma unroll
     for (int t0 = 0; t0 < MAXR; t0 += R) {
-      const int ib = wave + 4 * t0;
+      const int ib = wave + W * t0;
       if (ib >= Nk) break;
       int jlo = 1 << 30, jhi = 0;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        const int i = ib + 4 * t;
+        const int i = ib + W * t;
         if (i < Nk) {
-          const int2 b = B[i];
-          if (b.y > b.x) {
-            jlo = b.x < jlo ? b.x : jlo;
-            jhi = b.y > jhi ? b.y : jhi;
+          const int bx = B[2 * i], by = B[2 * i + 1];
+          if (by > bx) {
+            jlo = bx < jlo ? bx : jlo;
+            jhi = by > jhi ? by : jhi;
           }
         }
       }
       double acc[R];
 #pragma unroll
       for (int t = 0; t < R; ++t) acc[t] = 0.0;
-      const double* prow[R];
+      GlobalF64 prow[R];
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        const int i = ib + 4 * t < Nk ? ib + 4 * t : ib;  // rows past the end repeat row ib
+        const int i = ib + W * t < Nk ? ib + W * t : ib;  // rows past the end repeat row ib
         prow[t] = P + (int64_t)i * N1p;
       }
-      for (int j = jlo; j < jhi; j += 4) {
-        double v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = Vs[(j + u) * 64 + lane];
+      if (jlo < jhi) {
+        double w[R][4];
 #pragma unroll
         for (int t = 0; t < R; ++t)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[t] = fma(prow[t][j + u], v[u], acc[t]);
+          for (int u = 0; u < 4; ++u) w[t][u] = prow[t][jlo + u];
+        for (int j = jlo; j < jhi; j += 4) {
+          double v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = Vs[(j + u) * 64 + lane];
+          // this group's V and weights are in; only then the next group's
+          // weights are requested (the last group re-reads its own)
+          __builtin_amdgcn_sched_barrier(0);
+          __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+          __builtin_amdgcn_sched_barrier(0);
+          const int jn = j + 4 < jhi ? j + 4 : j;
+          double wn[R][4];
+#pragma unroll
+          for (int t = 0; t < R; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wn[t][u] = prow[t][jn + u];
+#pragma unroll
+          for (int t = 0; t < R; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[t] = fma(w[t][u], v[u], acc[t]);
+#pragma unroll
+          for (int t = 0; t < R; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[t][u] = wn[t][u];
+        }
       }
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        const int i = ib + 4 * t;
+        const int i = ib + W * t;
         if (i < Nk) {
           float xs[3];
-          grid_point<D>(a, L, i, xs);
+          grid_point<D>(T, pt, i, xs);
           const double f = obstacle<D>(C, ob, xs);
           res[t0 + t] = f > acc[t] ? f : acc[t];
         }
@@ -440,36 +513,40 @@ __global__ __launch_bounds__(256) void bdp_many_kernel(ManyArgs a) {
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < MAXR; ++t) {
-      const int i = wave + 4 * t;
+      const int i = wave + W * t;
       if (i < Nk) Vs[i * 64 + lane] = res[t];
     }
     __syncthreads();
   }
-  if (wave == 0 && q < a.nq) a.V0[q] = Vs[lane];
+  if (wave == 0 && q < qe) a.V0[q] = Vs[lane];
 }
 
+constexpr int kManyWaves = 8;  // waves per workgroup sharing the LDS of 64 contracts
+
 int bdp_many_maxr(int max_n) {
-  const int rows = (max_n + 3) / 4;
-  return rows <= 8 ? 8 : rows <= 16 ? 16 : rows <= 32 ? 32 : rows <= 64 ? 64 : -1;
+  const int rows = (max_n + kManyWaves - 1) / kManyWaves;
+  return rows <= 8 ? 8 : rows <= 16 ? 16 : rows <= 32 ? 32 : -1;
 }
 
 size_t bdp_many_lds(int max_np) { return sizeof(double) * 64 * (size_t)max_np; }
 
 template <int D>
 static hipError_t launch_bdp_many_d(const ManyArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.nq + 63) / 64));
+  const dim3 grid(a.trees ? (unsigned)a.blocks : (unsigned)((a.nq + 63) / 64));
   const size_t lds = bdp_many_lds(a.np_max);
   hipError_t e = hipSuccess;
   switch (bdp_many_maxr(a.max_n)) {
-#define QTREE_MANY(MR)                                                                   \
-  case MR:                                                                               \
-    if (lds > 65536)                                                                     \
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(bdp_many_kernel<D, MR, 4>),  \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
-    if (e != hipSuccess) return e;                                                       \
-    hipLaunchKernelGGL((bdp_many_kernel<D, MR, 4>), grid, dim3(256), lds, s, a);         \
+#define QTREE_MANY(MR)                                                                        \
+  case MR:                                                                                    \
+    if (lds > 65536)                                                                          \
+      e = hipFuncSetAttribute(                                                                \
+          reinterpret_cast<const void*>(bdp_many_kernel<D, kManyWaves, MR, 4>),               \
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                              \
+    if (e != hipSuccess) return e;                                                            \
+    hipLaunchKernelGGL((bdp_many_kernel<D, kManyWaves, MR, 4>), grid, dim3(64 * kManyWaves),  \
+                       lds, s, a);                                                            \
     break;
-    QTREE_MANY(8) QTREE_MANY(16) QTREE_MANY(32) QTREE_MANY(64)
+    QTREE_MANY(8) QTREE_MANY(16) QTREE_MANY(32)
 #undef QTREE_MANY
     default:
       return hipErrorInvalidValue;
@@ -478,7 +555,7 @@ static hipError_t launch_bdp_many_d(const ManyArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_bdp_many(const ManyArgs& a, hipStream_t s) {
-  if (a.nq <= 0) return hipSuccess;
+  if (a.trees ? a.blocks <= 0 : a.nq <= 0) return hipSuccess;
   if (a.d == 1) return launch_bdp_many_d<1>(a, s);
   if (a.d == 2) return launch_bdp_many_d<2>(a, s);
   return launch_bdp_many_d<3>(a, s);

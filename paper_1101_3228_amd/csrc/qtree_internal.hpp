@@ -192,6 +192,18 @@ struct PiArgs {
 hipError_t launch_pi(const PiArgs& a, hipStream_t s);
 
 // Backward recursion of many contracts on one tree (64 per workgroup).
+// One tree of a many-tree launch: its tables and weights, and the contracts
+// q0 .. q0 + nq - 1 it prices (workgroups blk0 .. blk0 + ceil(nq / 64) - 1).
+struct alignas(16) ManyTree {
+  const LayerDev* layers;
+  const float* pts1;
+  const float4* pts;
+  const int64_t* pi_off;
+  const double* pi;
+  const int2* band;
+  int64_t q0, nq;
+  int32_t blk0, n;
+};
 struct ManyArgs {
   const LayerDev* layers;
   const float* pts1;
@@ -203,6 +215,11 @@ struct ManyArgs {
   double* V0;             // [nq] (device)
   int64_t nq;
   int32_t n, d, max_n, np_max;  // np_max: largest N_k rounded up to a multiple of 4
+  // many trees (else null): the table of n_trees trees, ordered by blk0;
+  // the fields above then come from the workgroup's tree (max_n, np_max: the
+  // largest over the trees)
+  const ManyTree* trees;
+  int32_t n_trees, blocks;
 };
 int bdp_many_maxr(int max_n);  // -1: beyond the supported 256 points per layer
 size_t bdp_many_lds(int max_np);

@@ -21,8 +21,8 @@ import math
 
 import numpy as np
 
-from . import (EUROPEAN, PUT, Plan, _check, _np_ptr, _stream_handle, gauss_quantizer, lib,
-               payoff_specs)
+from . import (EUROPEAN, PAYOFF_SPEC, PUT, Plan, _check, _np_ptr, _stream_handle,
+               bdp_many_trees, gauss_quantizer, lib, payoff_specs)
 
 N_PARAMS = 133633
 N_INPUTS = 6
@@ -194,41 +194,51 @@ class PutTreePricer:
         return self._trees[n]
 
     def specs(self, x) -> dict:
-        """Contract records of the queries, grouped by n: {n: (rows, device
-        qtree_payoff_spec bytes)}; x: host [Q, 6] rows (S0/K, sigma, r, T, n, rho)."""
+        """Contract records of the queries grouped by n, for one many-tree
+        launch: {"n": [n per group], "rows": [query rows per group],
+        "q_begin": int64 [groups + 1], "specs": device qtree_payoff_spec bytes
+        of every group in order}; x: host [Q, 6] rows (S0/K, sigma, r, T, n,
+        rho)."""
         import torch
         x = np.asarray(x, np.float64)
         kind = PUT if self.american else PUT | EUROPEAN
         ns = np.rint(x[:, 4]).astype(np.int64)
         if np.any(ns < 1):
             raise ValueError("n must be >= 1")
-        out = {}
+        out = {"n": [], "rows": [], "q_begin": [0]}
+        recs = []
         for n in np.unique(ns):
             rows = np.flatnonzero(ns == n)
             q = x[rows]
-            rec = payoff_specs(1, np.full(rows.size, kind, np.int32), q[:, 0], 1.0, q[:, 2],
-                               q[:, 3], q[:, 1].reshape(-1, 1),
-                               np.sqrt(q[:, 3]).reshape(-1, 1, 1))
-            out[int(n)] = (rows, torch.from_numpy(rec.view(np.uint8).reshape(-1)).to(self.device))
+            recs.append(payoff_specs(1, np.full(rows.size, kind, np.int32), q[:, 0], 1.0,
+                                     q[:, 2], q[:, 3], q[:, 1].reshape(-1, 1),
+                                     np.sqrt(q[:, 3]).reshape(-1, 1, 1)))
+            out["n"].append(int(n))
+            out["rows"].append(rows)
+            out["q_begin"].append(out["q_begin"][-1] + rows.size)
+        out["q_begin"] = np.asarray(out["q_begin"], np.int64)
+        allrec = np.concatenate(recs) if recs else np.zeros(0, PAYOFF_SPEC)
+        out["specs"] = torch.from_numpy(allrec.view(np.uint8).reshape(-1)).to(self.device)
         return out
 
     def price_specs(self, groups: dict, out=None, stream=None):
-        """V_0 / K of pre-built query groups (see specs) on the device:
-        one qtree_bdp_many launch per n.  Returns {n: device float64 [rows]}."""
-        res = {} if out is None else out
-        for n, (rows, sp) in groups.items():
-            plan, _, pi = self.tree(n)
-            res[n] = plan.bdp_many(pi, sp, V0=res.get(n), stream=stream)
-        return res
+        """V_0 / K of pre-built query groups (see specs) on the device, every
+        n in one qtree_bdp_many_trees launch.  Returns device float64
+        [queries] in group order."""
+        trees = [self.tree(n) for n in groups["n"]]
+        return bdp_many_trees([(p, pi) for p, _, pi in trees], groups["specs"],
+                              groups["q_begin"], V0=out, stream=stream)
 
     def price(self, x, stream=None) -> np.ndarray:
         """x: host float [Q, 6] rows (S0/K, sigma, r, T, n, rho) -> V_0 / K (float64)."""
         x = np.asarray(x, np.float64)
         out = np.empty(x.shape[0], np.float64)
+        if x.shape[0] == 0:
+            return out
         groups = self.specs(x)
-        vals = self.price_specs(groups, stream=stream)
-        for n, (rows, _) in groups.items():
-            out[rows] = vals[n].cpu().numpy()
+        vals = self.price_specs(groups, stream=stream).cpu().numpy()
+        for g, rows in enumerate(groups["rows"]):
+            out[rows] = vals[groups["q_begin"][g]:groups["q_begin"][g + 1]]
         return out
 
 

@@ -105,3 +105,37 @@ def test_bdp_many_rejects_large_layers():
         plan.bdp_many(pi, specs)
     assert e.value.status == 5
     torch.cuda.synchronize()
+
+
+def test_bdp_many_trees_equals_one_tree_at_a_time():
+    """Trees of 3, 17 and 40 layers (one of them given no contract, one with
+    a ragged last workgroup) in one qtree_bdp_many_trees launch: every V_0
+    equals qtree_bdp_many on its own tree bit for bit, and the oracle's BDP
+    within 1e-9."""
+    _case("bdp_many_trees: n = 40, 3, 17, 9 (empty)")
+    rng = np.random.default_rng(11)
+    trees, recs, want, q_begin = [], [], [], [0]
+    for n, nq in ((40, 200), (3, 64), (17, 1), (9, 0)):
+        spec = synth.bm_model(1, n, T=1.0)
+        grid, N = synth.layer_grids(spec, [1] + [int(rng.integers(20, 120)) for _ in range(n)],
+                                    base=qt.gauss_quantizer)
+        plan = qt.Plan(spec, grid, N)
+        counts = plan.transitions(200_000, 0x5EED0040 + n)
+        pi = plan.pi(counts)
+        kinds, S0, K, r, T, sigma, mix = _contracts(rng, max(nq, 1), 1)
+        sp = qt.payoff_specs(1, kinds, S0, K, r, T, sigma, mix)[:nq]
+        if nq:
+            one = plan.bdp_many(pi, sp).cpu().numpy()
+            c = counts.cpu().numpy()
+            for q in (0, nq - 1):
+                phi = O.payoff(int(kinds[q]), 1, N, grid, S0[q], K[q], r[q], T[q], sigma[q],
+                               mix[q])
+                ref = O.bdp(c, N, phi)[0][0]
+                assert abs(one[q] - ref) <= 1e-9 * abs(ref) + 1e-13
+            want.append(one)
+        trees.append((plan, pi))
+        recs.append(sp)
+        q_begin.append(q_begin[-1] + nq)
+    specs = torch.from_numpy(np.concatenate(recs).view(np.uint8).reshape(-1)).cuda()
+    got = qt.bdp_many_trees(trees, specs, q_begin).cpu().numpy()
+    assert np.array_equal(got[:q_begin[-1]].view(np.uint64), np.concatenate(want).view(np.uint64))
