@@ -393,10 +393,14 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
   // host image of the workspace
   std::vector<char> img(p.lay.total, 0);
   auto* layers = reinterpret_cast<qtree::LayerDev*>(img.data() + p.lay.layers);
-  // histogram parts: a layer with fewer super tiles than the largest layer
-  // splits each into up to that ratio (at most 16) parts over the chunks, so
-  // that no workgroup of the histogram pass takes many times the keys of
-  // another (a one-point first layer has a single super tile)
+  // histogram parts: every super tile is split into two parts over the
+  // chunks, and a layer with fewer super tiles than the largest layer into
+  // up to twice that ratio (at most 16), so that no workgroup of the
+  // histogram pass takes many times the keys of another (a one-point first
+  // layer has a single super tile) and the last layer group's histogram,
+  // which no sampling pass hides, has twice the workgroups (1-D workload,
+  // n = 50, N = 500, M = 1e7: 1.835 ms per step against 1.899 unsplit and
+  // 1.838 with four parts)
   int64_t st_max = 1;
   for (int k = 0; k < n; ++k)
     st_max = std::max<int64_t>(st_max, ((int64_t)N[k] * N[k + 1] + qtree::kSuper - 1) / qtree::kSuper);
@@ -417,7 +421,7 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     p.tile_off.push_back(p.total_tiles);
     const int64_t st_k = (entries_k + qtree::kSuper - 1) / qtree::kSuper;
     p.total_tiles += (int32_t)st_k;
-    L.split = st_k > 0 ? (int32_t)std::min<int64_t>(16, std::max<int64_t>(1, st_max / st_k)) : 1;
+    L.split = st_k > 0 ? (int32_t)std::min<int64_t>(16, 2 * std::max<int64_t>(1, st_max / st_k)) : 1;
     L.unit_off = total_units;
     p.split.push_back(L.split);
     p.unit_off.push_back(total_units);
