@@ -584,6 +584,30 @@ def run_batch(args):
                      "kernel": "whole step (batch_keys_nd + batch_keys_1d + batch_count + "
                                "bdp_batch_kernel); the per-kernel split is in the profile"},
     }
+    if not args.no_cpu_baseline:
+        # the oracle on the host cores over a sample of the contracts: the
+        # contracts in order (d alternating) at 1e5 pairs per layer until
+        # about 10 s of host time
+        import oracle as O
+        threads = min(os.cpu_count() or 1, 16)
+        Mc, done, t_cpu, used = 100_000, 0, 0.0, 0
+        for sp in specs:
+            if t_cpu >= 10.0:
+                break
+            used += 1
+            model = synth.bm_model(sp["d"], sp["n"], T=sp["T"], rho=sp["rho"])
+            grid, N = synth.layer_grids(model, sp["sizes"], base=q)
+            mdl = O.Model(model["d"], model["n"], model["A"], model["b"], model["T"],
+                          model["mu"], model["L"], model["x0"])
+            tc = time.perf_counter()
+            O.transitions(mdl, grid, N, Mc, seed=7, nthreads=threads)
+            t_cpu += time.perf_counter() - tc
+            done += sp["n"] * Mc
+        out["cpu_baseline"] = {"value": done / t_cpu, "unit": "pairs/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"the first {used} contracts (d alternating 1, 2) "
+                                         f"at {Mc} pairs per layer: {done:.3g} pairs in "
+                                         f"{t_cpu:.1f} s"}
     print(json.dumps(out), flush=True)
 
 
@@ -805,6 +829,20 @@ def run_p1(args):
             s_run = (time.perf_counter() - t0) / args.steps
             res[f"{name}_N{Nn}"] = {"s": s_run, "transitions_per_s": M * n / s_run}
         log(f"N={Nn} done")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the paper's serial figure (Algorithm I on one core): the oracle on
+        # one thread, pathwise, the whole N = 100 run (1e5 paths)
+        import oracle as O
+        grid, N = synth.layer_grids(spec, [1] + [100] * n, base=qt.gauss_quantizer)
+        mdl = O.Model(spec["d"], spec["n"], spec["A"], spec["b"], spec["T"], spec["mu"],
+                      spec["L"], spec["x0"])
+        t0 = time.perf_counter()
+        O.transitions(mdl, grid, N, M, seed=7, mode=O.PATHWISE, nthreads=1)
+        dt = time.perf_counter() - t0
+        cpu = {"value": M * n / dt, "unit": "transitions/s", "cores": 1, "kind": "oracle",
+               "sample": f"Algorithm I (pathwise), N = 100, all {M} paths, one thread: "
+                         f"{dt:.1f} s (paper, serial, i7 at 2.8 GHz: 30 s)"}
     print(json.dumps({
         "metric": "MC transition samples/s (cell search+count)",
         "value": res["alg3_N500"]["transitions_per_s"], "unit": "transitions/s",
@@ -818,6 +856,7 @@ def run_p1(args):
         "paper_context_gtx480_s": {"alg3": {"N100": 0.21, "N250": 0.50, "N500": 0.99},
                                    "alg2": {"N100": 0.11, "N250": 0.30, "N500": 0.63}},
         "roofline": None,
+        "cpu_baseline": cpu,
     }), flush=True)
 
 

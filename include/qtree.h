@@ -345,6 +345,9 @@ qtree_status qtree_swing(const qtree_plan *plan, const int32_t *counts, const do
  * qtree_batch_plan allocates the batch's device tables and its key scratch
  * (`scratch_bytes`, 0 = 4 GiB; contracts are grouped so that each group
  * fits) -- the only call besides the tuner that allocates device memory.
+ * An allocation that fails returns ENOMEM (nothing is kept); for tests of
+ * that path, QTREE_FAULT_ALLOC=k (k >= 1) in the environment makes the k-th
+ * device allocation of a qtree_batch_plan call fail that way.
  * flags bit 0: capture the run sequence into a hipGraph after the first run
  * and replay it from then on (needs a non-NULL stream).
  *

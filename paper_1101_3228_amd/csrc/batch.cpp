@@ -42,11 +42,27 @@ qtree_status hip_error(hipError_t e, const char* what) {
   return set_error(QTREE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Forced allocation failure, for tests of the error paths: with
+// QTREE_FAULT_ALLOC=k (k >= 1) in the environment, the k-th device
+// allocation of a call fails as if the device memory were exhausted.
+struct AllocFault {
+  int fail_at = 0, count = 0;
+  AllocFault() {
+    const char* v = std::getenv("QTREE_FAULT_ALLOC");
+    fail_at = v ? std::atoi(v) : 0;
+  }
+  hipError_t alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (fail_at > 0 && ++count == fail_at) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+  }
+};
+
 template <typename T>
-hipError_t upload(T** dst, const std::vector<T>& src) {
+hipError_t upload(T** dst, const std::vector<T>& src, AllocFault& f) {
   *dst = nullptr;
   if (src.empty()) return hipSuccess;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), sizeof(T) * src.size());
+  hipError_t e = f.alloc(reinterpret_cast<void**>(dst), sizeof(T) * src.size());
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
 }
@@ -550,18 +566,21 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     }
     b->step_off.push_back((int)b->bdp_tasks.size());
   }
-  hipError_t e = upload(&b->d_contracts, b->hc);
-  if (e == hipSuccess) e = upload(&b->d_units, b->units);
-  if (e == hipSuccess) e = upload(&b->d_tiles, b->tiles);
-  if (e == hipSuccess) e = upload(&b->d_jobs, b->jobs);
-  if (e == hipSuccess) e = upload(&b->d_bdp_tasks, b->bdp_tasks);
-  if (e == hipSuccess) e = upload(&b->d_chunk_off, b->chunk_off);
+  AllocFault fault;
+  hipError_t e = upload(&b->d_contracts, b->hc, fault);
+  if (e == hipSuccess) e = upload(&b->d_units, b->units, fault);
+  if (e == hipSuccess) e = upload(&b->d_tiles, b->tiles, fault);
+  if (e == hipSuccess) e = upload(&b->d_jobs, b->jobs, fault);
+  if (e == hipSuccess) e = upload(&b->d_bdp_tasks, b->bdp_tasks, fault);
+  if (e == hipSuccess) e = upload(&b->d_chunk_off, b->chunk_off, fault);
   if (e == hipSuccess)
-    e = hipMalloc(reinterpret_cast<void**>(&b->d_keys), scratch_keys * per_chunk_key + 16);
+    e = fault.alloc(reinterpret_cast<void**>(&b->d_keys), scratch_keys * per_chunk_key + 16);
   if (e == hipSuccess)
-    e = hipMalloc(reinterpret_cast<void**>(&b->d_segs), scratch_segs * sizeof(uint32_t) + 16);
+    e = fault.alloc(reinterpret_cast<void**>(&b->d_segs), scratch_segs * sizeof(uint32_t) + 16);
   if (e != hipSuccess) {
-    delete b;
+    delete b;  // frees what was allocated
+    if (e == hipErrorOutOfMemory)
+      return set_error(QTREE_ENOMEM, std::string("batch tables: ") + hipGetErrorString(e));
     return hip_error(e, "batch tables");
   }
   *out = b;

@@ -185,3 +185,26 @@ def test_c4_full_batch_equals_one_plan_at_a_time():
         ref = O.transitions(mdl, it["grid"], it["N"], it["M"], seed=it["seed"],
                             contract=it["contract_id"], nthreads=16)
         assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), ref), j
+
+
+def test_batch_plan_allocation_failures(monkeypatch):
+    """QTREE_FAULT_ALLOC=k makes the k-th device allocation of
+    qtree_batch_plan fail: every k up to the eight allocations of a batch
+    with both kinds of contract returns ENOMEM and no batch; with the
+    variable unset the same contracts plan and run to the counts of one plan
+    at a time."""
+    print("[gpu-case] batch forced allocation failures", flush=True)
+    items = _contracts(4, shrink=0.08, M=20_000, seed=21)
+    ref_counts, ref_v0 = _single(items)
+    for k in range(1, 9):
+        monkeypatch.setenv("QTREE_FAULT_ALLOC", str(k))
+        with pytest.raises(qt.QtreeError) as err:
+            qt.Batch(items)
+        assert err.value.status == 2, k
+    monkeypatch.delenv("QTREE_FAULT_ALLOC")
+    for it in items:
+        it["counts"].fill_(-1)
+    V0 = qt.Batch(items).run()
+    for it, rc in zip(items, ref_counts):
+        assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), rc)
+    assert np.allclose(V0, ref_v0, rtol=1e-12, atol=0)
