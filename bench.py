@@ -98,6 +98,15 @@ ALG_SLOTS_PER_PAIR = PHILOX_CALL // 2 + BOX_MULLER + 3 * F + 2 * guide_search(2)
 # AR(1) rows (2 x 2 for X_k, 2 x 4 for X_{k+1}: 12F), index and increment
 ALG_SLOTS_2D_PAIR = PHILOX_CALL + 2 * BOX_MULLER + 12 * F + KEY_INCR     # 277
 ALG_SLOTS_2D_POINT = ND_POINT
+# d = 2 bucketed search (the bucket holding the point lists every grid point
+# that can win there): bucket coordinates (two fmas 2F, two conversions 2H),
+# box test (four compares and their conjunction 4F), bucket index F; per
+# listed candidate: index unpack F, record address F, key 2F, compare F,
+# best key and index selects 2F; a point outside the box or in a full
+# bucket scans all N points (key 2F, compare F, two selects 2F).
+BUCKET_LOCATE = 2 * F + 2 * H + 4 * F + F                                # 11
+BUCKET_CAND = F + F + 2 * F + F + 2 * F                                  # 7
+SCAN_POINT = 2 * F + F + 2 * F                                           # 5
 # The same pair with every operation priced 1 (transcendental 4): the
 # unweighted count reported beside the weighted one.
 ALG_SLOTS_PER_PAIR_UNWEIGHTED = 30 + 71 + 3 + 2 * 11 + 2
@@ -401,6 +410,39 @@ def alg_slots_pair(d: int, Nk: int, Nk1: int, guide_k: int = 2) -> float:
     return ALG_SLOTS_2D_PAIR + ALG_SLOTS_2D_POINT * (Nk + Nk1)
 
 
+def bucketed_search_slots(plan, k: int, x) -> float:
+    """Mean algorithmic lane-slots of the d = 2 bucketed search of device
+    points x [count, 2] in layer k: the bucket is found in FP32 as the
+    kernel finds it, then priced by its listed candidates (not the padding
+    to groups of 8); outside the box or in a full bucket, the full scan."""
+    lo, sc, B = plan.buckets(k)
+    n_k = int(plan.N[k])
+    if B[0] == 0:
+        return BUCKET_LOCATE + SCAN_POINT * n_k
+    cnt = plan.bucket_counts(k).astype(np.int64)
+    xf = x.cpu().numpy().astype(np.float32)
+    f = ((xf - lo.astype(np.float32)) * sc.astype(np.float32)).astype(np.float32)
+    inside = np.all((f >= 0) & (f < B.astype(np.float32)), axis=1)
+    fi = np.where(inside[:, None], f, 0).astype(np.int64)
+    c = cnt[fi[:, 0], fi[:, 1]]
+    listed = inside & (c != 0xFFFF)
+    per = np.where(listed, BUCKET_CAND * c, SCAN_POINT * n_k)
+    return BUCKET_LOCATE + float(per.mean())
+
+
+def bucketed_pair_slots(plan, samples: int = 65_536, seed: int = 0x5EED0C00) -> list:
+    """Algorithmic lane-slots of one d = 2 pair from each layer k of the
+    plan (ALG_SLOTS_2D_PAIR plus both searches), the searches priced on
+    the layer samples 0..samples-1 of the given seed."""
+    import paper_1101_3228_amd as qt
+    out = []
+    for k in range(plan.n):
+        xs, ys = qt.layer_samples(plan, k, 0, samples, seed)
+        out.append(ALG_SLOTS_2D_PAIR + bucketed_search_slots(plan, k, xs)
+                   + bucketed_search_slots(plan, k + 1, ys))
+    return out
+
+
 C3_LAYERS, C3_SHAPE, C3_M = 30, (40, 50), 10_000_000
 
 
@@ -456,9 +498,15 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
     fwd_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in evs]))
     pairs = n * M
     points = sum(int(N[k]) + int(N[k + 1]) for k in range(n)) * M
-    alg = ALG_SLOTS_2D_PAIR * pairs + ALG_SLOTS_2D_POINT * points
+    bucketed = plan.tuning()["buckets"] > 0
+    if bucketed:
+        per_layer = bucketed_pair_slots(plan)
+        alg = M * float(np.sum(per_layer))
+        kernel = "fwd_keys_nd<2, 8, bucketed>"
+    else:
+        alg = ALG_SLOTS_2D_PAIR * pairs + ALG_SLOTS_2D_POINT * points
+        kernel = "fwd_keys_nd<2, 8>"
     achieved = alg / (keys_ms * 1e-3)
-    alg_unw = (60 + 142 + 12 + 2) * pairs + 2.5 * points   # every op 1
     V0 = V[:, 0].cpu().numpy()
     out = {
         "workload": "2-D max-call tree, time-layer parallel: n=30 layers, N=2000 (40x50 "
@@ -472,9 +520,8 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS,
                      "traffic": _measured_traffic("fwd_keys_nd"),
-                     "kernel": "fwd_keys_nd<2, 8>",
-                     "alg_slots_per_pair_avg": alg / pairs,
-                     "frac_unweighted": alg_unw / (keys_ms * 1e-3) / PEAK_SLOTS},
+                     "kernel": kernel,
+                     "alg_slots_per_pair_avg": alg / pairs},
     }
     if with_cpu:
         import oracle as O
@@ -563,9 +610,14 @@ def run_batch(args):
     options = sum(it["phi"].shape[0] for it in items)
     info = batch.info()
     alg = 0.0
-    for sp in specs:
+    for sp, it in zip(specs, items):
         Ns = [int(np.prod(v)) for v in sp["sizes"]]
-        alg += sp["M"] * sum(alg_slots_pair(sp["d"], Ns[k], Ns[k + 1]) for k in range(sp["n"]))
+        if sp["d"] == 2 and it["plan"].tuning()["buckets"] > 0:
+            # the batch searches d = 2 contracts through their bucket tables
+            alg += sp["M"] * float(np.sum(bucketed_pair_slots(it["plan"], samples=4096)))
+        else:
+            alg += sp["M"] * sum(alg_slots_pair(sp["d"], Ns[k], Ns[k + 1])
+                                 for k in range(sp["n"]))
     achieved = alg / (ms_step * 1e-3)
     out = {
         "metric": "MC transition samples/s (cell search+count); options/s (tree)",

@@ -113,6 +113,18 @@ int64_t qtree_plan_batch_samples(const qtree_plan *plan);
  * may be NULL.  EINVAL if plan is NULL. */
 qtree_status qtree_plan_cell_search(const qtree_plan *plan, int32_t *guide_k,
                                     int32_t *guide_buckets);
+/* The d = 2 bucket geometry of layer k (see QTREE_TUNE_BUCKETS): a point x
+ * is in bucket (floor((x_0 - lo[0]) scale[0]), floor((x_1 - lo[1]) scale[1]))
+ * (FP32 arithmetic) of the B[0] x B[1] buckets; B = {0, 0} when the layer
+ * has no tables (d != 2, or one point).  lo, scale: host float[2]; B: host
+ * int32[2].  Reads the layer's record back from the device (blocking). */
+qtree_status qtree_plan_buckets(const qtree_plan *plan, int32_t k, float *lo, float *scale,
+                                int32_t *B);
+/* The candidate count of every bucket of layer k, row-major (bucket (i, j)
+ * at i B[1] + j; 0xFFFF: more than 32 candidates, the full scan decides):
+ * counts, host uint16[B[0] B[1]] (nothing written when the layer has no
+ * tables).  Blocking. */
+qtree_status qtree_plan_bucket_counts(const qtree_plan *plan, int32_t k, uint16_t *counts);
 /* Shape queries (host). */
 int32_t qtree_plan_dim(const qtree_plan *plan);
 int32_t qtree_plan_layers(const qtree_plan *plan);
@@ -144,6 +156,13 @@ int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
  *                        layers in percent of each other group's (10..100,
  *                        default 100: equal groups); its histogram pass is
  *                        the one no sampling pass overlaps.
+ *   QTREE_TUNE_BUCKETS : d = 2: 1 (default) finds cells through the plan's
+ *                        bucket tables (each bucket of a layer's reachable box
+ *                        lists every point that can be the FP32 argmin in it,
+ *                        the key's rounding included, so the cell is the full
+ *                        scan's), 0 scans every point (the brute-force search
+ *                        of Sec. 4); used by the LAYERWISE two-pass forward
+ *                        and qtree_cells.
  */
 typedef enum {
   QTREE_TUNE_CHUNK = 0,
@@ -151,7 +170,8 @@ typedef enum {
   QTREE_TUNE_COUNT = 2,
   QTREE_TUNE_GROUPS = 3,
   QTREE_TUNE_ND_SAMPLES = 4,
-  QTREE_TUNE_TAIL = 5
+  QTREE_TUNE_TAIL = 5,
+  QTREE_TUNE_BUCKETS = 6
 } qtree_tune_key;
 qtree_status qtree_plan_tune(qtree_plan *plan, int32_t key, int64_t value);
 /* Current value of a tuning key (-1 for a NULL plan or an unknown key). */
@@ -415,9 +435,10 @@ void qtree_batch_destroy(qtree_batch *batch);
  *   of layer k (0 <= k < n), device float[count][d] each.
  * qtree_cells: Voronoi cell in layer k (0 <= k <= n) of `count` device points
  *   x (float[count][d]); cell: device int32[count].  d >= 2: the forward's
- *   tiled scan over the layer's records staged in LDS, eight points per lane
- *   (the brute-force search of Sec. 4); d = 1: the binary search over the
- *   layer's sorted midpoints.
+ *   search -- with bucket tables (d = 2, QTREE_TUNE_BUCKETS on) each point's
+ *   bucket list, else the tiled scan over the layer's records staged in LDS,
+ *   eight points per lane (the brute-force search of Sec. 4); d = 1: the
+ *   binary search over the layer's sorted midpoints.
  * All asynchronous on `stream`. */
 qtree_status qtree_box_muller(const uint32_t *ra, const uint32_t *rb, int64_t count, float *z0,
                               float *z1, void *stream);

@@ -205,9 +205,12 @@ class Plan:
 
     def tune(self, chunk: int | None = None, xcd_map: int | None = None,
              count: int | None = None, groups: int | None = None,
-             nd_samples: int | None = None, tail: int | None = None):
+             nd_samples: int | None = None, tail: int | None = None,
+             buckets: int | None = None):
         """Launch tuning (QTREE_TUNE_CHUNK / _XCD_MAP / _COUNT / _GROUPS /
-        _ND_SAMPLES / _TAIL); results unchanged."""
+        _ND_SAMPLES / _TAIL / _BUCKETS); results unchanged."""
+        if buckets is not None:
+            _check(lib().qtree_plan_tune(self._h, 6, int(buckets)))
         if nd_samples is not None:
             _check(lib().qtree_plan_tune(self._h, 4, int(nd_samples)))
         if tail is not None:
@@ -237,13 +240,15 @@ class Plan:
         return {"ms": ms.value, **self.tuning()}
 
     def tuning(self) -> dict:
-        """The plan's launch tuning (groups, tail share, samples per lane)."""
+        """The plan's launch tuning (groups, tail share, samples per lane,
+        d = 2 bucket tables on or off)."""
         L = lib()
         L.qtree_plan_get_tune.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.qtree_plan_get_tune.restype = ctypes.c_int64
         return {"groups": int(L.qtree_plan_get_tune(self._h, 3)),
                 "tail": int(L.qtree_plan_get_tune(self._h, 5)),
-                "nd_samples": int(L.qtree_plan_get_tune(self._h, 4))}
+                "nd_samples": int(L.qtree_plan_get_tune(self._h, 4)),
+                "buckets": int(L.qtree_plan_get_tune(self._h, 6))}
 
     def count_offsets(self) -> np.ndarray:
         N = self.N.astype(np.int64)
@@ -350,6 +355,32 @@ class Plan:
         _check(lib().qtree_transitions_add(self._h, int(m0), int(M), int(seed), int(contract),
                                            int(mode), counts.data_ptr(), _stream_handle(stream)))
         return counts
+
+    def buckets(self, k: int):
+        """(lo float32[2], scale float32[2], B int32[2]) of layer k's d = 2
+        bucket tables (B = 0: none)."""
+        lo = np.zeros(2, np.float32)
+        sc = np.zeros(2, np.float32)
+        B = np.zeros(2, np.int32)
+        L = lib()
+        L.qtree_plan_buckets.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+        L.qtree_plan_buckets.restype = ctypes.c_int
+        _check(L.qtree_plan_buckets(self._h, int(k), _np_ptr(lo), _np_ptr(sc), _np_ptr(B)))
+        return lo, sc, B
+
+    def bucket_counts(self, k: int) -> np.ndarray:
+        """Candidate counts of layer k's buckets, uint16 [B0, B1] (empty when
+        the layer has no tables; 0xFFFF: a full bucket)."""
+        lo, sc, B = self.buckets(k)
+        out = np.zeros((int(B[0]), int(B[1])), np.uint16)
+        if B[0] == 0:
+            return out
+        L = lib()
+        L.qtree_plan_bucket_counts.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+        L.qtree_plan_bucket_counts.restype = ctypes.c_int
+        _check(L.qtree_plan_bucket_counts(self._h, int(k), _np_ptr(out)))
+        return out
 
     def cell_search(self):
         """(guide K, guide buckets) of the 1-D cell search; (-1, 0): the

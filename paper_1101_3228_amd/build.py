@@ -13,7 +13,7 @@ BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["api.cpp", "batch.cpp", "quantizer.cpp", "mlp_api.cpp", "fwd.hip", "count.hip",
            "bdp.hip", "diag.hip", "mlp.hip", "swing.hip", "lloyd.hip", "lloyd_api.cpp",
-           "strat.hip", "fixed_scratch.hip"]
+           "strat.hip", "fixed_scratch.hip", "buckets.hip"]
 
 # -ffp-contract=off: the sample arithmetic is a fixed sequence of IEEE
 # operations (explicit fmaf only); packed FP32 instructions are disabled.

@@ -88,6 +88,15 @@ bool two_pass_fits(int d, int n, const int32_t* N) {
   return max_tiles_of(n, N) <= kMaxTiles && keys_lds_bytes(d, n, N) <= 160 * 1024;
 }
 
+// Buckets of the d = 2 cell search over all layers (layers of one point
+// have none).
+int64_t total_buckets(int n, const int32_t* N) {
+  int64_t b = 0;
+  for (int k = 0; k <= n; ++k)
+    if (N[k] > 1) b += (int64_t)bucket_side(N[k]) * bucket_side(N[k]);
+  return b;
+}
+
 WsLayout ws_layout(int d, int n, const int32_t* N, int64_t batch_chunks) {
   WsLayout l{};
   size_t off = 0;
@@ -112,6 +121,11 @@ WsLayout ws_layout(int d, int n, const int32_t* N, int64_t batch_chunks) {
     off = align_up(off + sizeof(int64_t) * (size_t)(rows + 1) + sizeof(int32_t) * (size_t)rows,
                    256);
   }
+  const int64_t buckets = d == 2 ? total_buckets(n, N) : 0;
+  l.bk_cnt = off;
+  off = align_up(off + sizeof(uint16_t) * (size_t)buckets, 256);
+  l.bk_cand = off;
+  off = align_up(off + sizeof(uint16_t) * kBucketCap * (size_t)buckets, 256);
   // scratch of the two-pass counting (only when every count block has at
   // most kMaxTiles tiles)
   const int mt = max_tiles_of(n, N);
@@ -321,6 +335,72 @@ static void band_table(qtree_plan& p, const qtree_model* model, const float* mid
               sizeof(int32_t) * (size_t)R);
 }
 
+// Boxes of the d = 2 bucketed cell search.  Layer k's time-layer samples
+// are X_k = mu_k + L_k z (as the first point of a pair) and
+// A_{k-1} X_{k-1} + b_{k-1} + T_{k-1} eps (as the second), every normal
+// within +-5.7684 (the largest Box-Muller radius), so X_k lies in the union
+// of two boxes (interval arithmetic, FP64); with the layer's own points and
+// a margin for FP32 rounding, that union is cut into bucket_side(N_k)^2
+// buckets.  A point outside the box (a pathwise state, a diagnostic query)
+// is found by the full scan.
+static void bucket_boxes(qtree_plan& p, const qtree_model* model, const float* grid,
+                         qtree::LayerDev* layers) {
+  constexpr double kZ = 5.7684;
+  const int n = p.n;
+  std::vector<double> slo((size_t)(n + 1) * 2), shi((size_t)(n + 1) * 2);
+  for (int k = 0; k <= n; ++k)
+    for (int r = 0; r < 2; ++r) {
+      double w = 0.0;
+      for (int c = 0; c < 2; ++c) w += std::fabs((double)model->L[(size_t)k * 4 + r * 2 + c]);
+      slo[(size_t)k * 2 + r] = (double)model->mu[(size_t)k * 2 + r] - kZ * w;
+      shi[(size_t)k * 2 + r] = (double)model->mu[(size_t)k * 2 + r] + kZ * w;
+    }
+  int64_t off = 0;
+  for (int k = 0; k <= n; ++k) {
+    qtree::LayerDev& L = layers[k];
+    L.bk_B[0] = L.bk_B[1] = 0;
+    L.bk_off = (int32_t)off;
+    if (p.N[k] <= 1) continue;
+    double lo[2], hi[2];
+    for (int r = 0; r < 2; ++r) {
+      lo[r] = slo[(size_t)k * 2 + r];
+      hi[r] = shi[(size_t)k * 2 + r];
+    }
+    if (k > 0) {
+      const float* A = model->A + (size_t)(k - 1) * 4;
+      const float* T = model->T + (size_t)(k - 1) * 4;
+      for (int r = 0; r < 2; ++r) {
+        double c = (double)model->b[(size_t)(k - 1) * 2 + r], w = 0.0;
+        for (int q = 0; q < 2; ++q) {
+          const double m = 0.5 * (slo[(size_t)(k - 1) * 2 + q] + shi[(size_t)(k - 1) * 2 + q]);
+          const double h = 0.5 * (shi[(size_t)(k - 1) * 2 + q] - slo[(size_t)(k - 1) * 2 + q]);
+          c += (double)A[r * 2 + q] * m;
+          w += std::fabs((double)A[r * 2 + q]) * h + kZ * std::fabs((double)T[r * 2 + q]);
+        }
+        lo[r] = std::min(lo[r], c - w);
+        hi[r] = std::max(hi[r], c + w);
+      }
+    }
+    const float* g = grid + (size_t)p.pt_off[k] * 2;
+    for (int i = 0; i < p.N[k]; ++i)
+      for (int r = 0; r < 2; ++r) {
+        lo[r] = std::min(lo[r], (double)g[(size_t)i * 2 + r]);
+        hi[r] = std::max(hi[r], (double)g[(size_t)i * 2 + r]);
+      }
+    const int B = qtree::bucket_side(p.N[k]);
+    for (int r = 0; r < 2; ++r) {
+      const double m = 1e-3 * (hi[r] - lo[r]) + 1e-6 * (1.0 + std::fabs(lo[r]) + std::fabs(hi[r]));
+      lo[r] -= m;
+      hi[r] += m;
+      L.bk_lo[r] = (float)lo[r];
+      L.bk_scale[r] = (float)((double)B / (hi[r] - (double)L.bk_lo[r]));
+      L.bk_B[r] = B;
+    }
+    off += (int64_t)B * B;
+  }
+  p.buckets = off;
+}
+
 qtree_status qtree_plan_create(const qtree_model* model, const float* grid, const int32_t* N,
                                void* workspace, size_t workspace_bytes, qtree_plan** out) {
   if (!out) return fail(QTREE_EINVAL, "out is NULL");
@@ -497,10 +577,21 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
       h = 0.5f * h;
       pts[t] = make_float4(g[0], d > 1 ? g[1] : 0.f, d > 2 ? g[2] : 0.f, h);
     }
+    if (d == 2) bucket_boxes(p, model, grid, layers);
   }
   hipError_t e = hipMemcpy(workspace, img.data(), p.lay.total, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(workspace)");
   p.ws = static_cast<char*>(workspace);
+  if (p.buckets > 0) {
+    // the candidate lists, from the records just uploaded
+    e = qtree::launch_bucket_build(
+        reinterpret_cast<const qtree::LayerDev*>(p.ws + p.lay.layers), n + 1, nullptr,
+        (int)p.buckets, reinterpret_cast<const float4*>(p.ws + p.lay.points),
+        reinterpret_cast<uint16_t*>(p.ws + p.lay.bk_cnt),
+        reinterpret_cast<uint16_t*>(p.ws + p.lay.bk_cand), nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return hip_fail(e, "bucket tables");
+  }
   *out = new qtree_plan(std::move(p));
   return QTREE_OK;
 }
@@ -541,6 +632,9 @@ static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uin
   a.seg_stride = p->max_tiles + 1;
   a.total_tiles = p->unit_off[p->n];
   a.nd_samples = p->tune_nd_samples;
+  a.bucketed = (p->buckets > 0 && p->tune_buckets) ? 1 : 0;
+  a.bk_cnt = reinterpret_cast<const uint16_t*>(p->ws + p->lay.bk_cnt);
+  a.bk_cand = reinterpret_cast<const uint4*>(p->ws + p->lay.bk_cand);
   return a;
 }
 
@@ -675,6 +769,41 @@ qtree_status qtree_plan_trace(qtree_plan* plan, void* event_after_keys) {
   return QTREE_OK;
 }
 
+qtree_status qtree_plan_buckets(const qtree_plan* plan, int32_t k, float* lo, float* scale,
+                                int32_t* B) {
+  if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
+  if (k < 0 || k > plan->n) return fail(QTREE_EINVAL, "layer index out of range");
+  if (!lo || !scale || !B) return fail(QTREE_EINVAL, "NULL output");
+  // the host image of the layer record is not kept: read it back
+  qtree::LayerDev L{};
+  const hipError_t e =
+      hipMemcpy(&L, plan->ws + plan->lay.layers + sizeof(qtree::LayerDev) * (size_t)k,
+                sizeof(L), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "layer record copy");
+  for (int r = 0; r < 2; ++r) {
+    lo[r] = L.bk_lo[r];
+    scale[r] = L.bk_scale[r];
+    B[r] = L.bk_B[r];
+  }
+  return QTREE_OK;
+}
+
+qtree_status qtree_plan_bucket_counts(const qtree_plan* plan, int32_t k, uint16_t* counts) {
+  float lo[2], scale[2];
+  int32_t B[2];
+  const qtree_status st = qtree_plan_buckets(plan, k, lo, scale, B);
+  if (st != QTREE_OK) return st;
+  if (!counts) return fail(QTREE_EINVAL, "counts is NULL");
+  if (B[0] == 0) return QTREE_OK;
+  qtree::LayerDev L{};
+  hipError_t e = hipMemcpy(&L, plan->ws + plan->lay.layers + sizeof(qtree::LayerDev) * (size_t)k,
+                           sizeof(L), hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(counts, plan->ws + plan->lay.bk_cnt + sizeof(uint16_t) * (size_t)L.bk_off,
+                  sizeof(uint16_t) * (size_t)B[0] * (size_t)B[1], hipMemcpyDeviceToHost);
+  return e == hipSuccess ? QTREE_OK : hip_fail(e, "bucket counts copy");
+}
+
 qtree_status qtree_plan_cell_search(const qtree_plan* plan, int32_t* guide_k,
                                     int32_t* guide_buckets) {
   if (!plan) return fail(QTREE_EINVAL, "plan is NULL");
@@ -725,6 +854,11 @@ qtree_status qtree_plan_tune(qtree_plan* plan, int32_t key, int64_t value) {
   if (key == QTREE_TUNE_XCD_MAP) {
     if (value != 0 && value != 1) return fail(QTREE_EINVAL, "xcd map must be 0 or 1");
     plan->tune_xcd_map = (int32_t)value;
+    return QTREE_OK;
+  }
+  if (key == QTREE_TUNE_BUCKETS) {
+    if (value != 0 && value != 1) return fail(QTREE_EINVAL, "buckets must be 0 or 1");
+    plan->tune_buckets = (int32_t)value;
     return QTREE_OK;
   }
   return fail(QTREE_EINVAL, "unknown tuning key");
@@ -836,6 +970,7 @@ int64_t qtree_plan_get_tune(const qtree_plan* plan, int32_t key) {
     case QTREE_TUNE_GROUPS: return plan->tune_groups;
     case QTREE_TUNE_ND_SAMPLES: return plan->tune_nd_samples;
     case QTREE_TUNE_TAIL: return plan->tune_tail;
+    case QTREE_TUNE_BUCKETS: return plan->tune_buckets;
   }
   return -1;
 }

@@ -110,6 +110,7 @@ struct BatchConfig {
 }  // namespace
 
 struct qtree_batch {
+  int bucketed = 1;  // every 2-D contract's plan has bucket tables in use
   std::vector<qtree_contract> c;
   std::vector<qtree::BatchContract> hc;
   std::vector<qtree::BatchUnit> units;
@@ -179,6 +180,7 @@ qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x, const B
   a.gt_Bmax = b->gtB1;
   a.n_tiles = g.n_tiles;
   a.nd_samples = c.nd_samples;
+  a.bucketed = (b->dmax == 2 && b->bucketed) ? 1 : 0;
   a.keys = b->d_keys;
   a.segs = b->d_segs;
   return a;
@@ -397,6 +399,11 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     bc.chunks = p->d == 1 ? (int32_t)(((C.M + 1) / 2 + qtree::kChunk / 2 - 1) / (qtree::kChunk / 2))
                           : (int32_t)((C.M + qtree::kChunk - 1) / qtree::kChunk);
     bc.seg_stride = p->max_tiles + 1;
+    bc.bk_cnt = reinterpret_cast<const uint16_t*>(p->ws + p->lay.bk_cnt);
+    bc.bk_cand = reinterpret_cast<const uint4*>(p->ws + p->lay.bk_cand);
+    // the d = 2 launch searches through bucket tables when every 2-D
+    // contract has them (results are the same either way)
+    if (p->d == 2 && !(p->buckets > 0 && p->tune_buckets)) b->bucketed = 0;
     b->hc.push_back(bc);
     for (int q0 = 0; q0 < C.n_pay; q0 += 16) {
       qtree::BdpJob j{};
@@ -436,7 +443,8 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     if (x == 1 && b->dmax == 1) continue;
     b->max_per_cu[x] =
         std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lg1,
-                                                x == 0 ? b->gk1 : -1, b->lds[x], 8));
+                                                x == 0 ? b->gk1 : -1, b->lds[x], 8,
+                                                (b->dmax == 2 && b->bucketed) ? 1 : 0));
   }
   int dev = 0;
   hipDeviceProp_t prop;
@@ -485,7 +493,8 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     }
   }
   for (int x = 0; x <= gi; ++x) {
-    // cost model: lane-slots per sample (1-D ~200; d >= 2 ~5 per grid point)
+    // cost model: lane-slots per sample (1-D ~200; d >= 2 ~5 per grid point
+    // scanned, ~500 in all with the bucket tables)
     std::vector<qtree::BatchUnit> gu;
     std::vector<double> gc;
     double total = 0.0;
@@ -493,7 +502,10 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
       if (group_of[i] != x) continue;
       const qtree_plan* p = contracts[i].plan;
       for (int k = 0; k < p->n; ++k) {
-        const double per = p->d == 1 ? 200.0 : 300.0 + 5.0 * p->d / 2.0 * (p->N[k] + p->N[k + 1]);
+        const double per =
+            p->d == 1 ? 200.0
+            : (p->d == 2 && b->bucketed) ? 500.0
+                                        : 300.0 + 5.0 * p->d / 2.0 * (p->N[k] + p->N[k + 1]);
         total += per * (double)contracts[i].M;
       }
     }

@@ -57,6 +57,8 @@ struct KeysJob {
   uint64_t lo, hi;
   uint16_t* keys;  // kChunk slots of this chunk
   uint32_t* seg;   // T + 1 segment starts of this chunk
+  const uint16_t* bk_cnt;  // d = 2 bucket tables (bucketed search only)
+  const uint4* bk_cand;
 };
 
 // One pass-B job: super tile t of a layer whose chunks start at keys / seg.
@@ -346,7 +348,7 @@ __device__ __forceinline__ void guide_chunk(const KeysJob& j, const GuideLds& g)
 // third of the scan's issue time; 8 records: 5 % faster; tiles of 16 and
 // groups of 2 or 4 tiles per running-best update: 2.5 %, 3.4 % and 20 %
 // slower at N = 2000).
-template <int D, int S, int KB>
+template <int D, int S, int KB, bool BK = false>
 __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   constexpr int kKeys = kChunk / KB;
   constexpr int kNdTile = kScanTile;
@@ -384,8 +386,17 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
       layer_pair<D>(L0, z, e, xs[s], ys[s]);
     }
     int ii[S], jj[S];
-    argmin_scan_tiled<D, S, kNdTile>(gk, P0, xs, ii);
-    argmin_scan_tiled<D, S, kNdTile>(gk1, P1, ys, jj);
+    if constexpr (BK && D == 2) {
+      // each sample's own bucket list (the same cells as the full scan)
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        ii[s] = cell_2d_buckets(gk, N0, L0, j.bk_cnt, j.bk_cand, xs[s][0], xs[s][1]);
+        jj[s] = cell_2d_buckets(gk1, N1, L1, j.bk_cnt, j.bk_cand, ys[s][0], ys[s][1]);
+      }
+    } else {
+      argmin_scan_tiled<D, S, kNdTile>(gk, P0, xs, ii);
+      argmin_scan_tiled<D, S, kNdTile>(gk1, P1, ys, jj);
+    }
     // the round is not unrolled, so its keys go to fixed registers by a
     // uniform select (a dynamic index would put the array in scratch)
 #pragma unroll
@@ -507,6 +518,8 @@ __device__ __forceinline__ KeysJob plan_job(const FwdArgs& a, int k, int c) {
   j.hi = a.m0 + a.M;
   j.keys = a.keys + ((size_t)k * a.chunks + c) * kChunk;
   j.seg = a.segs + ((size_t)k * a.chunks + c) * a.seg_stride;
+  j.bk_cnt = a.bk_cnt;
+  j.bk_cand = a.bk_cand;
   return j;
 }
 
@@ -533,12 +546,12 @@ __global__ __launch_bounds__(kBlock) void fwd_keys_1d_guide(FwdArgs a) {
   guide_chunk<kBlock, GK, S>(j, g);
 }
 
-template <int D, int S>
+template <int D, int S, bool BK = false>
 __global__ __launch_bounds__(kBlockNd) void fwd_keys_nd(FwdArgs a) {
   extern __shared__ float4 lds4[];
   int k, c;
   if (!unit_of_block_keys(a, k, c)) return;
-  keys_chunk_nd<D, S, kBlockNd>(plan_job(a, k, c), lds4);
+  keys_chunk_nd<D, S, kBlockNd, BK>(plan_job(a, k, c), lds4);
 }
 
 // Workgroup b owns histogram unit tile0 + u (super tile t of layer k, or
@@ -620,6 +633,8 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
       j.hi = C.M;
       j.keys = a.keys + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
       j.seg = a.segs + (size_t)C.seg_base + ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
+      j.bk_cnt = C.bk_cnt;
+      j.bk_cand = C.bk_cand;
       body(C, j);
     }
   }
@@ -648,11 +663,11 @@ __global__ __launch_bounds__(kBlock) void batch_keys_1d_guide(BatchArgs a) {
   });
 }
 
-template <int DMAX, int S2>
+template <int DMAX, int S2, bool BK = false>
 __global__ __launch_bounds__(kBlockNd) void batch_keys_nd(BatchArgs a) {
   extern __shared__ float4 lds4[];
   batch_loop<kBlockNd>(a, [&](const BatchContract& C, const KeysJob& j) {
-    if (DMAX < 3 || C.d == 2) keys_chunk_nd<2, S2, kBlockNd>(j, lds4);
+    if (DMAX < 3 || C.d == 2) keys_chunk_nd<2, S2, kBlockNd, BK>(j, lds4);
     else keys_chunk_nd<3, 4, kBlockNd>(j, lds4);
   });
 }
@@ -751,6 +766,15 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
         if ((e = allow_lds(fwd_keys_1d<0>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(fwd_keys_1d<0>, keys_grid(a), dim3(kBlock), lds, s, a);
     }
+  } else if (a.d == 2 && a.bucketed && a.nd_samples == 4) {
+    const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
+    if ((e = allow_lds(fwd_keys_nd<2, 4, true>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_keys_nd<2, 4, true>), keys_grid(a), dim3(kBlockNd), lds, s, a);
+  } else if (a.d == 2 && a.bucketed) {
+    const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
+    if ((e = allow_lds(fwd_keys_nd<2, kSamplesNd2, true>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_keys_nd<2, kSamplesNd2, true>), keys_grid(a), dim3(kBlockNd), lds, s,
+                       a);
   } else if (a.d == 2 && a.nd_samples == 4) {
     const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
     if ((e = allow_lds(fwd_keys_nd<2, 4>, lds)) != hipSuccess) return e;
@@ -846,24 +870,29 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
 #undef QTREE_LAUNCH_1D
     if (e != hipSuccess) return e;
   } else {
-#define QTREE_LAUNCH_ND(DM, S2)                                                            \
-  if ((e = allow_lds(batch_keys_nd<DM, S2>, lds)) != hipSuccess) return e;                 \
-  hipLaunchKernelGGL((batch_keys_nd<DM, S2>), dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
-    if (dmax == 2 && a.nd_samples == 4) {
-      QTREE_LAUNCH_ND(2, 4)
+#define QTREE_LAUNCH_ND(DM, S2, BK)                                                          \
+  if ((e = allow_lds(batch_keys_nd<DM, S2, BK>, lds)) != hipSuccess) return e;               \
+  hipLaunchKernelGGL((batch_keys_nd<DM, S2, BK>), dim3((unsigned)grid), dim3(kBlockNd), lds, s, \
+                     a);
+    if (dmax == 2 && a.bucketed && a.nd_samples == 4) {
+      QTREE_LAUNCH_ND(2, 4, true)
+    } else if (dmax == 2 && a.bucketed) {
+      QTREE_LAUNCH_ND(2, kSamplesNd2, true)
+    } else if (dmax == 2 && a.nd_samples == 4) {
+      QTREE_LAUNCH_ND(2, 4, false)
     } else if (dmax == 2) {
-      QTREE_LAUNCH_ND(2, kSamplesNd2)
+      QTREE_LAUNCH_ND(2, kSamplesNd2, false)
     } else if (a.nd_samples == 4) {
-      QTREE_LAUNCH_ND(3, 4)
+      QTREE_LAUNCH_ND(3, 4, false)
     } else {
-      QTREE_LAUNCH_ND(3, kSamplesNd2)
+      QTREE_LAUNCH_ND(3, kSamplesNd2, false)
     }
 #undef QTREE_LAUNCH_ND
   }
   return hipGetLastError();
 }
 
-int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples) {
+int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples, int bucketed) {
   int blocks = 0;
   hipError_t e = hipSuccess;
   if (dmax <= 1 && gk >= 0) {
@@ -878,19 +907,23 @@ int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples) 
     QTREE_BATCH_1D_SWITCH(lg1, QTREE_OCC_1D)
 #undef QTREE_OCC_1D
   } else {
-#define QTREE_OCC_ND(DM, S2)                                                               \
-  e = allow_lds(batch_keys_nd<DM, S2>, lds);                                               \
-  if (e == hipSuccess)                                                                     \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_nd<DM, S2>, kBlockNd, \
-                                                     lds);
-    if (dmax == 2 && nd_samples == 4) {
-      QTREE_OCC_ND(2, 4)
+#define QTREE_OCC_ND(DM, S2, BK)                                                              \
+  e = allow_lds(batch_keys_nd<DM, S2, BK>, lds);                                              \
+  if (e == hipSuccess)                                                                        \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_nd<DM, S2, BK>,        \
+                                                     kBlockNd, lds);
+    if (dmax == 2 && bucketed && nd_samples == 4) {
+      QTREE_OCC_ND(2, 4, true)
+    } else if (dmax == 2 && bucketed) {
+      QTREE_OCC_ND(2, kSamplesNd2, true)
+    } else if (dmax == 2 && nd_samples == 4) {
+      QTREE_OCC_ND(2, 4, false)
     } else if (dmax == 2) {
-      QTREE_OCC_ND(2, kSamplesNd2)
+      QTREE_OCC_ND(2, kSamplesNd2, false)
     } else if (nd_samples == 4) {
-      QTREE_OCC_ND(3, 4)
+      QTREE_OCC_ND(3, 4, false)
     } else {
-      QTREE_OCC_ND(3, kSamplesNd2)
+      QTREE_OCC_ND(3, kSamplesNd2, false)
     }
 #undef QTREE_OCC_ND
   }

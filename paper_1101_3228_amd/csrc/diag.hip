@@ -50,7 +50,9 @@ __global__ void cells_1d_kernel(FwdArgs a, int k, const float* x, int64_t count,
 // whole kScanTile-record tiles with records whose key is +inf; kCellsS points
 // per lane share every record read (argmin_scan_tiled, tiles of kScanTile).
 constexpr int kCellsS = 8;
-template <int D>
+// With bucket tables (d = 2, BK): each point's bucket list, as the
+// forward's bucketed search.
+template <int D, bool BK = false>
 __global__ __launch_bounds__(kBlock) void cells_kernel(FwdArgs a, int k, const float* x,
                                                        int64_t count, int32_t* cell) {
   extern __shared__ float4 recs[];
@@ -70,7 +72,13 @@ __global__ __launch_bounds__(kBlock) void cells_kernel(FwdArgs a, int k, const f
 #pragma unroll
     for (int c = 0; c < D; ++c) q[s][c] = x[ii * D + c];
   }
-  argmin_scan_tiled<D, kCellsS, kScanTile>(recs, Npad, q, idx);
+  if constexpr (BK && D == 2) {
+#pragma unroll
+    for (int s = 0; s < kCellsS; ++s)
+      idx[s] = cell_2d_buckets(recs, N, L, a.bk_cnt, a.bk_cand, q[s][0], q[s][1]);
+  } else {
+    argmin_scan_tiled<D, kCellsS, kScanTile>(recs, Npad, q, idx);
+  }
 #pragma unroll
   for (int s = 0; s < kCellsS; ++s) {
     const int64_t i = base + (int64_t)s * kBlock;
@@ -144,13 +152,18 @@ hipError_t launch_cells(const FwdArgs& a, int k, const float* x, int64_t count, 
   }
   const unsigned blocks = (unsigned)((count + kBlock * kCellsS - 1) / (kBlock * kCellsS));
   const size_t lds = sizeof(float4) * (size_t)((a.maxN + kScanTile - 1) / kScanTile * kScanTile);
-  const void* fn = a.d == 2 ? reinterpret_cast<const void*>(cells_kernel<2>)
+  const bool bk = a.d == 2 && a.bucketed;
+  const void* fn = bk ? reinterpret_cast<const void*>(cells_kernel<2, true>)
+                 : a.d == 2 ? reinterpret_cast<const void*>(cells_kernel<2>)
                             : reinterpret_cast<const void*>(cells_kernel<3>);
   hipError_t e = lds <= 65536 ? hipSuccess
                               : hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                     (int)lds);
   if (e != hipSuccess) return e;
-  if (a.d == 2)
+  if (bk)
+    hipLaunchKernelGGL((cells_kernel<2, true>), dim3(blocks), dim3(kBlock), lds, s, a, k, x, count,
+                       cell);
+  else if (a.d == 2)
     hipLaunchKernelGGL((cells_kernel<2>), dim3(blocks), dim3(kBlock), lds, s, a, k, x, count, cell);
   else
     hipLaunchKernelGGL((cells_kernel<3>), dim3(blocks), dim3(kBlock), lds, s, a, k, x, count, cell);

@@ -22,6 +22,8 @@ struct BatchContract {
   int64_t seg_base;      // first segment word of layer 0 in the group scratch
   int32_t chunks;        // chunks per layer
   int32_t seg_stride;    // tiles of the contract's largest count block + 1
+  const uint16_t* bk_cnt;  // d = 2: the plan's bucket tables
+  const uint4* bk_cand;
 };
 
 // Pass-A work unit: chunks [chunk0, chunk0 + nchunks) of layer k of contract c.
@@ -45,6 +47,7 @@ struct BatchArgs {
   // tables of up to gt_Bmax entries, sub sub-counters per tile in the sort
   int32_t gk, sub, maxP, gt_Bmax;
   int32_t nd_samples;  // d >= 2 launch: samples per lane sharing each grid read (8 or 4)
+  int32_t bucketed;    // d = 2 launch (every d >= 2 contract 2-D with bucket tables)
   uint16_t* keys;
   uint32_t* segs;
 };
@@ -58,7 +61,7 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
 hipError_t launch_batch_count(const BatchArgs& a, hipStream_t s);
 // Workgroups of the pass-A kernel (dmax as above; gk >= 0: the 1-D guide
 // kernel) that fit on one CU with `lds` bytes of dynamic LDS each.
-int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples);
+int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples, int bucketed);
 size_t keys_lds_1d(int maxP, int max_tiles);
 size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles);
 int guide_sub_counters(int max_tiles);

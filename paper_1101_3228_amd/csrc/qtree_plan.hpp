@@ -23,6 +23,8 @@ struct qtree_plan {
   int32_t tune_groups = 0;  // layer groups of the two-pass forward (0: automatic)
   int32_t tune_nd_samples = 8;  // d >= 2 pass A: samples per lane sharing each grid read
   int32_t tune_tail = 100;      // last layer group's share, percent of the others
+  int32_t tune_buckets = 1;     // d = 2: cells through the bucket tables
+  int64_t buckets = 0;          // d = 2: buckets over all layers (0: no tables)
   int32_t max_tiles = 0, total_tiles = 0;
   std::vector<int32_t> tile_off;  // first super tile of every layer (host copy)
   std::vector<int32_t> unit_off;  // first histogram unit of every layer (host copy)

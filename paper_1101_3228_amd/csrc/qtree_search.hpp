@@ -201,6 +201,125 @@ __device__ __forceinline__ void argmin_scan_tiled(const float4* __restrict__ g, 
   }
 }
 
+// d = 2 cell of x by the layer's bucket tables: x's bucket lists every
+// point that can be the FP32 argmin of h - <x, g> anywhere in the bucket, in
+// increasing index (padded to a multiple of 8 with its first entry), so the
+// first minimum over the list is the full scan's cell (the lowest index of
+// the minimal key).  Outside the box, in a bucket whose candidates did not
+// fit, or in a layer without tables, the full scan over the N records.
+__device__ __forceinline__ int cell_2d_buckets(const float4* __restrict__ g, int N,
+                                               const LayerDev& L,
+                                               const uint16_t* __restrict__ cnt,
+                                               const uint4* __restrict__ cand, float x0,
+                                               float x1) {
+  const float f0 = (x0 - L.bk_lo[0]) * L.bk_scale[0];
+  const float f1 = (x1 - L.bk_lo[1]) * L.bk_scale[1];
+  // false for a layer without tables (bk_B = 0) and for NaN
+  const bool in = f0 >= 0.0f && f1 >= 0.0f && f0 < (float)L.bk_B[0] && f1 < (float)L.bk_B[1];
+  int c = kBucketFull;
+  int64_t slot = 0;
+  if (in) {
+    slot = (int64_t)L.bk_off + (int64_t)((int)f0 * L.bk_B[1] + (int)f1);
+    c = cnt[slot];
+  }
+  float best = __builtin_huge_valf();
+  int idx = 0;
+  if (c != kBucketFull) {
+    const uint4* lst = cand + slot * (kBucketCap / 8);
+    for (int q = 0; q < c; q += 8) {
+      const uint4 w = lst[q >> 3];
+      const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int p = (int)((ww[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
+        const float4 r = g[p];
+        const float key = fmaf(-x1, r.y, fmaf(-x0, r.x, r.w));
+        const bool lt = key < best;
+        best = lt ? key : best;
+        idx = lt ? p : idx;
+      }
+    }
+  } else {
+    for (int p = 0; p < N; ++p) {
+      const float4 r = g[p];
+      const float key = fmaf(-x1, r.y, fmaf(-x0, r.x, r.w));
+      const bool lt = key < best;
+      best = lt ? key : best;
+      idx = lt ? p : idx;
+    }
+  }
+  return idx;
+}
+
+// The same for S points at once: the list entries of all S points are read
+// together (their loads overlap) and walked in step, groups of 4 at a time; a
+// point whose list is shorter re-reads its first group (a repeated candidate
+// never wins a strict comparison).  Points outside the box or in a full
+// bucket take the full scan afterwards.
+template <int S>
+__device__ __forceinline__ void cells_2d_buckets_joint(const float4* __restrict__ g, int N,
+                                                       const LayerDev& L,
+                                                       const uint16_t* __restrict__ cnt,
+                                                       const uint2* __restrict__ cand,
+                                                       const float (*xs)[2], int* idx) {
+  int c[S];
+  const uint2* lst[S];
+  float best[S];
+  int cmax = 0;
+  bool full = L.bk_B[0] == 0;  // a layer without tables: every point scans
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const float f0 = (xs[s][0] - L.bk_lo[0]) * L.bk_scale[0];
+    const float f1 = (xs[s][1] - L.bk_lo[1]) * L.bk_scale[1];
+    const bool in =
+        f0 >= 0.0f && f1 >= 0.0f && f0 < (float)L.bk_B[0] && f1 < (float)L.bk_B[1];
+    // outside: the layer's first bucket, whose entries are valid indices for
+    // the re-reads below (a layer without tables reads nothing: cmax = 0)
+    const int64_t slot = (int64_t)L.bk_off + (in ? (int64_t)((int)f0 * L.bk_B[1] + (int)f1) : 0);
+    c[s] = in ? (int)cnt[slot] : (int)kBucketFull;
+    lst[s] = cand + slot * (kBucketCap / 4);
+    full = full || c[s] == (int)kBucketFull;
+    const int cs = c[s] == (int)kBucketFull ? 0 : c[s];
+    cmax = cs > cmax ? cs : cmax;
+    best[s] = __builtin_huge_valf();
+    idx[s] = 0;
+  }
+  for (int q = 0; q < cmax; q += 4) {
+    uint2 w[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) w[s] = lst[s][q < c[s] && c[s] != (int)kBucketFull ? q >> 2 : 0];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t ww[2] = {w[s].x, w[s].y};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int p = (int)((ww[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
+        const float4 r = g[p];
+        const float key = fmaf(-xs[s][1], r.y, fmaf(-xs[s][0], r.x, r.w));
+        const bool lt = key < best[s];
+        best[s] = lt ? key : best[s];
+        idx[s] = lt ? p : idx[s];
+      }
+    }
+  }
+  if (full) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (c[s] != (int)kBucketFull) continue;
+      float b = __builtin_huge_valf();
+      int bi = 0;
+      for (int p = 0; p < N; ++p) {
+        const float4 r = g[p];
+        const float key = fmaf(-xs[s][1], r.y, fmaf(-xs[s][0], r.x, r.w));
+        const bool lt = key < b;
+        b = lt ? key : b;
+        bi = lt ? p : bi;
+      }
+      idx[s] = bi;
+    }
+  }
+}
+
 // Standard normals z (for X_k) and eps (for the innovation) of LAYERWISE
 // sample m of layer k.  Philox counter (block, k, contract, tag): d = 1 uses
 // block m >> 1 and the Box-Muller pair m & 1; d = 2 block m; d = 3 blocks
