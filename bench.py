@@ -410,7 +410,7 @@ def alg_slots_pair(d: int, Nk: int, Nk1: int, guide_k: int = 2) -> float:
     return ALG_SLOTS_2D_PAIR + ALG_SLOTS_2D_POINT * (Nk + Nk1)
 
 
-def bucketed_search_slots(plan, k: int, x) -> float:
+def bucketed_search_slots(plan, k: int, x, cache: dict | None = None) -> float:
     """Mean algorithmic lane-slots of the d = 2 bucketed search of device
     points x [count, 2] in layer k: the bucket is found in FP32 as the
     kernel finds it, then priced by its listed candidates (not the padding
@@ -419,7 +419,12 @@ def bucketed_search_slots(plan, k: int, x) -> float:
     n_k = int(plan.N[k])
     if B[0] == 0:
         return BUCKET_LOCATE + SCAN_POINT * n_k
-    cnt = plan.bucket_counts(k).astype(np.int64)
+    if cache is not None and k in cache:
+        cnt = cache[k]
+    else:
+        cnt = plan.bucket_counts(k).astype(np.int64)
+        if cache is not None:
+            cache[k] = cnt
     xf = x.cpu().numpy().astype(np.float32)
     f = ((xf - lo.astype(np.float32)) * sc.astype(np.float32)).astype(np.float32)
     inside = np.all((f >= 0) & (f < B.astype(np.float32)), axis=1)
@@ -435,11 +440,12 @@ def bucketed_pair_slots(plan, samples: int = 65_536, seed: int = 0x5EED0C00) -> 
     plan (ALG_SLOTS_2D_PAIR plus both searches), the searches priced on
     the layer samples 0..samples-1 of the given seed."""
     import paper_1101_3228_amd as qt
-    out = []
+    out, cache = [], {}
     for k in range(plan.n):
         xs, ys = qt.layer_samples(plan, k, 0, samples, seed)
-        out.append(ALG_SLOTS_2D_PAIR + bucketed_search_slots(plan, k, xs)
-                   + bucketed_search_slots(plan, k + 1, ys))
+        out.append(ALG_SLOTS_2D_PAIR + bucketed_search_slots(plan, k, xs, cache)
+                   + bucketed_search_slots(plan, k + 1, ys, cache))
+        cache.pop(k, None)
     return out
 
 
@@ -502,10 +508,10 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
     if bucketed:
         per_layer = bucketed_pair_slots(plan)
         alg = M * float(np.sum(per_layer))
-        kernel = "fwd_keys_nd<2, 8, bucketed>"
+        kernel = f"fwd_keys_nd<2, {plan.tuning()['nd_samples']}, bucketed>"
     else:
         alg = ALG_SLOTS_2D_PAIR * pairs + ALG_SLOTS_2D_POINT * points
-        kernel = "fwd_keys_nd<2, 8>"
+        kernel = f"fwd_keys_nd<2, {plan.tuning()['nd_samples']}>"
     achieved = alg / (keys_ms * 1e-3)
     V0 = V[:, 0].cpu().numpy()
     out = {
@@ -610,7 +616,10 @@ def run_batch(args):
     options = sum(it["phi"].shape[0] for it in items)
     info = batch.info()
     alg = 0.0
-    for sp, it in zip(specs, items):
+    log("pricing the step's algorithmic work")
+    for i, (sp, it) in enumerate(zip(specs, items)):
+        if (i + 1) % 64 == 0:
+            log(f"priced {i + 1}/{len(specs)} contracts")
         Ns = [int(np.prod(v)) for v in sp["sizes"]]
         if sp["d"] == 2 and it["plan"].tuning()["buckets"] > 0:
             # the batch searches d = 2 contracts through their bucket tables

@@ -90,10 +90,17 @@ bool two_pass_fits(int d, int n, const int32_t* N) {
 
 // Buckets of the d = 2 cell search over all layers (layers of one point
 // have none).
+// Layers take bucket tables in order while the rows so far stay within
+// int32 indices; later layers (beyond about 32 000 layers of 4096 points)
+// keep the full scan.  bucket_boxes follows the same rule.
+constexpr int64_t kMaxBuckets = 0x7FFFFFFF;
 int64_t total_buckets(int n, const int32_t* N) {
   int64_t b = 0;
-  for (int k = 0; k <= n; ++k)
-    if (N[k] > 1) b += (int64_t)bucket_side(N[k]) * bucket_side(N[k]);
+  for (int k = 0; k <= n; ++k) {
+    if (N[k] <= 1) continue;
+    const int64_t b2 = (int64_t)bucket_side(N[k]) * bucket_side(N[k]);
+    if (b + b2 <= kMaxBuckets) b += b2;
+  }
   return b;
 }
 
@@ -122,10 +129,8 @@ WsLayout ws_layout(int d, int n, const int32_t* N, int64_t batch_chunks) {
                    256);
   }
   const int64_t buckets = d == 2 ? total_buckets(n, N) : 0;
-  l.bk_cnt = off;
-  off = align_up(off + sizeof(uint16_t) * (size_t)buckets, 256);
-  l.bk_cand = off;
-  off = align_up(off + sizeof(uint16_t) * kBucketCap * (size_t)buckets, 256);
+  l.bk_rows = off;
+  off = align_up(off + sizeof(uint16_t) * kBucketRow * (size_t)buckets, 256);
   // scratch of the two-pass counting (only when every count block has at
   // most kMaxTiles tiles)
   const int mt = max_tiles_of(n, N);
@@ -361,6 +366,8 @@ static void bucket_boxes(qtree_plan& p, const qtree_model* model, const float* g
     L.bk_B[0] = L.bk_B[1] = 0;
     L.bk_off = (int32_t)off;
     if (p.N[k] <= 1) continue;
+    const int B = qtree::bucket_side(p.N[k]);
+    if (off + (int64_t)B * B > qtree::kMaxBuckets) continue;
     double lo[2], hi[2];
     for (int r = 0; r < 2; ++r) {
       lo[r] = slo[(size_t)k * 2 + r];
@@ -387,7 +394,6 @@ static void bucket_boxes(qtree_plan& p, const qtree_model* model, const float* g
         lo[r] = std::min(lo[r], (double)g[(size_t)i * 2 + r]);
         hi[r] = std::max(hi[r], (double)g[(size_t)i * 2 + r]);
       }
-    const int B = qtree::bucket_side(p.N[k]);
     for (int r = 0; r < 2; ++r) {
       const double m = 1e-3 * (hi[r] - lo[r]) + 1e-6 * (1.0 + std::fabs(lo[r]) + std::fabs(hi[r]));
       lo[r] -= m;
@@ -583,12 +589,11 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(workspace)");
   p.ws = static_cast<char*>(workspace);
   if (p.buckets > 0) {
-    // the candidate lists, from the records just uploaded
+    // the bucket rows, from the records just uploaded
     e = qtree::launch_bucket_build(
-        reinterpret_cast<const qtree::LayerDev*>(p.ws + p.lay.layers), n + 1, nullptr,
-        (int)p.buckets, reinterpret_cast<const float4*>(p.ws + p.lay.points),
-        reinterpret_cast<uint16_t*>(p.ws + p.lay.bk_cnt),
-        reinterpret_cast<uint16_t*>(p.ws + p.lay.bk_cand), nullptr);
+        reinterpret_cast<const qtree::LayerDev*>(p.ws + p.lay.layers), n + 1, (int)p.buckets,
+        reinterpret_cast<const float4*>(p.ws + p.lay.points),
+        reinterpret_cast<uint16_t*>(p.ws + p.lay.bk_rows), nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) return hip_fail(e, "bucket tables");
   }
@@ -633,8 +638,7 @@ static qtree::FwdArgs fwd_args(const qtree_plan* p, uint64_t m0, uint64_t M, uin
   a.total_tiles = p->unit_off[p->n];
   a.nd_samples = p->tune_nd_samples;
   a.bucketed = (p->buckets > 0 && p->tune_buckets) ? 1 : 0;
-  a.bk_cnt = reinterpret_cast<const uint16_t*>(p->ws + p->lay.bk_cnt);
-  a.bk_cand = reinterpret_cast<const uint4*>(p->ws + p->lay.bk_cand);
+  a.bk_rows = reinterpret_cast<const uint4*>(p->ws + p->lay.bk_rows);
   return a;
 }
 
@@ -798,10 +802,20 @@ qtree_status qtree_plan_bucket_counts(const qtree_plan* plan, int32_t k, uint16_
   qtree::LayerDev L{};
   hipError_t e = hipMemcpy(&L, plan->ws + plan->lay.layers + sizeof(qtree::LayerDev) * (size_t)k,
                            sizeof(L), hipMemcpyDeviceToHost);
+  const size_t nb = (size_t)B[0] * (size_t)B[1];
+  std::vector<uint16_t> rows;
+  try {
+    rows.resize(nb * qtree::kBucketRow);
+  } catch (const std::bad_alloc&) {
+    return fail(QTREE_ENOMEM, "host copy of the bucket rows");
+  }
   if (e == hipSuccess)
-    e = hipMemcpy(counts, plan->ws + plan->lay.bk_cnt + sizeof(uint16_t) * (size_t)L.bk_off,
-                  sizeof(uint16_t) * (size_t)B[0] * (size_t)B[1], hipMemcpyDeviceToHost);
-  return e == hipSuccess ? QTREE_OK : hip_fail(e, "bucket counts copy");
+    e = hipMemcpy(rows.data(),
+                  plan->ws + plan->lay.bk_rows + sizeof(uint16_t) * qtree::kBucketRow * (size_t)L.bk_off,
+                  sizeof(uint16_t) * rows.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "bucket rows copy");
+  for (size_t t = 0; t < nb; ++t) counts[t] = rows[t * qtree::kBucketRow];  // entry 0: the count
+  return QTREE_OK;
 }
 
 qtree_status qtree_plan_cell_search(const qtree_plan* plan, int32_t* guide_k,

@@ -399,8 +399,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     bc.chunks = p->d == 1 ? (int32_t)(((C.M + 1) / 2 + qtree::kChunk / 2 - 1) / (qtree::kChunk / 2))
                           : (int32_t)((C.M + qtree::kChunk - 1) / qtree::kChunk);
     bc.seg_stride = p->max_tiles + 1;
-    bc.bk_cnt = reinterpret_cast<const uint16_t*>(p->ws + p->lay.bk_cnt);
-    bc.bk_cand = reinterpret_cast<const uint4*>(p->ws + p->lay.bk_cand);
+    bc.bk_rows = reinterpret_cast<const uint4*>(p->ws + p->lay.bk_rows);
     // the d = 2 launch searches through bucket tables when every 2-D
     // contract has them (results are the same either way)
     if (p->d == 2 && !(p->buckets > 0 && p->tune_buckets)) b->bucketed = 0;

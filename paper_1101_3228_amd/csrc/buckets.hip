@@ -9,8 +9,11 @@
 // g_p to R; so every p with lo_p <= U + 4 E_R (E_R the bound over R, doubled
 // here for margin) is kept.  R is the bucket widened by 1/64 of its width
 // on every side, more than the FP32 rounding of the bucket index can move a
-// point.  FP64 throughout; a list longer than kBucketCap marks the bucket
-// full (the search then scans every point).
+// point.  FP64 throughout.  Row t: entry 0 the count c, entries 1..c the
+// candidates in increasing index, then the layer's point count N (the
+// search's pad record, which never wins) to the end of the last 8-entry
+// group; more than kBucketCap candidates mark the bucket full (entry 0 =
+// kBucketFull: the search then scans every point).
 #include "qtree_internal.hpp"
 
 namespace qtree {
@@ -21,7 +24,7 @@ constexpr int kBlock = 256;
 
 __global__ __launch_bounds__(kBlock) void bucket_build_kernel(const LayerDev* layers, int nl,
                                                               int total, const float4* pts,
-                                                              uint16_t* cnt, uint16_t* cand) {
+                                                              uint16_t* rows) {
   const int t = (int)(blockIdx.x * kBlock + threadIdx.x);
   if (t >= total) return;
   int lo = 0, hi = nl - 1;  // the layer holding bucket t: largest k with bk_off_k <= t
@@ -51,33 +54,33 @@ __global__ __launch_bounds__(kBlock) void bucket_build_kernel(const LayerDev* la
   const double X0 = fmax(fabs(a0), fabs(b0)), X1 = fmax(fabs(a1), fabs(b1));
   const double E = 2.0 * 4.1 * 0x1p-24 * (hmax + X0 * G0 + X1 * G1);
   const double thr = U * (1.0 + 1e-9) + 4.0 * E;
-  uint16_t* out = cand + (int64_t)t * kBucketCap;
+  uint16_t* out = rows + (int64_t)t * kBucketRow;
   int c = 0;
   for (int p = 0; p < L.N; ++p) {
     const float4 q = g[p];
     const double e0 = fmax(0.0, fmax(a0 - (double)q.x, (double)q.x - b0));
     const double e1 = fmax(0.0, fmax(a1 - (double)q.y, (double)q.y - b1));
     if (e0 * e0 + e1 * e1 <= thr) {
-      if (c < kBucketCap) out[c] = (uint16_t)p;
+      if (c < kBucketCap) out[1 + c] = (uint16_t)p;
       ++c;
     }
   }
   if (c > kBucketCap) {
-    cnt[t] = kBucketFull;
+    out[0] = kBucketFull;
     return;
   }
-  // pad to a multiple of 8 with the first (lowest) candidate: a repeat never
-  // wins a strict comparison, and the search reads whole groups of 8
-  for (int q = c; q < ((c + 7) & ~7); ++q) out[q] = out[0];
-  cnt[t] = (uint16_t)c;
+  // c >= 1: the point whose farthest corner distance is U lies within U.
+  // The search reads whole groups of 8 entries; the pads all name one
+  // record, so the lanes of a wave that read it share one LDS access.
+  for (int q = 1 + c; q < ((c + 8) & ~7); ++q) out[q] = (uint16_t)L.N;
+  out[0] = (uint16_t)c;
 }
 
-hipError_t launch_bucket_build(const LayerDev* layers, int n_layers_total,
-                               const int32_t* /*bucket_layer_off*/, int total_buckets,
-                               const float4* pts, uint16_t* cnt, uint16_t* cand, hipStream_t s) {
+hipError_t launch_bucket_build(const LayerDev* layers, int n_layers_total, int total_buckets,
+                               const float4* pts, uint16_t* rows, hipStream_t s) {
   if (total_buckets <= 0) return hipSuccess;
   hipLaunchKernelGGL(bucket_build_kernel, dim3((unsigned)((total_buckets + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, s, layers, n_layers_total, total_buckets, pts, cnt, cand);
+                     dim3(kBlock), 0, s, layers, n_layers_total, total_buckets, pts, rows);
   return hipGetLastError();
 }
 

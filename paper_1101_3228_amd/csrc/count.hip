@@ -41,6 +41,10 @@ constexpr int kBlockNd = 512;    // pass-A workgroup, d >= 2 (two waves per SIMD
 // the LDS reads of 4 at 90 VGPRs, 9 % faster on the 2-D workload); d = 3
 // keeps 4 (three coordinates per sample)
 constexpr int kSamplesNd2 = 8;
+// samples per lane of the d = 2 bucketed search (the tuned choice between
+// the two): the first-group reads of all 2 S searches of a round are in
+// flight together, so S sets the registers and the overlap of LDS reads
+constexpr int kBkSamplesLo = 2, kBkSamplesHi = 4;
 constexpr int kCountBlock = 1024;
 constexpr int kGuideSub = 4;         // sub-counters per tile in the guide kernel's sort
 constexpr int kGuideSubTiles = 256;  // ... when a layer has at most this many tiles
@@ -57,8 +61,7 @@ struct KeysJob {
   uint64_t lo, hi;
   uint16_t* keys;  // kChunk slots of this chunk
   uint32_t* seg;   // T + 1 segment starts of this chunk
-  const uint16_t* bk_cnt;  // d = 2 bucket tables (bucketed search only)
-  const uint4* bk_cand;
+  const uint4* bk_rows;  // d = 2 bucket rows (bucketed search only)
 };
 
 // One pass-B job: super tile t of a layer whose chunks start at keys / seg.
@@ -358,14 +361,33 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   // both grids padded to whole scan tiles with records whose key is +inf
   const int P0 = (N0 + kScanTile - 1) / kScanTile * kScanTile;
   const int P1 = (N1 + kScanTile - 1) / kScanTile * kScanTile;
+  // the scan: 16-byte records (x, .., h); the bucketed search: (x, y)
+  // pairs and the pad pair at N, each layer's block a whole number of 16
+  // bytes
+  constexpr bool kXY = BK && D == 2;
+  const int Q0 = kXY ? (N0 + 2) / 2 : P0, Q1 = kXY ? (N1 + 2) / 2 : P1;
   float4* gk = lds4;
-  float4* gk1 = lds4 + P0;
-  uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + P0 + P1);
+  float4* gk1 = lds4 + Q0;
+  float2* xy0 = reinterpret_cast<float2*>(gk);
+  float2* xy1 = reinterpret_cast<float2*>(gk1);
+  uint16_t* stage = reinterpret_cast<uint16_t*>(lds4 + Q0 + Q1);
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
-  const float4 pad = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
-  for (int i = threadIdx.x; i < P0; i += KB) gk[i] = i < N0 ? j.pts[L0.pt_off + i] : pad;
-  for (int i = threadIdx.x; i < P1; i += KB) gk1[i] = i < N1 ? j.pts[L1.pt_off + i] : pad;
+  if constexpr (kXY) {
+    const float2 nan2 = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    for (int i = threadIdx.x; i <= N0; i += KB) {
+      const float4 r = i < N0 ? j.pts[L0.pt_off + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      xy0[i] = i < N0 ? make_float2(r.x, r.y) : nan2;
+    }
+    for (int i = threadIdx.x; i <= N1; i += KB) {
+      const float4 r = i < N1 ? j.pts[L1.pt_off + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      xy1[i] = i < N1 ? make_float2(r.x, r.y) : nan2;
+    }
+  } else {
+    const float4 pad = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
+    for (int i = threadIdx.x; i < P0; i += KB) gk[i] = i < N0 ? j.pts[L0.pt_off + i] : pad;
+    for (int i = threadIdx.x; i < P1; i += KB) gk1[i] = i < N1 ? j.pts[L1.pt_off + i] : pad;
+  }
   for (int t = threadIdx.x; t <= T; t += KB) tcount[t] = 0;
   __syncthreads();
 
@@ -387,12 +409,17 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
     }
     int ii[S], jj[S];
     if constexpr (BK && D == 2) {
-      // each sample's own bucket list (the same cells as the full scan)
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        ii[s] = cell_2d_buckets(gk, N0, L0, j.bk_cnt, j.bk_cand, xs[s][0], xs[s][1]);
-        jj[s] = cell_2d_buckets(gk1, N1, L1, j.bk_cnt, j.bk_cand, ys[s][0], ys[s][1]);
-      }
+      // each sample's own bucket list (the same cells as the full scan); the
+      // rows of all 2 S searches are fetched before the first is walked
+      int sx[S], sy[S];
+      uint4 wx[S], wy[S];
+      bucket_rows<S>(L0, j.bk_rows, xs, sx, wx);
+      bucket_rows<S>(L1, j.bk_rows, ys, sy, wy);
+      float bx[S], by[S];
+      bucket_first<S>(xy0, N0, xs, sx, wx, bx, ii);
+      bucket_first<S>(xy1, N1, ys, sy, wy, by, jj);
+      bucket_rest<S>(xy0, N0, j.bk_rows, xs, sx, wx, bx, ii);
+      bucket_rest<S>(xy1, N1, j.bk_rows, ys, sy, wy, by, jj);
     } else {
       argmin_scan_tiled<D, S, kNdTile>(gk, P0, xs, ii);
       argmin_scan_tiled<D, S, kNdTile>(gk1, P1, ys, jj);
@@ -518,8 +545,7 @@ __device__ __forceinline__ KeysJob plan_job(const FwdArgs& a, int k, int c) {
   j.hi = a.m0 + a.M;
   j.keys = a.keys + ((size_t)k * a.chunks + c) * kChunk;
   j.seg = a.segs + ((size_t)k * a.chunks + c) * a.seg_stride;
-  j.bk_cnt = a.bk_cnt;
-  j.bk_cand = a.bk_cand;
+  j.bk_rows = a.bk_rows;
   return j;
 }
 
@@ -633,8 +659,7 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
       j.hi = C.M;
       j.keys = a.keys + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
       j.seg = a.segs + (size_t)C.seg_base + ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
-      j.bk_cnt = C.bk_cnt;
-      j.bk_cand = C.bk_cand;
+      j.bk_rows = C.bk_rows;
       body(C, j);
     }
   }
@@ -663,13 +688,27 @@ __global__ __launch_bounds__(kBlock) void batch_keys_1d_guide(BatchArgs a) {
   });
 }
 
-template <int DMAX, int S2, bool BK = false>
-__global__ __launch_bounds__(kBlockNd) void batch_keys_nd(BatchArgs a) {
+template <int DMAX, int S2, bool BK>
+__device__ __forceinline__ void batch_keys_nd_body(const BatchArgs& a) {
   extern __shared__ float4 lds4[];
   batch_loop<kBlockNd>(a, [&](const BatchContract& C, const KeysJob& j) {
     if (DMAX < 3 || C.d == 2) keys_chunk_nd<2, S2, kBlockNd, BK>(j, lds4);
     else keys_chunk_nd<3, 4, kBlockNd>(j, lds4);
   });
+}
+
+template <int DMAX, int S2>
+__global__ __launch_bounds__(kBlockNd) void batch_keys_nd(BatchArgs a) {
+  batch_keys_nd_body<DMAX, S2, false>(a);
+}
+
+// The bucketed d = 2 search, held to 128 VGPRs (four waves per SIMD) so that
+// two workgroups share a CU: the contract table's registers otherwise leave
+// room for one.
+template <int S2>
+__global__ __launch_bounds__(kBlockNd) __attribute__((amdgpu_waves_per_eu(4)))
+void batch_keys_nd_bk(BatchArgs a) {
+  batch_keys_nd_body<2, S2, true>(a);
 }
 
 // Pass B of a batch: workgroup b handles tile record b.
@@ -768,12 +807,13 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
     }
   } else if (a.d == 2 && a.bucketed && a.nd_samples == 4) {
     const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
-    if ((e = allow_lds(fwd_keys_nd<2, 4, true>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL((fwd_keys_nd<2, 4, true>), keys_grid(a), dim3(kBlockNd), lds, s, a);
+    if ((e = allow_lds(fwd_keys_nd<2, kBkSamplesLo, true>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_keys_nd<2, kBkSamplesLo, true>), keys_grid(a), dim3(kBlockNd), lds, s,
+                       a);
   } else if (a.d == 2 && a.bucketed) {
     const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
-    if ((e = allow_lds(fwd_keys_nd<2, kSamplesNd2, true>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL((fwd_keys_nd<2, kSamplesNd2, true>), keys_grid(a), dim3(kBlockNd), lds, s,
+    if ((e = allow_lds(fwd_keys_nd<2, kBkSamplesHi, true>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_keys_nd<2, kBkSamplesHi, true>), keys_grid(a), dim3(kBlockNd), lds, s,
                        a);
   } else if (a.d == 2 && a.nd_samples == 4) {
     const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
@@ -870,22 +910,21 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
 #undef QTREE_LAUNCH_1D
     if (e != hipSuccess) return e;
   } else {
-#define QTREE_LAUNCH_ND(DM, S2, BK)                                                          \
-  if ((e = allow_lds(batch_keys_nd<DM, S2, BK>, lds)) != hipSuccess) return e;               \
-  hipLaunchKernelGGL((batch_keys_nd<DM, S2, BK>), dim3((unsigned)grid), dim3(kBlockNd), lds, s, \
-                     a);
+#define QTREE_LAUNCH_ND(KER)                                                                 \
+  if ((e = allow_lds(KER, lds)) != hipSuccess) return e;                                     \
+  hipLaunchKernelGGL((KER), dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
     if (dmax == 2 && a.bucketed && a.nd_samples == 4) {
-      QTREE_LAUNCH_ND(2, 4, true)
+      QTREE_LAUNCH_ND(batch_keys_nd_bk<kBkSamplesLo>)
     } else if (dmax == 2 && a.bucketed) {
-      QTREE_LAUNCH_ND(2, kSamplesNd2, true)
+      QTREE_LAUNCH_ND(batch_keys_nd_bk<kBkSamplesHi>)
     } else if (dmax == 2 && a.nd_samples == 4) {
-      QTREE_LAUNCH_ND(2, 4, false)
+      QTREE_LAUNCH_ND((batch_keys_nd<2, 4>))
     } else if (dmax == 2) {
-      QTREE_LAUNCH_ND(2, kSamplesNd2, false)
+      QTREE_LAUNCH_ND((batch_keys_nd<2, kSamplesNd2>))
     } else if (a.nd_samples == 4) {
-      QTREE_LAUNCH_ND(3, 4, false)
+      QTREE_LAUNCH_ND((batch_keys_nd<3, 4>))
     } else {
-      QTREE_LAUNCH_ND(3, kSamplesNd2, false)
+      QTREE_LAUNCH_ND((batch_keys_nd<3, kSamplesNd2>))
     }
 #undef QTREE_LAUNCH_ND
   }
@@ -907,23 +946,21 @@ int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples, 
     QTREE_BATCH_1D_SWITCH(lg1, QTREE_OCC_1D)
 #undef QTREE_OCC_1D
   } else {
-#define QTREE_OCC_ND(DM, S2, BK)                                                              \
-  e = allow_lds(batch_keys_nd<DM, S2, BK>, lds);                                              \
-  if (e == hipSuccess)                                                                        \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_keys_nd<DM, S2, BK>,        \
-                                                     kBlockNd, lds);
+#define QTREE_OCC_ND(KER)                                                                   \
+  e = allow_lds(KER, lds);                                                                   \
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, KER, kBlockNd, lds);
     if (dmax == 2 && bucketed && nd_samples == 4) {
-      QTREE_OCC_ND(2, 4, true)
+      QTREE_OCC_ND(batch_keys_nd_bk<kBkSamplesLo>)
     } else if (dmax == 2 && bucketed) {
-      QTREE_OCC_ND(2, kSamplesNd2, true)
+      QTREE_OCC_ND(batch_keys_nd_bk<kBkSamplesHi>)
     } else if (dmax == 2 && nd_samples == 4) {
-      QTREE_OCC_ND(2, 4, false)
+      QTREE_OCC_ND((batch_keys_nd<2, 4>))
     } else if (dmax == 2) {
-      QTREE_OCC_ND(2, kSamplesNd2, false)
+      QTREE_OCC_ND((batch_keys_nd<2, kSamplesNd2>))
     } else if (nd_samples == 4) {
-      QTREE_OCC_ND(3, 4, false)
+      QTREE_OCC_ND((batch_keys_nd<3, 4>))
     } else {
-      QTREE_OCC_ND(3, kSamplesNd2, false)
+      QTREE_OCC_ND((batch_keys_nd<3, kSamplesNd2>))
     }
 #undef QTREE_OCC_ND
   }

@@ -59,8 +59,16 @@ __global__ __launch_bounds__(kBlock) void cells_kernel(FwdArgs a, int k, const f
   const LayerDev& L = a.layers[k];
   const int N = L.N;
   const int Npad = (N + kScanTile - 1) / kScanTile * kScanTile;
-  const float4 pad = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
-  for (int r = threadIdx.x; r < Npad; r += kBlock) recs[r] = r < N ? a.pts[L.pt_off + r] : pad;
+  float2* xy = reinterpret_cast<float2*>(recs);  // the bucketed search's (x, y) pairs
+  if constexpr (BK && D == 2) {
+    for (int r = threadIdx.x; r <= N; r += kBlock) {  // and the pad pair at N
+      const float4 g = r < N ? a.pts[L.pt_off + r] : make_float4(0.f, 0.f, 0.f, 0.f);
+      xy[r] = r < N ? make_float2(g.x, g.y) : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    }
+  } else {
+    const float4 pad = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
+    for (int r = threadIdx.x; r < Npad; r += kBlock) recs[r] = r < N ? a.pts[L.pt_off + r] : pad;
+  }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kBlock * kCellsS + threadIdx.x;
   float q[kCellsS][D];
@@ -73,9 +81,10 @@ __global__ __launch_bounds__(kBlock) void cells_kernel(FwdArgs a, int k, const f
     for (int c = 0; c < D; ++c) q[s][c] = x[ii * D + c];
   }
   if constexpr (BK && D == 2) {
-#pragma unroll
-    for (int s = 0; s < kCellsS; ++s)
-      idx[s] = cell_2d_buckets(recs, N, L, a.bk_cnt, a.bk_cand, q[s][0], q[s][1]);
+    int slot[kCellsS];
+    uint4 w[kCellsS];
+    bucket_rows<kCellsS>(L, a.bk_rows, q, slot, w);
+    bucket_argmin<kCellsS>(xy, N, a.bk_rows, q, slot, w, idx);
   } else {
     argmin_scan_tiled<D, kCellsS, kScanTile>(recs, Npad, q, idx);
   }

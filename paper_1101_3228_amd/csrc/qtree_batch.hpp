@@ -22,8 +22,7 @@ struct BatchContract {
   int64_t seg_base;      // first segment word of layer 0 in the group scratch
   int32_t chunks;        // chunks per layer
   int32_t seg_stride;    // tiles of the contract's largest count block + 1
-  const uint16_t* bk_cnt;  // d = 2: the plan's bucket tables
-  const uint4* bk_cand;
+  const uint4* bk_rows;  // d = 2: the plan's bucket rows
 };
 
 // Pass-A work unit: chunks [chunk0, chunk0 + nchunks) of layer k of contract c.

@@ -13,7 +13,9 @@ constexpr int kMaxDim = 3;
 // consecutive entries, kSuper / kTile tiles); pass B gives every (layer,
 // super tile) to one workgroup that histograms its keys in LDS and writes the
 // super tile with plain stores.
-constexpr int kTileBits = 12;
+// One tile per super tile: the sort's scan and a chunk's segment table have
+// one entry per super tile, all that pass B reads.
+constexpr int kTileBits = 14;
 constexpr int kTile = 1 << kTileBits;
 constexpr int kSuperBits = 14;
 constexpr int kSuper = 1 << kSuperBits;
@@ -57,17 +59,18 @@ struct alignas(16) LayerDev {
   // d = 2 bucketed cell search (bk_B[0] = 0: none): the layer's reachable box
   // from bk_lo in bk_B[0] x bk_B[1] buckets; x is in bucket
   // (floor((x_0 - bk_lo[0]) bk_scale[0]), floor((x_1 - bk_lo[1]) bk_scale[1]))
-  // in FP32, and bucket (i, j)'s candidates -- every point that can be the
-  // FP32 argmin anywhere in it, in increasing index -- are entries
-  // [(bk_off + i bk_B[1] + j) kBucketCap, + count) of the candidate array,
-  // count = bk_cnt[bk_off + i bk_B[1] + j] (0xFFFF: more than kBucketCap,
-  // the full scan decides)
+  // in FP32, and bucket (i, j) owns row bk_off + i bk_B[1] + j of the row
+  // array: entry 0 its candidate count c (kBucketFull: more than kBucketCap,
+  // the full scan decides), entries 1..c every point that can be the FP32
+  // argmin anywhere in it, in increasing index, padded to a whole 8-entry
+  // group with N (the search's pad record, whose key is NaN)
   float bk_lo[2], bk_scale[2];
   int32_t bk_B[2];
   int32_t bk_off;
 };
-constexpr int kBucketCap = 32;           // candidate slots per bucket (d = 2)
-constexpr uint16_t kBucketFull = 0xFFFF; // bucket count: candidates did not fit
+constexpr int kBucketRow = 32;            // uint16 entries of a bucket row (64 bytes)
+constexpr int kBucketCap = kBucketRow - 1; // candidates a row holds
+constexpr uint16_t kBucketFull = 0xFFFF;  // row count: candidates did not fit
 // Buckets per side of a d = 2 layer of N points: about 32 buckets per point,
 // at most 256 per side (the 2-D workload's sampling pass, N = 2000: 5.16 ms
 // at 32 per point, 5.68 at 24, 6.28 at 16, 8.42 at 8).
@@ -87,8 +90,7 @@ struct WsLayout {
   size_t guide;    // d == 1: uint16[(n + 1) kGuideMax] guide tables of the cell search
   size_t band;     // d == 1: int64[R + 1] band offsets, then int32[R] first band columns
                    // of the R = sum_{k<n} N_k count rows (banded stratified counts)
-  size_t bk_cnt;   // d == 2: uint16 candidate counts of every bucket of every layer
-  size_t bk_cand;  // d == 2: uint16[buckets][kBucketCap] candidate indices
+  size_t bk_rows;  // d == 2: uint16[buckets][kBucketRow] bucket rows (count, candidates)
   size_t keys;     // uint16[n][batch chunks][kChunk] pass-A keys
   size_t segs;     // uint32[n][batch chunks][max tiles + 1] segment starts
   size_t total;
@@ -131,8 +133,7 @@ struct FwdArgs {
   int32_t tile0;          // first histogram unit of this launch
   // d = 2 bucketed cell search (bucketed = 0: the full scan)
   int32_t bucketed;
-  const uint16_t* bk_cnt;
-  const uint4* bk_cand;
+  const uint4* bk_rows;
 };
 
 // Forward obstacle on the sum of the factors (see qtree_payoff_forward).
@@ -322,11 +323,10 @@ struct LloydArgs {
 };
 constexpr int kLloydMaxBlocks = 512;  // accumulation workgroups per step at most
 size_t lloyd_lds_bytes(int d, int N, int Npad, int P);
-// Candidate lists of the d = 2 bucketed cell search of every layer (records
+// Bucket rows of the d = 2 bucketed cell search of every layer (records
 // and LayerDev already in the workspace).
-hipError_t launch_bucket_build(const LayerDev* layers, int n_layers_total,
-                               const int32_t* bucket_layer_off, int total_buckets,
-                               const float4* pts, uint16_t* cnt, uint16_t* cand, hipStream_t s);
+hipError_t launch_bucket_build(const LayerDev* layers, int n_layers_total, int total_buckets,
+                               const float4* pts, uint16_t* rows, hipStream_t s);
 hipError_t launch_lloyd_prepare(const LloydArgs& a, hipStream_t s);
 hipError_t launch_lloyd_step(const LloydArgs& a, int blocks, hipStream_t s);
 // Moment-matching grids: exact integer moment sums of a device sample set,

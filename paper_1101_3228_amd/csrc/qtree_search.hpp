@@ -201,123 +201,120 @@ __device__ __forceinline__ void argmin_scan_tiled(const float4* __restrict__ g, 
   }
 }
 
-// d = 2 cell of x by the layer's bucket tables: x's bucket lists every
-// point that can be the FP32 argmin of h - <x, g> anywhere in the bucket, in
-// increasing index (padded to a multiple of 8 with its first entry), so the
-// first minimum over the list is the full scan's cell (the lowest index of
-// the minimal key).  Outside the box, in a bucket whose candidates did not
-// fit, or in a layer without tables, the full scan over the N records.
-__device__ __forceinline__ int cell_2d_buckets(const float4* __restrict__ g, int N,
-                                               const LayerDev& L,
-                                               const uint16_t* __restrict__ cnt,
-                                               const uint4* __restrict__ cand, float x0,
-                                               float x1) {
-  const float f0 = (x0 - L.bk_lo[0]) * L.bk_scale[0];
-  const float f1 = (x1 - L.bk_lo[1]) * L.bk_scale[1];
-  // false for a layer without tables (bk_B = 0) and for NaN
-  const bool in = f0 >= 0.0f && f1 >= 0.0f && f0 < (float)L.bk_B[0] && f1 < (float)L.bk_B[1];
-  int c = kBucketFull;
-  int64_t slot = 0;
-  if (in) {
-    slot = (int64_t)L.bk_off + (int64_t)((int)f0 * L.bk_B[1] + (int)f1);
-    c = cnt[slot];
-  }
-  float best = __builtin_huge_valf();
-  int idx = 0;
-  if (c != kBucketFull) {
-    const uint4* lst = cand + slot * (kBucketCap / 8);
-    for (int q = 0; q < c; q += 8) {
-      const uint4 w = lst[q >> 3];
-      const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int p = (int)((ww[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
-        const float4 r = g[p];
-        const float key = fmaf(-x1, r.y, fmaf(-x0, r.x, r.w));
-        const bool lt = key < best;
-        best = lt ? key : best;
-        idx = lt ? p : idx;
-      }
-    }
-  } else {
-    for (int p = 0; p < N; ++p) {
-      const float4 r = g[p];
-      const float key = fmaf(-x1, r.y, fmaf(-x0, r.x, r.w));
-      const bool lt = key < best;
-      best = lt ? key : best;
-      idx = lt ? p : idx;
-    }
-  }
-  return idx;
+// d = 2 cells by the layer's bucket tables, in two steps so that the row
+// loads of many points are in flight together.  A bucket's row (kBucketRow
+// uint16, 16-byte aligned) holds its candidate count c in entry 0 and, in
+// entries 1..c, every point that can be the FP32 argmin of h - <x, g>
+// anywhere in the bucket, in increasing index, then the pad index N to the
+// end of its last 8-entry group.  The first minimum over the list is the
+// full scan's cell (the lowest index of the minimal key).  Outside the box,
+// in a bucket whose candidates did not fit (c = kBucketFull), or in a layer
+// without tables, the full scan over the N points decides.
+//
+// The points are (x, y) pairs in LDS, 8 bytes each, with a pad pair (NaN,
+// NaN) at index N: its key is NaN, which never wins a comparison, and the
+// lanes that read it share one LDS access.  Consecutive points fall in
+// different bank pairs, where 16-byte records would share a quarter of the
+// banks (and 12-byte (x, y, h) triples take two reads).  The half norm is
+// recomputed as h = (x x + y y) / 2 with one product, one fma and one
+// halving, the order in which the records' own half norms are formed, so
+// the key is bit for bit the scan's.
+__device__ __forceinline__ float half_norm_key(float2 r, float x0, float x1) {
+  const float h = 0.5f * fmaf(r.y, r.y, r.x * r.x);
+  return fmaf(-x1, r.y, fmaf(-x0, r.x, h));
 }
 
-// The same for S points at once: the list entries of all S points are read
-// together (their loads overlap) and walked in step, groups of 4 at a time; a
-// point whose list is shorter re-reads its first group (a repeated candidate
-// never wins a strict comparison).  Points outside the box or in a full
-// bucket take the full scan afterwards.
+// bucket_rows: the row index of each of S points (-1: full scan) and the
+// first 16 bytes of its row (count and candidates 1..7).  Every point loads
+// a row (row 0 when it has none, so that the load is not under a branch and
+// all S stay in flight); bucket_argmin ignores what a -1 point loaded.
 template <int S>
-__device__ __forceinline__ void cells_2d_buckets_joint(const float4* __restrict__ g, int N,
-                                                       const LayerDev& L,
-                                                       const uint16_t* __restrict__ cnt,
-                                                       const uint2* __restrict__ cand,
-                                                       const float (*xs)[2], int* idx) {
-  int c[S];
-  const uint2* lst[S];
-  float best[S];
-  int cmax = 0;
-  bool full = L.bk_B[0] == 0;  // a layer without tables: every point scans
+__device__ __forceinline__ void bucket_rows(const LayerDev& L, const uint4* __restrict__ rows,
+                                            const float (*xs)[2], int* slot, uint4* w) {
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const float f0 = (xs[s][0] - L.bk_lo[0]) * L.bk_scale[0];
     const float f1 = (xs[s][1] - L.bk_lo[1]) * L.bk_scale[1];
+    // false for a layer without tables (bk_B = 0) and for NaN
     const bool in =
         f0 >= 0.0f && f1 >= 0.0f && f0 < (float)L.bk_B[0] && f1 < (float)L.bk_B[1];
-    // outside: the layer's first bucket, whose entries are valid indices for
-    // the re-reads below (a layer without tables reads nothing: cmax = 0)
-    const int64_t slot = (int64_t)L.bk_off + (in ? (int64_t)((int)f0 * L.bk_B[1] + (int)f1) : 0);
-    c[s] = in ? (int)cnt[slot] : (int)kBucketFull;
-    lst[s] = cand + slot * (kBucketCap / 4);
-    full = full || c[s] == (int)kBucketFull;
-    const int cs = c[s] == (int)kBucketFull ? 0 : c[s];
-    cmax = cs > cmax ? cs : cmax;
+    const int r = in ? L.bk_off + (int)f0 * L.bk_B[1] + (int)f1 : 0;
+    slot[s] = in ? r : -1;
+    w[s] = rows[(int64_t)r * (kBucketRow / 8)];
+  }
+}
+
+// One 8-entry group of a row: entries e0..7 (candidates or pads).
+__device__ __forceinline__ void bucket_group(const float2* __restrict__ g, uint4 w, int e0,
+                                             float x0, float x1, float& best, int& idx) {
+  const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int e = e0; e < 8; ++e) {
+    const int p = (int)((ww[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
+    const float key = half_norm_key(g[p], x0, x1);
+    const bool lt = key < best;
+    best = lt ? key : best;
+    idx = lt ? p : idx;
+  }
+}
+
+// bucket_first: the minimum over the first group of each of S points'
+// rows, in straight-line code so that the LDS reads of all S points can be
+// in flight together.  A point without a row (outside the box) walks pads
+// only; a full row's first entries are valid points of the layer, and
+// bucket_rest replaces what they give.
+template <int S>
+__device__ __forceinline__ void bucket_first(const float2* __restrict__ g, int N,
+                                             const float (*xs)[2], const int* slot,
+                                             const uint4* w, float* best, int* idx) {
+  const uint32_t pads = (uint32_t)N | ((uint32_t)N << 16);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const uint4 v = slot[s] >= 0 ? w[s] : make_uint4(pads, pads, pads, pads);
     best[s] = __builtin_huge_valf();
     idx[s] = 0;
+    bucket_group(g, v, 1, xs[s][0], xs[s][1], best[s], idx[s]);
   }
-  for (int q = 0; q < cmax; q += 4) {
-    uint2 w[S];
+}
+
+// bucket_rest: the further groups of rows longer than 7 candidates, and the
+// full scan for points outside the box or in a full bucket; idx then holds
+// the cells.
+template <int S>
+__device__ __forceinline__ void bucket_rest(const float2* __restrict__ g, int N,
+                                            const uint4* __restrict__ rows,
+                                            const float (*xs)[2], const int* slot,
+                                            const uint4* w, float* best, int* idx) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) w[s] = lst[s][q < c[s] && c[s] != (int)kBucketFull ? q >> 2 : 0];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const uint32_t ww[2] = {w[s].x, w[s].y};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int p = (int)((ww[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
-        const float4 r = g[p];
-        const float key = fmaf(-xs[s][1], r.y, fmaf(-xs[s][0], r.x, r.w));
-        const bool lt = key < best[s];
-        best[s] = lt ? key : best[s];
-        idx[s] = lt ? p : idx[s];
-      }
-    }
-  }
-  if (full) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (c[s] != (int)kBucketFull) continue;
+  for (int s = 0; s < S; ++s) {
+    const int c = slot[s] >= 0 ? (int)(w[s].x & 0xFFFFu) : (int)kBucketFull;
+    if (c == (int)kBucketFull) {
       float b = __builtin_huge_valf();
       int bi = 0;
       for (int p = 0; p < N; ++p) {
-        const float4 r = g[p];
-        const float key = fmaf(-xs[s][1], r.y, fmaf(-xs[s][0], r.x, r.w));
+        const float key = half_norm_key(g[p], xs[s][0], xs[s][1]);
         const bool lt = key < b;
         b = lt ? key : b;
         bi = lt ? p : bi;
       }
       idx[s] = bi;
+    } else {
+      for (int q = 8; q <= c; q += 8)
+        bucket_group(g, rows[(int64_t)slot[s] * (kBucketRow / 8) + (q >> 3)], 0, xs[s][0],
+                     xs[s][1], best[s], idx[s]);
     }
   }
+}
+
+// bucket_argmin: the cells of the S points whose rows bucket_rows fetched.
+template <int S>
+__device__ __forceinline__ void bucket_argmin(const float2* __restrict__ g, int N,
+                                              const uint4* __restrict__ rows,
+                                              const float (*xs)[2], const int* slot,
+                                              const uint4* w, int* idx) {
+  float best[S];
+  bucket_first<S>(g, N, xs, slot, w, best, idx);
+  bucket_rest<S>(g, N, rows, xs, slot, w, best, idx);
 }
 
 // Standard normals z (for X_k) and eps (for the innovation) of LAYERWISE
