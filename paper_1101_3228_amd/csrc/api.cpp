@@ -80,8 +80,9 @@ size_t keys_lds_bytes(int d, int n, const int32_t* N) {
   }
   const size_t grids =
       d == 1 ? sizeof(float) * (2 * (size_t)maxP + 4) : 16 * 2 * (size_t)(maxN + kScanTile);
-  return grids + sizeof(uint16_t) * kChunk +
-         sizeof(uint32_t) * (2 * (size_t)max_tiles_of(n, N) + 1 + 256);
+  const int mt = max_tiles_of(n, N);
+  const size_t sub = d == 1 ? 1 : (size_t)nd_sub_counters(mt);  // the d >= 2 sort's sub-counters
+  return grids + sizeof(uint16_t) * kChunk + sizeof(uint32_t) * (2 * (size_t)mt * sub + 1 + 256);
 }
 
 bool two_pass_fits(int d, int n, const int32_t* N) {

@@ -136,6 +136,7 @@ struct qtree_batch {
   int lg1 = 0;                // search depth of the 1-D launch class (log2 of its largest P)
   int gk1 = -1;               // 1-D launch: largest guide K (-1: breadth-first search)
   int sub1 = 1, maxP1 = 1, gtB1 = 1;  // its sub-counters, midpoint slots, largest table
+  int subn = 1;                      // sub-counters per tile of the d >= 2 sort
   int cus = 256;
   int max_per_cu[2] = {1, 1};  // workgroups per CU that fit, of each sampling launch
   BatchConfig cfg;
@@ -175,7 +176,7 @@ qtree::BatchArgs group_args(const qtree_batch* b, const Group& g, int x, const B
   a.tiles = b->d_tiles + g.tile_off;
   a.n_units = g.n_units[x];
   a.gk = x == 0 ? b->gk1 : -1;
-  a.sub = b->sub1;
+  a.sub = x == 0 ? b->sub1 : b->subn;
   a.maxP = b->maxP1;
   a.gt_Bmax = b->gtB1;
   a.n_tiles = g.n_tiles;
@@ -434,6 +435,7 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     b->lds[0] = qtree::keys_lds_1d_guide(maxP, gtB, max_tiles1);
   }
   b->lds[1] = qtree::keys_lds_nd(maxN, max_tilesn);
+  b->subn = qtree::nd_sub_counters(max_tilesn);
   if (b->lds[0] > 160 * 1024 || (b->dmax > 1 && b->lds[1] > 160 * 1024)) {
     delete b;
     return set_error(QTREE_EUNSUPPORTED, "batch needs more LDS than a workgroup has");

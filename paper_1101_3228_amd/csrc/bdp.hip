@@ -15,6 +15,41 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kPay = 16;
+constexpr int kRowUnroll = 8;
+
+// One wave's share of a count row (len entries from row) against nq <= kPay
+// value vectors V + (q0 + q) P + col0: the row total p and the sums
+// s_q = sum_j c_j V_q(j) of this lane's columns.  kRowUnroll row loads are
+// in flight per lane (a long dense row is otherwise one HBM round trip per
+// 64 columns); a column whose count is zero adds nothing, and its V entries
+// are not read.
+__device__ __forceinline__ void row_sums(const int32_t* __restrict__ row, int len,
+                                         const double* __restrict__ V, int64_t P, int q0,
+                                         int nq, int64_t col0, int lane, int64_t& p,
+                                         double (&s)[kPay]) {
+  p = 0;
+#pragma unroll
+  for (int q = 0; q < kPay; ++q) s[q] = 0.0;
+  for (int j0 = lane; j0 < len; j0 += 64 * kRowUnroll) {
+    int32_t c[kRowUnroll];
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) {
+      const int j = j0 + 64 * u;
+      c[u] = j < len ? row[j] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) {
+      p += c[u];
+      if (c[u] != 0) {
+        const double cd = (double)c[u];
+        const int64_t col = col0 + j0 + 64 * u;
+#pragma unroll
+        for (int q = 0; q < kPay; ++q)
+          if (q < nq) s[q] = fma(cd, V[(int64_t)(q0 + q) * P + col], s[q]);
+      }
+    }
+  }
+}
 }  // namespace
 
 // One layer for every payoff: blockIdx.y selects the group of kPay payoffs
@@ -41,20 +76,9 @@ __global__ __launch_bounds__(kBlock) void bdp_layer_kernel(BdpArgs a, int N_k, i
     row = a.counts + cnt_k + (int64_t)i * N_k1;
     len = N_k1;
   }
-  int64_t p = 0;
+  int64_t p;
   double s[kPay];
-#pragma unroll
-  for (int q = 0; q < kPay; ++q) s[q] = 0.0;
-  for (int j = lane; j < len; j += 64) {
-    const int32_t c = row[j];
-    p += c;
-    if (c != 0) {
-      const double cd = (double)c;
-#pragma unroll
-      for (int q = 0; q < kPay; ++q)
-        if (q < nq) s[q] = fma(cd, a.V[(int64_t)(q0 + q) * a.P + col0 + j], s[q]);
-    }
-  }
+  row_sums(row, len, a.V, a.P, q0, nq, col0, lane, p, s);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     p += __shfl_xor(p, off, 64);
@@ -128,20 +152,9 @@ __global__ __launch_bounds__(kBdpBlock) void bdp_step_kernel(const BdpJob* jobs,
   const LayerDev& L1 = J.layers[T.k + 1];
   const int i = T.row0 + wave;
   const int32_t* row = J.counts + L.cnt_off + (int64_t)i * L.N1;
-  int64_t p = 0;
+  int64_t p;
   double s[kPay];
-#pragma unroll
-  for (int q = 0; q < kPay; ++q) s[q] = 0.0;
-  for (int j = lane; j < L.N1; j += 64) {
-    const int32_t c = row[j];
-    p += c;
-    if (c != 0) {
-      const double cd = (double)c;
-#pragma unroll
-      for (int q = 0; q < kPay; ++q)
-        if (q < J.nq) s[q] = fma(cd, J.V[(int64_t)(J.q0 + q) * J.P + L1.pt_off + j], s[q]);
-    }
-  }
+  row_sums(row, L.N1, J.V, J.P, J.q0, J.nq, L1.pt_off, lane, p, s);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     p += __shfl_xor(p, off, 64);

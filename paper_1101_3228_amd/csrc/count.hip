@@ -48,6 +48,13 @@ constexpr int kBkSamplesLo = 2, kBkSamplesHi = 4;
 constexpr int kCountBlock = 1024;
 constexpr int kGuideSub = 4;         // sub-counters per tile in the guide kernel's sort
 constexpr int kGuideSubTiles = 256;  // ... when a layer has at most this many tiles
+// The same for the d >= 2 sort, where the tiles of a wave's keys are few (the
+// samples of a row band of the count block share one tile)
+constexpr int kNdSub = 4;
+constexpr int kNdSubTiles = 256;
+__host__ __device__ constexpr int nd_subs(int max_tiles) {
+  return max_tiles <= kNdSubTiles ? kNdSub : 1;
+}
 
 // One pass-A job: chunk c of the samples [lo, hi) of layer k.
 struct KeysJob {
@@ -62,6 +69,7 @@ struct KeysJob {
   uint16_t* keys;  // kChunk slots of this chunk
   uint32_t* seg;   // T + 1 segment starts of this chunk
   const uint4* bk_rows;  // d = 2 bucket rows (bucketed search only)
+  int nd_sub;            // d >= 2: sub-counters per tile in the sort (kNdSub or 1)
 };
 
 // One pass-B job: super tile t of a layer whose chunks start at keys / seg.
@@ -388,7 +396,7 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
     for (int i = threadIdx.x; i < P0; i += KB) gk[i] = i < N0 ? j.pts[L0.pt_off + i] : pad;
     for (int i = threadIdx.x; i < P1; i += KB) gk1[i] = i < N1 ? j.pts[L1.pt_off + i] : pad;
   }
-  for (int t = threadIdx.x; t <= T; t += KB) tcount[t] = 0;
+  for (int t = threadIdx.x; t <= T * j.nd_sub; t += KB) tcount[t] = 0;
   __syncthreads();
 
   const uint64_t lo = j.lo + (uint64_t)j.c * kChunk;
@@ -434,7 +442,17 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
       for (int q = 0; q < kKeys / S; ++q) key[q * S + s] = q == r ? v : key[q * S + s];
     }
   }
-  sort_and_write<KB>(j, key, T, stage, tcount, cursor);
+  // tcount holds T nd_sub + 1 counters and cursor T nd_sub; a chunk inside
+  // [lo, hi) has no dead slots
+  const bool all = lo + kChunk <= j.hi;
+  if (j.nd_sub == kNdSub) {
+    uint32_t* cur = tcount + (T * kNdSub + 1);
+    if (all) sort_and_write<KB, true, kNdSub>(j, key, T, stage, tcount, cur);
+    else sort_and_write<KB, false, kNdSub>(j, key, T, stage, tcount, cur);
+  } else {
+    if (all) sort_and_write<KB, true>(j, key, T, stage, tcount, cursor);
+    else sort_and_write<KB, false>(j, key, T, stage, tcount, cursor);
+  }
 }
 
 // Pass B for one super tile: tiles [t kTilesPerSuper, (t+1) kTilesPerSuper)
@@ -546,6 +564,7 @@ __device__ __forceinline__ KeysJob plan_job(const FwdArgs& a, int k, int c) {
   j.keys = a.keys + ((size_t)k * a.chunks + c) * kChunk;
   j.seg = a.segs + ((size_t)k * a.chunks + c) * a.seg_stride;
   j.bk_rows = a.bk_rows;
+  j.nd_sub = nd_subs(a.max_tiles);
   return j;
 }
 
@@ -660,6 +679,7 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
       j.keys = a.keys + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
       j.seg = a.segs + (size_t)C.seg_base + ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
       j.bk_rows = C.bk_rows;
+      j.nd_sub = a.sub;
       body(C, j);
     }
   }
@@ -747,6 +767,8 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
 
 int guide_sub_counters(int max_tiles) { return max_tiles <= kGuideSubTiles ? kGuideSub : 1; }
 
+int nd_sub_counters(int max_tiles) { return nd_subs(max_tiles); }
+
 size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles) {
   const size_t words = (2 * (size_t)(maxP + kGuideKMax) + (size_t)maxB + 3) & ~(size_t)3;
   const size_t ts = (size_t)max_tiles * guide_sub_counters(max_tiles);
@@ -759,8 +781,9 @@ size_t keys_lds_1d(int maxP, int max_tiles) {
 }
 
 size_t keys_lds_nd(int maxN, int max_tiles) {
+  const size_t ts = (size_t)max_tiles * nd_subs(max_tiles);
   return sizeof(float4) * 2 * (size_t)(maxN + kScanTile) + sizeof(uint16_t) * kChunk +
-         sizeof(uint32_t) * (size_t)(2 * max_tiles + 1);
+         sizeof(uint32_t) * (2 * ts + 1);
 }
 
 hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {

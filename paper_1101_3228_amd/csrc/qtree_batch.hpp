@@ -43,7 +43,8 @@ struct BatchArgs {
   int32_t n_units, n_tiles;
   // 1-D launch with guide tables (every 1-D contract has them): gk = the
   // batch's largest K (-1: breadth-first search), over maxP midpoints and
-  // tables of up to gt_Bmax entries, sub sub-counters per tile in the sort
+  // tables of up to gt_Bmax entries; sub: sub-counters per tile in the sort
+  // (of the 1-D or of the d >= 2 launch)
   int32_t gk, sub, maxP, gt_Bmax;
   int32_t nd_samples;  // d >= 2 launch: samples per lane sharing each grid read (8 or 4)
   int32_t bucketed;    // d = 2 launch (every d >= 2 contract 2-D with bucket tables)
@@ -64,6 +65,7 @@ int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples, 
 size_t keys_lds_1d(int maxP, int max_tiles);
 size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles);
 int guide_sub_counters(int max_tiles);
+int nd_sub_counters(int max_tiles);
 size_t keys_lds_nd(int maxN, int max_tiles);
 
 // BDP of one contract for payoffs [q0, q0 + nq) (nq <= 16).
