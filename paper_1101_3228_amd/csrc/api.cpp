@@ -54,6 +54,7 @@ int log2i(int p) {
 // LDS limits of the kernels (160 KiB per CU; the 1-D layerwise kernel stages
 // two padded midpoint arrays, the d >= 2 kernel two point arrays of 16 B).
 constexpr int kMaxN1d = 16384;
+constexpr int64_t kManySuperTiles = 2048;  // histogram units that fill the chip unsplit
 constexpr int kMaxNnd = 4096;
 
 }  // namespace
@@ -480,17 +481,22 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
   // host image of the workspace
   std::vector<char> img(p.lay.total, 0);
   auto* layers = reinterpret_cast<qtree::LayerDev*>(img.data() + p.lay.layers);
-  // histogram parts: every super tile is split into two parts over the
-  // chunks, and a layer with fewer super tiles than the largest layer into
-  // up to twice that ratio (at most 16), so that no workgroup of the
-  // histogram pass takes many times the keys of another (a one-point first
-  // layer has a single super tile) and the last layer group's histogram,
-  // which no sampling pass hides, has twice the workgroups (1-D workload,
-  // n = 50, N = 500, M = 1e7: 1.835 ms per step against 1.899 unsplit and
-  // 1.838 with four parts)
-  int64_t st_max = 1;
-  for (int k = 0; k < n; ++k)
-    st_max = std::max<int64_t>(st_max, ((int64_t)N[k] * N[k + 1] + qtree::kSuper - 1) / qtree::kSuper);
+  // histogram parts: a layer with fewer super tiles than the largest layer
+  // is split over the chunks into up to that ratio (at most 16), so that no
+  // workgroup of the histogram pass takes many times the keys of another (a
+  // one-point first layer has a single super tile).  With few super tiles
+  // in all, every super tile is split in two besides, so that the last
+  // layer group's histogram, which no sampling pass hides, has twice the
+  // workgroups (1-D workload, n = 50, N = 500, M = 1e7: 1.835 ms per step
+  // against 1.899 unsplit and 1.838 with four parts); with many, splitting
+  // only costs the clearing of the split blocks (the parts add into them).
+  int64_t st_max = 1, st_all = 0;
+  for (int k = 0; k < n; ++k) {
+    const int64_t st = ((int64_t)N[k] * N[k + 1] + qtree::kSuper - 1) / qtree::kSuper;
+    st_max = std::max<int64_t>(st_max, st);
+    st_all += st;
+  }
+  const int64_t split_base = st_all >= kManySuperTiles ? 1 : 2;
   int32_t total_units = 0;
   for (int k = 0; k <= n; ++k) {
     qtree::LayerDev L{};
@@ -508,7 +514,9 @@ qtree_status qtree_plan_create(const qtree_model* model, const float* grid, cons
     p.tile_off.push_back(p.total_tiles);
     const int64_t st_k = (entries_k + qtree::kSuper - 1) / qtree::kSuper;
     p.total_tiles += (int32_t)st_k;
-    L.split = st_k > 0 ? (int32_t)std::min<int64_t>(16, 2 * std::max<int64_t>(1, st_max / st_k)) : 1;
+    L.split = st_k > 0
+                  ? (int32_t)std::min<int64_t>(16, split_base * std::max<int64_t>(1, st_max / st_k))
+                  : 1;
     L.unit_off = total_units;
     p.split.push_back(L.split);
     p.unit_off.push_back(total_units);
@@ -682,8 +690,9 @@ static hipError_t two_pass(const qtree_plan* p, qtree::FwdArgs a, bool zero, hip
   a.keys = sc.keys;
   a.segs = sc.segs;
   // automatic: four groups hide most of the 1-D histogram pass; for d >= 2
-  // that pass is ~1 % of the forward and more launches only add tails
-  const int want = p->tune_groups > 0 ? p->tune_groups : (p->d == 1 ? 4 : 1);
+  // two (with the bucketed search that pass is a fifth of the forward, and
+  // more launches add tails)
+  const int want = p->tune_groups > 0 ? p->tune_groups : (p->d == 1 ? 4 : 2);
   const int groups = std::max(1, std::min(std::min(want, sc.max_groups), p->n));
   if (groups > 1) {
     hipError_t e = ensure_aux(p, groups);

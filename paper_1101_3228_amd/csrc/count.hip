@@ -44,7 +44,7 @@ constexpr int kSamplesNd2 = 8;
 // samples per lane of the d = 2 bucketed search (the tuned choice between
 // the two): the first-group reads of all 2 S searches of a round are in
 // flight together, so S sets the registers and the overlap of LDS reads
-constexpr int kBkSamplesLo = 2, kBkSamplesHi = 4;
+constexpr int kBkSamplesLo = 1, kBkSamplesHi = 2;
 constexpr int kCountBlock = 1024;
 constexpr int kGuideSub = 4;         // sub-counters per tile in the guide kernel's sort
 constexpr int kGuideSubTiles = 256;  // ... when a layer has at most this many tiles
@@ -856,17 +856,21 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
 
 // One workgroup per layer of [layer0, layer0 + gridDim.x): a split layer's
 // count block is cleared before its histogram parts add into it.
+// Clears the count blocks of the split layers: layer layer0 + blockIdx.y,
+// kZeroBlocks workgroups per layer, each a strided share of the block.
+constexpr int kZeroBlocks = 16;
 __global__ __launch_bounds__(256) void zero_split_kernel(FwdArgs a) {
-  const LayerDev& L = a.layers[a.layer0 + (int)blockIdx.x];
+  const LayerDev& L = a.layers[a.layer0 + (int)blockIdx.y];
   if (L.split <= 1) return;
   const int64_t n = (int64_t)L.N * L.N1;
   int32_t* dst = a.counts + L.cnt_off;
-  for (int64_t i = threadIdx.x; i < n; i += 256) dst[i] = 0;
+  const int64_t stride = (int64_t)kZeroBlocks * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = 0;
 }
 
 hipError_t launch_zero_split(const FwdArgs& a, int nl, hipStream_t s) {
   if (nl <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_split_kernel, dim3((unsigned)nl), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(zero_split_kernel, dim3(kZeroBlocks, (unsigned)nl), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
