@@ -456,11 +456,16 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
 }
 
 // Pass B for one super tile: tiles [t kTilesPerSuper, (t+1) kTilesPerSuper)
-// are one contiguous segment of every chunk.  Segment bounds of kCountBlock
-// chunks at a time are fetched with one load per lane into LDS; each wave
-// then walks kInFlight segments at once, 8 keys per lane per 16-byte load
-// (a chunk's key block is 16-byte aligned), adding into the kSuper-bin LDS
-// histogram; keys outside [s0, s1) are skipped.
+// are one contiguous segment of every chunk, walked with 16-byte loads of 8
+// keys (a chunk's key block is 16-byte aligned) into the kSuper-bin LDS
+// histogram; keys outside [s0, s1) are skipped.  Long segments (a layer of
+// few super tiles): segment bounds of kCountBlock chunks at a time are
+// fetched with one load per lane into LDS, then each wave walks kInFlight
+// segments at once, 8 keys per lane.  Short segments (under kShortSegment
+// keys on average, a layer of many super tiles, where a wave would leave
+// most lanes idle): each lane walks whole segments of its own chunks, two
+// loads at a time.
+constexpr int kShortSegment = 64;
 __device__ __forceinline__ void count_tile(const TileJob& j, uint32_t* hist, uint32_t* sb,
                                            uint32_t* se) {
   const LayerDev& L0 = *j.L0;
@@ -470,7 +475,28 @@ __device__ __forceinline__ void count_tile(const TileJob& j, uint32_t* hist, uin
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   constexpr int kWaves = kCountBlock / 64;
   constexpr int kInFlight = 4;
-  for (int c0 = j.c_lo; c0 < j.c_hi; c0 += kCountBlock) {
+  const int64_t supers = ((int64_t)L0.N * L0.N1 + kSuper - 1) / kSuper;
+  const bool lanes = (int64_t)kChunk < (int64_t)kShortSegment * supers;
+  if (lanes) {
+    __syncthreads();  // the cleared histogram
+    for (int c = j.c_lo + (int)threadIdx.x; c < j.c_hi; c += kCountBlock) {
+      const uint32_t s0 = j.seg[(size_t)c * j.seg_stride + f0];
+      const uint32_t s1 = j.seg[(size_t)c * j.seg_stride + f1];
+      const uint4* kv = reinterpret_cast<const uint4*>(j.keys + (size_t)c * kChunk);
+      for (uint32_t v = s0 >> 3; v * 8 < s1; v += 2) {
+        const uint4 w0 = kv[v];
+        const uint4 w1 = (v + 1) * 8 < s1 ? kv[v + 1] : make_uint4(0, 0, 0, 0);
+        const uint32_t words[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const uint32_t q = v * 8 + e;
+          const uint32_t key = (words[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu;
+          if (q >= s0 && q < s1) atomicAdd(&hist[key], 1u);
+        }
+      }
+    }
+  }
+  for (int c0 = j.c_lo; !lanes && c0 < j.c_hi; c0 += kCountBlock) {
     __syncthreads();
     const int c = c0 + (int)threadIdx.x;
     if (c < j.c_hi) {
