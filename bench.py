@@ -508,10 +508,11 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
     if bucketed:
         per_layer = bucketed_pair_slots(plan)
         alg = M * float(np.sum(per_layer))
-        kernel = f"fwd_keys_nd<2, {plan.tuning()['nd_samples']}, bucketed>"
+        # the bucketed kernel takes 2 samples per lane for the tuning's 8, 1 for 4
+        kernel = f"fwd_keys_nd<2, {2 if plan.tuning()['nd_samples'] == 8 else 1}, true>"
     else:
         alg = ALG_SLOTS_2D_PAIR * pairs + ALG_SLOTS_2D_POINT * points
-        kernel = f"fwd_keys_nd<2, {plan.tuning()['nd_samples']}>"
+        kernel = f"fwd_keys_nd<2, {plan.tuning()['nd_samples']}, false>"
     achieved = alg / (keys_ms * 1e-3)
     V0 = V[:, 0].cpu().numpy()
     out = {
