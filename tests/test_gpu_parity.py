@@ -194,12 +194,16 @@ def test_payoff_matches_oracle(small_case):
             assert np.allclose(got[fin], ref[fin], rtol=1e-13, atol=1e-12)
 
 
-def test_bdp_matches_oracle_with_edge_rows():
-    _print_case("bdp edges")
+@pytest.mark.parametrize("sizes,M", [([1, 30, 40, 50, 60, 70], 3_000),
+                                     ([1, 1100, 1023, 1024, 2000, 1500], 1_500)])
+def test_bdp_matches_oracle_with_edge_rows(sizes, M):
+    """Few samples leave empty rows; the second shape's rows of 1023 to 2000
+    columns take several rounds of the row walk's eight loads per lane."""
+    _print_case(f"bdp edges {sizes}")
     spec = synth.bm_model(1, 5)
-    grid, N = synth.layer_grids(spec, [1, 30, 40, 50, 60, 70])
+    grid, N = synth.layer_grids(spec, sizes)
     plan = _plan(spec, grid, N)
-    counts = plan.transitions(3_000, 7).cpu().numpy()       # few samples: empty rows
+    counts = plan.transitions(M, 7).cpu().numpy()           # few samples: empty rows
     phis = []
     for kind in (0, 2):
         for K in (80.0, 100.0, 120.0):
