@@ -16,6 +16,8 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kPay = 16;
 constexpr int kRowUnroll = 8;
+constexpr int kFewPay = 2;  // payoffs per pass whose V entries are loaded with the counts
+constexpr int kFewUnroll = 16;  // ... and the row loads in flight per lane then
 
 // One wave's share of a count row (len entries from row) against nq <= kPay
 // value vectors V + (q0 + q) P + col0: the row total p and the sums
@@ -30,6 +32,31 @@ __device__ __forceinline__ void row_sums(const int32_t* __restrict__ row, int le
   p = 0;
 #pragma unroll
   for (int q = 0; q < kPay; ++q) s[q] = 0.0;
+  if (nq <= kFewPay) {
+    // few payoffs: the V entries are loaded with the counts, not after them
+    // (a load that waits on its count is a second round trip per group);
+    // a zero count still adds nothing (a select, not a multiply by zero)
+    for (int j0 = lane; j0 < len; j0 += 64 * kFewUnroll) {
+      int32_t c[kFewUnroll];
+      double v[kFewUnroll][kFewPay];
+#pragma unroll
+      for (int u = 0; u < kFewUnroll; ++u) {
+        const int j = j0 + 64 * u;
+        c[u] = j < len ? row[j] : 0;
+#pragma unroll
+        for (int q = 0; q < kFewPay; ++q)
+          v[u][q] = (j < len && q < nq) ? V[(int64_t)(q0 + q) * P + col0 + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kFewUnroll; ++u) {
+        p += c[u];
+        const double cd = (double)c[u];
+#pragma unroll
+        for (int q = 0; q < kFewPay; ++q) s[q] = c[u] != 0 ? fma(cd, v[u][q], s[q]) : s[q];
+      }
+    }
+    return;
+  }
   for (int j0 = lane; j0 < len; j0 += 64 * kRowUnroll) {
     int32_t c[kRowUnroll];
 #pragma unroll
