@@ -25,6 +25,7 @@ constexpr int kFewUnroll = 16;  // ... and the row loads in flight per lane then
 // in flight per lane (a long dense row is otherwise one HBM round trip per
 // 64 columns); a column whose count is zero adds nothing, and its V entries
 // are not read.
+template <bool FEW>
 __device__ __forceinline__ void row_sums(const int32_t* __restrict__ row, int len,
                                          const double* __restrict__ V, int64_t P, int q0,
                                          int nq, int64_t col0, int lane, int64_t& p,
@@ -32,7 +33,7 @@ __device__ __forceinline__ void row_sums(const int32_t* __restrict__ row, int le
   p = 0;
 #pragma unroll
   for (int q = 0; q < kPay; ++q) s[q] = 0.0;
-  if (nq <= kFewPay) {
+  if (FEW && nq <= kFewPay) {
     // few payoffs: the V entries are loaded with the counts, not after them
     // (a load that waits on its count is a second round trip per group);
     // a zero count still adds nothing (a select, not a multiply by zero)
@@ -81,6 +82,12 @@ __device__ __forceinline__ void row_sums(const int32_t* __restrict__ row, int le
 
 // One layer for every payoff: blockIdx.y selects the group of kPay payoffs
 // (the count row is re-read per group, from L2 for all but the first).
+// FEW: the instance for at most kFewPay payoffs.  The general instance does
+// not carry the few-payoff path's registers (98 VGPRs against 119): its
+// workgroups, launched beside a sampling pass on another stream, then find
+// room on the CUs sooner (the 1-D workload's pipelined step: 1.86 against
+// 2.14-2.19 ms with one instance for both).
+template <bool FEW>
 __global__ __launch_bounds__(kBlock) void bdp_layer_kernel(BdpArgs a, int N_k, int N_k1,
                                                            int64_t pt_k, int64_t pt_k1,
                                                            int64_t cnt_k) {
@@ -105,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void bdp_layer_kernel(BdpArgs a, int N_k, i
   }
   int64_t p;
   double s[kPay];
-  row_sums(row, len, a.V, a.P, q0, nq, col0, lane, p, s);
+  row_sums<FEW>(row, len, a.V, a.P, q0, nq, col0, lane, p, s);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     p += __shfl_xor(p, off, 64);
@@ -139,8 +146,12 @@ hipError_t launch_bdp_layer(const BdpArgs& a, int k, int N_k, int N_k1, int64_t 
   (void)k;
   const unsigned blocks = (unsigned)((N_k + kWaves - 1) / kWaves);
   const unsigned groups = (unsigned)((a.n_pay + kPay - 1) / kPay);
-  hipLaunchKernelGGL(bdp_layer_kernel, dim3(blocks, groups), dim3(kBlock), 0, s, a, N_k, N_k1,
-                     pt_k, pt_k1, cnt_k);
+  if (a.n_pay <= kFewPay)
+    hipLaunchKernelGGL(bdp_layer_kernel<true>, dim3(blocks, groups), dim3(kBlock), 0, s, a, N_k,
+                       N_k1, pt_k, pt_k1, cnt_k);
+  else
+    hipLaunchKernelGGL(bdp_layer_kernel<false>, dim3(blocks, groups), dim3(kBlock), 0, s, a, N_k,
+                       N_k1, pt_k, pt_k1, cnt_k);
   return hipGetLastError();
 }
 
@@ -181,7 +192,7 @@ __global__ __launch_bounds__(kBdpBlock) void bdp_step_kernel(const BdpJob* jobs,
   const int32_t* row = J.counts + L.cnt_off + (int64_t)i * L.N1;
   int64_t p;
   double s[kPay];
-  row_sums(row, L.N1, J.V, J.P, J.q0, J.nq, L1.pt_off, lane, p, s);
+  row_sums<true>(row, L.N1, J.V, J.P, J.q0, J.nq, L1.pt_off, lane, p, s);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     p += __shfl_xor(p, off, 64);

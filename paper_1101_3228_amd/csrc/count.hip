@@ -45,6 +45,7 @@ constexpr int kSamplesNd2 = 8;
 // the two): the first-group reads of all 2 S searches of a round are in
 // flight together, so S sets the registers and the overlap of LDS reads
 constexpr int kBkSamplesLo = 1, kBkSamplesHi = 2;
+constexpr int kStageLoads = 4;  // grid records in flight per lane while staging (bucketed)
 constexpr int kCountBlock = 1024;
 constexpr int kGuideSub = 4;         // sub-counters per tile in the guide kernel's sort
 constexpr int kGuideSubTiles = 256;  // ... when a layer has at most this many tiles
@@ -109,14 +110,44 @@ __device__ __forceinline__ void count_keys(const uint32_t* key, uint32_t* tcount
 }
 
 // Exclusive scan of tcount[0..T) in place (tcount[T] = total), copied to
-// cursor, by wave 0 alone: each lane sums a run of consecutive counters, the
-// 64 run sums are scanned with shuffles, then the runs are rewritten.  Must
-// sit between two barriers.
+// cursor: each lane sums a run of consecutive counters, the run sums are
+// scanned with shuffles, then the runs are rewritten.  Up to kWaveScan
+// counters, wave 0 alone (runs of at most 4); beyond, the whole workgroup,
+// the wave sums meeting in LDS (wave 0 alone, with runs of 16 counters at
+// the 2-D workload's 980, left the other waves idle behind 32 dependent LDS
+// round trips per chunk; at the 1-D workload's 64 counters the extra
+// barrier cost more than it saved).  T is uniform over the workgroup; every
+// lane must call it, between two barriers.
+constexpr int kWaveScan = 256;
+template <int KB>
 __device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, int T) {
-  if (threadIdx.x >= 64) return;
-  const int lane = (int)threadIdx.x;
-  const int per = (T + 63) / 64;
-  const int t0 = lane * per;
+  if (T <= kWaveScan) {
+    if (threadIdx.x >= 64) return;
+    const int lane = (int)threadIdx.x;
+    const int per = (T + 63) / 64;
+    const int t0 = lane * per;
+    uint32_t sum = 0;
+    for (int t = t0; t < t0 + per && t < T; ++t) sum += tcount[t];
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    uint32_t run = incl - sum;
+    for (int t = t0; t < t0 + per && t < T; ++t) {
+      const uint32_t v = tcount[t];
+      tcount[t] = run;
+      cursor[t] = run;
+      run += v;
+    }
+    if (lane == 63) tcount[T] = incl;
+    return;
+  }
+  __shared__ uint32_t wave_total[KB / 64];
+  const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (T + KB - 1) / KB;
+  const int t0 = tid * per;
   uint32_t sum = 0;
   for (int t = t0; t < t0 + per && t < T; ++t) sum += tcount[t];
   uint32_t incl = sum;
@@ -125,14 +156,19 @@ __device__ __forceinline__ void scan_tiles(uint32_t* tcount, uint32_t* cursor, i
     const uint32_t v = __shfl_up(incl, off, 64);
     if (lane >= off) incl += v;
   }
-  uint32_t run = incl - sum;
+  if (lane == 63) wave_total[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+#pragma unroll
+  for (int w = 0; w < KB / 64; ++w) before += w < wave ? wave_total[w] : 0u;
+  uint32_t run = before + incl - sum;
   for (int t = t0; t < t0 + per && t < T; ++t) {
     const uint32_t v = tcount[t];
     tcount[t] = run;
     cursor[t] = run;
     run += v;
   }
-  if (lane == 63) tcount[T] = incl;
+  if (tid == KB - 1) tcount[T] = before + incl;
 }
 
 template <int KB, bool ALL = false, int S = 1>
@@ -153,7 +189,7 @@ __device__ __forceinline__ void sort_and_write(const KeysJob& j, const uint32_t*
                                                uint32_t* cursor) {
   count_keys<KB, ALL, S>(key, tcount);
   __syncthreads();
-  scan_tiles(tcount, cursor, T * S);
+  scan_tiles<KB>(tcount, cursor, T * S);
   __syncthreads();
   place_keys<KB, ALL, S>(key, cursor, stage);
   __syncthreads();
@@ -382,14 +418,23 @@ __device__ __forceinline__ void keys_chunk_nd(const KeysJob& j, float4* lds4) {
   uint32_t* tcount = reinterpret_cast<uint32_t*>(stage + kChunk);
   uint32_t* cursor = tcount + (T + 1);
   if constexpr (kXY) {
+    // kStageLoads records of each layer in flight per lane
     const float2 nan2 = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-    for (int i = threadIdx.x; i <= N0; i += KB) {
-      const float4 r = i < N0 ? j.pts[L0.pt_off + i] : make_float4(0.f, 0.f, 0.f, 0.f);
-      xy0[i] = i < N0 ? make_float2(r.x, r.y) : nan2;
-    }
-    for (int i = threadIdx.x; i <= N1; i += KB) {
-      const float4 r = i < N1 ? j.pts[L1.pt_off + i] : make_float4(0.f, 0.f, 0.f, 0.f);
-      xy1[i] = i < N1 ? make_float2(r.x, r.y) : nan2;
+    const int Nm = N0 > N1 ? N0 : N1;
+    for (int i0 = threadIdx.x; i0 <= Nm; i0 += KB * kStageLoads) {
+      float4 r0[kStageLoads], r1[kStageLoads];
+#pragma unroll
+      for (int u = 0; u < kStageLoads; ++u) {
+        const int i = i0 + u * KB;
+        r0[u] = i < N0 ? j.pts[L0.pt_off + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        r1[u] = i < N1 ? j.pts[L1.pt_off + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < kStageLoads; ++u) {
+        const int i = i0 + u * KB;
+        if (i <= N0) xy0[i] = i < N0 ? make_float2(r0[u].x, r0[u].y) : nan2;
+        if (i <= N1) xy1[i] = i < N1 ? make_float2(r1[u].x, r1[u].y) : nan2;
+      }
     }
   } else {
     const float4 pad = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
