@@ -456,7 +456,9 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
     """2-D max-call state, n = 30, N = 2000 (40 x 50 product of Lloyd grids
     mapped by sqrt(t_k) chol(R)), rho = 0.3, M = 1e7 pairs per layer; BDP of
     the American and European max-call (sigma 0.2 / 0.3).  One step = the
-    forward (sampling and histogram passes), the obstacles and the BDP."""
+    forward (sampling and histogram passes), the obstacles and the BDP,
+    pipelined as in the 1-D workload: step s's obstacles and BDP run on a
+    second stream while step s+1 samples (counts double-buffered)."""
     import torch
     import paper_1101_3228_amd as qt
     import synth
@@ -465,23 +467,36 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
     spec = synth.bm_model(2, n, T=MATURITY, rho=0.3)
     grid, N = synth.layer_grids(spec, [1] + [C3_SHAPE] * n, base=qt.gauss_quantizer)
     plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M)
-    counts = plan.new_counts()
+    counts = [plan.new_counts(), plan.new_counts()]
     if groups:
         plan.tune(groups=groups)
         tuning = {"fixed": plan.tuning()}
     else:
-        tuning = plan.autotune(M, seed=0x5EED00FF, counts=counts)
+        tuning = plan.autotune(M, seed=0x5EED00FF, counts=counts[0])
+    dev = counts[0].device
     s_fwd = torch.cuda.current_stream()
+    s_bdp = torch.cuda.Stream()
+    phi = [torch.empty((2, plan.points), dtype=torch.float64, device=dev) for _ in range(2)]
+    Vb = [torch.empty((2, plan.points), dtype=torch.float64, device=dev) for _ in range(2)]
+    fwd_done = [torch.cuda.Event() for _ in range(2)]
+    bdp_done = [torch.cuda.Event() for _ in range(2)]
+    for e in bdp_done:
+        e.record(s_bdp)
 
     def step(i, ev=None):
+        b = i % 2
+        s_fwd.wait_event(bdp_done[b])              # counts[b] free again
         if ev is not None:
             ev[0].record(s_fwd)
-        plan.transitions(M, 0x5EED0000 + i, counts=counts, stream=s_fwd)
-        if ev is not None:
-            ev[2].record(s_fwd)
-        phi = plan.payoff_batch([qt.MAX_CALL, qt.MAX_CALL | qt.EUROPEAN], S0, S0, RATE,
-                                MATURITY, [[0.2, 0.3], [0.2, 0.3]], stream=s_fwd)
-        return plan.bdp(counts, phi, want_v0=False, stream=s_fwd)[1]
+        plan.transitions(M, 0x5EED0000 + i, counts=counts[b], stream=s_fwd)
+        done = fwd_done[b] if ev is None else ev[2]
+        done.record(s_fwd)
+        s_bdp.wait_event(done)
+        plan.payoff_batch([qt.MAX_CALL, qt.MAX_CALL | qt.EUROPEAN], S0, S0, RATE, MATURITY,
+                          [[0.2, 0.3], [0.2, 0.3]], out=phi[b], stream=s_bdp)
+        plan.bdp(counts[b], phi[b], V=Vb[b], want_v0=False, stream=s_bdp)
+        bdp_done[b].record(s_bdp)
+        return Vb[b]
 
     for i in range(warmup):
         step(i)
@@ -497,6 +512,7 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
         plan.trace(evs[i][1])
         V = step(i, evs[i])
     plan.trace(None)
+    s_fwd.wait_stream(s_bdp)
     t1.record(s_fwd)
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / steps
