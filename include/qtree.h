@@ -50,7 +50,7 @@ typedef enum {
   QTREE_ENOMEM = 2,      /* workspace too small */
   QTREE_EOVERFLOW = 3,   /* a count could exceed int32 (M >= 2^31) or m0 + M > 2^32 */
   QTREE_EDEVICE = 4,     /* a HIP runtime call failed (detail in qtree_last_error) */
-  QTREE_EUNSUPPORTED = 5 /* valid request this build does not implement */
+  QTREE_EUNSUPPORTED = 5 /* valid request the library does not implement */
 } qtree_status;
 
 typedef enum {

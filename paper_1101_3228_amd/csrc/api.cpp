@@ -249,7 +249,7 @@ const char* qtree_status_string(qtree_status s) {
     case QTREE_ENOMEM: return "workspace too small";
     case QTREE_EOVERFLOW: return "count overflow (M >= 2^31 or m0 + M > 2^32)";
     case QTREE_EDEVICE: return "HIP runtime error";
-    case QTREE_EUNSUPPORTED: return "unsupported by this build";
+    case QTREE_EUNSUPPORTED: return "unsupported by the library";
   }
   return "unknown status";
 }
