@@ -71,14 +71,17 @@ struct alignas(16) LayerDev {
 constexpr int kBucketRow = 32;            // uint16 entries of a bucket row (64 bytes)
 constexpr int kBucketCap = kBucketRow - 1; // candidates a row holds
 constexpr uint16_t kBucketFull = 0xFFFF;  // row count: candidates did not fit
-// Buckets per side of a d = 2 layer of N points: about 32 buckets per point,
-// at most 256 per side (the 2-D workload's sampling pass, N = 2000: 5.16 ms
-// at 32 per point, 5.68 at 24, 6.28 at 16, 8.42 at 8).
+// Buckets per side of a d = 2 layer of N points: about 64 buckets per point,
+// at most 512 per side, 4 KB of rows per point (the 2-D workload, N = 2000:
+// a step of 3.82 ms at 64 per point, 3.89 at 96, 3.97 at 128, 4.15 at 32;
+// its first form's sampling pass 5.16 ms at 32, 5.68 at 24, 6.28 at 16,
+// 8.42 at 8).  Denser buckets list fewer candidates, so fewer waves walk a
+// second group; beyond 64 the rows no longer stay in the caches.
 inline int bucket_side(int N) {
   if (N <= 1) return 1;
   int b = 1;
-  while ((double)b * b < 32.0 * N) ++b;
-  return b < 256 ? b : 256;
+  while ((double)b * b < 64.0 * N) ++b;
+  return b < 512 ? b : 512;
 }
 
 // Workspace layout (byte offsets from the workspace base).
