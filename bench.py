@@ -99,14 +99,17 @@ ALG_SLOTS_PER_PAIR = PHILOX_CALL // 2 + BOX_MULLER + 3 * F + 2 * guide_search(2)
 ALG_SLOTS_2D_PAIR = PHILOX_CALL + 2 * BOX_MULLER + 12 * F + KEY_INCR     # 277
 ALG_SLOTS_2D_POINT = ND_POINT
 # d = 2 bucketed search (the bucket holding the point lists every grid point
-# that can win there): bucket coordinates (two fmas 2F, two conversions 2H),
-# box test (four compares and their conjunction 4F), bucket index F; per
-# listed candidate: index unpack F, record address F, key 2F, compare F,
-# best key and index selects 2F; a point outside the box or in a full
-# bucket scans all N points (key 2F, compare F, two selects 2F).
-BUCKET_LOCATE = 2 * F + 2 * H + 4 * F + F                                # 11
-BUCKET_CAND = F + F + 2 * F + F + 2 * F                                  # 7
-SCAN_POINT = 2 * F + F + 2 * F                                           # 5
+# that can win there), in the issue classes above (compares, selects,
+# conversions and 3-input ops at half rate): bucket coordinates (two fmas
+# 2F), box test (four compares 4H; their conjunction is scalar), two
+# conversions 2H, bucket index (a 24-bit multiply-add H, the layer's offset
+# F) and the row address H; per listed candidate: index unpack F, record
+# address (shift and add) 2F, key 2F, compare H, best key and index selects
+# 2H; a point outside the box or in a full bucket scans all N points (key
+# 2F, compare H, two selects 2H).
+BUCKET_LOCATE = 2 * F + 4 * H + 2 * H + H + F + H                        # 19
+BUCKET_CAND = F + 2 * F + 2 * F + H + 2 * H                              # 11
+SCAN_POINT = 2 * F + H + 2 * H                                           # 8
 # The same pair with every operation priced 1 (transcendental 4): the
 # unweighted count reported beside the weighted one.
 ALG_SLOTS_PER_PAIR_UNWEIGHTED = 30 + 71 + 3 + 2 * 11 + 2
