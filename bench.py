@@ -173,7 +173,7 @@ def main():
                     help="default run: skip the 2-D workload's nested line")
     ap.add_argument("--c3-steps", type=int, default=3,
                     help="default run: timed steps of the 2-D workload")
-    ap.add_argument("--cpu-pairs", type=int, default=4_000_000,
+    ap.add_argument("--cpu-pairs", type=int, default=7_000_000,
                     help="pairs per layer in the oracle sample")
     ap.add_argument("--workload", choices=("c2", "c3", "batch", "c5", "c1", "p1", "swing",
                                            "rng", "nn", "lloyd", "strat"),
@@ -551,7 +551,7 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
     }
     if with_cpu:
         import oracle as O
-        Mc = 20_000
+        Mc = 400_000
         threads = min(os.cpu_count() or 1, n)
         mdl = O.Model(spec["d"], spec["n"], spec["A"], spec["b"], spec["T"], spec["mu"],
                       spec["L"], spec["x0"])
