@@ -93,7 +93,7 @@ bool two_pass_fits(int d, int n, const int32_t* N) {
 // Buckets of the d = 2 cell search over all layers (layers of one point
 // have none).
 // Layers take bucket tables in order while the rows so far stay within
-// int32 indices; later layers (beyond about 32 000 layers of 4096 points)
+// int32 indices; later layers (beyond about 8000 layers of 4096 points)
 // keep the full scan.  bucket_boxes follows the same rule.
 constexpr int64_t kMaxBuckets = 0x7FFFFFFF;
 int64_t total_buckets(int n, const int32_t* N) {
