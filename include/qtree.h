@@ -82,8 +82,10 @@ const char *qtree_version(void);
 /* Bytes of device workspace a plan for this shape needs (d in 1..3,
  * N: host [n+1]) when its counting scratch is to hold `batch_samples`
  * LAYERWISE samples per layer per pass (0: 2^22).  Larger M runs in several
- * passes; a plan uses all the scratch its workspace has room for.  Pure host
- * arithmetic. */
+ * passes; a plan uses all the scratch its workspace has room for.  For d = 2
+ * it includes the bucket tables of the cell search, 64 bytes per bucket and
+ * about 64 buckets per grid point (8 MB for a layer of 2000 points).  Pure
+ * host arithmetic. */
 qtree_status qtree_workspace_size(int32_t d, int32_t n, const int32_t *N, uint64_t batch_samples,
                                   size_t *bytes);
 
@@ -121,7 +123,7 @@ qtree_status qtree_plan_cell_search(const qtree_plan *plan, int32_t *guide_k,
 qtree_status qtree_plan_buckets(const qtree_plan *plan, int32_t k, float *lo, float *scale,
                                 int32_t *B);
 /* The candidate count of every bucket of layer k, row-major (bucket (i, j)
- * at i B[1] + j; 0xFFFF: more than 32 candidates, the full scan decides):
+ * at i B[1] + j; 0xFFFF: more than 31 candidates, the full scan decides):
  * counts, host uint16[B[0] B[1]] (nothing written when the layer has no
  * tables).  Blocking. */
 qtree_status qtree_plan_bucket_counts(const qtree_plan *plan, int32_t k, uint16_t *counts);
