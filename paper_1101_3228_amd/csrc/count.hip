@@ -670,6 +670,16 @@ __global__ __launch_bounds__(kBlockNd) void fwd_keys_nd(FwdArgs a) {
   keys_chunk_nd<D, S, kBlockNd, BK>(plan_job(a, k, c), lds4);
 }
 
+// The bucketed search with one sample per lane and round, held to 80 VGPRs
+// (six waves per SIMD): with its smaller LDS, three workgroups per CU.
+__global__ __launch_bounds__(kBlockNd) __attribute__((amdgpu_waves_per_eu(6)))
+void fwd_keys_nd_bk1(FwdArgs a) {
+  extern __shared__ float4 lds4[];
+  int k, c;
+  if (!unit_of_block_keys(a, k, c)) return;
+  keys_chunk_nd<2, kBkSamplesLo, kBlockNd, true>(plan_job(a, k, c), lds4);
+}
+
 // Workgroup b owns histogram unit tile0 + u (super tile t of layer k, or
 // one part of it).  With the XCD map, workgroup b runs on XCD b mod 8 and
 // takes unit u = (b mod 8) per + b / 8: consecutive units -- the super tiles
@@ -857,6 +867,15 @@ size_t keys_lds_nd(int maxN, int max_tiles) {
          sizeof(uint32_t) * (2 * ts + 1);
 }
 
+// The bucketed d = 2 search stages (x, y) pairs and a pad pair per layer, a
+// whole number of 16 bytes each: a third less LDS than the scan's records,
+// so a CU holds three workgroups where their registers allow.
+static size_t keys_lds_nd_bk(int maxN, int max_tiles) {
+  const size_t ts = (size_t)max_tiles * nd_subs(max_tiles);
+  return sizeof(float4) * 2 * (size_t)((maxN + 2) / 2) + sizeof(uint16_t) * kChunk +
+         sizeof(uint32_t) * (2 * ts + 1);
+}
+
 hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
   hipError_t e;
   if (a.d == 1 && a.gt_Kmax >= 0) {
@@ -900,12 +919,11 @@ hipError_t launch_fwd_keys(const FwdArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(fwd_keys_1d<0>, keys_grid(a), dim3(kBlock), lds, s, a);
     }
   } else if (a.d == 2 && a.bucketed && a.nd_samples == 4) {
-    const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
-    if ((e = allow_lds(fwd_keys_nd<2, kBkSamplesLo, true>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL((fwd_keys_nd<2, kBkSamplesLo, true>), keys_grid(a), dim3(kBlockNd), lds, s,
-                       a);
+    const size_t lds = keys_lds_nd_bk(a.maxN, a.max_tiles);
+    if ((e = allow_lds(fwd_keys_nd_bk1, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(fwd_keys_nd_bk1, keys_grid(a), dim3(kBlockNd), lds, s, a);
   } else if (a.d == 2 && a.bucketed) {
-    const size_t lds = keys_lds_nd(a.maxN, a.max_tiles);
+    const size_t lds = keys_lds_nd_bk(a.maxN, a.max_tiles);
     if ((e = allow_lds(fwd_keys_nd<2, kBkSamplesHi, true>, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL((fwd_keys_nd<2, kBkSamplesHi, true>), keys_grid(a), dim3(kBlockNd), lds, s,
                        a);
