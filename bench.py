@@ -193,7 +193,7 @@ def main():
                          "samples per cell")
     ap.add_argument("--epochs", type=int, default=6000, help="c5 training epochs")
     ap.add_argument("--tail", type=int, default=100,
-                    help="c2 with --groups: the last layer group's share in percent")
+                    help="c2/c3 with --groups: the last layer group's share in percent")
     ap.add_argument("--groups", type=int, default=0,
                     help="c2/c3: layer groups of the two-pass forward (0: library default)")
     ap.add_argument("--act-terms", type=int, default=1, choices=(1, 2),
@@ -455,7 +455,8 @@ def bucketed_pair_slots(plan, samples: int = 65_536, seed: int = 0x5EED0C00) -> 
 C3_LAYERS, C3_SHAPE, C3_M = 30, (40, 50), 10_000_000
 
 
-def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict:
+def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0,
+               tail: int = 100) -> dict:
     """2-D max-call state, n = 30, N = 2000 (40 x 50 product of Lloyd grids
     mapped by sqrt(t_k) chol(R)), rho = 0.3, M = 1e7 pairs per layer; BDP of
     the American and European max-call (sigma 0.2 / 0.3).  One step = the
@@ -472,7 +473,7 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
     plan = qt.Plan(spec, grid, N, device="cuda:0", batch_samples=M)
     counts = [plan.new_counts(), plan.new_counts()]
     if groups:
-        plan.tune(groups=groups)
+        plan.tune(groups=groups, tail=tail)
         tuning = {"fixed": plan.tuning()}
     else:
         tuning = plan.autotune(M, seed=0x5EED00FF, counts=counts[0])
@@ -527,8 +528,10 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
     if bucketed:
         per_layer = bucketed_pair_slots(plan)
         alg = M * float(np.sum(per_layer))
-        # the bucketed kernel takes 2 samples per lane for the tuning's 8, 1 for 4
-        kernel = f"fwd_keys_nd<2, {2 if plan.tuning()['nd_samples'] == 8 else 1}, true>"
+        # the bucketed kernel takes 2 samples per lane and round for the
+        # tuning's 8; for 4, one, in its six-waves-per-SIMD instance
+        kernel = ("fwd_keys_nd<2, 2, true>" if plan.tuning()["nd_samples"] == 8
+                  else "fwd_keys_nd_bk1")
     else:
         alg = ALG_SLOTS_2D_PAIR * pairs + ALG_SLOTS_2D_POINT * points
         kernel = f"fwd_keys_nd<2, {plan.tuning()['nd_samples']}, false>"
@@ -567,7 +570,7 @@ def measure_c3(steps: int, warmup: int, with_cpu: bool, groups: int = 0) -> dict
 
 def run_c3(args):
     """The 2-D workload as its own line (see measure_c3)."""
-    r = measure_c3(args.steps, args.warmup, not args.no_cpu_baseline, args.groups)
+    r = measure_c3(args.steps, args.warmup, not args.no_cpu_baseline, args.groups, args.tail)
     out = {
         "metric": "MC transition samples/s (cell search+count)",
         "value": r["value"], "unit": "pairs/s", "n_gpus": 1,

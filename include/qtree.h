@@ -153,7 +153,8 @@ int64_t qtree_plan_points(const qtree_plan *plan);        /* sum_k N_k */
  *                        A plan used with groups > 1 must not be used from
  *                        two host threads at once.
  *   QTREE_TUNE_ND_SAMPLES : d >= 2 two-pass sampling: samples per lane that
- *                        share each grid record read from LDS, 8 (default) or 4.
+ *                        share each grid record read from LDS, 8 or 4 (default
+ *                        8; 4 for a d = 2 plan that has bucket tables).
  *   QTREE_TUNE_TAIL    : with layer groups, the last group's share of the
  *                        layers in percent of each other group's (10..100,
  *                        default 100: equal groups); its histogram pass is

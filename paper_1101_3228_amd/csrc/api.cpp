@@ -407,6 +407,9 @@ static void bucket_boxes(qtree_plan& p, const qtree_model* model, const float* g
     off += (int64_t)B * B;
   }
   p.buckets = off;
+  // with the bucket tables, one sample per lane and round runs at six waves
+  // per SIMD and beats two per round's shared grid reads
+  if (off > 0) p.tune_nd_samples = 4;
 }
 
 qtree_status qtree_plan_create(const qtree_model* model, const float* grid, const int32_t* N,

@@ -110,11 +110,15 @@ def test_bucketed_counts_equal_full_scan_and_oracle():
     spec = synth.bm_model(2, 8, T=1.0, rho=0.3)
     grid, N = synth.layer_grids(spec, [1] + [(40, 50)] * 8, base=qt.gauss_quantizer)
     plan = qt.Plan(spec, grid, N)
+    assert plan.tuning()["nd_samples"] == 4  # the default with bucket tables
     M, seed = 400_001, 0x5EED0051
-    on = plan.transitions(M, seed, contract=3).cpu().numpy()
-    plan.tune(buckets=0)
-    off_ = plan.transitions(M, seed, contract=3).cpu().numpy()
-    plan.tune(buckets=1)
     ref = O.transitions(_omodel(spec), grid, N, M, seed=seed, contract=3, nthreads=16)
-    assert np.array_equal(off_, ref)
-    assert np.array_equal(on, ref)
+    # both samples-per-lane settings, with and without the tables
+    for s in (4, 8):
+        plan.tune(nd_samples=s, buckets=1)
+        on = plan.transitions(M, seed, contract=3).cpu().numpy()
+        plan.tune(buckets=0)
+        off_ = plan.transitions(M, seed, contract=3).cpu().numpy()
+        assert np.array_equal(off_, ref), s
+        assert np.array_equal(on, ref), s
+    plan.tune(nd_samples=4, buckets=1)
