@@ -452,6 +452,16 @@ def bucketed_pair_slots(plan, samples: int = 65_536, seed: int = 0x5EED0C00) -> 
     return out
 
 
+def _batch_tuning(batch) -> dict:
+    """The batch's configuration in use, its code decoded (bit 0: 4 samples
+    per lane in the d >= 2 launch, else 8; bit 1: the 1-D launch overlapped
+    on a side stream; bits 8-15: a cap on that launch's workgroups per CU)."""
+    t = batch.tuning()
+    c = t["config"]
+    return {**t, "nd_samples": 4 if c & 1 else 8, "overlap": bool(c & 2),
+            "nd_cap": (c >> 8) & 0xFF}
+
+
 C3_LAYERS, C3_SHAPE, C3_M = 30, (40, 50), 10_000_000
 
 
@@ -662,6 +672,7 @@ def run_batch(args):
                    "contracts": len(items), "pairs": pairs, "options": options},
         "options_per_s": options / (ms_step * 1e-3),
         "batch": info, "prep_s": prep_s,
+        "tuning": _batch_tuning(batch),
         "V0_mean": float(np.mean(V0)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,

@@ -138,7 +138,9 @@ struct qtree_batch {
   int sub1 = 1, maxP1 = 1, gtB1 = 1;  // its sub-counters, midpoint slots, largest table
   int subn = 1;                      // sub-counters per tile of the d >= 2 sort
   int cus = 256;
-  int max_per_cu[2] = {1, 1};  // workgroups per CU that fit, of each sampling launch
+  // workgroups per CU that fit, of each sampling launch: the 1-D one, then the
+  // d >= 2 one at 8 and at 4 samples per lane (different kernels)
+  int max_per_cu[3] = {1, 1, 1};
   BatchConfig cfg;
   bool cfg_fixed = false;      // set by qtree_batch_set_config: the tuner keeps out
   double tuned_ms = 0.0;       // measured forward time of cfg (0: not measured)
@@ -196,8 +198,13 @@ size_t nd_lds(const qtree_batch* b, const BatchConfig& c) {
   return lds;
 }
 
+int nd_fit(const qtree_batch* b, int nd_samples) {
+  return b->max_per_cu[nd_samples == 4 ? 2 : 1];
+}
+
 int nd_per_cu(const qtree_batch* b, const BatchConfig& c) {
-  return c.nd_cap > 0 ? std::min(c.nd_cap, b->max_per_cu[1]) : b->max_per_cu[1];
+  const int fit = nd_fit(b, c.nd_samples);
+  return c.nd_cap > 0 ? std::min(c.nd_cap, fit) : fit;
 }
 
 hipError_t ensure_side(qtree_batch* b) {
@@ -259,7 +266,7 @@ std::vector<BatchConfig> candidates(const qtree_batch* b) {
         BatchConfig c;
         c.nd_samples = ns;
         c.overlap = ov;
-        c.nd_cap = cap && b->max_per_cu[1] > 1 ? b->max_per_cu[1] - 1 : 0;
+        c.nd_cap = cap && nd_fit(b, ns) > 1 ? nd_fit(b, ns) - 1 : 0;
         if (cap && c.nd_cap == 0) continue;
         if (!nd && (ns != 8 || cap)) continue;  // no d >= 2 launch: nothing to vary there
         out.push_back(c);
@@ -434,17 +441,20 @@ qtree_status qtree_batch_plan(const qtree_contract* contracts, int32_t n, qtree_
     b->gtB1 = gtB;
     b->lds[0] = qtree::keys_lds_1d_guide(maxP, gtB, max_tiles1);
   }
-  b->lds[1] = qtree::keys_lds_nd(maxN, max_tilesn);
+  // every d >= 2 contract a bucketed d = 2 one: the launch stages pairs only
+  b->lds[1] = (b->dmax == 2 && b->bucketed) ? qtree::keys_lds_nd_bk(maxN, max_tilesn)
+                                            : qtree::keys_lds_nd(maxN, max_tilesn);
   b->subn = qtree::nd_sub_counters(max_tilesn);
   if (b->lds[0] > 160 * 1024 || (b->dmax > 1 && b->lds[1] > 160 * 1024)) {
     delete b;
     return set_error(QTREE_EUNSUPPORTED, "batch needs more LDS than a workgroup has");
   }
-  for (int x = 0; x < 2; ++x) {
-    if (x == 1 && b->dmax == 1) continue;
+  for (int x = 0; x < 3; ++x) {
+    if (x >= 1 && b->dmax == 1) continue;
+    const int lx = x == 0 ? 0 : 1;
     b->max_per_cu[x] =
         std::min(8, qtree::batch_keys_occupancy(x == 0 ? 1 : b->dmax, b->lg1,
-                                                x == 0 ? b->gk1 : -1, b->lds[x], 8,
+                                                x == 0 ? b->gk1 : -1, b->lds[lx], x == 2 ? 4 : 8,
                                                 (b->dmax == 2 && b->bucketed) ? 1 : 0));
   }
   int dev = 0;

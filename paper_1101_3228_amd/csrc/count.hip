@@ -730,26 +730,40 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
 // register allocation of the chunk routine alone (a persistent claim loop
 // around it held ~40 more).  One launch takes the 1-D units (256 lanes),
 // another the d >= 2 units (512 lanes under one grid pair).
+// A pointer read from a batch record is a generic address to the compiler,
+// which then loads through it with flat instructions: a 64-bit address in
+// VGPRs, no scalar loads of uniform fields, and waits shared with LDS
+// operations.  Every table a record points to is device memory: reading the
+// field as a global pointer and converting it gives the single-plan kernels'
+// global and scalar loads.
+template <class T>
+__device__ __forceinline__ T* as_global(T* const& field) {
+  typedef __attribute__((address_space(1))) T* G;
+  return (T*)*reinterpret_cast<const G*>(&field);
+}
+
 template <int KB, typename Body>
 __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
   const int b = (int)blockIdx.x;
+  const int* chunk_off = as_global(a.chunk_off);
   int lo = 0, hi = a.n_units - 1;  // largest u with chunk_off[u] <= b
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (a.chunk_off[mid] <= b) lo = mid; else hi = mid - 1;
+    if (chunk_off[mid] <= b) lo = mid; else hi = mid - 1;
   }
   const int u = lo;
-  const BatchUnit U = a.units[u];
-  const BatchContract& C = a.contracts[U.c];
+  const BatchUnit U = as_global(a.units)[u];
+  const BatchContract& C = as_global(a.contracts)[U.c];
   {
-    const int c = U.chunk0 + (b - a.chunk_off[u]);
+    const int c = U.chunk0 + (b - chunk_off[u]);
     {
       KeysJob j;
-      j.L0 = &C.layers[U.k];
-      j.L1 = &C.layers[U.k + 1];
-      j.mids = C.mids;
-      j.guide = C.guide;
-      j.pts = C.pts;
+      const LayerDev* layers = as_global(C.layers);
+      j.L0 = &layers[U.k];
+      j.L1 = &layers[U.k + 1];
+      j.mids = as_global(C.mids);
+      j.guide = as_global(C.guide);
+      j.pts = as_global(C.pts);
       j.key0 = C.key0;
       j.key1 = C.key1;
       j.contract = C.contract;
@@ -757,9 +771,10 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
       j.c = c;
       j.lo = 0;
       j.hi = C.M;
-      j.keys = a.keys + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
-      j.seg = a.segs + (size_t)C.seg_base + ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
-      j.bk_rows = C.bk_rows;
+      j.keys = as_global(a.keys) + ((size_t)C.chunk_base + (size_t)U.k * C.chunks + c) * kChunk;
+      j.seg = as_global(a.segs) + (size_t)C.seg_base +
+              ((size_t)U.k * C.chunks + c) * (size_t)C.seg_stride;
+      j.bk_rows = as_global(C.bk_rows);
       j.nd_sub = a.sub;
       body(C, j);
     }
@@ -812,22 +827,29 @@ void batch_keys_nd_bk(BatchArgs a) {
   batch_keys_nd_body<2, S2, true>(a);
 }
 
+// One sample per lane and round, held to 80 VGPRs (six waves per SIMD): with
+// the pairs-only LDS block, three workgroups per CU.
+__global__ __launch_bounds__(kBlockNd) __attribute__((amdgpu_waves_per_eu(6)))
+void batch_keys_nd_bk1(BatchArgs a) {
+  batch_keys_nd_body<2, kBkSamplesLo, true>(a);
+}
+
 // Pass B of a batch: workgroup b handles tile record b.
 __global__ __launch_bounds__(kCountBlock) void batch_count(BatchArgs a) {
   extern __shared__ uint32_t hist[];
-  const BatchTile T = a.tiles[blockIdx.x];
-  const BatchContract& C = a.contracts[T.c];
+  const BatchTile T = as_global(a.tiles)[blockIdx.x];
+  const BatchContract& C = as_global(a.contracts)[T.c];
   TileJob j;
-  j.L0 = &C.layers[T.k];
-  j.keys = a.keys + ((size_t)C.chunk_base + (size_t)T.k * C.chunks) * kChunk;
-  j.seg = a.segs + (size_t)C.seg_base + (size_t)T.k * C.chunks * (size_t)C.seg_stride;
+  j.L0 = &as_global(C.layers)[T.k];
+  j.keys = as_global(a.keys) + ((size_t)C.chunk_base + (size_t)T.k * C.chunks) * kChunk;
+  j.seg = as_global(a.segs) + (size_t)C.seg_base + (size_t)T.k * C.chunks * (size_t)C.seg_stride;
   j.seg_stride = C.seg_stride;
   j.chunks = C.chunks;
   j.c_lo = 0;
   j.c_hi = C.chunks;
   j.atomic = 0;
   j.t = T.t;
-  j.counts_k = C.counts + C.layers[T.k].cnt_off;
+  j.counts_k = as_global(C.counts) + j.L0->cnt_off;
   j.first = 1;
   count_tile(j, hist, hist + kSuper, hist + kSuper + kCountBlock);
 }
@@ -870,7 +892,7 @@ size_t keys_lds_nd(int maxN, int max_tiles) {
 // The bucketed d = 2 search stages (x, y) pairs and a pad pair per layer, a
 // whole number of 16 bytes each: a third less LDS than the scan's records,
 // so a CU holds three workgroups where their registers allow.
-static size_t keys_lds_nd_bk(int maxN, int max_tiles) {
+size_t keys_lds_nd_bk(int maxN, int max_tiles) {
   const size_t ts = (size_t)max_tiles * nd_subs(max_tiles);
   return sizeof(float4) * 2 * (size_t)((maxN + 2) / 2) + sizeof(uint16_t) * kChunk +
          sizeof(uint32_t) * (2 * ts + 1);
@@ -1030,7 +1052,7 @@ hipError_t launch_batch_keys(const BatchArgs& a, int dmax, int lg1, int grid, si
   if ((e = allow_lds(KER, lds)) != hipSuccess) return e;                                     \
   hipLaunchKernelGGL((KER), dim3((unsigned)grid), dim3(kBlockNd), lds, s, a);
     if (dmax == 2 && a.bucketed && a.nd_samples == 4) {
-      QTREE_LAUNCH_ND(batch_keys_nd_bk<kBkSamplesLo>)
+      QTREE_LAUNCH_ND(batch_keys_nd_bk1)
     } else if (dmax == 2 && a.bucketed) {
       QTREE_LAUNCH_ND(batch_keys_nd_bk<kBkSamplesHi>)
     } else if (dmax == 2 && a.nd_samples == 4) {
@@ -1066,7 +1088,7 @@ int batch_keys_occupancy(int dmax, int lg1, int gk, size_t lds, int nd_samples, 
   e = allow_lds(KER, lds);                                                                   \
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, KER, kBlockNd, lds);
     if (dmax == 2 && bucketed && nd_samples == 4) {
-      QTREE_OCC_ND(batch_keys_nd_bk<kBkSamplesLo>)
+      QTREE_OCC_ND(batch_keys_nd_bk1)
     } else if (dmax == 2 && bucketed) {
       QTREE_OCC_ND(batch_keys_nd_bk<kBkSamplesHi>)
     } else if (dmax == 2 && nd_samples == 4) {

@@ -67,6 +67,7 @@ size_t keys_lds_1d_guide(int maxP, int maxB, int max_tiles);
 int guide_sub_counters(int max_tiles);
 int nd_sub_counters(int max_tiles);
 size_t keys_lds_nd(int maxN, int max_tiles);
+size_t keys_lds_nd_bk(int maxN, int max_tiles);  // the bucketed d = 2 launches
 
 // BDP of one contract for payoffs [q0, q0 + nq) (nq <= 16).
 struct BdpJob {
