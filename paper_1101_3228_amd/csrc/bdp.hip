@@ -171,12 +171,14 @@ hipError_t launch_copy_last_layer(const BdpArgs& a, int64_t pt_n, int N_n, hipSt
 constexpr int kBdpBlock = 64 * kBdpTaskRows;
 
 __global__ void bdp_batch_copy_kernel(const BdpJob* jobs) {
-  const BdpJob J = jobs[blockIdx.y];
-  const LayerDev& Ln = J.layers[J.n];
+  const BdpJob& J = jobs[blockIdx.y];
+  const LayerDev& Ln = as_global(J.layers)[J.n];
+  const double* phi = as_global(J.phi);
+  double* V = as_global(J.V);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < J.nq * Ln.N; t += gridDim.x * blockDim.x) {
     const int q = t / Ln.N, i = t - q * Ln.N;
     const int64_t at = (int64_t)(J.q0 + q) * J.P + Ln.pt_off + i;
-    J.V[at] = J.phi[at];
+    V[at] = phi[at];
   }
 }
 
@@ -186,13 +188,15 @@ __global__ __launch_bounds__(kBdpBlock) void bdp_step_kernel(const BdpJob* jobs,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (wave >= T.nrows) return;
   const BdpJob& J = jobs[T.job];
-  const LayerDev& L = J.layers[T.k];
-  const LayerDev& L1 = J.layers[T.k + 1];
+  const LayerDev* layers = as_global(J.layers);
+  const LayerDev& L = layers[T.k];
+  const LayerDev& L1 = layers[T.k + 1];
+  double* V = as_global(J.V);
   const int i = T.row0 + wave;
-  const int32_t* row = J.counts + L.cnt_off + (int64_t)i * L.N1;
+  const int32_t* row = as_global(J.counts) + L.cnt_off + (int64_t)i * L.N1;
   int64_t p;
   double s[kPay];
-  row_sums<true>(row, L.N1, J.V, J.P, J.q0, J.nq, L1.pt_off, lane, p, s);
+  row_sums<true>(row, L.N1, V, J.P, J.q0, J.nq, L1.pt_off, lane, p, s);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     p += __shfl_xor(p, off, 64);
@@ -206,8 +210,8 @@ __global__ __launch_bounds__(kBdpBlock) void bdp_step_kernel(const BdpJob* jobs,
       if (lane == q) sq = s[q];
     const double cont = p > 0 ? sq / (double)p : 0.0;
     const int64_t at = (int64_t)(J.q0 + lane) * J.P + L.pt_off + i;
-    const double f = J.phi[at];
-    J.V[at] = f > cont ? f : cont;
+    const double f = as_global(J.phi)[at];
+    V[at] = f > cont ? f : cont;
   }
 }
 

@@ -730,18 +730,6 @@ __global__ __launch_bounds__(kCountBlock) void count_tiles(FwdArgs a) {
 // register allocation of the chunk routine alone (a persistent claim loop
 // around it held ~40 more).  One launch takes the 1-D units (256 lanes),
 // another the d >= 2 units (512 lanes under one grid pair).
-// A pointer read from a batch record is a generic address to the compiler,
-// which then loads through it with flat instructions: a 64-bit address in
-// VGPRs, no scalar loads of uniform fields, and waits shared with LDS
-// operations.  Every table a record points to is device memory: reading the
-// field as a global pointer and converting it gives the single-plan kernels'
-// global and scalar loads.
-template <class T>
-__device__ __forceinline__ T* as_global(T* const& field) {
-  typedef __attribute__((address_space(1))) T* G;
-  return (T*)*reinterpret_cast<const G*>(&field);
-}
-
 template <int KB, typename Body>
 __device__ __forceinline__ void batch_loop(const BatchArgs& a, Body body) {
   const int b = (int)blockIdx.x;

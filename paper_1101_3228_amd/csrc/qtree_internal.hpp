@@ -21,6 +21,18 @@ constexpr int kSuperBits = 14;
 constexpr int kSuper = 1 << kSuperBits;
 constexpr int kTilesPerSuper = kSuper / kTile;
 constexpr int kChunk = 4096;          // samples per pass-A workgroup
+
+// A pointer read from device memory (a batch or job record, a kernel
+// argument's struct field) is a generic address to the compiler, which then
+// loads through it with flat instructions: a 64-bit address in VGPRs, no
+// scalar loads of uniform fields, and waits shared with LDS operations.
+// Every table such a field points to is device memory: reading the field as
+// a global pointer and converting it gives global and scalar loads.
+template <class T>
+__device__ __forceinline__ T* as_global(T* const& field) {
+  typedef __attribute__((address_space(1))) T* G;
+  return (T*)*reinterpret_cast<const G*>(&field);
+}
 constexpr int kMaxTiles = 4096;       // larger count blocks use direct atomics
 constexpr int kDefaultBatch = 1 << 22;  // samples per layer per pass by default
 constexpr int kScanTile = 8;            // records per tile of the d >= 2 argmin scan
