@@ -403,17 +403,21 @@ __device__ __forceinline__ double obstacle(const Contract& C, const LayerObstacl
   return o.euro ? -__builtin_huge_val() : v;
 }
 
+// The grid is read through global pointers: taken from the tree table, the
+// generic ones were read with flat loads, which count against the same wait
+// counter as the kernel's scalar weight loads.
 template <int D>
 __device__ __forceinline__ void grid_point(const ManyTree& a, int64_t pt_off, int i,
                                            float* xs) {
   const int64_t at = pt_off + i;
+  typedef const float __attribute__((address_space(1)))* GlobalF32;
   if (D == 1) {
-    xs[0] = a.pts1[at];
+    xs[0] = ((GlobalF32)a.pts1)[at];
   } else {
-    const float4 g = a.pts[at];
-    xs[0] = g.x;
-    xs[1] = g.y;
-    if (D == 3) xs[2] = g.z;
+    const GlobalF32 g = (GlobalF32)(a.pts + at);  // the point's x, y (, z)
+    xs[0] = g[0];
+    xs[1] = g[1];
+    if (D == 3) xs[2] = g[2];
   }
 }
 
