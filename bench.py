@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true",
                     help="default run: skip the 2-D workload's nested line")
-    ap.add_argument("--c3-steps", type=int, default=3,
+    ap.add_argument("--c3-steps", type=int, default=10,
                     help="default run: timed steps of the 2-D workload")
     ap.add_argument("--cpu-pairs", type=int, default=7_000_000,
                     help="pairs per layer in the oracle sample")
@@ -351,7 +351,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_c3:
         log("2-D workload")
-        out["c3"] = measure_c3(args.c3_steps, 1, not args.no_cpu_baseline)
+        out["c3"] = measure_c3(args.c3_steps, 2, not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)
 
 
