@@ -74,6 +74,42 @@ def test_batch_equals_one_plan_at_a_time():
         assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("case", ["tables_off", "with_3d"])
+def test_batch_scan_launches_equal_one_plan_at_a_time(case):
+    """The d >= 2 launch without the bucketed search, whose LDS block holds
+    the scan's grid records rather than (x, y) pairs: 2-D contracts whose
+    plans have the bucket tables turned off, and a batch that adds 3-D
+    contracts to the 2-D ones.  Counts bit-exact and values to 1e-12 against
+    one plan at a time, under both samples-per-lane settings."""
+    print(f"[gpu-case] batch scan launch, {case}", flush=True)
+    items = _contracts(6, shrink=0.12, M=40_001, seed=21)
+    if case == "tables_off":
+        for it in items:
+            if it["model"]["d"] == 2:
+                it["plan"].tune(buckets=0)
+    else:
+        for j, sizes in enumerate(([1, (3, 3, 3), (4, 4, 4), (4, 5, 5)],
+                                   [1, (2, 3, 5), (5, 5, 5)])):
+            model = synth.bm_model(3, len(sizes) - 1, T=1.0, rho=-0.2)
+            grid, N = synth.layer_grids(model, sizes)
+            plan = qt.Plan(model, grid, N, batch_samples=1)
+            phi = torch.stack([plan.payoff(qt.MAX_CALL, 100.0, 100.0, 0.05, 1.0,
+                                           [0.2, 0.25, 0.3])])
+            items.append(dict(plan=plan, M=40_001, seed=synth.SEED_BASE + 100 + j,
+                              contract_id=100 + j, counts=plan.new_counts(), phi=phi,
+                              V=torch.empty_like(phi), model=model, grid=grid, N=N))
+    ref_counts, ref_v0 = _single(items)
+    batch = qt.Batch(items)
+    for code in (0, 1):  # 8, then 4 samples per lane in the d >= 2 launch
+        batch.set_config(code)
+        for it in items:
+            it["counts"].fill_(-1)
+        V0 = batch.run()
+        for it, rc in zip(items, ref_counts):
+            assert np.array_equal(it["counts"][:it["plan"].entries].cpu().numpy(), rc), code
+        assert np.allclose(V0, ref_v0, rtol=1e-12, atol=0), code
+
+
 def test_batch_scratch_groups_and_graph_replay(tmp_path):
     print("[gpu-case] batch groups + graph", flush=True)
     items = _contracts(9, shrink=0.1, M=40_000, seed=11)
