@@ -182,7 +182,7 @@ int64_t qtree_plan_get_tune(const qtree_plan *plan, int32_t key);
 /* Autotuner of a plan's LAYERWISE forward: times, with HIP events on
  * `stream`, one forward of M samples per layer (seed `seed`, contract 0,
  * written to `counts`, device int32 [entries]) under each candidate --
- * d = 1: one layer group, or 2, 4, 6 groups with the last at 100, 50 or 33
+ * d = 1: one layer group, or 2, 4, 6, 8 groups with the last at 100, 50 or 33
  * percent of the others; d >= 2: 8 or 4 samples per lane, 1 or 2 groups --
  * three runs each (the fastest counts) after one warm-up, and sets the
  * fastest (QTREE_TUNE_GROUPS, _TAIL,

@@ -1014,7 +1014,7 @@ qtree_status qtree_plan_autotune(qtree_plan* plan, uint64_t M, uint64_t seed, in
   std::vector<Cand> cand;
   if (plan->d == 1) {
     cand.push_back({1, 100, 8});
-    for (int g : {2, 4, 6})
+    for (int g : {2, 4, 6, 8})
       for (int t : {100, 50, 33}) cand.push_back({g, t, 8});
   } else {
     for (int nds : {8, 4})

@@ -437,7 +437,7 @@ def test_autotune_choice_and_every_candidate_give_the_same_counts(name):
     got = plan.autotune(M, seed=seed)
     assert got["ms"] > 0.0
     assert np.array_equal(plan.transitions(M, seed, contract=3).cpu().numpy(), ref)
-    cands = ([(1, 100, 8)] + [(g, t, 8) for g in (2, 4, 6) for t in (100, 50, 33)]
+    cands = ([(1, 100, 8)] + [(g, t, 8) for g in (2, 4, 6, 8) for t in (100, 50, 33)]
              if spec["d"] == 1 else [(g, 100, s) for s in (8, 4) for g in (1, 2)])
     assert (got["groups"], got["tail"], got["nd_samples"]) in cands
     for g, t, s in cands:
